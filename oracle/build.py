@@ -1,0 +1,26 @@
+"""Build the CPU oracle (test infrastructure only) into oracle/liborc.so.
+
+Plain gcc at -O2: no vector intrinsics, no threading, so what it computes
+can be read straight off the C source.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ckks_oracle.c")
+LIB = os.path.join(HERE, "liborc.so")
+
+
+def build(force: bool = True) -> str:
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", SRC, "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force="--lazy" not in sys.argv))
