@@ -1,0 +1,211 @@
+/*
+ * rbk.h -- C ABI of librbk: RNS-CKKS ciphertext arithmetic on AMD gfx950.
+ *
+ * The operations are those ReBoot trains its encrypted MLPs with (paper
+ * Section 3): the parameter set {N, q, Delta}, slot-wise add / sub / mult
+ * (eqs. add, sub, mult), plaintext-ciphertext ops, the rotation Rot(a, k)
+ * with one key per index, and rescaling ("switching to the next prime").
+ * The multiplication is relinearised with hybrid key switching (Han-Ki 2020)
+ * and rotations are Galois automorphisms X -> X^(5^k).
+ *
+ * Memory model
+ *  - Every `d_` pointer is DEVICE memory owned by the caller (PyTorch in the
+ *    Python binding); every other pointer is host memory owned by the caller.
+ *    The library never frees caller memory.
+ *  - A ciphertext at level l is `uint64_t[2][l+1][N]`, a plaintext
+ *    `uint64_t[l+1][N]`; limb i holds residues modulo q_i, canonical in
+ *    [0, q_i).  Batched calls take `count` of them back to back.
+ *  - Device ciphertexts and plaintexts are in the NTT (evaluation) domain:
+ *    limb i of the transform of a(X) holds a(psi_i^(2k+1)) at index
+ *    bit_reverse(k), psi_i the smallest primitive 2N-th root modulo q_i.
+ *    rbk_ntt converts; host-side import/export uses the coefficient domain.
+ *  - Key material (secret, public key, relinearisation and Galois keys)
+ *    lives in device memory owned by the context.
+ *  - Calls are asynchronous on the context's stream unless they return host
+ *    data (rbk_decode, rbk_key_export, rbk_moduli...), which synchronise.
+ *    Device inputs must stay valid until the stream reaches the call.
+ *  - A context is not thread-safe.  Scales are tracked by the caller: these
+ *    functions only transform residues.
+ *
+ * Errors: 0 on success, else a negative RBK_E* code; rbk_last_error()
+ * returns a message for the calling thread.  No C++ exception crosses the ABI.
+ */
+#ifndef RBK_H
+#define RBK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBK_OK 0
+#define RBK_EINVAL (-1)      /* bad argument or shape */
+#define RBK_ENOMEM (-2)      /* host or device allocation failed */
+#define RBK_ELEVEL (-3)      /* level out of range for the operation */
+#define RBK_ENOKEY (-4)      /* secret, public, relinearisation or Galois key missing */
+#define RBK_EDEVICE (-5)     /* HIP runtime error */
+#define RBK_ESTATE (-6)      /* operation needs state that is not set up */
+#define RBK_EUNSUPPORTED (-7)
+
+typedef struct rbk_ctx rbk_ctx;
+
+/* Parameters Theta = {N, q, Delta} of Section 3, in RNS form.
+ *  log_n  : N = 2^log_n, 4 <= log_n <= 17
+ *  n_q    : number of primes of the modulus chain q_0..q_{n_q-1}; the top
+ *           level is L = n_q - 1 and each rescale drops the last prime
+ *  q_bits : bit size of each q_i (log_n+2 .. 60)
+ *  n_p    : number of special primes p_0..p_{n_p-1} of key switching
+ *  p_bits : their bit sizes
+ *  alpha  : primes per key-switching digit (1..16); the number of digits at
+ *           level l is ceil((l+1)/alpha)
+ * Primes: for each requested size b, in the order q_bits then p_bits, the
+ * first q = 2^b - j*2N + 1 (j = 1, 2, ...) that is prime and not yet taken. */
+typedef struct {
+    uint32_t log_n;
+    uint32_t n_q;
+    const uint32_t *q_bits;
+    uint32_t n_p;
+    const uint32_t *p_bits;
+    uint32_t alpha;
+} rbk_params;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on the current HIP device: finds the primes, builds the
+ * NTT and base-conversion tables in device memory.  *out owned by caller,
+ * released with rbk_ctx_destroy. */
+int rbk_ctx_create(const rbk_params *params, rbk_ctx **out);
+int rbk_ctx_destroy(rbk_ctx *ctx);
+/* Stream (hipStream_t, may be NULL for the default stream) for later calls. */
+int rbk_set_stream(rbk_ctx *ctx, void *hip_stream);
+int rbk_sync(rbk_ctx *ctx);
+const char *rbk_last_error(void);
+/* host out[n_q + n_p]: q_0..q_{n_q-1}, p_0..p_{n_p-1} */
+int rbk_moduli(const rbk_ctx *ctx, uint64_t *out);
+/* host out[n_q + n_p]: the psi of each prime */
+int rbk_psi(const rbk_ctx *ctx, uint64_t *out);
+/* number of key-switching digits at `level` (>= 0 on success) */
+int rbk_num_digits(const rbk_ctx *ctx, int level);
+/* Pre-size the device workspace for `count` ciphertexts at `level` doing
+ * hoisted rotations (optional; calls grow it on demand otherwise). */
+int rbk_reserve(rbk_ctx *ctx, int level, int count);
+
+/* ---- transforms --------------------------------------------------------- */
+
+/* In-place forward (inverse = 0) or inverse NTT of d_data[count][n_limbs][N];
+ * limb i of every polynomial uses the prime with table index prime_idx[i]
+ * (host array; 0..n_q-1 are Q primes, n_q.. the special primes).  The index
+ * list must be a run of Q primes 0..a-1 optionally followed by a run of
+ * consecutive special primes starting at p_0, or a run of special primes. */
+int rbk_ntt(rbk_ctx *ctx, uint64_t *d_data, int count, const int *prime_idx, int n_limbs, int inverse);
+
+/* ---- keys (Section 3: sk/pk; rotation keys, one per index) -------------- */
+/* Every random input is drawn by the caller and passed in, so that the same
+ * draws can be replayed elsewhere.  All host arrays, coefficient domain. */
+
+/* s[N]: secret key coefficients (ternary). */
+int rbk_set_secret(rbk_ctx *ctx, const int64_t *s);
+/* pk = (-a s + e, a) over q_0..q_{n_q-1}; a[n_q][N] uniform residues, e[N]. */
+int rbk_keygen_public(rbk_ctx *ctx, const uint64_t *a, const int64_t *e);
+/* Relinearisation key (switches s^2 -> s).  beta = ceil(n_q/alpha) digits;
+ * a[beta][n_q+n_p][N] uniform residues, e[beta][N] errors.  Digit j:
+ *   b_j = -a_j s + e_j + [P]_{q_i} s'  mod q_i for q_i in digit j,
+ *   b_j = -a_j s + e_j                  for every other prime. */
+int rbk_keygen_relin(rbk_ctx *ctx, const uint64_t *a, const int64_t *e);
+/* Key for the automorphism X -> X^g (g odd, < 2N): switches sigma_g(s) -> s.
+ * Same randomness layout as rbk_keygen_relin. */
+int rbk_keygen_galois(rbk_ctx *ctx, uint64_t g, const uint64_t *a, const int64_t *e);
+/* Galois element of a left rotation by k slots: 5^(k mod N/2) mod 2N;
+ * conjugation is 2N-1. */
+uint64_t rbk_galois_elt(const rbk_ctx *ctx, int64_t k);
+/* Copy a key to the host, coefficient domain, [beta][2][n_q+n_p][N]
+ * (g = 0 selects the relinearisation key). */
+int rbk_key_export(rbk_ctx *ctx, uint64_t g, uint64_t *out);
+
+/* ---- encoding and encryption ------------------------------------------- */
+
+/* Encode n <= N/2 complex slot values (im may be NULL) at `scale` into the
+ * plaintext d_pt[level+1][N] (NTT domain).  Slot j sits at zeta^(5^j),
+ * zeta = exp(i pi/N); coefficients are round-half-even(scale * t_k).
+ * RBK_EINVAL if a coefficient reaches 2^62. */
+int rbk_encode(rbk_ctx *ctx, const double *re, const double *im, size_t n, int level, double scale, uint64_t *d_pt);
+/* Decode the first n slots of d_pt (NTT domain, level `level`) at `scale`
+ * into host re[n] / im[n] (im may be NULL).  Uses the exact centred value
+ * modulo q_0 q_1 (q_0 at level 0): the plaintext must satisfy
+ * |m| < q_0 q_1 / 2.  Synchronises. */
+int rbk_decode(rbk_ctx *ctx, const uint64_t *d_pt, int level, double scale, double *re, double *im, size_t n);
+/* ct = (v pk0 + e0 + m, v pk1 + e1); v, e0, e1: host [N] small integers. */
+int rbk_encrypt(rbk_ctx *ctx, const uint64_t *d_pt, int level, const int64_t *v, const int64_t *e0, const int64_t *e1,
+                uint64_t *d_ct);
+/* m = c0 + c1 s (NTT domain), d_pt[level+1][N]. */
+int rbk_decrypt(rbk_ctx *ctx, const uint64_t *d_ct, int level, uint64_t *d_pt);
+
+/* ---- slot-wise ring operations (Section 3, eqs. add / sub / mult) -------- */
+/* npoly polynomials of level+1 limbs each (2 for a ciphertext). */
+int rbk_add(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level, int npoly);
+int rbk_sub(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level, int npoly);
+int rbk_neg(rbk_ctx *ctx, const uint64_t *d_a, uint64_t *d_out, int level, int npoly);
+/* pointwise product of npoly polynomials with as many polynomials */
+int rbk_mul_poly(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level, int npoly);
+/* ct (x) pt: both ciphertext polynomials times the plaintext d_pt[l+1][N] */
+int rbk_mul_plain(rbk_ctx *ctx, const uint64_t *d_ct, const uint64_t *d_pt, uint64_t *d_out, int level);
+/* ct (+) pt: the plaintext is added to c0 */
+int rbk_add_plain(rbk_ctx *ctx, const uint64_t *d_ct, const uint64_t *d_pt, uint64_t *d_out, int level);
+/* every limb i of npoly polynomials times the integer scal[i] (host, < q_i) */
+int rbk_mul_scalar(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *scal, uint64_t *d_out, int level, int npoly);
+/* ct + the constant polynomial with residues scal[i] (host, < q_i) */
+int rbk_add_scalar(rbk_ctx *ctx, const uint64_t *d_ct, const uint64_t *scal, uint64_t *d_out, int level);
+/* (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); d_out[3][l+1][N] */
+int rbk_tensor(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level);
+
+/* ---- hybrid key switching ----------------------------------------------- */
+
+/* ModUp: digits of alpha limbs of d_d[l+1][N], each extended by fast base
+ * conversion to q_0..q_l, p_0..p_{n_p-1}: d_ext[beta_l][l+1+n_p][N]. */
+int rbk_modup(rbk_ctx *ctx, const uint64_t *d_d, uint64_t *d_ext, int level);
+/* (u0, u1) = sum_j ext_j (b_j, a_j) with the key of Galois element g
+ * (g = 0: relinearisation key); d_u[2][l+1+n_p][N]. */
+int rbk_key_inner_product(rbk_ctx *ctx, const uint64_t *d_ext, uint64_t g, uint64_t *d_u, int level);
+/* ModDown of npoly polynomials d_u[npoly][l+1+n_p][N] -> d_out[npoly][l+1][N]:
+ * (u_Q - BConv_{P->Q}(u_P)) * P^-1. */
+int rbk_moddown(rbk_ctx *ctx, const uint64_t *d_u, uint64_t *d_out, int level, int npoly);
+/* KS(d) = ModDown(<ModUp(d), key_g>), d_out[2][l+1][N] */
+int rbk_keyswitch(rbk_ctx *ctx, uint64_t g, const uint64_t *d_d, uint64_t *d_out, int level);
+
+/* ---- ciphertext operations ---------------------------------------------- */
+
+/* Homomorphic product with relinearisation (eq. mult): (d0, d1) + KS(d2).
+ * The scale of the result is the product of the scales. */
+int rbk_mult_relin(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level);
+/* Rescale by q_l: out_i = (c_i - centred(c_l)) q_l^-1 mod q_i; d_out[2][l][N] */
+int rbk_rescale(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level);
+/* NTT-domain automorphism X -> X^g of npoly polynomials of level+1 limbs */
+int rbk_automorph(rbk_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, int level, int npoly, uint64_t g);
+/* Rot(ct, k) of Section 3: slot j of the result is slot j+k (mod N/2) of ct.
+ * Needs the Galois key of 5^k.  ENOKEY otherwise. */
+int rbk_rotate(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level, int64_t k);
+/* complex conjugation of every slot (Galois element 2N-1) */
+int rbk_conjugate(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level);
+/* Hoisted rotations (Halevi-Shoup 2018): one ModUp of c1 shared by n
+ * rotations ks[n]; d_outs[n][2][l+1][N]. */
+int rbk_rotate_hoisted(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, int n, uint64_t *d_outs, int level);
+
+/* ---- batched forms ------------------------------------------------------ */
+/* The same results as `count` separate calls, from one set of launches: the
+ * NTTs, base conversions and key inner products of all ciphertexts go into
+ * single kernels, and each key word is read once per launch for the batch. */
+
+/* d_a, d_b, d_out: [count][2][l+1][N] */
+int rbk_mult_relin_batch(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level, int count);
+/* d_ct: [count][2][l+1][N] -> d_out: [count][2][l][N] */
+int rbk_rescale_batch(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level, int count);
+/* d_ct: [count][2][l+1][N] -> d_outs: [count][n][2][l+1][N] */
+int rbk_rotate_hoisted_batch(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, int n, uint64_t *d_outs, int level,
+                             int count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,497 @@
+// Ring and key-switching kernels of librbk (gfx950).
+//
+// Every polynomial on the device is in the NTT (evaluation) domain unless a
+// kernel says otherwise; a limb is N consecutive uint64 residues in [0, q).
+// Layouts: ciphertext [2][l+1][N]; batch of ciphertexts outermost;
+// ModUp output [beta_l][E][N] with E = l+1+nP positions (q_0..q_l, p_0..);
+// inner-product output [2][E][N].
+#include "rbk_ctx.hpp"
+
+#define EW_THREADS 256
+
+__device__ __forceinline__ u32 brv_bits(u32 x, int bits) { return __brev(x) >> (32 - bits); }
+
+// Source index of an NTT-domain automorphism X -> X^g: the value stored at
+// brv(k) is a(psi^(2k+1)); after sigma_g it is a(psi^((2k+1) g)).
+__device__ __forceinline__ u32 auto_src(u32 o, u64 g, int logN)
+{
+    u32 k = brv_bits(o, logN);
+    u64 e = ((2 * (u64)k + 1) * g) & ((2ull << logN) - 1);
+    return brv_bits((u32)((e - 1) >> 1), logN);
+}
+
+// ---------------------------------------------------------------- elementwise
+
+template <int OP>
+__global__ void k_ew(const u64 *a, const u64 *b, u64 *out, size_t total, int logN, int nlimbs, LimbMap map,
+                     const PrimeC *pc)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= total) return;
+    int limb = (int)((i >> logN) % nlimbs);
+    u64 q = pc[map.prime(limb)].q;
+    u64 x = a[i];
+    if (OP == EW_ADD) out[i] = add_mod(x, b[i], q);
+    else if (OP == EW_SUB) out[i] = sub_mod(x, b[i], q);
+    else if (OP == EW_NEG) out[i] = x == 0 ? 0 : q - x;
+    else if (OP == EW_MUL) out[i] = mul_mod(x, b[i], pc[map.prime(limb)]);
+    else out[i] = x;
+}
+
+void ew_launch(const rbk_ctx_impl *c, EwOp op, const u64 *a, const u64 *b, u64 *out, int npoly, int nlimbs, LimbMap map,
+               hipStream_t st)
+{
+    size_t total = (size_t)npoly * nlimbs * c->N;
+    if (total == 0) return;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    switch (op) {
+    case EW_ADD: hipLaunchKernelGGL(k_ew<EW_ADD>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
+    case EW_SUB: hipLaunchKernelGGL(k_ew<EW_SUB>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
+    case EW_NEG: hipLaunchKernelGGL(k_ew<EW_NEG>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
+    case EW_MUL: hipLaunchKernelGGL(k_ew<EW_MUL>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
+    default: hipLaunchKernelGGL(k_ew<EW_COPY>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
+    }
+}
+
+__global__ void k_mul_scalar(const u64 *a, u64 *out, size_t total, int logN, int nlimbs, LimbMap map, const PrimeC *pc,
+                             ScalArg s)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= total) return;
+    int limb = (int)((i >> logN) % nlimbs);
+    u64 q = pc[map.prime(limb)].q;
+    out[i] = shoup(a[i], s.w[limb], s.wsh[limb], q);
+}
+
+void mul_scalar_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int npoly, int nlimbs, LimbMap map, const ScalArg &s,
+                       hipStream_t st)
+{
+    size_t total = (size_t)npoly * nlimbs * c->N;
+    if (total == 0) return;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_mul_scalar, grid, dim3(EW_THREADS), 0, st, a, out, total, c->logN, nlimbs, map, c->d_pc, s);
+}
+
+// ct + constant: a constant polynomial evaluates to itself at every root, so
+// in the NTT domain it is added to every entry of every limb of c0.
+__global__ void k_add_scalar(const u64 *a, u64 *out, size_t per_poly, int logN, const PrimeC *pc, ScalArg s)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= 2 * per_poly) return;
+    if (i >= per_poly) { out[i] = a[i]; return; }
+    int limb = (int)(i >> logN);
+    out[i] = add_mod(a[i], s.w[limb], pc[limb].q);
+}
+
+void add_scalar_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int nlimbs, const ScalArg &s, hipStream_t st)
+{
+    size_t per = (size_t)nlimbs * c->N;
+    dim3 grid((unsigned)((2 * per + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_add_scalar, grid, dim3(EW_THREADS), 0, st, a, out, per, c->logN, c->d_pc, s);
+}
+
+// small signed integers (coefficient domain) reduced into each limb's prime
+__global__ void k_signed_to_limbs(const i64 *v, u64 *out, size_t total, int logN, int nlimbs, LimbMap map, const PrimeC *pc)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= total) return;
+    size_t k = i & (((size_t)1 << logN) - 1);
+    size_t poly = (i >> logN) / nlimbs;
+    int limb = (int)((i >> logN) % nlimbs);
+    u64 q = pc[map.prime(limb)].q;
+    i64 x = v[(poly << logN) + k];
+    u64 m = x >= 0 ? (u64)x : (u64)(-x);
+    m = m % q;
+    out[i] = (x >= 0 || m == 0) ? m : q - m;
+}
+
+void signed_to_limbs_launch(const rbk_ctx_impl *c, const i64 *v, u64 *out, int npoly, int nlimbs, LimbMap map,
+                            hipStream_t st)
+{
+    size_t total = (size_t)npoly * nlimbs * c->N;
+    if (total == 0) return;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_signed_to_limbs, grid, dim3(EW_THREADS), 0, st, v, out, total, c->logN, nlimbs, map, c->d_pc);
+}
+
+// Tensor product (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1).
+// a, b: [count][2][l+1][N]; out: [count][3][l+1][N].
+__global__ void k_tensor(const u64 *a, const u64 *b, u64 *out, int logN, int L1, int count, const PrimeC *pc)
+{
+    size_t per = (size_t)L1 << logN;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= per * count) return;
+    size_t ct = i / per, r = i % per;
+    int limb = (int)(r >> logN);
+    const PrimeC p = pc[limb];
+    const u64 *A = a + ct * 2 * per, *B = b + ct * 2 * per;
+    u64 a0 = A[r], a1 = A[per + r], b0 = B[r], b1 = B[per + r];
+    u64 *O = out + ct * 3 * per;
+    O[r] = mul_mod(a0, b0, p);
+    u128w s = mul_wide(a0, b1);
+    acc_wide(s, mul_wide(a1, b0));
+    u64 t = redc(s, p.q, p.qneg);                       // (a0 b1 + a1 b0) 2^-64
+    O[per + r] = redc(mul_wide(t, p.r2), p.q, p.qneg);  // undo the 2^-64
+    O[2 * per + r] = mul_mod(a1, b1, p);
+}
+
+void tensor_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, int level, int count, hipStream_t st)
+{
+    size_t total = (size_t)count * (level + 1) * c->N;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_tensor, grid, dim3(EW_THREADS), 0, st, a, b, out, c->logN, level + 1, count, c->d_pc);
+}
+
+// NTT-domain automorphism of npoly x nlimbs limbs (a pure permutation).
+__global__ void k_automorph(const u64 *in, u64 *out, size_t total, int logN, u64 g)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= total) return;
+    size_t base = i & ~(((size_t)1 << logN) - 1);
+    u32 o = (u32)(i & (((size_t)1 << logN) - 1));
+    out[i] = in[base + auto_src(o, g, logN)];
+}
+
+void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int nlimbs, u64 g, hipStream_t st)
+{
+    size_t total = (size_t)npoly * nlimbs * c->N;
+    if (total == 0) return;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_automorph, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, g);
+}
+
+// ---------------------------------------------------------------- base conversion
+
+#define BCONV_MAX_IN 16
+#define BCONV_CHUNK 8
+
+// ModUp conversion.  For digit j (primes [lo, lo+n_in)) and coefficient k:
+//   y_i = x_i (D_j/q_i)^-1 mod q_i,  out_e = sum_i y_i ((D_j/q_i) mod t_e)  mod t_e
+// for every extended-basis position e outside the digit.  Input: coefficient
+// domain [l+1][N] per ciphertext; output written into ext (coefficient domain).
+__global__ __launch_bounds__(EW_THREADS) void k_bconv_modup(const u64 *coef, long coef_stride, u64 *ext, long ext_stride,
+                                                            int logN, int L1, int E, int alpha, int nchunk,
+                                                            const u64 *A, const u64 *Ash, const u64 *M, LimbMap emap,
+                                                            const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int j = blockIdx.y / nchunk, chunk = blockIdx.y % nchunk;
+    const int ct = blockIdx.z;
+    const int lo = j * alpha;
+    int n_in = L1 - lo;
+    if (n_in > alpha) n_in = alpha;
+    const int n_out = E - n_in;
+    const int o0 = chunk * BCONV_CHUNK;
+    if (o0 >= n_out || k >= N) return;
+    const int o1 = min(o0 + BCONV_CHUNK, n_out);
+    const u64 *x = coef + ct * coef_stride;
+    u64 *dst = ext + ct * ext_stride + (size_t)j * E * N;
+
+    u64 y[BCONV_MAX_IN];
+#pragma unroll
+    for (int i = 0; i < BCONV_MAX_IN; i++) {
+        if (i < n_in) {
+            int pi = lo + i;
+            y[i] = shoup(x[(size_t)pi * N + k], A[j * alpha + i], Ash[j * alpha + i], pc[pi].q);
+        }
+    }
+    for (int o = o0; o < o1; o++) {
+        int e = o < lo ? o : o + n_in;
+        const PrimeC p = pc[emap.prime(e)];
+        u128w acc = {0, 0};
+#pragma unroll
+        for (int i = 0; i < BCONV_MAX_IN; i++)
+            if (i < n_in) acc_wide(acc, mul_wide(y[i], M[((size_t)(j * alpha + i)) * E + o]));
+        dst[(size_t)e * N + k] = redc_any(acc, p.q, p.qneg, p.one_sh);
+    }
+}
+
+void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, u64 *ext, long ext_stride, int level,
+                        int count, hipStream_t st)
+{
+    const ModUpTables &T = modup_tables(const_cast<rbk_ctx_impl *>(c), level);
+    int L1 = level + 1, E = L1 + c->nP;
+    int nchunk = (E + BCONV_CHUNK - 1) / BCONV_CHUNK;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), T.beta * nchunk, count);
+    LimbMap emap{0, L1, c->nQ};
+    hipLaunchKernelGGL(k_bconv_modup, grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1, E,
+                       c->alpha, nchunk, T.d_A, T.d_Ash, T.d_M, emap, c->d_pc);
+}
+
+// ModDown conversion P -> q_0..q_l of npoly polynomials (coefficient domain):
+//   y_t = u_t (P/p_t)^-1 mod p_t,  conv_i = sum_t y_t ((P/p_t) mod q_i) mod q_i.
+__global__ __launch_bounds__(EW_THREADS) void k_bconv_moddown(const u64 *pcoef, long p_stride, u64 *conv, long conv_stride,
+                                                              int logN, int L1, int nP, int nQ, int nchunk, const u64 *A,
+                                                              const u64 *Ash, const u64 *M, const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int chunk = blockIdx.y, poly = blockIdx.z;
+    const int o0 = chunk * BCONV_CHUNK;
+    if (o0 >= L1 || k >= N) return;
+    const int o1 = min(o0 + BCONV_CHUNK, L1);
+    const u64 *x = pcoef + poly * p_stride;
+    u64 *dst = conv + poly * conv_stride;
+    u64 y[BCONV_MAX_IN];
+#pragma unroll
+    for (int t = 0; t < BCONV_MAX_IN; t++)
+        if (t < nP) y[t] = shoup(x[(size_t)t * N + k], A[t], Ash[t], pc[nQ + t].q);
+    for (int o = o0; o < o1; o++) {
+        const PrimeC p = pc[o];
+        u128w acc = {0, 0};
+#pragma unroll
+        for (int t = 0; t < BCONV_MAX_IN; t++)
+            if (t < nP) acc_wide(acc, mul_wide(y[t], M[(size_t)t * nQ + o]));
+        dst[(size_t)o * N + k] = redc_any(acc, p.q, p.qneg, p.one_sh);
+    }
+}
+
+void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride, u64 *conv, long conv_stride, int level,
+                          int count, hipStream_t st)
+{
+    int L1 = level + 1;
+    int nchunk = (L1 + BCONV_CHUNK - 1) / BCONV_CHUNK;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), nchunk, count);
+    hipLaunchKernelGGL(k_bconv_moddown, grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
+                       c->nP, c->nQ, nchunk, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
+}
+
+// ---------------------------------------------------------------- key inner product
+
+// (u0, u1)[e] = sum_j ext_j[e] * (b_j, a_j)[t_e], one REDC per output (the key
+// is stored times 2^64).  With g != 0 every digit is read through the
+// automorphism sigma_g (hoisted rotation).  One thread serves one (e, k) for
+// all 'count' ciphertexts, so each key word is fetched once per launch.
+#define IP_MAX_BETA 8
+__global__ __launch_bounds__(EW_THREADS) void k_ip(const u64 *ext, long ext_stride, const u64 *key, u64 *u, long u_stride,
+                                                   int logN, int E, int beta, int nT, int count, LimbMap emap, u64 g,
+                                                   const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int e = blockIdx.y;
+    if (k >= N) return;
+    const int t = emap.prime(e);
+    const PrimeC p = pc[t];
+    u64 kb[IP_MAX_BETA], ka[IP_MAX_BETA];
+#pragma unroll
+    for (int j = 0; j < IP_MAX_BETA; j++)
+        if (j < beta) {
+            kb[j] = key[(((size_t)j * 2 + 0) * nT + t) * N + k];
+            ka[j] = key[(((size_t)j * 2 + 1) * nT + t) * N + k];
+        }
+    const size_t src = g ? auto_src((u32)k, g, logN) : k;
+    for (int ct = 0; ct < count; ct++) {
+        const u64 *x = ext + ct * ext_stride + (size_t)e * N + src;
+        u128w s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < IP_MAX_BETA; j++)
+            if (j < beta) {
+                u64 d = x[(size_t)j * E * N];
+                acc_wide(s0, mul_wide(d, kb[j]));
+                acc_wide(s1, mul_wide(d, ka[j]));
+            }
+        u64 *o = u + ct * u_stride + (size_t)e * N + k;
+        o[0] = redc_any(s0, p.q, p.qneg, p.one_sh);
+        o[(size_t)E * N] = redc_any(s1, p.q, p.qneg, p.one_sh);
+    }
+}
+
+void ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *u, long u_stride, int level,
+               int count, u64 g, hipStream_t st)
+{
+    int L1 = level + 1, E = L1 + c->nP;
+    int beta_l = (L1 + c->alpha - 1) / c->alpha;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), E, 1);
+    LimbMap emap{0, L1, c->nQ};
+    hipLaunchKernelGGL(k_ip, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, u, u_stride, c->logN, E, beta_l, c->nT,
+                       count, emap, g, c->d_pc);
+}
+
+// out[p][i] = (u[p][i] - conv[p][i]) * P^-1 mod q_i  (+ add_p[i], read through
+// sigma_{add_g} when add_g != 0).  u: [2][E][N] per ct (Q positions first);
+// conv/out/add: [2][l+1][N] per ct.  add may be null; add is applied to
+// poly 0 always and to poly 1 only when add_both != 0.
+__global__ void k_moddown_finish(const u64 *u, long u_stride, const u64 *conv, long conv_stride, const u64 *add,
+                                 long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int logN, int L1, int E,
+                                 int count, const u64 *Pinv, const u64 *Pinv_sh, const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t per = (size_t)L1 * N;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= 2 * per * count) return;
+    size_t ct = i / (2 * per), r = i % (2 * per);
+    int poly = (int)(r / per);
+    size_t rr = r % per;
+    int limb = (int)(rr >> logN);
+    size_t k = rr & (N - 1);
+    u64 q = pc[limb].q;
+    u64 uv = u[ct * u_stride + (size_t)poly * E * N + rr];
+    u64 cv = conv[ct * conv_stride + r];
+    u64 v = shoup(sub_mod(uv, cv, q), Pinv[limb], Pinv_sh[limb], q);
+    if (add && (poly == 0 || add_both)) {
+        size_t src = add_g ? auto_src((u32)k, add_g, logN) : k;
+        v = add_mod(v, add[ct * add_stride + (size_t)poly * per + ((size_t)limb << logN) + src], q);
+    }
+    out[ct * out_stride + r] = v;
+}
+
+void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, const u64 *conv, long conv_stride,
+                           const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
+                           int count, hipStream_t st)
+{
+    int L1 = level + 1, E = L1 + c->nP;
+    size_t total = (size_t)2 * L1 * c->N * count;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_moddown_finish, grid, dim3(EW_THREADS), 0, st, u, u_stride, conv, conv_stride, add, add_stride,
+                       add_g, add_both, out, out_stride, c->logN, L1, E, count, c->d_Pinv, c->d_Pinv_sh, c->d_pc);
+}
+
+// ---------------------------------------------------------------- rescale
+
+// lifted[p][i] = centred(last[p]) mod q_i  for i < l   (coefficient domain)
+__global__ void k_rescale_lift(const u64 *last, u64 *lifted, int logN, int level, int npoly, const PrimeC *pc,
+                               const u64 *qmod)
+{
+    const size_t N = (size_t)1 << logN;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    size_t per = (size_t)level * N;
+    if (i >= per * npoly) return;
+    size_t poly = i / per, r = i % per;
+    int limb = (int)(r >> logN);
+    size_t k = r & (N - 1);
+    const PrimeC p = pc[limb];
+    u64 ql = pc[level].q;
+    u64 x = last[poly * N + k];
+    u64 xm = shoup(x, 1, p.one_sh, p.q);
+    lifted[i] = (x <= (ql - 1) / 2) ? xm : sub_mod(xm, qmod[limb], p.q);
+}
+
+void rescale_lift_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, int level, int npoly, hipStream_t st)
+{
+    size_t total = (size_t)npoly * level * c->N;
+    if (total == 0) return;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_rescale_lift, grid, dim3(EW_THREADS), 0, st, last, lifted, c->logN, level, npoly, c->d_pc,
+                       c->d_rs_qmod + (size_t)level * c->nQ);
+}
+
+// out[p][i] = (in[p][i] - lifted[p][i]) * q_l^-1 mod q_i;  in: [npoly][l+1][N], out/lifted: [npoly][l][N]
+__global__ void k_rescale_finish(const u64 *in, const u64 *lifted, u64 *out, int logN, int level, int npoly,
+                                 const PrimeC *pc, const u64 *inv, const u64 *inv_sh)
+{
+    const size_t N = (size_t)1 << logN;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    size_t per = (size_t)level * N;
+    if (i >= per * npoly) return;
+    size_t poly = i / per, r = i % per;
+    int limb = (int)(r >> logN);
+    u64 q = pc[limb].q;
+    u64 x = in[poly * (per + N) + r];
+    out[i] = shoup(sub_mod(x, lifted[i], q), inv[limb], inv_sh[limb], q);
+}
+
+void rescale_finish_launch(const rbk_ctx_impl *c, const u64 *in, const u64 *lifted, u64 *out, int level, int npoly,
+                           hipStream_t st)
+{
+    size_t total = (size_t)npoly * level * c->N;
+    if (total == 0) return;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_rescale_finish, grid, dim3(EW_THREADS), 0, st, in, lifted, out, c->logN, level, npoly, c->d_pc,
+                       c->d_rs_inv + (size_t)level * c->nQ, c->d_rs_inv_sh + (size_t)level * c->nQ);
+}
+
+// ---------------------------------------------------------------- keys, encryption
+
+// Switching key, NTT domain, every prime of the table:
+//   b_j = -a_j s + e_j (+ [P]_{q_t} s' on the primes of digit j),  stored with a_j
+// in Montgomery form.  a, e: [beta][nT][N]; s, s_from: [nT][N]; key: [beta][2][nT][N].
+__global__ void k_keygen(const u64 *a, const u64 *e, const u64 *s, const u64 *s_from, u64 *key, int logN, int nT, int nQ,
+                         int alpha, int beta, const PrimeC *pc, const u64 *Pmod, const u64 *Pmod_sh)
+{
+    const size_t N = (size_t)1 << logN;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    size_t per = (size_t)nT * N;
+    if (i >= per * beta) return;
+    int j = (int)(i / per);
+    size_t r = i % per;
+    int t = (int)(r >> logN);
+    const PrimeC p = pc[t];
+    u64 av = a[i], ev = e[i], sv = s[r];
+    u64 b = sub_mod(ev, mul_mod(av, sv, p), p.q);
+    if (t < nQ && t / alpha == j) b = add_mod(b, shoup(s_from[r], Pmod[t], Pmod_sh[t], p.q), p.q);
+    u64 *kj = key + (size_t)j * 2 * per;
+    kj[r] = redc(mul_wide(b, p.r2), p.q, p.qneg);
+    kj[per + r] = redc(mul_wide(av, p.r2), p.q, p.qneg);
+}
+
+void keygen_launch(const rbk_ctx_impl *c, const u64 *a_ntt, const u64 *e_ntt, const u64 *s_from, u64 *key_out,
+                   hipStream_t st)
+{
+    size_t total = (size_t)c->beta * c->nT * c->N;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_keygen, grid, dim3(EW_THREADS), 0, st, a_ntt, e_ntt, c->d_s, s_from, key_out, c->logN, c->nT,
+                       c->nQ, c->alpha, c->beta, c->d_pc, c->d_Pmod, c->d_Pmod_sh);
+}
+
+// x -> x 2^64 mod q (forward) or x 2^-64 mod q (inverse)
+__global__ void k_to_mont(u64 *d, size_t total, int logN, int nlimbs, LimbMap map, const PrimeC *pc, int inverse)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= total) return;
+    int limb = (int)((i >> logN) % nlimbs);
+    const PrimeC p = pc[map.prime(limb)];
+    u128w x = {d[i], 0};
+    d[i] = inverse ? redc(x, p.q, p.qneg) : redc(mul_wide(d[i], p.r2), p.q, p.qneg);
+}
+
+void to_mont_launch(const rbk_ctx_impl *c, u64 *data, int npoly, int nlimbs, LimbMap map, bool inverse, hipStream_t st)
+{
+    size_t total = (size_t)npoly * nlimbs * c->N;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_to_mont, grid, dim3(EW_THREADS), 0, st, data, total, c->logN, nlimbs, map, c->d_pc, inverse ? 1 : 0);
+}
+
+// ct = (v pk0 + e0 + m, v pk1 + e1) at level l; all operands NTT domain.
+__global__ void k_encrypt(const u64 *pt, const u64 *v, const u64 *e0, const u64 *e1, const u64 *pk, u64 *ct, int logN,
+                          int L1, int nQ, const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    size_t per = (size_t)L1 * N;
+    if (i >= per) return;
+    int limb = (int)(i >> logN);
+    const PrimeC p = pc[limb];
+    u64 vv = v[i];
+    ct[i] = add_mod(add_mod(mul_mod(vv, pk[i], p), e0[i], p.q), pt[i], p.q);
+    ct[per + i] = add_mod(mul_mod(vv, pk[(size_t)nQ * N + i], p), e1[i], p.q);
+}
+
+void encrypt_launch(const rbk_ctx_impl *c, const u64 *pt, const u64 *v, const u64 *e0, const u64 *e1, u64 *ct, int level,
+                    hipStream_t st)
+{
+    size_t total = (size_t)(level + 1) * c->N;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_encrypt, grid, dim3(EW_THREADS), 0, st, pt, v, e0, e1, c->d_pk, ct, c->logN, level + 1, c->nQ,
+                       c->d_pc);
+}
+
+// m = c0 + c1 s at level l (NTT domain)
+__global__ void k_decrypt(const u64 *ct, const u64 *s, u64 *pt, int logN, int L1, const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    size_t per = (size_t)L1 * N;
+    if (i >= per) return;
+    int limb = (int)(i >> logN);
+    const PrimeC p = pc[limb];
+    pt[i] = add_mod(ct[i], mul_mod(ct[per + i], s[i], p), p.q);
+}
+
+void decrypt_launch(const rbk_ctx_impl *c, const u64 *ct, u64 *pt, int level, hipStream_t st)
+{
+    size_t total = (size_t)(level + 1) * c->N;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_decrypt, grid, dim3(EW_THREADS), 0, st, ct, c->d_s, pt, c->logN, level + 1, c->d_pc);
+}

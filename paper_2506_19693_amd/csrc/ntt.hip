@@ -1,0 +1,214 @@
+// Negacyclic NTT / inverse NTT over 64-bit primes for gfx950.
+//
+// Convention: the forward transform of a limb a (coefficient order) writes
+// a(psi^(2k+1)) to index brv(k) (Cooley-Tukey with psi merged into the
+// twiddles, Longa-Naehrig 2016); the inverse (Gentleman-Sande) takes that
+// order back to coefficients and folds N^-1 into its last stage.
+//
+// Work split: one limb is viewed as an R x C matrix (C = 2^logC contiguous
+// elements per row).  Stages whose butterfly distance is >= C only mix
+// elements of one column; the others only mix elements of one row.  The
+// forward transform therefore runs a column pass (stages 0..r-1) then a row
+// pass (stages r..n-1); the inverse runs them in the other order.  Each pass
+// stages a 4096-element tile (32 KiB) through LDS: a column tile is R rows x
+// (4096/R) adjacent columns, so every row segment is a 128-byte (or longer)
+// coalesced run; a row tile is 4096/C whole rows.  When N <= 4096 one row
+// pass does the whole transform.
+//
+// Value ranges follow Harvey: forward butterflies keep [0, 4q), inverse
+// butterflies [0, 2q); each pass that ends a transform reduces to [0, q).
+#include "rbk_internal.hpp"
+#include "rbk_ctx.hpp"
+
+#define NTT_TILE 4096
+#define NTT_THREADS 256
+
+__device__ __forceinline__ void bfly_ct(u64 &x, u64 &y, u64 w, u64 wsh, u64 q, u64 q2)
+{
+    u64 xx = csub(x, q2);
+    u64 t = shoup_lazy(y, w, wsh, q);
+    x = xx + t;
+    y = xx + q2 - t;
+}
+
+__device__ __forceinline__ void bfly_gs(u64 &x, u64 &y, u64 w, u64 wsh, u64 q, u64 q2)
+{
+    u64 s = csub(x + y, q2);
+    u64 d = x + q2 - y;
+    x = s;
+    y = shoup_lazy(d, w, wsh, q);
+}
+
+// Row pass.  Forward: stages (logN-logC) .. logN-1, output reduced to [0, q).
+// Inverse: distances 1 .. C/2; if logC == logN this is the whole inverse
+// (N^-1 folded into the last stage, output in [0, q)), else output in [0, 2q).
+template <bool INV>
+__global__ __launch_bounds__(NTT_THREADS) void k_ntt_rows(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN,
+                                                          int logC, int rows_per_tile)
+{
+    __shared__ u64 s[NTT_TILE];
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    const int pr = map.prime(limb);
+    const size_t N = (size_t)1 << logN;
+    const PrimeC pc = T.pc[pr];
+    const u64 q = pc.q, q2 = 2 * q;
+    const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
+    const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
+    const int C = 1 << logC;
+    const int row0 = blockIdx.x * rows_per_tile;
+    const int nel = rows_per_tile * C;
+    u64 *g = data + (size_t)poly * poly_stride + (size_t)limb * N + (size_t)row0 * C;
+
+    for (int i = threadIdx.x; i < nel; i += NTT_THREADS) s[i] = g[i];
+    __syncthreads();
+
+    const int half = nel >> 1;
+    const int hmask = (C >> 1) - 1;
+    if (!INV) {
+        for (int st = logN - logC; st < logN; st++) {
+            const int lt = logN - 1 - st;  // log2 of the butterfly distance
+            for (int b = threadIdx.x; b < half; b += NTT_THREADS) {
+                int rl = b >> (logC - 1), kk = b & hmask;
+                int grp = kk >> lt, off = kk & ((1 << lt) - 1);
+                int x0 = (grp << (lt + 1)) + off;
+                int gi = ((row0 + rl) << (logC - lt - 1)) + grp;
+                int ti = (1 << st) + gi;
+                u64 &x = s[rl * C + x0];
+                u64 &y = s[rl * C + x0 + (1 << lt)];
+                bfly_ct(x, y, tw[ti], tws[ti], q, q2);
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < nel; i += NTT_THREADS) g[i] = csub(csub(s[i], q2), q);
+    } else {
+        const bool whole = (logC == logN);
+        for (int lt = 0; lt < logC; lt++) {
+            const int h = 1 << (logN - 1 - lt);
+            const bool last = whole && (lt == logC - 1);
+            for (int b = threadIdx.x; b < half; b += NTT_THREADS) {
+                int rl = b >> (logC - 1), kk = b & hmask;
+                int grp = kk >> lt, off = kk & ((1 << lt) - 1);
+                int x0 = (grp << (lt + 1)) + off;
+                int gi = ((row0 + rl) << (logC - lt - 1)) + grp;
+                u64 &x = s[rl * C + x0];
+                u64 &y = s[rl * C + x0 + (1 << lt)];
+                if (!last) {
+                    bfly_gs(x, y, tw[h + gi], tws[h + gi], q, q2);
+                } else {
+                    u64 sum = csub(x + y, q2);
+                    u64 d = x + q2 - y;
+                    x = shoup_lazy(sum, pc.ninv, pc.ninv_sh, q);
+                    y = shoup_lazy(d, T.last[pr], T.last_sh[pr], q);
+                }
+            }
+            __syncthreads();
+        }
+        if (whole)
+            for (int i = threadIdx.x; i < nel; i += NTT_THREADS) g[i] = csub(s[i], q);
+        else
+            for (int i = threadIdx.x; i < nel; i += NTT_THREADS) g[i] = s[i];
+    }
+}
+
+// Column pass over R = 2^(logN-logC) rows and 'cols' adjacent columns.
+// Forward: stages 0 .. r-1, output in [0, 4q).  Inverse: distances C .. N/2,
+// N^-1 folded into the last stage, output in [0, q).
+template <bool INV>
+__global__ __launch_bounds__(NTT_THREADS) void k_ntt_cols(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN,
+                                                          int logC, int logCt)
+{
+    __shared__ u64 s[NTT_TILE];
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    const int pr = map.prime(limb);
+    const size_t N = (size_t)1 << logN;
+    const PrimeC pc = T.pc[pr];
+    const u64 q = pc.q, q2 = 2 * q;
+    const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
+    const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
+    const int r = logN - logC, R = 1 << r, C = 1 << logC, Ct = 1 << logCt;
+    const int c0 = blockIdx.x * Ct;
+    const int nel = R * Ct;
+    u64 *g = data + (size_t)poly * poly_stride + (size_t)limb * N + c0;
+
+    for (int i = threadIdx.x; i < nel; i += NTT_THREADS) {
+        int row = i >> logCt, col = i & (Ct - 1);
+        s[i] = g[(size_t)row * C + col];
+    }
+    __syncthreads();
+
+    const int half = nel >> 1;
+    if (!INV) {
+        for (int st = 0; st < r; st++) {
+            const int ltr = r - 1 - st;
+            for (int b = threadIdx.x; b < half; b += NTT_THREADS) {
+                int col = b & (Ct - 1), k = b >> logCt;
+                int grp = k >> ltr, off = k & ((1 << ltr) - 1);
+                int r0 = (grp << (ltr + 1)) + off;
+                int ti = (1 << st) + grp;
+                u64 &x = s[(r0 << logCt) + col];
+                u64 &y = s[((r0 + (1 << ltr)) << logCt) + col];
+                bfly_ct(x, y, tw[ti], tws[ti], q, q2);
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < nel; i += NTT_THREADS) {
+            int row = i >> logCt, col = i & (Ct - 1);
+            g[(size_t)row * C + col] = s[i];
+        }
+    } else {
+        for (int ltr = 0; ltr < r; ltr++) {
+            const int h = 1 << (r - 1 - ltr);
+            const bool last = (ltr == r - 1);
+            for (int b = threadIdx.x; b < half; b += NTT_THREADS) {
+                int col = b & (Ct - 1), k = b >> logCt;
+                int grp = k >> ltr, off = k & ((1 << ltr) - 1);
+                int r0 = (grp << (ltr + 1)) + off;
+                u64 &x = s[(r0 << logCt) + col];
+                u64 &y = s[((r0 + (1 << ltr)) << logCt) + col];
+                if (!last) {
+                    bfly_gs(x, y, tw[h + grp], tws[h + grp], q, q2);
+                } else {
+                    u64 sum = csub(x + y, q2);
+                    u64 d = x + q2 - y;
+                    x = shoup_lazy(sum, pc.ninv, pc.ninv_sh, q);
+                    y = shoup_lazy(d, T.last[pr], T.last_sh[pr], q);
+                }
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < nel; i += NTT_THREADS) {
+            int row = i >> logCt, col = i & (Ct - 1);
+            g[(size_t)row * C + col] = csub(s[i], q);
+        }
+    }
+}
+
+void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, bool inverse,
+                hipStream_t st)
+{
+    if (npoly <= 0 || nlimbs <= 0) return;
+    const int logN = c->logN, logC = c->ntt_logC;
+    const int r = logN - logC;
+    NttTables T = c->tabs;
+    if (r == 0) {
+        dim3 grid(1, nlimbs, npoly);
+        if (inverse)
+            hipLaunchKernelGGL(k_ntt_rows<true>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, 1);
+        else
+            hipLaunchKernelGGL(k_ntt_rows<false>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, 1);
+        return;
+    }
+    const int rows_per_tile = NTT_TILE >> logC;       // row pass
+    const int logCt = 12 - r;                          // column pass: 4096 / R columns
+    dim3 grow((1 << r) / rows_per_tile, nlimbs, npoly);
+    dim3 gcol((1 << logC) >> logCt, nlimbs, npoly);
+    if (!inverse) {
+        hipLaunchKernelGGL(k_ntt_cols<false>, gcol, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, logCt);
+        hipLaunchKernelGGL(k_ntt_rows<false>, grow, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC,
+                           rows_per_tile);
+    } else {
+        hipLaunchKernelGGL(k_ntt_rows<true>, grow, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC,
+                           rows_per_tile);
+        hipLaunchKernelGGL(k_ntt_cols<true>, gcol, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, logCt);
+    }
+}

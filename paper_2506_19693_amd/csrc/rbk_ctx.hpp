@@ -1,0 +1,107 @@
+// Host-side context of librbk: parameters, prime tables, device constant
+// tables, key material and the device workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rbk_internal.hpp"
+
+// ModUp base-conversion tables of one level: digit j converts its own
+// primes D_j = [lo_j, hi_j) to every other position of the extended basis.
+struct ModUpTables {
+    int level = -1;
+    int beta = 0;
+    std::vector<int> lo, n_in;
+    u64 *d_A = nullptr;    // [beta][alpha]   (D_j / q_i)^-1 mod q_i
+    u64 *d_Ash = nullptr;  // [beta][alpha]   Shoup quotients
+    u64 *d_M = nullptr;    // [beta][alpha][E] (D_j / q_i) mod t * 2^64 mod t, by output position
+};
+
+struct rbk_ctx_impl {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int logN = 0;
+    size_t N = 0;
+    int nQ = 0, nP = 0, nT = 0, alpha = 1, beta = 1;
+    int ntt_logC = 0;
+    std::vector<u64> mod, psi;
+    std::vector<PrimeC> h_pc;
+
+    // device constant tables
+    PrimeC *d_pc = nullptr;
+    u64 *d_tw = nullptr, *d_tw_sh = nullptr, *d_itw = nullptr, *d_itw_sh = nullptr;
+    u64 *d_last = nullptr, *d_last_sh = nullptr;
+    NttTables tabs{};
+
+    // ModDown P -> Q (level independent, indexed by Q prime)
+    u64 *d_md_A = nullptr, *d_md_Ash = nullptr;  // [nP]
+    u64 *d_md_M = nullptr;                       // [nP][nQ]   Montgomery form
+    u64 *d_Pinv = nullptr, *d_Pinv_sh = nullptr; // [nQ]
+    std::vector<u64> h_Pmod;                     // P mod q_i, every prime of Q
+    u64 *d_Pmod = nullptr, *d_Pmod_sh = nullptr; // [nQ]
+    int *d_pow5 = nullptr;                       // [N/2]  (5^j mod 2N - 1) / 2
+
+    // rescale by q_l: [l][i] = q_l^-1 mod q_i, its Shoup quotient, q_l mod q_i
+    u64 *d_rs_inv = nullptr, *d_rs_inv_sh = nullptr, *d_rs_qmod = nullptr;  // [nQ][nQ]
+
+    std::map<int, ModUpTables> modup;
+
+    // key material (NTT domain)
+    u64 *d_s = nullptr;   // [nT][N] secret
+    u64 *d_pk = nullptr;  // [2][nQ][N]
+    DevKey relin;
+    std::map<u64, DevKey> gal;
+
+    // workspace (grow-only)
+    u64 *ws = nullptr;
+    size_t ws_words = 0;
+
+    std::vector<void *> owned;  // device allocations freed at destroy
+};
+
+// ---- helpers implemented in api.hip ----
+u64 *ws_reserve(rbk_ctx_impl *c, size_t words);
+const ModUpTables &modup_tables(rbk_ctx_impl *c, int level);
+
+// ---- kernel launchers implemented in kernels.hip ----
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_MUL = 3, EW_COPY = 4 };
+
+struct ScalArg {
+    u64 w[RBK_MAX_PRIMES];
+    u64 wsh[RBK_MAX_PRIMES];
+};
+
+void ew_launch(const rbk_ctx_impl *c, EwOp op, const u64 *a, const u64 *b, u64 *out, int npoly, int nlimbs, LimbMap map,
+               hipStream_t st);
+void mul_scalar_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int npoly, int nlimbs, LimbMap map, const ScalArg &s,
+                       hipStream_t st);
+void add_scalar_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int nlimbs, const ScalArg &s, hipStream_t st);
+void signed_to_limbs_launch(const rbk_ctx_impl *c, const i64 *v, u64 *out, int npoly, int nlimbs, LimbMap map,
+                            hipStream_t st);
+void tensor_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, int level, int count, hipStream_t st);
+void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int nlimbs, u64 g, hipStream_t st);
+void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, u64 *ext, long ext_stride, int level,
+                        int count, hipStream_t st);
+void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride, u64 *conv, long conv_stride, int level,
+                          int count, hipStream_t st);
+void ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *u, long u_stride, int level,
+               int count, u64 g, hipStream_t st);
+void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, const u64 *conv, long conv_stride,
+                           const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
+                           int count, hipStream_t st);
+void rescale_lift_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, int level, int npoly, hipStream_t st);
+void rescale_finish_launch(const rbk_ctx_impl *c, const u64 *in, const u64 *lifted, u64 *out, int level, int npoly,
+                           hipStream_t st);
+void keygen_launch(const rbk_ctx_impl *c, const u64 *a_ntt, const u64 *e_ntt, const u64 *s_from, u64 *key_out,
+                   hipStream_t st);
+void to_mont_launch(const rbk_ctx_impl *c, u64 *data, int npoly, int nlimbs, LimbMap map, bool inverse, hipStream_t st);
+void encrypt_launch(const rbk_ctx_impl *c, const u64 *pt, const u64 *v, const u64 *e0, const u64 *e1, u64 *ct, int level,
+                    hipStream_t st);
+void encode_launch(const rbk_ctx_impl *c, const double *d_re, const double *d_im, size_t n, int level, double scale,
+                   u64 *pt, double *fft_ws, int *err_flag, hipStream_t st);
+void decode_launch(const rbk_ctx_impl *c, const u64 *pt_coef, int level, double scale, double *d_re, double *d_im,
+                   size_t n, double *fft_ws, hipStream_t st);
+void decrypt_launch(const rbk_ctx_impl *c, const u64 *ct, u64 *pt, int level, hipStream_t st);

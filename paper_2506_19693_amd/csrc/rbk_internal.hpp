@@ -1,0 +1,48 @@
+// Internal declarations shared by the HIP translation units of librbk.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "modarith.hpp"
+
+#define RBK_MAX_PRIMES 80
+
+// Position -> prime-table index of a run of limbs.  Position p of the run is
+// (pos0 + i); positions below 'split' are Q primes with the same index,
+// the others are special primes P_(p - split), stored after the nQ Q primes.
+// A run over the Q basis at level l uses split >= l+1; a run over the
+// extended basis (q_0..q_l, p_0..p_{k-1}) uses split = l+1.
+struct LimbMap {
+    int pos0;
+    int split;
+    int nQ;
+    __host__ __device__ int prime(int i) const
+    {
+        int p = pos0 + i;
+        return p < split ? p : nQ + (p - split);
+    }
+};
+
+struct NttTables {
+    const u64 *tw, *tw_sh;    // [nprimes][N], psi^brv(k) and Shoup quotients
+    const u64 *itw, *itw_sh;  // [nprimes][N], psi^-brv(k)
+    const u64 *last, *last_sh;  // [nprimes], psi^-brv(1) * N^-1
+    const PrimeC *pc;
+};
+
+// A switching key on the device: beta digits of (b, a) over every prime,
+// NTT domain, each residue stored times 2^64 (Montgomery form).
+struct DevKey {
+    u64 *data = nullptr;  // [beta][2][nT][N]
+    u64 g = 0;            // Galois element, 0 for the relinearisation key
+};
+
+struct rbk_ctx_impl;
+
+// ---- launchers (defined in the .hip files) ----
+void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, bool inverse,
+                hipStream_t st);

@@ -1,0 +1,409 @@
+"""Thin ctypes binding of librbk (include/rbk.h).
+
+Argument marshalling only: every operation runs in the HIP kernels of
+librbk.so.  PyTorch supplies device memory (int64 tensors that hold the
+uint64 residues bit for bit) and the current stream.  If the library is not
+built, or no GPU is visible, calls fail loudly: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbk.so")
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+dblp = ctypes.POINTER(ctypes.c_double)
+vp = ctypes.c_void_p
+ci = ctypes.c_int
+cu64 = ctypes.c_uint64
+
+
+class RbkParams(ctypes.Structure):
+    _fields_ = [
+        ("log_n", ctypes.c_uint32),
+        ("n_q", ctypes.c_uint32),
+        ("q_bits", ctypes.POINTER(ctypes.c_uint32)),
+        ("n_p", ctypes.c_uint32),
+        ("p_bits", ctypes.POINTER(ctypes.c_uint32)),
+        ("alpha", ctypes.c_uint32),
+    ]
+
+
+# name -> (restype, argtypes); the declarations of include/rbk.h
+SIGNATURES = {
+    "rbk_ctx_create": (ci, [ctypes.POINTER(RbkParams), ctypes.POINTER(vp)]),
+    "rbk_ctx_destroy": (ci, [vp]),
+    "rbk_set_stream": (ci, [vp, vp]),
+    "rbk_sync": (ci, [vp]),
+    "rbk_last_error": (ctypes.c_char_p, []),
+    "rbk_moduli": (ci, [vp, u64p]),
+    "rbk_psi": (ci, [vp, u64p]),
+    "rbk_num_digits": (ci, [vp, ci]),
+    "rbk_reserve": (ci, [vp, ci, ci]),
+    "rbk_ntt": (ci, [vp, vp, ci, ctypes.POINTER(ci), ci, ci]),
+    "rbk_set_secret": (ci, [vp, i64p]),
+    "rbk_keygen_public": (ci, [vp, u64p, i64p]),
+    "rbk_keygen_relin": (ci, [vp, u64p, i64p]),
+    "rbk_keygen_galois": (ci, [vp, cu64, u64p, i64p]),
+    "rbk_galois_elt": (cu64, [vp, ctypes.c_int64]),
+    "rbk_key_export": (ci, [vp, cu64, u64p]),
+    "rbk_encode": (ci, [vp, dblp, dblp, ctypes.c_size_t, ci, ctypes.c_double, vp]),
+    "rbk_decode": (ci, [vp, vp, ci, ctypes.c_double, dblp, dblp, ctypes.c_size_t]),
+    "rbk_encrypt": (ci, [vp, vp, ci, i64p, i64p, i64p, vp]),
+    "rbk_decrypt": (ci, [vp, vp, ci, vp]),
+    "rbk_add": (ci, [vp, vp, vp, vp, ci, ci]),
+    "rbk_sub": (ci, [vp, vp, vp, vp, ci, ci]),
+    "rbk_neg": (ci, [vp, vp, vp, ci, ci]),
+    "rbk_mul_poly": (ci, [vp, vp, vp, vp, ci, ci]),
+    "rbk_mul_plain": (ci, [vp, vp, vp, vp, ci]),
+    "rbk_add_plain": (ci, [vp, vp, vp, vp, ci]),
+    "rbk_mul_scalar": (ci, [vp, vp, u64p, vp, ci, ci]),
+    "rbk_add_scalar": (ci, [vp, vp, u64p, vp, ci]),
+    "rbk_tensor": (ci, [vp, vp, vp, vp, ci]),
+    "rbk_modup": (ci, [vp, vp, vp, ci]),
+    "rbk_key_inner_product": (ci, [vp, vp, cu64, vp, ci]),
+    "rbk_moddown": (ci, [vp, vp, vp, ci, ci]),
+    "rbk_keyswitch": (ci, [vp, cu64, vp, vp, ci]),
+    "rbk_mult_relin": (ci, [vp, vp, vp, vp, ci]),
+    "rbk_rescale": (ci, [vp, vp, vp, ci]),
+    "rbk_automorph": (ci, [vp, vp, vp, ci, ci, cu64]),
+    "rbk_rotate": (ci, [vp, vp, vp, ci, ctypes.c_int64]),
+    "rbk_conjugate": (ci, [vp, vp, vp, ci]),
+    "rbk_rotate_hoisted": (ci, [vp, vp, i64p, ci, vp, ci]),
+    "rbk_mult_relin_batch": (ci, [vp, vp, vp, vp, ci, ci]),
+    "rbk_rescale_batch": (ci, [vp, vp, vp, ci, ci]),
+    "rbk_rotate_hoisted_batch": (ci, [vp, vp, i64p, ci, vp, ci, ci]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load librbk.so (built by paper_2506_19693_amd/build.py).  Raises if absent."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librbk.so is not built: run python paper_2506_19693_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class RbkError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc < 0:
+        raise RbkError("librbk error %d: %s" % (rc, load().rbk_last_error().decode()))
+    return rc
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("librbk needs a ROCm GPU: torch.cuda.is_available() is False")
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _h_u64(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return a, a.ctypes.data_as(u64p)
+
+
+def _h_i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(i64p)
+
+
+def to_device(arr):
+    """uint64 numpy array -> int64 CUDA tensor with the same bits."""
+    torch = _torch()
+    a = np.ascontiguousarray(arr, dtype=np.uint64).view(np.int64)
+    return torch.from_numpy(a.copy()).to("cuda")
+
+
+def to_host(t):
+    """int64 CUDA tensor -> uint64 numpy array with the same bits."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+class Context:
+    """One librbk context: ring degree 2^log_n, Q chain of sizes q_bits,
+    special primes p_bits, alpha primes per key-switching digit."""
+
+    def __init__(self, log_n, q_bits, p_bits, alpha):
+        torch = _torch()
+        self.lib = load()
+        self.log_n = int(log_n)
+        self.N = 1 << self.log_n
+        self.nQ = len(q_bits)
+        self.nP = len(p_bits)
+        self.alpha = int(alpha)
+        self.L = self.nQ - 1
+        qb = (ctypes.c_uint32 * max(1, len(q_bits)))(*q_bits)
+        pb = (ctypes.c_uint32 * max(1, len(p_bits)))(*p_bits)
+        prm = RbkParams(self.log_n, self.nQ, qb, self.nP, pb, self.alpha)
+        h = vp()
+        _check(self.lib.rbk_ctx_create(ctypes.byref(prm), ctypes.byref(h)))
+        self.h = h
+        self.set_stream(torch.cuda.current_stream())
+        m = np.zeros(self.nQ + self.nP, dtype=np.uint64)
+        _check(self.lib.rbk_moduli(self.h, m.ctypes.data_as(u64p)))
+        self.moduli = [int(x) for x in m]
+        p = np.zeros(self.nQ + self.nP, dtype=np.uint64)
+        _check(self.lib.rbk_psi(self.h, p.ctypes.data_as(u64p)))
+        self.psi = [int(x) for x in p]
+        self.beta = self.num_digits(self.L)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbk_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- misc
+    def set_stream(self, stream):
+        _check(self.lib.rbk_set_stream(self.h, vp(stream.cuda_stream)))
+
+    def sync(self):
+        _check(self.lib.rbk_sync(self.h))
+
+    def num_digits(self, level):
+        return _check(self.lib.rbk_num_digits(self.h, level))
+
+    def reserve(self, level, count):
+        _check(self.lib.rbk_reserve(self.h, level, count))
+
+    def empty(self, *shape):
+        torch = _torch()
+        return torch.empty(shape, dtype=torch.int64, device="cuda")
+
+    def empty_ct(self, level, count=None):
+        if count is None:
+            return self.empty(2, level + 1, self.N)
+        return self.empty(count, 2, level + 1, self.N)
+
+    def ntt(self, t, prime_idx, inverse=False):
+        """In-place NTT of t viewed as [count][len(prime_idx)][N]."""
+        nl = len(prime_idx)
+        count = t.numel() // (nl * self.N)
+        idx = (ci * nl)(*prime_idx)
+        _check(self.lib.rbk_ntt(self.h, _ptr(t), count, idx, nl, 1 if inverse else 0))
+        return t
+
+    def to_ntt(self, arr, level):
+        """Host coefficient-domain residues [..][level+1][N] -> device NTT domain."""
+        t = to_device(arr)
+        return self.ntt(t, list(range(level + 1)))
+
+    def to_coef(self, t, level):
+        """Device NTT-domain residues [..][level+1][N] -> host coefficient domain."""
+        c = t.clone()
+        self.ntt(c, list(range(level + 1)), inverse=True)
+        return to_host(c)
+
+    # ---------------------------------------------------------------- keys
+    def set_secret(self, s):
+        s, ps = _h_i64(s)
+        _check(self.lib.rbk_set_secret(self.h, ps))
+
+    def keygen_public(self, a, e):
+        a, pa = _h_u64(a)
+        e, pe = _h_i64(e)
+        _check(self.lib.rbk_keygen_public(self.h, pa, pe))
+
+    def keygen_relin(self, a, e):
+        a, pa = _h_u64(a)
+        e, pe = _h_i64(e)
+        _check(self.lib.rbk_keygen_relin(self.h, pa, pe))
+
+    def keygen_galois(self, g, a, e):
+        a, pa = _h_u64(a)
+        e, pe = _h_i64(e)
+        _check(self.lib.rbk_keygen_galois(self.h, int(g), pa, pe))
+
+    def galois_elt(self, k):
+        return int(self.lib.rbk_galois_elt(self.h, int(k)))
+
+    def galois_conj(self):
+        return 2 * self.N - 1
+
+    def key_export(self, g=0):
+        out = np.zeros((self.beta, 2, self.nQ + self.nP, self.N), dtype=np.uint64)
+        _check(self.lib.rbk_key_export(self.h, int(g), out.ctypes.data_as(u64p)))
+        return out
+
+    # ---------------------------------------------------------------- encoding
+    def encode(self, z, level, scale):
+        z = np.asarray(z)
+        re = np.ascontiguousarray(z.real, dtype=np.float64)
+        im = np.ascontiguousarray(z.imag, dtype=np.float64) if np.iscomplexobj(z) else None
+        pt = self.empty(level + 1, self.N)
+        _check(self.lib.rbk_encode(self.h, re.ctypes.data_as(dblp), im.ctypes.data_as(dblp) if im is not None else None,
+                                   len(re), level, float(scale), _ptr(pt)))
+        return pt
+
+    def decode(self, pt, level, scale, n=None):
+        n = self.N // 2 if n is None else n
+        re = np.zeros(n)
+        im = np.zeros(n)
+        _check(self.lib.rbk_decode(self.h, _ptr(pt), level, float(scale), re.ctypes.data_as(dblp), im.ctypes.data_as(dblp), n))
+        return re + 1j * im
+
+    def encrypt(self, pt, level, v, e0, e1):
+        v, pv = _h_i64(v)
+        e0, p0 = _h_i64(e0)
+        e1, p1 = _h_i64(e1)
+        ct = self.empty_ct(level)
+        _check(self.lib.rbk_encrypt(self.h, _ptr(pt), level, pv, p0, p1, _ptr(ct)))
+        return ct
+
+    def decrypt(self, ct, level):
+        pt = self.empty(level + 1, self.N)
+        _check(self.lib.rbk_decrypt(self.h, _ptr(ct), level, _ptr(pt)))
+        return pt
+
+    # ---------------------------------------------------------------- ring ops
+    def _npoly(self, t, level):
+        return t.numel() // ((level + 1) * self.N)
+
+    def add(self, a, b, level):
+        out = self.empty(*a.shape)
+        _check(self.lib.rbk_add(self.h, _ptr(a), _ptr(b), _ptr(out), level, self._npoly(a, level)))
+        return out
+
+    def sub(self, a, b, level):
+        out = self.empty(*a.shape)
+        _check(self.lib.rbk_sub(self.h, _ptr(a), _ptr(b), _ptr(out), level, self._npoly(a, level)))
+        return out
+
+    def neg(self, a, level):
+        out = self.empty(*a.shape)
+        _check(self.lib.rbk_neg(self.h, _ptr(a), _ptr(out), level, self._npoly(a, level)))
+        return out
+
+    def mul_poly(self, a, b, level):
+        out = self.empty(*a.shape)
+        _check(self.lib.rbk_mul_poly(self.h, _ptr(a), _ptr(b), _ptr(out), level, self._npoly(a, level)))
+        return out
+
+    def mul_plain(self, ct, pt, level):
+        out = self.empty_ct(level)
+        _check(self.lib.rbk_mul_plain(self.h, _ptr(ct), _ptr(pt), _ptr(out), level))
+        return out
+
+    def add_plain(self, ct, pt, level):
+        out = self.empty_ct(level)
+        _check(self.lib.rbk_add_plain(self.h, _ptr(ct), _ptr(pt), _ptr(out), level))
+        return out
+
+    def mul_scalar(self, a, scal, level):
+        s, ps = _h_u64(scal)
+        out = self.empty(*a.shape)
+        _check(self.lib.rbk_mul_scalar(self.h, _ptr(a), ps, _ptr(out), level, self._npoly(a, level)))
+        return out
+
+    def add_scalar(self, ct, scal, level):
+        s, ps = _h_u64(scal)
+        out = self.empty_ct(level)
+        _check(self.lib.rbk_add_scalar(self.h, _ptr(ct), ps, _ptr(out), level))
+        return out
+
+    def tensor(self, a, b, level):
+        out = self.empty(3, level + 1, self.N)
+        _check(self.lib.rbk_tensor(self.h, _ptr(a), _ptr(b), _ptr(out), level))
+        return out
+
+    # ---------------------------------------------------------------- key switching
+    def modup(self, d, level):
+        E = level + 1 + self.nP
+        out = self.empty(self.num_digits(level), E, self.N)
+        _check(self.lib.rbk_modup(self.h, _ptr(d), _ptr(out), level))
+        return out
+
+    def key_inner_product(self, ext, g, level):
+        E = level + 1 + self.nP
+        out = self.empty(2, E, self.N)
+        _check(self.lib.rbk_key_inner_product(self.h, _ptr(ext), int(g), _ptr(out), level))
+        return out
+
+    def moddown(self, u, level):
+        E = level + 1 + self.nP
+        npoly = u.numel() // (E * self.N)
+        out = self.empty(npoly, level + 1, self.N)
+        _check(self.lib.rbk_moddown(self.h, _ptr(u), _ptr(out), level, npoly))
+        return out
+
+    def keyswitch(self, g, d, level):
+        out = self.empty_ct(level)
+        _check(self.lib.rbk_keyswitch(self.h, int(g), _ptr(d), _ptr(out), level))
+        return out
+
+    def mult_relin(self, a, b, level):
+        out = self.empty_ct(level)
+        _check(self.lib.rbk_mult_relin(self.h, _ptr(a), _ptr(b), _ptr(out), level))
+        return out
+
+    def rescale(self, ct, level):
+        out = self.empty_ct(level - 1)
+        _check(self.lib.rbk_rescale(self.h, _ptr(ct), _ptr(out), level))
+        return out
+
+    def automorph(self, t, g, level):
+        out = self.empty(*t.shape)
+        _check(self.lib.rbk_automorph(self.h, _ptr(t), _ptr(out), level, self._npoly(t, level), int(g)))
+        return out
+
+    def rotate(self, ct, k, level):
+        out = self.empty_ct(level)
+        _check(self.lib.rbk_rotate(self.h, _ptr(ct), _ptr(out), level, int(k)))
+        return out
+
+    def conjugate(self, ct, level):
+        out = self.empty_ct(level)
+        _check(self.lib.rbk_conjugate(self.h, _ptr(ct), _ptr(out), level))
+        return out
+
+    def rotate_hoisted(self, ct, ks, level):
+        ks_a, pk = _h_i64(ks)
+        out = self.empty(len(ks), 2, level + 1, self.N)
+        _check(self.lib.rbk_rotate_hoisted(self.h, _ptr(ct), pk, len(ks), _ptr(out), level))
+        return out
+
+    # ---------------------------------------------------------------- batched
+    def mult_relin_batch(self, a, b, level, out=None):
+        count = a.shape[0]
+        out = self.empty_ct(level, count) if out is None else out
+        _check(self.lib.rbk_mult_relin_batch(self.h, _ptr(a), _ptr(b), _ptr(out), level, count))
+        return out
+
+    def rescale_batch(self, ct, level, out=None):
+        count = ct.shape[0]
+        out = self.empty_ct(level - 1, count) if out is None else out
+        _check(self.lib.rbk_rescale_batch(self.h, _ptr(ct), _ptr(out), level, count))
+        return out
+
+    def rotate_hoisted_batch(self, ct, ks, level, out=None):
+        count = ct.shape[0]
+        ks_a, pk = _h_i64(ks)
+        out = self.empty(count, len(ks), 2, level + 1, self.N) if out is None else out
+        _check(self.lib.rbk_rotate_hoisted_batch(self.h, _ptr(ct), pk, len(ks), _ptr(out), level, count))
+        return out

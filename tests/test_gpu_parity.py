@@ -1,0 +1,280 @@
+"""GPU (librbk) against the CPU oracle, residue by residue, on the same seeded
+inputs.  Integer results must be bit-exact; the float64 encoder must agree to
+within one unit of the rounded coefficient."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+ROTS = (1, 2, 7, -1, -3, 16)
+
+PARAMS = {
+    # N = 2^10, 5 Q primes, 2 special primes, digits of 2, 2, 1 primes
+    "tiny": (10, [60, 50, 50, 50, 50], [60, 60], 2),
+    # N = 2^12, one 50-bit and three 40-bit primes, one 50-bit special prime, one prime per digit
+    "c0": (12, [50, 40, 40, 40], [50], 1),
+    # N = 2^13 exercises the two-pass NTT inside the whole pipeline
+    "mid": (13, [60, 50, 50, 50], [60, 60], 3),
+}
+
+
+class Pair:
+    """The same keys, built from the same random draws, on both sides."""
+
+    def __init__(self, name, seed=5):
+        from paper_2506_19693_amd import Context
+
+        logN, qb, pb, alpha = PARAMS[name]
+        self.g = S.rng(seed, logN)
+        self.orc = O.Oracle(logN, qb, pb, alpha)
+        self.gpu = Context(logN, qb, pb, alpha)
+        o, d = self.orc, self.gpu
+        assert o.moduli == d.moduli and o.psi == d.psi
+        N = o.N
+        self.N = N
+        self.s = S.ternary(self.g, N)
+        d.set_secret(self.s)
+        a, e = S.uniform_residues(self.g, o.Q, N), S.gaussian(self.g, N)
+        self.pk = o.keygen_public(self.s, a, e)
+        d.keygen_public(a, e)
+        a, e = S.key_randomness(self.g, o.beta, o.moduli, N)
+        self.rlk = o.keygen_relin(self.s, a, e)
+        d.keygen_relin(a, e)
+        self.gal = {}
+        for k in ROTS + ("conj",):
+            gal = o.galois_conj() if k == "conj" else o.galois_rot(k)
+            assert k == "conj" or gal == d.galois_elt(k)
+            a, e = S.key_randomness(self.g, o.beta, o.moduli, N)
+            self.gal[k] = (gal, o.keygen_galois(self.s, gal, a, e))
+            d.keygen_galois(gal, a, e)
+
+    def rand_ct(self, level, lead=(2,)):
+        return S.uniform_residues(self.g, self.orc.Q[: level + 1], self.N, lead=lead)
+
+    def ext_idx(self, level):
+        return self.orc.ext_indices(level)
+
+
+_PAIRS = {}
+
+
+def pair(name):
+    if name not in _PAIRS:
+        _PAIRS[name] = Pair(name)
+    return _PAIRS[name]
+
+
+def up(p, arr, level):
+    return p.gpu.to_ntt(arr, level)
+
+
+def down(p, t, level):
+    return p.gpu.to_coef(t, level)
+
+
+# ---------------------------------------------------------------- NTT
+
+@pytest.mark.parametrize("logN", [4, 10, 12, 13, 14, 15, 16])
+def test_ntt_matches_oracle(logN):
+    from paper_2506_19693_amd import Context, to_device, to_host
+
+    qb, pb = [60, 50, 40], [60, 55]
+    ctx = Context(logN, qb, pb, 1)
+    orc = O.Oracle(logN, qb, pb, 1)
+    assert ctx.moduli == orc.moduli and ctx.psi == orc.psi
+    g = S.rng(21, logN)
+    N = 1 << logN
+    idx = [0, 1, 2, 3, 4]            # every prime, Q then P
+    a = S.uniform_residues(g, orc.moduli, N, lead=(3,))
+    t = to_device(a)
+    ctx.ntt(t, idx)
+    got = to_host(t)
+    for c in range(3):
+        for l in range(5):
+            assert np.array_equal(got[c][l], orc.limb_ntt(l, a[c][l])), (c, l)
+    ctx.ntt(t, idx, inverse=True)
+    assert np.array_equal(to_host(t), a)
+    # special primes alone (as in ModDown)
+    b = S.uniform_residues(g, orc.P, N)
+    tb = to_device(b)
+    ctx.ntt(tb, [3, 4])
+    got = to_host(tb)
+    for l in range(2):
+        assert np.array_equal(got[l], orc.limb_ntt(3 + l, b[l]))
+
+
+# ---------------------------------------------------------------- keys, enc/dec
+
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_keys_bit_exact(name):
+    p = pair(name)
+    assert np.array_equal(p.gpu.key_export(0), p.rlk)
+    for k in (1, -3, "conj"):
+        gal, key = p.gal[k]
+        assert np.array_equal(p.gpu.key_export(gal), key)
+
+
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_encrypt_decrypt_bit_exact(name):
+    p = pair(name)
+    o, d = p.orc, p.gpu
+    for level in (o.L, 1, 0):
+        m = S.uniform_residues(p.g, o.Q[: level + 1], p.N)
+        v, e0, e1 = S.encryption_randomness(p.g, p.N)
+        want = o.encrypt(level, p.pk, m, v, e0, e1)
+        ct = d.encrypt(up(p, m, level), level, v, e0, e1)
+        assert np.array_equal(down(p, ct, level), want)
+        assert np.array_equal(down(p, d.decrypt(ct, level), level), o.decrypt(level, p.s, want))
+
+
+# ---------------------------------------------------------------- ring ops
+
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_ring_ops_bit_exact(name):
+    p = pair(name)
+    o, d = p.orc, p.gpu
+    for level in (o.L, 1):
+        a, b = p.rand_ct(level), p.rand_ct(level)
+        pt = S.uniform_residues(p.g, o.Q[: level + 1], p.N)
+        A, B, PT = up(p, a, level), up(p, b, level), up(p, pt, level)
+        assert np.array_equal(down(p, d.add(A, B, level), level), o.add(level, a, b))
+        assert np.array_equal(down(p, d.sub(A, B, level), level), o.sub(level, a, b))
+        assert np.array_equal(down(p, d.neg(A, level), level), o.neg(level, a))
+        assert np.array_equal(down(p, d.mul_plain(A, PT, level), level), o.mul_plain(level, a, pt))
+        assert np.array_equal(down(p, d.add_plain(A, PT, level), level), o.add_plain(level, a, pt))
+        sc = np.array([int(p.g.integers(0, q)) for q in o.Q[: level + 1]], dtype=np.uint64)
+        assert np.array_equal(down(p, d.mul_scalar(A, sc, level), level), o.mul_scalar(level, a, sc))
+        assert np.array_equal(down(p, d.add_scalar(A, sc, level), level), o.add_scalar(level, a, sc))
+        assert np.array_equal(down(p, d.tensor(A, B, level), level), o.tensor(level, a, b))
+        for gal in (5, 25, 2 * p.N - 1):
+            assert np.array_equal(down(p, d.automorph(A, gal, level), level), o.automorph(level, gal, a))
+
+
+# ---------------------------------------------------------------- key switching pieces
+
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_modup_ip_moddown_bit_exact(name):
+    p = pair(name)
+    o, d = p.orc, p.gpu
+    for level in sorted({o.L, o.L - 1, 0}):
+        x = S.uniform_residues(p.g, o.Q[: level + 1], p.N)
+        ext_o = o.modup(level, x)
+        ext_d = d.modup(up(p, x, level), level)
+        idx = p.ext_idx(level)
+        assert np.array_equal(d.ntt(ext_d.clone(), idx, inverse=True).cpu().numpy().view(np.uint64), ext_o)
+        for gk in (0, p.gal[1][0]):
+            key = p.rlk if gk == 0 else p.gal[1][1]
+            u_o = o.key_inner_product(level, ext_o, key)
+            u_d = d.key_inner_product(ext_d, gk, level)
+            got = d.ntt(u_d.clone(), idx, inverse=True).cpu().numpy().view(np.uint64)
+            assert np.array_equal(got, u_o)
+            md_o = np.stack([o.moddown(level, u_o[0]), o.moddown(level, u_o[1])])
+            md_d = d.moddown(u_d, level)
+            assert np.array_equal(down(p, md_d, level), md_o)
+        # odd polynomial count through moddown
+        md1 = d.moddown(u_d[0:1].contiguous(), level)
+        assert np.array_equal(down(p, md1, level)[0], o.moddown(level, u_o[0]))
+
+
+# ---------------------------------------------------------------- ciphertext operations
+
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_ciphertext_ops_bit_exact(name):
+    p = pair(name)
+    o, d = p.orc, p.gpu
+    for level in sorted({o.L, o.L - 1, 1}):
+        a, b = p.rand_ct(level), p.rand_ct(level)
+        A, B = up(p, a, level), up(p, b, level)
+        x = S.uniform_residues(p.g, o.Q[: level + 1], p.N)
+        assert np.array_equal(down(p, d.keyswitch(0, up(p, x, level), level), level), o.keyswitch(level, p.rlk, x))
+        assert np.array_equal(down(p, d.mult_relin(A, B, level), level), o.mult_relin(level, p.rlk, a, b))
+        assert np.array_equal(down(p, d.rescale(A, level), level - 1), o.rescale(level, a))
+        for k in (1, -3, 16):
+            gal, key = p.gal[k]
+            assert np.array_equal(down(p, d.rotate(A, k, level), level), o.rotate(level, key, gal, a)), k
+        gal, key = p.gal["conj"]
+        assert np.array_equal(down(p, d.conjugate(A, level), level), o.rotate(level, key, gal, a))
+        ks = [1, 2, 7, -1]
+        h_o = o.rotate_hoisted(level, [p.gal[k][1] for k in ks], [p.gal[k][0] for k in ks], a)
+        h_d = d.rotate_hoisted(A, ks, level)
+        assert np.array_equal(down(p, h_d, level), h_o)
+        # rotation by 0 is the identity
+        assert np.array_equal(down(p, d.rotate_hoisted(A, [0], level), level)[0], a)
+
+
+@pytest.mark.parametrize("name", ["tiny", "mid"])
+def test_batched_equals_plain(name):
+    p = pair(name)
+    d = p.gpu
+    level = p.orc.L
+    cnt = 3
+    a = p.rand_ct(level, lead=(cnt, 2))
+    b = p.rand_ct(level, lead=(cnt, 2))
+    A, B = up(p, a, level), up(p, b, level)
+    mb = d.mult_relin_batch(A, B, level)
+    rb = d.rescale_batch(A, level)
+    ks = [1, 2, 7, 16, 0]
+    hb = d.rotate_hoisted_batch(A, ks, level)
+    for c in range(cnt):
+        assert np.array_equal(down(p, mb[c], level), down(p, d.mult_relin(A[c], B[c], level), level))
+        assert np.array_equal(down(p, rb[c], level - 1), down(p, d.rescale(A[c], level), level - 1))
+        assert np.array_equal(down(p, hb[c], level), down(p, d.rotate_hoisted(A[c], ks, level), level))
+
+
+# ---------------------------------------------------------------- encoding and end to end
+
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_encoder_within_one_unit(name):
+    p = pair(name)
+    o, d = p.orc, p.gpu
+    n = p.N // 2
+    z = S.uniform_slots(p.g, n) + 1j * S.uniform_slots(p.g, n)
+    for scale in (2.0 ** 30, 2.0 ** 45):
+        level = o.L
+        want = O.crt_centered(O.encode(z, p.N, scale, o.Q), o.Q)
+        got = O.crt_centered(down(p, d.encode(z, level, scale), level), o.Q)
+        assert max(abs(int(a) - int(b)) for a, b in zip(want, got)) <= 1
+        # decode of the oracle's plaintext
+        pt = up(p, O.encode(z, p.N, scale, o.Q), level)
+        back = d.decode(pt, level, scale)
+        assert np.max(np.abs(back - z)) < 1e-6
+    # partial slot vectors are zero padded
+    zz = S.uniform_slots(p.g, 5)
+    back = d.decode(d.encode(zz, 0, 2.0 ** 30), 0, 2.0 ** 30, n=8)
+    assert np.max(np.abs(back[:5] - zz)) < 1e-6 and np.max(np.abs(back[5:])) < 1e-6
+
+
+def test_c0_end_to_end_gpu_precision():
+    """Encrypt two vectors, mult_relin, rescale, rotate +1 and +7, add, decrypt:
+    within 2^-20 of float64, all on the GPU."""
+    p = pair("c0")
+    o, d = p.orc, p.gpu
+    N, L = p.N, o.L
+    D = 2.0 ** 40
+    x, y = S.uniform_slots(p.g, N // 2), S.uniform_slots(p.g, N // 2)
+    cx = d.encrypt(d.encode(x, L, D), L, *S.encryption_randomness(p.g, N))
+    cy = d.encrypt(d.encode(y, L, D), L, *S.encryption_randomness(p.g, N))
+    cr = d.rescale(d.mult_relin(cx, cy, L), L)
+    sc = D * D / o.Q[L]
+    tot = d.add(d.rotate(cr, 1, L - 1), d.rotate(cr, 7, L - 1), L - 1)
+    got = d.decode(d.decrypt(tot, L - 1), L - 1, sc).real
+    xy = x * y
+    want = np.roll(xy, -1) + np.roll(xy, -7)
+    assert np.max(np.abs(got - want)) < 2.0 ** -20
+
+
+def test_errors_are_reported():
+    from paper_2506_19693_amd import RbkError
+
+    p = pair("tiny")
+    d = p.gpu
+    A = up(p, p.rand_ct(2), 2)
+    with pytest.raises(RbkError):
+        d.rotate(A, 5, 2)             # no key for 5
+    with pytest.raises(RbkError):
+        d.rescale(up(p, p.rand_ct(0), 0), 0)   # nothing to drop at level 0
+    with pytest.raises(RbkError):
+        d.mult_relin(A, A, 9)
