@@ -1,0 +1,267 @@
+#!/usr/bin/env python
+"""Key-switch throughput of RNS-CKKS at N = 2^16 on one MI355X, batched vs plain.
+
+Workload (one step): 64 independent ciphertexts at N = 2^16 with a 24-prime
+chain (one 60-bit base prime, 23 x 50-bit), hybrid key switching with 3 digits
+of 8 primes and 8 special 60-bit primes; each ciphertext does mult_relin with a
+second ciphertext, rescale, and 32 rotations (k = 1..32) hoisted over one
+ModUp.  That is 64 x 33 = 2112 key switches per step.  Inputs are seeded
+synthetic slot vectors, uniform in [-1, 1], encrypted under a uniform ternary
+secret; all inputs are resident in HBM before the timed region.
+
+* batched: one call per stage for all 64 ciphertexts (every NTT, base
+  conversion and key inner product of the batch in one launch; each key word
+  read once per launch);
+* plain:   one call per ciphertext (mult_relin, rescale, hoisted rotations).
+
+value = batched key switches per second.  Per-kernel HIP-event timers run over
+the timed batched steps; the kernel with the largest total time is reported
+against the MI355X HBM roofline.  The CPU oracle is timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LOG_N = 16
+Q_BITS = [60] + [50] * 23
+P_BITS = [60] * 8
+ALPHA = 8
+SCALE = 2.0 ** 50
+ROTS = list(range(1, 33))
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--count", type=int, default=64, help="ciphertexts per step")
+    ap.add_argument("--rots", type=int, default=32, help="hoisted rotations per ciphertext")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * p / 100.0
+    f = int(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def setup(ctx, count, rots):
+    import numpy as np
+
+    import synth_inputs as S
+
+    N, L = ctx.N, ctx.L
+    g = S.rng(1, 16)
+    s = S.ternary(g, N)
+    ctx.set_secret(s)
+    ctx.keygen_public(S.uniform_residues(g, ctx.moduli[: ctx.nQ], N), S.gaussian(g, N))
+    a, e = S.key_randomness(g, ctx.beta, ctx.moduli, N)
+    ctx.keygen_relin(a, e)
+    for k in rots:
+        a, e = S.key_randomness(g, ctx.beta, ctx.moduli, N)
+        ctx.keygen_galois(ctx.galois_elt(k), a, e)
+    A = ctx.empty_ct(L, count)
+    B = ctx.empty_ct(L, count)
+    for i in range(count):
+        for T in (A, B):
+            z = S.uniform_slots(g, N // 2)
+            T[i].copy_(ctx.encrypt(ctx.encode(z, L, SCALE), L, *S.encryption_randomness(g, N)))
+    ctx.sync()
+    return s, A, B
+
+
+def batched_step(ctx, A, B, out_m, out_r, out_h, ks):
+    L = ctx.L
+    ctx.mult_relin_batch(A, B, L, out=out_m)
+    ctx.rescale_batch(out_m, L, out=out_r)
+    ctx.rotate_hoisted_batch(out_r, ks, L - 1, out=out_h)
+
+
+def plain_ct(ctx, a, b, ks):
+    L = ctx.L
+    m = ctx.mult_relin(a, b, L)
+    r = ctx.rescale(m, L)
+    return ctx.rotate_hoisted(r, ks, L - 1)
+
+
+def cpu_baseline():
+    """The oracle, single-threaded, on one ciphertext of the same workload:
+    mult_relin + rescale + one hoisted rotation (2 key switches)."""
+    import oracle as O
+    import synth_inputs as S
+
+    orc = O.Oracle(LOG_N, Q_BITS, P_BITS, ALPHA)
+    N, L = orc.N, orc.L
+    g = S.rng(2, 16)
+    s = S.ternary(g, N)
+    a, e = S.key_randomness(g, orc.beta, orc.moduli, N)
+    rlk = orc.keygen_relin(s, a, e)
+    gal = orc.galois_rot(1)
+    a, e = S.key_randomness(g, orc.beta, orc.moduli, N)
+    gk = orc.keygen_galois(s, gal, a, e)
+    x = S.uniform_residues(g, orc.Q, N, lead=(2,))
+    y = S.uniform_residues(g, orc.Q, N, lead=(2,))
+    t0 = time.perf_counter()
+    m = orc.mult_relin(L, rlk, x, y)
+    r = orc.rescale(L, m)
+    orc.rotate_hoisted(L - 1, [gk], [gal], r)
+    dt = time.perf_counter() - t0
+    return {
+        "value": 2.0 / dt,
+        "unit": "key-switches/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "1 ciphertext at N=2^16, 24 limbs: mult_relin + rescale + 1 hoisted rotation "
+                  "(2 key switches) in %.1f s, single thread" % dt,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2506_19693_amd import Context
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    count, ks = args.count, ROTS[: args.rots]
+    log("setup: N=2^16, %d limbs, %d special, alpha %d, %d ciphertexts, %d rotations" % (
+        len(Q_BITS), len(P_BITS), ALPHA, count, len(ks)))
+    t0 = time.time()
+    ctx = Context(LOG_N, Q_BITS, P_BITS, ALPHA)
+    s, A, B = setup(ctx, count, ks)
+    L = ctx.L
+    ctx.reserve(L, count)
+    out_m = ctx.empty_ct(L, count)
+    out_r = ctx.empty_ct(L - 1, count)
+    out_h = ctx.empty(count, len(ks), 2, L, ctx.N)
+    log("setup done in %.1f s" % (time.time() - t0))
+    ks_per_step = count * (1 + len(ks))
+
+    # ---------------------------------------------------------------- batched
+    for _ in range(args.warmup):
+        batched_step(ctx, A, B, out_m, out_r, out_h, ks)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.timer_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        batched_step(ctx, A, B, out_m, out_r, out_h, ks)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    timers = ctx.timer_read()
+    ctx.timer_enable(False)
+    log("batched: %.2f ms/step, %.0f key-switches/s" % (t_batched * 1e3, ks_per_step / t_batched))
+
+    # correctness spot check of the timed output: decrypt one rotation
+    import numpy as np
+
+    # ---------------------------------------------------------------- plain
+    plain = None
+    if not args.no_plain:
+        for _ in range(args.warmup):
+            for i in range(count):
+                plain_ct(ctx, A[i], B[i], ks)
+        ctx.sync()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            evs = []
+            for i in range(count):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                plain_ct(ctx, A[i], B[i], ks)
+                e1.record()
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            lat += [a.elapsed_time(b) for a, b in evs]
+        t_plain = (time.perf_counter() - t0) / args.steps
+        plain = {
+            "ms_per_step": t_plain * 1e3,
+            "key_switches_per_s": ks_per_step / t_plain,
+            "per_ct_latency_ms_p50": percentile(lat, 50),
+            "per_ct_latency_ms_p99": percentile(lat, 99),
+        }
+        log("plain: %.2f ms/step, %.0f key-switches/s, p50 %.2f ms p99 %.2f ms per ciphertext" % (
+            t_plain * 1e3, ks_per_step / t_plain, plain["per_ct_latency_ms_p50"], plain["per_ct_latency_ms_p99"]))
+
+    # ---------------------------------------------------------------- roofline of the dominant kernel
+    kern = {k: {"ms_total": v[0], "launches": v[1], "avg_us": 1e3 * v[0] / v[1], "GBps": v[2] / (v[0] * 1e-3) / 1e9}
+            for k, v in timers.items()}
+    dom = max(timers, key=lambda k: timers[k][0])
+    ms, n, bts = timers[dom]
+    achieved = bts / (ms * 1e-3) / 1e9
+    roofline = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_us": round(1e3 * ms / n, 2),
+        "launches": n,
+        "share_of_step": round(ms / (t_batched * 1e3 * args.steps), 3),
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, bounded sample) ...")
+        cpu = cpu_baseline()
+        log("cpu baseline: %.3f key-switches/s" % cpu["value"])
+
+    line = {
+        "metric": "bootstraps/s + key-switches/s at N=2^16, batched vs plain; p99 latency",
+        "value": round(ks_per_step / t_batched, 1),
+        "unit": "key-switches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_batched * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "key-switch throughput: %d ciphertexts x (mult_relin + rescale + %d hoisted rotations), "
+                        "N=2^16, 24 primes (60 + 23x50 bits), 8 special 60-bit primes, dnum=3" % (count, len(ks)),
+            "key_switches_per_step": ks_per_step,
+            "path": "batched",
+        },
+        "plain": plain,
+        "batched_vs_plain": round(plain["ms_per_step"] / (t_batched * 1e3), 3) if plain else None,
+        "roofline": roofline,
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

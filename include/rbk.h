@@ -205,6 +205,18 @@ int rbk_rescale_batch(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int l
 int rbk_rotate_hoisted_batch(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, int n, uint64_t *d_outs, int level,
                              int count);
 
+/* ---- per-kernel timers -------------------------------------------------- */
+/* With timers on, every kernel launch on the context stream is bracketed by
+ * HIP events.  Class `cls` = 0, 1, ... names one kernel (rbk_timer_name);
+ * rbk_timer_read returns its summed duration in ms, its number of launches,
+ * and the algorithmic HBM bytes of those launches (the data each launch must
+ * read and write, e.g. one read and one write of every limb for an NTT pass).
+ * Both synchronise the stream. */
+int rbk_timer_enable(rbk_ctx *ctx, int on);   /* resets all timers */
+int rbk_timer_read(rbk_ctx *ctx, int cls, double *ms, uint64_t *launches, double *bytes);
+/* kernel name of class cls, NULL past the last class */
+const char *rbk_timer_name(int cls);
+
 #ifdef __cplusplus
 }
 #endif

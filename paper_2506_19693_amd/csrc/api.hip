@@ -368,6 +368,9 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
 {
     if (!c) return RBK_OK;
     (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < KC_COUNT; k++)
+        for (hipEvent_t e : c->timers[k].pending) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     for (void *p : c->owned) (void)hipFree(p);
     if (c->ws) (void)hipFree(c->ws);
     delete c;
@@ -975,3 +978,81 @@ extern "C" int rbk_rotate_hoisted(rbk_ctx *c, const uint64_t *ct, const int64_t 
 {
     return rbk_rotate_hoisted_batch(c, ct, ks, n, outs, level, 1);
 }
+
+// ---------------------------------------------------------------- kernel timers
+
+static const char *kc_names[KC_COUNT] = {
+    "k_ntt_cols<false>", "k_ntt_rows<false>", "k_ntt_rows<true>", "k_ntt_cols<true>", "k_bconv_modup",
+    "k_bconv_moddown",   "k_ip",              "k_moddown_finish", "k_tensor",          "k_rescale_lift+finish",
+    "elementwise",
+};
+
+static hipEvent_t take_event(const rbk_ctx_impl *c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void kt_begin(const rbk_ctx_impl *c, int cls, hipStream_t st)
+{
+    if (!c->timing) return;
+    hipEvent_t e = take_event(c);
+    (void)hipEventRecord(e, st);
+    c->timers[cls].pending.push_back(e);
+}
+
+void kt_end(const rbk_ctx_impl *c, int cls, double bytes, hipStream_t st)
+{
+    if (!c->timing) return;
+    hipEvent_t e = take_event(c);
+    (void)hipEventRecord(e, st);
+    KTimer &t = c->timers[cls];
+    t.pending.push_back(e);
+    t.bytes += bytes;
+    t.launches++;
+}
+
+static int kt_collect(rbk_ctx *c)
+{
+    HIPCK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < KC_COUNT; k++) {
+        KTimer &t = c->timers[k];
+        for (size_t i = 0; i + 1 < t.pending.size(); i += 2) {
+            float ms = 0;
+            HIPCK(hipEventElapsedTime(&ms, t.pending[i], t.pending[i + 1]));
+            t.ms += ms;
+        }
+        for (hipEvent_t e : t.pending) c->event_pool.push_back(e);
+        t.pending.clear();
+    }
+    return RBK_OK;
+}
+
+extern "C" int rbk_timer_enable(rbk_ctx *c, int on)
+{
+    if (!c) return fail(RBK_EINVAL, "null context");
+    int rc = kt_collect(c);
+    if (rc) return rc;
+    for (int k = 0; k < KC_COUNT; k++) c->timers[k] = KTimer();
+    c->timing = on != 0;
+    return RBK_OK;
+}
+
+extern "C" int rbk_timer_read(rbk_ctx *c, int cls, double *ms, uint64_t *launches, double *bytes)
+{
+    if (!c || cls < 0 || cls >= KC_COUNT) return fail(RBK_EINVAL, "bad argument");
+    int rc = kt_collect(c);
+    if (rc) return rc;
+    if (ms) *ms = c->timers[cls].ms;
+    if (launches) *launches = c->timers[cls].launches;
+    if (bytes) *bytes = c->timers[cls].bytes;
+    return RBK_OK;
+}
+
+extern "C" const char *rbk_timer_name(int cls) { return (cls >= 0 && cls < KC_COUNT) ? kc_names[cls] : nullptr; }

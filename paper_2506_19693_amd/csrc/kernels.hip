@@ -44,6 +44,7 @@ void ew_launch(const rbk_ctx_impl *c, EwOp op, const u64 *a, const u64 *b, u64 *
     size_t total = (size_t)npoly * nlimbs * c->N;
     if (total == 0) return;
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
     switch (op) {
     case EW_ADD: hipLaunchKernelGGL(k_ew<EW_ADD>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
     case EW_SUB: hipLaunchKernelGGL(k_ew<EW_SUB>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
@@ -51,6 +52,7 @@ void ew_launch(const rbk_ctx_impl *c, EwOp op, const u64 *a, const u64 *b, u64 *
     case EW_MUL: hipLaunchKernelGGL(k_ew<EW_MUL>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
     default: hipLaunchKernelGGL(k_ew<EW_COPY>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
     }
+    kt_end(c, KC_ELEMENTWISE, (op == EW_NEG || op == EW_COPY ? 2.0 : 3.0) * total * sizeof(u64), st);
 }
 
 __global__ void k_mul_scalar(const u64 *a, u64 *out, size_t total, int logN, int nlimbs, LimbMap map, const PrimeC *pc,
@@ -69,7 +71,9 @@ void mul_scalar_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int npoly,
     size_t total = (size_t)npoly * nlimbs * c->N;
     if (total == 0) return;
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
     hipLaunchKernelGGL(k_mul_scalar, grid, dim3(EW_THREADS), 0, st, a, out, total, c->logN, nlimbs, map, c->d_pc, s);
+    kt_end(c, KC_ELEMENTWISE, 2.0 * total * sizeof(u64), st);
 }
 
 // ct + constant: a constant polynomial evaluates to itself at every root, so
@@ -87,7 +91,9 @@ void add_scalar_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int nlimbs
 {
     size_t per = (size_t)nlimbs * c->N;
     dim3 grid((unsigned)((2 * per + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
     hipLaunchKernelGGL(k_add_scalar, grid, dim3(EW_THREADS), 0, st, a, out, per, c->logN, c->d_pc, s);
+    kt_end(c, KC_ELEMENTWISE, 4.0 * per * sizeof(u64), st);
 }
 
 // small signed integers (coefficient domain) reduced into each limb's prime
@@ -139,7 +145,9 @@ void tensor_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, 
 {
     size_t total = (size_t)count * (level + 1) * c->N;
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_TENSOR, st);
     hipLaunchKernelGGL(k_tensor, grid, dim3(EW_THREADS), 0, st, a, b, out, c->logN, level + 1, count, c->d_pc);
+    kt_end(c, KC_TENSOR, 7.0 * total * sizeof(u64), st);
 }
 
 // NTT-domain automorphism of npoly x nlimbs limbs (a pure permutation).
@@ -157,7 +165,9 @@ void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly,
     size_t total = (size_t)npoly * nlimbs * c->N;
     if (total == 0) return;
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
     hipLaunchKernelGGL(k_automorph, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, g);
+    kt_end(c, KC_ELEMENTWISE, 2.0 * total * sizeof(u64), st);
 }
 
 // ---------------------------------------------------------------- base conversion
@@ -215,8 +225,10 @@ void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride
     int nchunk = (E + BCONV_CHUNK - 1) / BCONV_CHUNK;
     dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), T.beta * nchunk, count);
     LimbMap emap{0, L1, c->nQ};
+    kt_begin(c, KC_BCONV_UP, st);
     hipLaunchKernelGGL(k_bconv_modup, grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1, E,
                        c->alpha, nchunk, T.d_A, T.d_Ash, T.d_M, emap, c->d_pc);
+    kt_end(c, KC_BCONV_UP, (double)count * T.beta * E * c->N * sizeof(u64), st);
 }
 
 // ModDown conversion P -> q_0..q_l of npoly polynomials (coefficient domain):
@@ -253,8 +265,10 @@ void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride
     int L1 = level + 1;
     int nchunk = (L1 + BCONV_CHUNK - 1) / BCONV_CHUNK;
     dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), nchunk, count);
+    kt_begin(c, KC_BCONV_DOWN, st);
     hipLaunchKernelGGL(k_bconv_moddown, grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
                        c->nP, c->nQ, nchunk, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
+    kt_end(c, KC_BCONV_DOWN, (double)count * (c->nP + L1) * c->N * sizeof(u64), st);
 }
 
 // ---------------------------------------------------------------- key inner product
@@ -305,8 +319,10 @@ void ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64
     int beta_l = (L1 + c->alpha - 1) / c->alpha;
     dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), E, 1);
     LimbMap emap{0, L1, c->nQ};
+    kt_begin(c, KC_IP, st);
     hipLaunchKernelGGL(k_ip, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, u, u_stride, c->logN, E, beta_l, c->nT,
                        count, emap, g, c->d_pc);
+    kt_end(c, KC_IP, ((double)count * beta_l * E + 2.0 * beta_l * E + 2.0 * count * E) * c->N * sizeof(u64), st);
 }
 
 // out[p][i] = (u[p][i] - conv[p][i]) * P^-1 mod q_i  (+ add_p[i], read through
@@ -344,8 +360,10 @@ void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, c
     int L1 = level + 1, E = L1 + c->nP;
     size_t total = (size_t)2 * L1 * c->N * count;
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_MODDOWN_FIN, st);
     hipLaunchKernelGGL(k_moddown_finish, grid, dim3(EW_THREADS), 0, st, u, u_stride, conv, conv_stride, add, add_stride,
                        add_g, add_both, out, out_stride, c->logN, L1, E, count, c->d_Pinv, c->d_Pinv_sh, c->d_pc);
+    kt_end(c, KC_MODDOWN_FIN, ((double)count * L1 * (add ? (add_both ? 8 : 7) : 6)) * c->N * sizeof(u64), st);
 }
 
 // ---------------------------------------------------------------- rescale
@@ -373,8 +391,10 @@ void rescale_lift_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, in
     size_t total = (size_t)npoly * level * c->N;
     if (total == 0) return;
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_RESCALE, st);
     hipLaunchKernelGGL(k_rescale_lift, grid, dim3(EW_THREADS), 0, st, last, lifted, c->logN, level, npoly, c->d_pc,
                        c->d_rs_qmod + (size_t)level * c->nQ);
+    kt_end(c, KC_RESCALE, (double)npoly * (1 + level) * c->N * sizeof(u64), st);
 }
 
 // out[p][i] = (in[p][i] - lifted[p][i]) * q_l^-1 mod q_i;  in: [npoly][l+1][N], out/lifted: [npoly][l][N]
@@ -398,8 +418,10 @@ void rescale_finish_launch(const rbk_ctx_impl *c, const u64 *in, const u64 *lift
     size_t total = (size_t)npoly * level * c->N;
     if (total == 0) return;
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_RESCALE, st);
     hipLaunchKernelGGL(k_rescale_finish, grid, dim3(EW_THREADS), 0, st, in, lifted, out, c->logN, level, npoly, c->d_pc,
                        c->d_rs_inv + (size_t)level * c->nQ, c->d_rs_inv_sh + (size_t)level * c->nQ);
+    kt_end(c, KC_RESCALE, 3.0 * total * sizeof(u64), st);
 }
 
 // ---------------------------------------------------------------- keys, encryption

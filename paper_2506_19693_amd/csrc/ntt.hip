@@ -190,12 +190,16 @@ void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, i
     const int logN = c->logN, logC = c->ntt_logC;
     const int r = logN - logC;
     NttTables T = c->tabs;
+    const double bytes = 2.0 * npoly * nlimbs * c->N * sizeof(u64);  // one read and one write of every limb
     if (r == 0) {
         dim3 grid(1, nlimbs, npoly);
+        int cls = inverse ? KC_NTT_ROWS_INV : KC_NTT_ROWS_FWD;
+        kt_begin(c, cls, st);
         if (inverse)
             hipLaunchKernelGGL(k_ntt_rows<true>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, 1);
         else
             hipLaunchKernelGGL(k_ntt_rows<false>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, 1);
+        kt_end(c, cls, bytes, st);
         return;
     }
     const int rows_per_tile = NTT_TILE >> logC;       // row pass
@@ -203,12 +207,20 @@ void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, i
     dim3 grow((1 << r) / rows_per_tile, nlimbs, npoly);
     dim3 gcol((1 << logC) >> logCt, nlimbs, npoly);
     if (!inverse) {
+        kt_begin(c, KC_NTT_COLS_FWD, st);
         hipLaunchKernelGGL(k_ntt_cols<false>, gcol, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, logCt);
+        kt_end(c, KC_NTT_COLS_FWD, bytes, st);
+        kt_begin(c, KC_NTT_ROWS_FWD, st);
         hipLaunchKernelGGL(k_ntt_rows<false>, grow, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC,
                            rows_per_tile);
+        kt_end(c, KC_NTT_ROWS_FWD, bytes, st);
     } else {
+        kt_begin(c, KC_NTT_ROWS_INV, st);
         hipLaunchKernelGGL(k_ntt_rows<true>, grow, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC,
                            rows_per_tile);
+        kt_end(c, KC_NTT_ROWS_INV, bytes, st);
+        kt_begin(c, KC_NTT_COLS_INV, st);
         hipLaunchKernelGGL(k_ntt_cols<true>, gcol, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, logCt);
+        kt_end(c, KC_NTT_COLS_INV, bytes, st);
     }
 }

@@ -20,6 +20,30 @@ struct ModUpTables {
     u64 *d_M = nullptr;    // [beta][alpha][E] (D_j / q_i) mod t * 2^64 mod t, by output position
 };
 
+// Per-kernel timers (HIP events around every launch of a kernel on the
+// context stream), enabled by rbk_timer_enable.  'bytes' accumulates the
+// algorithmic HBM bytes of each launch: what the kernel must read and write.
+enum KClass {
+    KC_NTT_COLS_FWD = 0,
+    KC_NTT_ROWS_FWD,
+    KC_NTT_ROWS_INV,
+    KC_NTT_COLS_INV,
+    KC_BCONV_UP,
+    KC_BCONV_DOWN,
+    KC_IP,
+    KC_MODDOWN_FIN,
+    KC_TENSOR,
+    KC_RESCALE,
+    KC_ELEMENTWISE,
+    KC_COUNT
+};
+
+struct KTimer {
+    std::vector<hipEvent_t> pending;  // begin/end pairs not yet read
+    double ms = 0, bytes = 0;
+    unsigned long launches = 0;
+};
+
 struct rbk_ctx_impl {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -60,7 +84,15 @@ struct rbk_ctx_impl {
     size_t ws_words = 0;
 
     std::vector<void *> owned;  // device allocations freed at destroy
+
+    bool timing = false;
+    mutable KTimer timers[KC_COUNT];
+    mutable std::vector<hipEvent_t> event_pool;
 };
+
+// timer hooks around a launch (no-ops unless timing is enabled)
+void kt_begin(const rbk_ctx_impl *c, int cls, hipStream_t st);
+void kt_end(const rbk_ctx_impl *c, int cls, double bytes, hipStream_t st);
 
 // ---- helpers implemented in api.hip ----
 u64 *ws_reserve(rbk_ctx_impl *c, size_t words);

@@ -76,6 +76,9 @@ SIGNATURES = {
     "rbk_mult_relin_batch": (ci, [vp, vp, vp, vp, ci, ci]),
     "rbk_rescale_batch": (ci, [vp, vp, vp, ci, ci]),
     "rbk_rotate_hoisted_batch": (ci, [vp, vp, i64p, ci, vp, ci, ci]),
+    "rbk_timer_enable": (ci, [vp, ci]),
+    "rbk_timer_read": (ci, [vp, ci, dblp, u64p, dblp]),
+    "rbk_timer_name": (ctypes.c_char_p, [ci]),
 }
 
 _LIB = None
@@ -386,6 +389,26 @@ class Context:
         ks_a, pk = _h_i64(ks)
         out = self.empty(len(ks), 2, level + 1, self.N)
         _check(self.lib.rbk_rotate_hoisted(self.h, _ptr(ct), pk, len(ks), _ptr(out), level))
+        return out
+
+    # ---------------------------------------------------------------- timers
+    def timer_enable(self, on=True):
+        _check(self.lib.rbk_timer_enable(self.h, 1 if on else 0))
+
+    def timer_read(self):
+        """{kernel name: (ms, launches, algorithmic bytes)} of every timed kernel."""
+        out = {}
+        cls = 0
+        while True:
+            name = self.lib.rbk_timer_name(cls)
+            if name is None:
+                break
+            ms, bts = ctypes.c_double(), ctypes.c_double()
+            n = ctypes.c_uint64()
+            _check(self.lib.rbk_timer_read(self.h, cls, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(bts)))
+            if n.value:
+                out[name.decode()] = (ms.value, n.value, bts.value)
+            cls += 1
         return out
 
     # ---------------------------------------------------------------- batched
