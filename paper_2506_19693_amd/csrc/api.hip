@@ -982,7 +982,7 @@ extern "C" int rbk_rotate_hoisted(rbk_ctx *c, const uint64_t *ct, const int64_t 
 // ---------------------------------------------------------------- kernel timers
 
 static const char *kc_names[KC_COUNT] = {
-    "k_ntt_cols<false>", "k_ntt_rows<false>", "k_ntt_rows<true>", "k_ntt_cols<true>", "k_bconv_modup",
+    "ntt_cols_fwd",      "ntt_rows_fwd",      "ntt_rows_inv",     "ntt_cols_inv",      "k_bconv_modup",
     "k_bconv_moddown",   "k_ip",              "k_moddown_finish", "k_tensor",          "k_rescale_lift+finish",
     "elementwise",
 };

@@ -183,6 +183,168 @@ __global__ __launch_bounds__(NTT_THREADS) void k_ntt_cols(u64 *data, long poly_s
     }
 }
 
+// ---------------------------------------------------------------- radix-16 passes (13 <= logN <= 16)
+//
+// Each pass transforms lines of S = 2^LOGS elements (the columns of the R x C
+// view in the column pass, its rows in the row pass).  A thread keeps 16
+// elements of one line in registers and runs 4 butterfly stages on them
+// without touching LDS; one LDS exchange regroups the elements for the
+// remaining LOGS-4 stages.  Two index patterns are used:
+//   strided    e = t + TPL*i   (TPL = S/16 threads per line)
+//   contiguous e = 16*t + i
+// Global memory is always read and written with adjacent lanes on adjacent
+// addresses: in the column pass lanes run over adjacent columns, in the row
+// pass over adjacent strided positions (the contiguous pattern of the row
+// pass is staged through LDS).  LDS rows are padded (one slot every 16 and
+// one per line) so both patterns are free of bank conflicts.
+
+template <int LOGS>
+struct Geo {
+    static constexpr int S = 1 << LOGS;
+    static constexpr int TPL = S / 16;
+    static constexpr int LINES = 256 / TPL;
+    static constexpr int LS = S + S / 16 + 1;
+};
+
+__device__ __forceinline__ int lidx(int e) { return e + (e >> 4); }
+
+// NST butterfly stages on the 16 registers; register distance starts at RD0
+// and halves (forward) or doubles (inverse).  Element i has line index
+// ebase + estride*i.  Forward local stage s = s0+k uses twiddle
+// (1 << (off+s)) + (line_id << s) + (e >> (LOGS-s)); inverse local stage
+// (distance 2^s in the line) uses (1 << (logN-1-off-s)) + (line_id << (LOGS-s-1)) + (e >> (s+1)).
+template <bool INV, int NST, int RD0, int LOGS>
+__device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride, int s0, int off, int line_id, int logN,
+                                            const u64 *tw, const u64 *tws, u64 q, u64 q2, bool fold, u64 ninv,
+                                            u64 ninv_sh, u64 lw, u64 lw_sh)
+{
+#pragma unroll
+    for (int k = 0; k < NST; k++) {
+        const int d = INV ? (RD0 << k) : (RD0 >> k);
+        const int s = s0 + k;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int i0 = (j / d) * 2 * d + (j % d), i1 = i0 + d;
+            const int e = ebase + estride * i0;
+            if (!INV) {
+                const int ti = (1 << (off + s)) + (line_id << s) + (e >> (LOGS - s));
+                bfly_ct(x[i0], x[i1], tw[ti], tws[ti], q, q2);
+            } else if (fold && k == NST - 1) {
+                u64 sum = csub(x[i0] + x[i1], q2);
+                u64 dd = x[i0] + q2 - x[i1];
+                x[i0] = shoup_lazy(sum, ninv, ninv_sh, q);
+                x[i1] = shoup_lazy(dd, lw, lw_sh, q);
+            } else {
+                const int ti = (1 << (logN - 1 - off - s)) + (line_id << (LOGS - s - 1)) + (e >> (s + 1));
+                bfly_gs(x[i0], x[i1], tw[ti], tws[ti], q, q2);
+            }
+        }
+    }
+}
+
+template <int LOGS, bool INV, bool COLS>
+__global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN)
+{
+    typedef Geo<LOGS> G;
+    constexpr int NST2 = LOGS - 4;
+    __shared__ u64 sm[G::LINES * G::LS];
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    const int pr = map.prime(limb);
+    const size_t N = (size_t)1 << logN;
+    const PrimeC pc = T.pc[pr];
+    const u64 q = pc.q, q2 = 2 * q;
+    const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
+    const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
+    u64 *base = data + (size_t)poly * poly_stride + (size_t)limb * N;
+    const int tid = threadIdx.x;
+    int line, t;
+    if (COLS) {
+        line = tid % G::LINES;
+        t = tid / G::LINES;
+    } else {
+        t = tid % G::TPL;
+        line = tid / G::TPL;
+    }
+    const int gl = blockIdx.x * G::LINES + line;          // column (COLS) or row index
+    const size_t C = COLS ? (N >> LOGS) : (size_t)G::S;   // row length of the R x C view
+    u64 *sl = sm + line * G::LS;
+    auto addr = [&](int e) -> size_t { return COLS ? (size_t)e * C + gl : (size_t)gl * G::S + e; };
+    const int off_f = COLS ? 0 : logN - LOGS;             // forward: global stage offset
+    const int off_i = COLS ? logN - LOGS : 0;             // inverse: global log-distance offset
+    const int lid = COLS ? 0 : gl;
+    u64 x[16];
+
+    if (!INV) {
+#pragma unroll
+        for (int i = 0; i < 16; i++) x[i] = base[addr(t + G::TPL * i)];
+        ntt_round16<false, 4, 8, LOGS>(x, t, G::TPL, 0, off_f, lid, logN, tw, tws, q, q2, false, 0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = x[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
+        ntt_round16<false, NST2, (1 << (NST2 - 1)), LOGS>(x, 16 * t, 1, 4, off_f, lid, logN, tw, tws, q, q2, false, 0, 0, 0,
+                                                          0);
+        if (COLS) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(16 * t + i)] = x[i];
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = csub(csub(x[i], q2), q);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = sl[lidx(t + G::TPL * i)];
+        }
+    } else {
+        if (COLS) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) x[i] = base[addr(16 * t + i)];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
+            __syncthreads();
+        }
+        ntt_round16<true, 4, 1, LOGS>(x, 16 * t, 1, 0, off_i, lid, logN, tw, tws, q, q2, false, 0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = x[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; i++) x[i] = sl[lidx(t + G::TPL * i)];
+        ntt_round16<true, NST2, (16 >> NST2), LOGS>(x, t, G::TPL, 4, off_i, lid, logN, tw, tws, q, q2, COLS, pc.ninv,
+                                                    pc.ninv_sh, T.last[pr], T.last_sh[pr]);
+        if (COLS) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = csub(x[i], q);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = x[i];
+        }
+    }
+}
+
+template <int LOGS, bool INV, bool COLS>
+static void launch16(u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, const NttTables &T, int logN,
+                     hipStream_t st)
+{
+    dim3 grid((unsigned)(((size_t)1 << logN) / 4096), nlimbs, npoly);
+    hipLaunchKernelGGL((k_ntt16<LOGS, INV, COLS>), grid, dim3(256), 0, st, data, poly_stride, map, T, logN);
+}
+
+template <bool INV, bool COLS>
+static void launch16_logs(int logs, u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, const NttTables &T,
+                          int logN, hipStream_t st)
+{
+    switch (logs) {
+    case 6: launch16<6, INV, COLS>(data, poly_stride, npoly, nlimbs, map, T, logN, st); break;
+    case 7: launch16<7, INV, COLS>(data, poly_stride, npoly, nlimbs, map, T, logN, st); break;
+    default: launch16<8, INV, COLS>(data, poly_stride, npoly, nlimbs, map, T, logN, st); break;
+    }
+}
+
 void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, bool inverse,
                 hipStream_t st)
 {
@@ -200,6 +362,24 @@ void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, i
         else
             hipLaunchKernelGGL(k_ntt_rows<false>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, 1);
         kt_end(c, cls, bytes, st);
+        return;
+    }
+    if (logN >= 13 && logN <= 16 && r >= 6 && r <= 8 && logC >= 6 && logC <= 8) {
+        if (!inverse) {
+            kt_begin(c, KC_NTT_COLS_FWD, st);
+            launch16_logs<false, true>(r, data, poly_stride, npoly, nlimbs, map, T, logN, st);
+            kt_end(c, KC_NTT_COLS_FWD, bytes, st);
+            kt_begin(c, KC_NTT_ROWS_FWD, st);
+            launch16_logs<false, false>(logC, data, poly_stride, npoly, nlimbs, map, T, logN, st);
+            kt_end(c, KC_NTT_ROWS_FWD, bytes, st);
+        } else {
+            kt_begin(c, KC_NTT_ROWS_INV, st);
+            launch16_logs<true, false>(logC, data, poly_stride, npoly, nlimbs, map, T, logN, st);
+            kt_end(c, KC_NTT_ROWS_INV, bytes, st);
+            kt_begin(c, KC_NTT_COLS_INV, st);
+            launch16_logs<true, true>(r, data, poly_stride, npoly, nlimbs, map, T, logN, st);
+            kt_end(c, KC_NTT_COLS_INV, bytes, st);
+        }
         return;
     }
     const int rows_per_tile = NTT_TILE >> logC;       // row pass
