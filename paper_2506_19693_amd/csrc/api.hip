@@ -336,6 +336,8 @@ extern "C" int rbk_ctx_create(const rbk_params *p, rbk_ctx **out)
     if (p->alpha < 1 || p->alpha > 16) return fail(RBK_EINVAL, "alpha must be in [1, 16]");
     if (p->n_p > 16) return fail(RBK_EINVAL, "at most 16 special primes");
     if ((p->n_q + p->alpha - 1) / p->alpha > 8) return fail(RBK_EINVAL, "at most 8 key-switching digits");
+    if (p->alpha * (p->n_q + p->n_p) > 1024 || p->n_p * p->n_q > 1024)
+        return fail(RBK_EINVAL, "base-conversion table too large (alpha*(n_q+n_p) and n_p*n_q must be <= 1024)");
     if (!p->q_bits || (p->n_p && !p->p_bits)) return fail(RBK_EINVAL, "null bit-size list");
     std::vector<int> bits;
     for (uint32_t i = 0; i < p->n_q; i++) bits.push_back((int)p->q_bits[i]);
@@ -796,6 +798,28 @@ static int moddown_run(rbk_ctx *c, u64 *u, const u64 *add, long add_stride, u64 
     return RBK_OK;
 }
 
+// ModDown fused with the key inner product: only the special-prime part of
+// the inner product is stored; the Q part is recomputed in the final kernel.
+static int moddown_fused_run(rbk_ctx *c, const u64 *ext, long ext_stride, const DevKey *key, u64 perm_g, const u64 *add,
+                             long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count,
+                             u64 *tp, u64 *conv)
+{
+    const size_t N = c->N;
+    const int L1 = level + 1, nP = c->nP;
+    if (nP > 0) {
+        ip_p_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, c->stream);
+        ntt_launch(c, tp, (long)nP * N, 2 * count, nP, LimbMap{0, 0, c->nQ}, true, c->stream);
+        bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, c->stream);
+        ntt_launch(c, conv, (long)L1 * N, 2 * count, L1, qmap(c), false, c->stream);
+    } else {
+        HIPCK(hipMemsetAsync(conv, 0, 2 * count * L1 * N * sizeof(u64), c->stream));
+    }
+    moddown_ip_launch(c, ext, ext_stride, key->data, conv, (long)2 * L1 * N, add, add_stride, add_g, add_both, out,
+                      out_stride, level, count, perm_g, c->stream);
+    HIPCK_LAUNCH();
+    return RBK_OK;
+}
+
 struct KsBufs {
     u64 *ext, *u, *coef, *tp, *conv;
 };
@@ -858,8 +882,8 @@ static int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d
     KsBufs b = ks_layout(c, base, level, count);
     int rc = modup_run(c, d, d_stride, b.ext, (long)(beta * E * N), level, count, b.coef);
     if (rc) return rc;
-    ip_launch(c, b.ext, (long)(beta * E * N), key->data, b.u, (long)(2 * E * N), level, count, perm_g, c->stream);
-    return moddown_run(c, b.u, add, add_stride, add_g, add_both, out, out_stride, level, count, b.tp, b.conv);
+    return moddown_fused_run(c, b.ext, (long)(beta * E * N), key, perm_g, add, add_stride, add_g, add_both, out, out_stride,
+                             level, count, b.tp, b.conv);
 }
 
 extern "C" int rbk_keyswitch(rbk_ctx *c, uint64_t g, const uint64_t *d, uint64_t *out, int level)
@@ -967,8 +991,8 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
                                    hipMemcpyDeviceToDevice, c->stream));
             continue;
         }
-        ip_launch(c, b.ext, (long)(beta * E * N), keys[r]->data, b.u, (long)(2 * E * N), level, count, gs[r], c->stream);
-        rc = moddown_run(c, b.u, ct, (long)(2 * per), gs[r], 0, o, (long)(n * 2 * per), level, count, b.tp, b.conv);
+        rc = moddown_fused_run(c, b.ext, (long)(beta * E * N), keys[r], gs[r], ct, (long)(2 * per), gs[r], 0, o,
+                               (long)(n * 2 * per), level, count, b.tp, b.conv);
         if (rc) return rc;
     }
     return RBK_OK;

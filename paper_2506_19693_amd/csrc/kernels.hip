@@ -173,47 +173,76 @@ void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly,
 // ---------------------------------------------------------------- base conversion
 
 #define BCONV_MAX_IN 16
-#define BCONV_CHUNK 8
+#define BCONV_MAX_TAB 1024   // n_in * n_out words staged in LDS
 
-// ModUp conversion.  For digit j (primes [lo, lo+n_in)) and coefficient k:
-//   y_i = x_i (D_j/q_i)^-1 mod q_i,  out_e = sum_i y_i ((D_j/q_i) mod t_e)  mod t_e
-// for every extended-basis position e outside the digit.  Input: coefficient
-// domain [l+1][N] per ciphertext; output written into ext (coefficient domain).
-__global__ __launch_bounds__(EW_THREADS) void k_bconv_modup(const u64 *coef, long coef_stride, u64 *ext, long ext_stride,
-                                                            int logN, int L1, int E, int alpha, int nchunk,
-                                                            const u64 *A, const u64 *Ash, const u64 *M, LimbMap emap,
-                                                            const PrimeC *pc)
+// Fast base conversion, one thread per coefficient, all outputs in one pass:
+//   y_i = x_i * A_i mod b_i,   out_o = sum_i y_i * M[i][o] mod t_o
+// M (stored times 2^64) is staged in LDS once per block and read as a
+// broadcast; the sum is a lazy 128-bit accumulation with one REDC per output.
+//
+// ModUp (MODUP = true): block row blockIdx.y = digit j, inputs are the digit's
+// limbs [lo, lo+n_in) of the coefficient-domain copy, outputs every
+// extended-basis position outside the digit (written into ext).
+// ModDown (MODUP = false): inputs are the nP special-prime limbs of one
+// polynomial, outputs the l+1 Q limbs.
+template <bool MODUP>
+__global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_stride, u64 *out, long out_stride, int logN,
+                                                      int L1, int E, int alpha, int nP, int nQ, const u64 *A,
+                                                      const u64 *Ash, const u64 *M, long m_stride, const PrimeC *pc)
 {
+    __shared__ u64 tab[BCONV_MAX_TAB];
     const size_t N = (size_t)1 << logN;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
-    const int j = blockIdx.y / nchunk, chunk = blockIdx.y % nchunk;
-    const int ct = blockIdx.z;
-    const int lo = j * alpha;
-    int n_in = L1 - lo;
-    if (n_in > alpha) n_in = alpha;
-    const int n_out = E - n_in;
-    const int o0 = chunk * BCONV_CHUNK;
-    if (o0 >= n_out || k >= N) return;
-    const int o1 = min(o0 + BCONV_CHUNK, n_out);
-    const u64 *x = coef + ct * coef_stride;
-    u64 *dst = ext + ct * ext_stride + (size_t)j * E * N;
-
+    const int poly = blockIdx.z;
+    int lo, n_in, n_out;
+    const u64 *Aj, *Ashj, *Mj;
+    u64 *dst;
+    const u64 *x;
+    if (MODUP) {
+        const int j = blockIdx.y;
+        lo = j * alpha;
+        n_in = min(alpha, L1 - lo);
+        n_out = E - n_in;
+        Aj = A + j * alpha;
+        Ashj = Ash + j * alpha;
+        Mj = M + (size_t)j * alpha * m_stride;
+        x = in + poly * in_stride + (size_t)lo * N;
+        dst = out + poly * out_stride + (size_t)j * E * N;
+    } else {
+        lo = 0;
+        n_in = nP;
+        n_out = L1;
+        Aj = A;
+        Ashj = Ash;
+        Mj = M;
+        x = in + poly * in_stride;
+        dst = out + poly * out_stride;
+    }
+    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS) tab[w] = Mj[(size_t)(w / n_out) * m_stride + (w % n_out)];
+    __syncthreads();
+    if (k >= N) return;
     u64 y[BCONV_MAX_IN];
 #pragma unroll
-    for (int i = 0; i < BCONV_MAX_IN; i++) {
+    for (int i = 0; i < BCONV_MAX_IN; i++)
         if (i < n_in) {
-            int pi = lo + i;
-            y[i] = shoup(x[(size_t)pi * N + k], A[j * alpha + i], Ash[j * alpha + i], pc[pi].q);
+            const int pi = MODUP ? lo + i : nQ + i;
+            y[i] = shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[pi].q);
         }
-    }
-    for (int o = o0; o < o1; o++) {
-        int e = o < lo ? o : o + n_in;
-        const PrimeC p = pc[emap.prime(e)];
+    for (int o = 0; o < n_out; o++) {
+        int pos, pr;
+        if (MODUP) {
+            pos = o < lo ? o : o + n_in;
+            pr = pos < L1 ? pos : nQ + pos - L1;
+        } else {
+            pos = o;
+            pr = o;
+        }
+        const PrimeC p = pc[pr];
         u128w acc = {0, 0};
 #pragma unroll
         for (int i = 0; i < BCONV_MAX_IN; i++)
-            if (i < n_in) acc_wide(acc, mul_wide(y[i], M[((size_t)(j * alpha + i)) * E + o]));
-        dst[(size_t)e * N + k] = redc_any(acc, p.q, p.qneg, p.one_sh);
+            if (i < n_in) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
+        dst[(size_t)pos * N + k] = redc_any(acc, p.q, p.qneg, p.one_sh);
     }
 }
 
@@ -222,52 +251,21 @@ void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride
 {
     const ModUpTables &T = modup_tables(const_cast<rbk_ctx_impl *>(c), level);
     int L1 = level + 1, E = L1 + c->nP;
-    int nchunk = (E + BCONV_CHUNK - 1) / BCONV_CHUNK;
-    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), T.beta * nchunk, count);
-    LimbMap emap{0, L1, c->nQ};
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), T.beta, count);
     kt_begin(c, KC_BCONV_UP, st);
-    hipLaunchKernelGGL(k_bconv_modup, grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1, E,
-                       c->alpha, nchunk, T.d_A, T.d_Ash, T.d_M, emap, c->d_pc);
+    hipLaunchKernelGGL(k_bconv<true>, grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1, E,
+                       c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
     kt_end(c, KC_BCONV_UP, (double)count * T.beta * E * c->N * sizeof(u64), st);
-}
-
-// ModDown conversion P -> q_0..q_l of npoly polynomials (coefficient domain):
-//   y_t = u_t (P/p_t)^-1 mod p_t,  conv_i = sum_t y_t ((P/p_t) mod q_i) mod q_i.
-__global__ __launch_bounds__(EW_THREADS) void k_bconv_moddown(const u64 *pcoef, long p_stride, u64 *conv, long conv_stride,
-                                                              int logN, int L1, int nP, int nQ, int nchunk, const u64 *A,
-                                                              const u64 *Ash, const u64 *M, const PrimeC *pc)
-{
-    const size_t N = (size_t)1 << logN;
-    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
-    const int chunk = blockIdx.y, poly = blockIdx.z;
-    const int o0 = chunk * BCONV_CHUNK;
-    if (o0 >= L1 || k >= N) return;
-    const int o1 = min(o0 + BCONV_CHUNK, L1);
-    const u64 *x = pcoef + poly * p_stride;
-    u64 *dst = conv + poly * conv_stride;
-    u64 y[BCONV_MAX_IN];
-#pragma unroll
-    for (int t = 0; t < BCONV_MAX_IN; t++)
-        if (t < nP) y[t] = shoup(x[(size_t)t * N + k], A[t], Ash[t], pc[nQ + t].q);
-    for (int o = o0; o < o1; o++) {
-        const PrimeC p = pc[o];
-        u128w acc = {0, 0};
-#pragma unroll
-        for (int t = 0; t < BCONV_MAX_IN; t++)
-            if (t < nP) acc_wide(acc, mul_wide(y[t], M[(size_t)t * nQ + o]));
-        dst[(size_t)o * N + k] = redc_any(acc, p.q, p.qneg, p.one_sh);
-    }
 }
 
 void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride, u64 *conv, long conv_stride, int level,
                           int count, hipStream_t st)
 {
     int L1 = level + 1;
-    int nchunk = (L1 + BCONV_CHUNK - 1) / BCONV_CHUNK;
-    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), nchunk, count);
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), 1, count);
     kt_begin(c, KC_BCONV_DOWN, st);
-    hipLaunchKernelGGL(k_bconv_moddown, grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
-                       c->nP, c->nQ, nchunk, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
+    hipLaunchKernelGGL(k_bconv<false>, grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
+                       L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
     kt_end(c, KC_BCONV_DOWN, (double)count * (c->nP + L1) * c->N * sizeof(u64), st);
 }
 
@@ -364,6 +362,123 @@ void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, c
     hipLaunchKernelGGL(k_moddown_finish, grid, dim3(EW_THREADS), 0, st, u, u_stride, conv, conv_stride, add, add_stride,
                        add_g, add_both, out, out_stride, c->logN, L1, E, count, c->d_Pinv, c->d_Pinv_sh, c->d_pc);
     kt_end(c, KC_MODDOWN_FIN, ((double)count * L1 * (add ? (add_both ? 8 : 7) : 6)) * c->N * sizeof(u64), st);
+}
+
+// ---------------------------------------------------------------- key switching with a fused ModDown epilogue
+
+// Inner product restricted to the special-prime positions, written to
+// tp[count][2][nP][N] (the input of the ModDown inverse NTT).
+__global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int logN,
+                                                     int L1, int E, int beta, int nT, int nQ, int nP, int count, u64 g,
+                                                     const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int t = blockIdx.y;
+    if (k >= N) return;
+    const int pos = L1 + t, pr = nQ + t;
+    const PrimeC p = pc[pr];
+    u64 kb[IP_MAX_BETA], ka[IP_MAX_BETA];
+#pragma unroll
+    for (int j = 0; j < IP_MAX_BETA; j++)
+        if (j < beta) {
+            kb[j] = key[(((size_t)j * 2 + 0) * nT + pr) * N + k];
+            ka[j] = key[(((size_t)j * 2 + 1) * nT + pr) * N + k];
+        }
+    const size_t src = g ? auto_src((u32)k, g, logN) : k;
+    for (int ct = 0; ct < count; ct++) {
+        const u64 *x = ext + ct * ext_stride + (size_t)pos * N + src;
+        u128w s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < IP_MAX_BETA; j++)
+            if (j < beta) {
+                u64 d = x[(size_t)j * E * N];
+                acc_wide(s0, mul_wide(d, kb[j]));
+                acc_wide(s1, mul_wide(d, ka[j]));
+            }
+        u64 *o = tp + ((size_t)ct * 2 * nP + t) * N + k;
+        o[0] = redc_any(s0, p.q, p.qneg, p.one_sh);
+        o[(size_t)nP * N] = redc_any(s1, p.q, p.qneg, p.one_sh);
+    }
+}
+
+// Q positions: the inner product is recomputed here instead of being stored,
+//   out[h][i] = (sum_j ext_j[i] key_j[h][i] - conv[h][i]) * P^-1 mod q_i (+ add_h[i]).
+// add (through sigma_{add_g} when add_g != 0) goes to poly 0, and to poly 1
+// when add_both != 0.
+__global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
+                                                           long conv_stride, const u64 *add, long add_stride, u64 add_g,
+                                                           int add_both, u64 *out, long out_stride, int logN, int L1, int E,
+                                                           int beta, int nT, int count, u64 g, const u64 *Pinv,
+                                                           const u64 *Pinv_sh, const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int i = blockIdx.y;
+    if (k >= N) return;
+    const PrimeC p = pc[i];
+    const u64 pinv = Pinv[i], pinv_sh = Pinv_sh[i];
+    u64 kb[IP_MAX_BETA], ka[IP_MAX_BETA];
+#pragma unroll
+    for (int j = 0; j < IP_MAX_BETA; j++)
+        if (j < beta) {
+            kb[j] = key[(((size_t)j * 2 + 0) * nT + i) * N + k];
+            ka[j] = key[(((size_t)j * 2 + 1) * nT + i) * N + k];
+        }
+    const size_t src = g ? auto_src((u32)k, g, logN) : k;
+    const size_t asrc = add_g ? auto_src((u32)k, add_g, logN) : k;
+    const size_t per = (size_t)L1 * N, li = (size_t)i * N;
+    for (int ct = 0; ct < count; ct++) {
+        const u64 *x = ext + ct * ext_stride + li + src;
+        u128w s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < IP_MAX_BETA; j++)
+            if (j < beta) {
+                u64 d = x[(size_t)j * E * N];
+                acc_wide(s0, mul_wide(d, kb[j]));
+                acc_wide(s1, mul_wide(d, ka[j]));
+            }
+        const u64 *cv = conv + ct * conv_stride + li + k;
+        u64 v0 = shoup(sub_mod(redc_any(s0, p.q, p.qneg, p.one_sh), cv[0], p.q), pinv, pinv_sh, p.q);
+        u64 v1 = shoup(sub_mod(redc_any(s1, p.q, p.qneg, p.one_sh), cv[per], p.q), pinv, pinv_sh, p.q);
+        if (add) {
+            const u64 *ad = add + ct * add_stride + li;
+            v0 = add_mod(v0, ad[asrc], p.q);
+            if (add_both) v1 = add_mod(v1, ad[per + asrc], p.q);
+        }
+        u64 *o = out + ct * out_stride + li + k;
+        o[0] = v0;
+        o[per] = v1;
+    }
+}
+
+void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int level, int count,
+                 u64 g, hipStream_t st)
+{
+    int L1 = level + 1, E = L1 + c->nP;
+    int beta_l = (L1 + c->alpha - 1) / c->alpha;
+    if (c->nP == 0) return;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), c->nP, 1);
+    kt_begin(c, KC_IP, st);
+    hipLaunchKernelGGL(k_ip_p, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, tp, c->logN, L1, E, beta_l, c->nT, c->nQ,
+                       c->nP, count, g, c->d_pc);
+    kt_end(c, KC_IP, ((double)count * beta_l * c->nP + 2.0 * beta_l * c->nP + 2.0 * count * c->nP) * c->N * sizeof(u64),
+           st);
+}
+
+void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
+                       long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
+                       long out_stride, int level, int count, u64 g, hipStream_t st)
+{
+    int L1 = level + 1, E = L1 + c->nP;
+    int beta_l = (L1 + c->alpha - 1) / c->alpha;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), L1, 1);
+    kt_begin(c, KC_MODDOWN_FIN, st);
+    hipLaunchKernelGGL(k_moddown_ip, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, conv, conv_stride, add,
+                       add_stride, add_g, add_both, out, out_stride, c->logN, L1, E, beta_l, c->nT, count, g, c->d_Pinv,
+                       c->d_Pinv_sh, c->d_pc);
+    double words = (double)count * L1 * (beta_l + 2 + 2 + (add ? (add_both ? 2 : 1) : 0)) + 2.0 * beta_l * L1;
+    kt_end(c, KC_MODDOWN_FIN, words * c->N * sizeof(u64), st);
 }
 
 // ---------------------------------------------------------------- rescale

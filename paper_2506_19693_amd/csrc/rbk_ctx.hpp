@@ -124,6 +124,11 @@ void ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64
 void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, const u64 *conv, long conv_stride,
                            const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
                            int count, hipStream_t st);
+void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int level, int count,
+                 u64 g, hipStream_t st);
+void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
+                       long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
+                       long out_stride, int level, int count, u64 g, hipStream_t st);
 void rescale_lift_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, int level, int npoly, hipStream_t st);
 void rescale_finish_launch(const rbk_ctx_impl *c, const u64 *in, const u64 *lifted, u64 *out, int level, int npoly,
                            hipStream_t st);
