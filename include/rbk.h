@@ -205,6 +205,53 @@ int rbk_rescale_batch(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int l
 int rbk_rotate_hoisted_batch(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, int n, uint64_t *d_outs, int level,
                              int count);
 
+/* ---- approximate bootstrapping (Section 3: encoding step, scaled-sine
+ *      modular reduction, decoding step; Cheon et al. 2018, Bossuat et al.
+ *      2021) ------------------------------------------------------------- */
+
+/* K         : bound on |I| after ModRaise; EvalMod interpolates on [-K-1, K+1]
+ * degree    : degree of the Chebyshev interpolant of cos(2 pi (x - 1/4) / 2^r)
+ * double_angle : r, the number of y <- 2y^2 - 1 steps
+ * cts_levels, stc_levels : sparse transforms of CoeffToSlot and SlotToCoeff
+ * log2_rho  : inputs are pre-scaled by a power of two to a scale in
+ *             (D/2, D], D = 2^(bits(q_0) - log2_rho) */
+typedef struct {
+    uint32_t K;
+    uint32_t degree;
+    uint32_t double_angle;
+    uint32_t cts_levels;
+    uint32_t stc_levels;
+    uint32_t log2_rho;
+} rbk_boot_params;
+
+/* Build the bootstrapping plan for the full chain of the context: levels,
+ * scales, the encoded diagonals of the transforms (device encoder) and the
+ * scalar constants of EvalMod.  ELEVEL if the chain is too short. */
+int rbk_boot_setup(rbk_ctx *ctx, const rbk_boot_params *params);
+/* Rotation indices (0 < k < N/2) whose Galois keys bootstrapping needs, in
+ * increasing order; the conjugation key (2N-1) is needed as well.  Writes at
+ * most max entries, returns the total count. */
+int rbk_boot_rotations(const rbk_ctx *ctx, int64_t *ks, int max);
+/* levels[4] = {top level L, EvalMod input level, SlotToCoeff input level,
+ * output level}; counts of encoded diagonals and scalar constants. */
+int rbk_boot_info(const rbk_ctx *ctx, int *levels, int *n_plain, int *n_scalar);
+/* level of every diagonal / scalar constant, in plan order */
+int rbk_boot_constant_levels(const rbk_ctx *ctx, int *plain_levels, int *scalar_levels);
+/* Constants in plan order, coefficient domain: diagonal i is [level_i+1][N]
+ * residues, scalar i is [level_i+1] residues, all concatenated.  Plan order:
+ * CoeffToSlot transforms then SlotToCoeff transforms, each by giant step then
+ * baby step; EvalMod scalars in evaluation order.  Either pointer may be NULL.
+ * import replaces the plan's constants (residues must be below their prime). */
+int rbk_boot_export(rbk_ctx *ctx, uint64_t *plains, uint64_t *scalars);
+int rbk_boot_import(rbk_ctx *ctx, const uint64_t *plains, const uint64_t *scalars);
+/* Bootstrap count level-0 ciphertexts d_in[count][2][1][N] at scales
+ * scales_in[count] into d_out[count][2][out+1][N] (out = the output level).
+ * scales_out receives the scale of each result.  Needs the relinearisation
+ * key, the conjugation key and every key of rbk_boot_rotations. */
+int rbk_bootstrap_batch(rbk_ctx *ctx, const uint64_t *d_in, const double *scales_in, uint64_t *d_out, double *scales_out,
+                        int count);
+int rbk_bootstrap(rbk_ctx *ctx, const uint64_t *d_in, double scale_in, uint64_t *d_out, double *scale_out);
+
 /* ---- per-kernel timers -------------------------------------------------- */
 /* With timers on, every kernel launch on the context stream is bracketed by
  * HIP events.  Class `cls` = 0, 1, ... names one kernel (rbk_timer_name);

@@ -78,6 +78,8 @@ def lib():
             "orc_galois_rot": (ctypes.c_uint64, [ctypes.c_void_p, ctypes.c_int64]),
             "orc_rotate": (None, [ctypes.c_void_p, ctypes.c_int, u64p, ctypes.c_uint64, u64p, u64p]),
             "orc_rotate_hoisted": (None, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(u64p), u64p, u64p, u64p]),
+            "orc_modraise": (None, [ctypes.c_void_p, ctypes.c_int, u64p, u64p]),
+            "orc_monomial": (None, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, u64p, u64p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -415,6 +417,23 @@ class Oracle:
         out = self._new(len(keys), 2, level + 1, self.N)
         lib().orc_rotate_hoisted(self._h, level, len(keys), kp, gs_a.ctypes.data_as(u64p), pc, out.ctypes.data_as(u64p))
         return out
+
+    def modraise(self, level, ct0):
+        ct0, pc = _u(ct0)
+        out = self._new(2, level + 1, self.N)
+        lib().orc_modraise(self._h, level, pc, out.ctypes.data_as(u64p))
+        return out
+
+    def monomial(self, level, e, a):
+        a, pa = _u(a)
+        out = np.zeros_like(a)
+        lib().orc_monomial(self._h, level, a.size // ((level + 1) * self.N), int(e), pa, out.ctypes.data_as(u64p))
+        return out
+
+    def drop(self, level_from, level_to, ct):
+        """Keep limbs 0..level_to of every polynomial (the value is unchanged)."""
+        ct = np.asarray(ct, dtype=np.uint64)
+        return np.ascontiguousarray(ct[..., : level_to + 1, :])
 
 
 from .encoding import encode, decode, crt_centered, slot_exponents  # noqa: E402,F401

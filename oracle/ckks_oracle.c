@@ -813,3 +813,45 @@ void orc_secret_automorph(const orc_ctx *c, const i64 *s, u64 g, u64 *out)
     }
     free(sl);
 }
+
+/* ------------------------------------------------------------------ */
+/* bootstrapping primitives                                           */
+/* ------------------------------------------------------------------ */
+
+/* ModRaise: a ciphertext modulo q_0 ([2][1][N]) is read as centred integers
+ * in (-q_0/2, q_0/2] and reduced modulo every prime of level l:
+ * out [2][l+1][N].  The decryption then becomes m + q_0 I(X) for a small
+ * integer polynomial I (Cheon-Han-Kim-Kim-Song 2018). */
+void orc_modraise(const orc_ctx *c, int level, const u64 *in, u64 *out)
+{
+    size_t N = c->N, L1 = (size_t)level + 1;
+    u64 q0 = c->mod[0];
+    for (int p = 0; p < 2; p++)
+        for (size_t k = 0; k < N; k++) {
+            u64 x = in[(size_t)p * N + k];
+            for (size_t i = 0; i < L1; i++) {
+                u64 q = c->mod[i], v;
+                if (x <= (q0 - 1) / 2) v = x % q;
+                else v = subm(x % q, q0 % q, q);
+                out[((size_t)p * L1 + i) * N + k] = v;
+            }
+        }
+}
+
+/* Multiplication by the monomial X^e (0 <= e < 2N) of npoly polynomials:
+ * coefficient k moves to k+e, negated each time it wraps past X^N. */
+void orc_monomial(const orc_ctx *c, int level, int npoly, u64 e, const u64 *in, u64 *out)
+{
+    size_t N = c->N;
+    for (int p = 0; p < npoly; p++)
+        for (int t = 0; t <= level; t++) {
+            u64 q = c->mod[t];
+            const u64 *a = in + ((size_t)p * (level + 1) + t) * N;
+            u64 *o = out + ((size_t)p * (level + 1) + t) * N;
+            for (size_t k = 0; k < N; k++) {
+                u64 d = (k + e) % (2 * N);
+                if (d < N) o[d] = a[k];
+                else o[d - N] = negm(a[k], q);
+            }
+        }
+}

@@ -14,7 +14,6 @@
 
 typedef unsigned __int128 u128;
 
-struct rbk_ctx : rbk_ctx_impl {};
 
 static thread_local std::string g_err;
 
@@ -23,6 +22,8 @@ static int fail(int code, const std::string &msg)
     g_err = msg;
     return code;
 }
+
+int rbk_set_error(int code, const char *msg) { return fail(code, msg); }
 
 #define HIPCK(x)                                                                                     \
     do {                                                                                             \
@@ -320,6 +321,17 @@ static int build_tables(rbk_ctx *c)
         x = (x * 5) % (2 * N);
     }
     rc |= dev_upload(c, &c->d_pow5, pow5);
+
+    // bootstrapping: q_0 mod q_i and psi^(N/2) (a square root of -1) per Q prime
+    std::vector<u64> q0mod(nQ), iq(nQ), iqsh(nQ);
+    for (int i = 0; i < nQ; i++) {
+        q0mod[i] = c->mod[0] % c->mod[i];
+        iq[i] = h_pow(c->psi[i], N / 2, c->mod[i]);
+        iqsh[i] = h_shoup(iq[i], c->mod[i]);
+    }
+    rc |= dev_upload(c, &c->d_q0mod, q0mod);
+    rc |= dev_upload(c, &c->d_iq, iq);
+    rc |= dev_upload(c, &c->d_iq_sh, iqsh);
     return rc ? RBK_ENOMEM : RBK_OK;
 }
 
@@ -370,6 +382,7 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
 {
     if (!c) return RBK_OK;
     (void)hipStreamSynchronize(c->stream);
+    boot_free(c);
     for (int k = 0; k < KC_COUNT; k++)
         for (hipEvent_t e : c->timers[k].pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -935,6 +948,24 @@ extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, 
 extern "C" int rbk_rescale(rbk_ctx *c, const uint64_t *ct, uint64_t *out, int level)
 {
     return rbk_rescale_batch(c, ct, out, level, 1);
+}
+
+// Rot for count ciphertexts [count][2][l+1][N] by the Galois element g:
+// out = (sigma_g(c0), 0) + KS(sigma_g(c1)), as rbk_rotate does for one.
+int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g)
+{
+    const size_t L1 = level + 1, N = c->N, per = L1 * N;
+    if (g == 1) {
+        HIPCK(hipMemcpyAsync(out, in, count * 2 * per * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
+        return RBK_OK;
+    }
+    const DevKey *k = find_key(c, g);
+    if (!k) return fail(RBK_ENOKEY, "no Galois key for element " + std::to_string(g));
+    WS(ws, count * 2 * per + ks_words(c, level, count));
+    u64 *rot = ws;
+    automorph_launch(c, in, rot, 2 * count, (int)L1, g, c->stream);
+    return keyswitch_run(c, k, 0, rot + per, (long)(2 * per), rot, (long)(2 * per), 0, 0, out, (long)(2 * per), level, count,
+                         ws + count * 2 * per);
 }
 
 static int rotate_g(rbk_ctx *c, const u64 *ct, u64 *out, int level, u64 g)

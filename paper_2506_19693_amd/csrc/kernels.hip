@@ -539,6 +539,111 @@ void rescale_finish_launch(const rbk_ctx_impl *c, const u64 *in, const u64 *lift
     kt_end(c, KC_RESCALE, 3.0 * total * sizeof(u64), st);
 }
 
+// ---------------------------------------------------------------- bootstrapping helpers
+
+// ModRaise, lifting step: x (coefficient domain, residues mod q_0, one limb
+// per polynomial, npoly polynomials) is read as a centred integer and reduced
+// into limbs 0..l: out [npoly][l+1][N].
+__global__ void k_modraise_lift(const u64 *in, u64 *out, int logN, int L1, int npoly, const PrimeC *pc, const u64 *q0mod)
+{
+    const size_t N = (size_t)1 << logN;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    size_t per = (size_t)L1 * N;
+    if (i >= per * npoly) return;
+    size_t poly = i / per, r = i % per;
+    int limb = (int)(r >> logN);
+    size_t k = r & (N - 1);
+    const PrimeC p = pc[limb];
+    const u64 q0 = pc[0].q;
+    u64 x = in[poly * N + k];
+    u64 xm = shoup(x, 1, p.one_sh, p.q);
+    out[i] = (x <= (q0 - 1) / 2) ? xm : sub_mod(xm, q0mod[limb], p.q);
+}
+
+void modraise_lift_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int level, int npoly, hipStream_t st)
+{
+    size_t total = (size_t)npoly * (level + 1) * c->N;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
+    hipLaunchKernelGGL(k_modraise_lift, grid, dim3(EW_THREADS), 0, st, in, out, c->logN, level + 1, npoly, c->d_pc,
+                       c->d_q0mod);
+    kt_end(c, KC_ELEMENTWISE, (double)npoly * (level + 2) * c->N * sizeof(u64), st);
+}
+
+// Multiplication by sign * X^(N/2) in the NTT domain: at psi^(2k+1) the
+// monomial is i_q^(2k+1) = i_q (-1)^k with i_q = psi^(N/2) (a square root of -1),
+// and k = bit_reverse(o) is odd exactly when the top index bit of o is set.
+__global__ void k_monomial_half(const u64 *in, u64 *out, size_t total, int logN, int nlimbs, int neg, const PrimeC *pc,
+                                const u64 *iq, const u64 *iq_sh)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= total) return;
+    int limb = (int)((i >> logN) % nlimbs);
+    u64 q = pc[limb].q;
+    u64 v = shoup(in[i], iq[limb], iq_sh[limb], q);
+    int odd = (int)((i >> (logN - 1)) & 1);
+    if ((odd ^ neg) && v) v = q - v;
+    out[i] = v;
+}
+
+void monomial_half_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int level, int neg, hipStream_t st)
+{
+    size_t total = (size_t)npoly * (level + 1) * c->N;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
+    hipLaunchKernelGGL(k_monomial_half, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, level + 1, neg, c->d_pc,
+                       c->d_iq, c->d_iq_sh);
+    kt_end(c, KC_ELEMENTWISE, 2.0 * total * sizeof(u64), st);
+}
+
+// acc (+)= ct * pt for count ciphertexts (both polynomials), pt [l+1][N] shared.
+__global__ void k_mac_plain(u64 *acc, const u64 *ct, long ct_stride, const u64 *pt, int logN, int L1, int count, int first,
+                            const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t per = (size_t)L1 * N;
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= 2 * per * count) return;
+    size_t cc = i / (2 * per), r = i % (2 * per);
+    size_t rr = r % per;
+    int limb = (int)(rr >> logN);
+    const PrimeC p = pc[limb];
+    u64 v = mul_mod(ct[cc * ct_stride + r], pt[rr], p);
+    acc[i] = first ? v : add_mod(acc[i], v, p.q);
+}
+
+void mac_plain_launch(const rbk_ctx_impl *c, u64 *acc, const u64 *ct, long ct_stride, const u64 *pt, int level, int count,
+                      int first, hipStream_t st)
+{
+    size_t total = (size_t)2 * (level + 1) * c->N * count;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
+    hipLaunchKernelGGL(k_mac_plain, grid, dim3(EW_THREADS), 0, st, acc, ct, ct_stride, pt, c->logN, level + 1, count,
+                       first, c->d_pc);
+    kt_end(c, KC_ELEMENTWISE, (first ? 2.0 : 3.0) * total * sizeof(u64) + (double)(level + 1) * c->N * sizeof(u64), st);
+}
+
+// ct + constant for count ciphertexts (the constant goes to every NTT point of c0)
+__global__ void k_add_scalar_batch(const u64 *a, u64 *out, size_t per, int logN, int count, const PrimeC *pc, ScalArg s)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= 2 * per * count) return;
+    size_t r = i % (2 * per);
+    if (r >= per) { out[i] = a[i]; return; }
+    int limb = (int)(r >> logN);
+    out[i] = add_mod(a[i], s.w[limb], pc[limb].q);
+}
+
+void add_scalar_batch_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int level, int count, const ScalArg &s,
+                             hipStream_t st)
+{
+    size_t per = (size_t)(level + 1) * c->N;
+    dim3 grid((unsigned)((2 * per * count + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_ELEMENTWISE, st);
+    hipLaunchKernelGGL(k_add_scalar_batch, grid, dim3(EW_THREADS), 0, st, a, out, per, c->logN, count, c->d_pc, s);
+    kt_end(c, KC_ELEMENTWISE, 4.0 * per * count * sizeof(u64), st);
+}
+
 // ---------------------------------------------------------------- keys, encryption
 
 // Switching key, NTT domain, every prime of the table:

@@ -67,6 +67,8 @@ struct rbk_ctx_impl {
     std::vector<u64> h_Pmod;                     // P mod q_i, every prime of Q
     u64 *d_Pmod = nullptr, *d_Pmod_sh = nullptr; // [nQ]
     int *d_pow5 = nullptr;                       // [N/2]  (5^j mod 2N - 1) / 2
+    u64 *d_q0mod = nullptr;                      // [nQ]  q_0 mod q_i
+    u64 *d_iq = nullptr, *d_iq_sh = nullptr;     // [nQ]  psi_i^(N/2), a square root of -1 mod q_i
 
     // rescale by q_l: [l][i] = q_l^-1 mod q_i, its Shoup quotient, q_l mod q_i
     u64 *d_rs_inv = nullptr, *d_rs_inv_sh = nullptr, *d_rs_qmod = nullptr;  // [nQ][nQ]
@@ -85,10 +87,15 @@ struct rbk_ctx_impl {
 
     std::vector<void *> owned;  // device allocations freed at destroy
 
+    struct BootPlan *boot = nullptr;   // bootstrapping plan (boot.hip)
+
     bool timing = false;
     mutable KTimer timers[KC_COUNT];
     mutable std::vector<hipEvent_t> event_pool;
 };
+
+// the opaque handle of the C ABI
+struct rbk_ctx : rbk_ctx_impl {};
 
 // timer hooks around a launch (no-ops unless timing is enabled)
 void kt_begin(const rbk_ctx_impl *c, int cls, hipStream_t st);
@@ -142,3 +149,10 @@ void encode_launch(const rbk_ctx_impl *c, const double *d_re, const double *d_im
 void decode_launch(const rbk_ctx_impl *c, const u64 *pt_coef, int level, double scale, double *d_re, double *d_im,
                    size_t n, double *fft_ws, hipStream_t st);
 void decrypt_launch(const rbk_ctx_impl *c, const u64 *ct, u64 *pt, int level, hipStream_t st);
+void modraise_lift_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int level, int npoly, hipStream_t st);
+void monomial_half_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int level, int neg, hipStream_t st);
+void mac_plain_launch(const rbk_ctx_impl *c, u64 *acc, const u64 *ct, long ct_stride, const u64 *pt, int level, int count,
+                      int first, hipStream_t st);
+void add_scalar_batch_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int level, int count, const ScalArg &s,
+                             hipStream_t st);
+void boot_free(rbk_ctx_impl *c);

@@ -32,6 +32,17 @@ class RbkParams(ctypes.Structure):
     ]
 
 
+class RbkBootParams(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_uint32),
+        ("degree", ctypes.c_uint32),
+        ("double_angle", ctypes.c_uint32),
+        ("cts_levels", ctypes.c_uint32),
+        ("stc_levels", ctypes.c_uint32),
+        ("log2_rho", ctypes.c_uint32),
+    ]
+
+
 # name -> (restype, argtypes); the declarations of include/rbk.h
 SIGNATURES = {
     "rbk_ctx_create": (ci, [ctypes.POINTER(RbkParams), ctypes.POINTER(vp)]),
@@ -76,6 +87,14 @@ SIGNATURES = {
     "rbk_mult_relin_batch": (ci, [vp, vp, vp, vp, ci, ci]),
     "rbk_rescale_batch": (ci, [vp, vp, vp, ci, ci]),
     "rbk_rotate_hoisted_batch": (ci, [vp, vp, i64p, ci, vp, ci, ci]),
+    "rbk_boot_setup": (ci, [vp, ctypes.POINTER(RbkBootParams)]),
+    "rbk_boot_rotations": (ci, [vp, i64p, ci]),
+    "rbk_boot_info": (ci, [vp, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]),
+    "rbk_boot_constant_levels": (ci, [vp, ctypes.POINTER(ci), ctypes.POINTER(ci)]),
+    "rbk_boot_export": (ci, [vp, u64p, u64p]),
+    "rbk_boot_import": (ci, [vp, u64p, u64p]),
+    "rbk_bootstrap_batch": (ci, [vp, vp, dblp, vp, dblp, ci]),
+    "rbk_bootstrap": (ci, [vp, vp, ctypes.c_double, vp, dblp]),
     "rbk_timer_enable": (ci, [vp, ci]),
     "rbk_timer_read": (ci, [vp, ci, dblp, u64p, dblp]),
     "rbk_timer_name": (ctypes.c_char_p, [ci]),
@@ -390,6 +409,69 @@ class Context:
         out = self.empty(len(ks), 2, level + 1, self.N)
         _check(self.lib.rbk_rotate_hoisted(self.h, _ptr(ct), pk, len(ks), _ptr(out), level))
         return out
+
+    # ---------------------------------------------------------------- bootstrapping
+    def boot_setup(self, K=23, degree=59, double_angle=2, cts_levels=3, stc_levels=3, log2_rho=2):
+        prm = RbkBootParams(K, degree, double_angle, cts_levels, stc_levels, log2_rho)
+        _check(self.lib.rbk_boot_setup(self.h, ctypes.byref(prm)))
+        self.boot_levels, self.boot_nplain, self.boot_nscalar = self.boot_info()
+
+    def boot_rotations(self):
+        n = _check(self.lib.rbk_boot_rotations(self.h, None, 0))
+        ks = np.zeros(max(n, 1), dtype=np.int64)
+        _check(self.lib.rbk_boot_rotations(self.h, ks.ctypes.data_as(i64p), n))
+        return [int(k) for k in ks[:n]]
+
+    def boot_info(self):
+        lv = (ci * 4)()
+        npl, nsc = ci(), ci()
+        _check(self.lib.rbk_boot_info(self.h, lv, ctypes.byref(npl), ctypes.byref(nsc)))
+        return list(lv), npl.value, nsc.value
+
+    def boot_constant_levels(self):
+        _, npl, nsc = self.boot_info()
+        pl = (ci * max(npl, 1))()
+        sl = (ci * max(nsc, 1))()
+        _check(self.lib.rbk_boot_constant_levels(self.h, pl, sl))
+        return list(pl)[:npl], list(sl)[:nsc]
+
+    def boot_export(self):
+        pl, sl = self.boot_constant_levels()
+        P = np.zeros(sum((l + 1) * self.N for l in pl), dtype=np.uint64)
+        S = np.zeros(max(1, sum(l + 1 for l in sl)), dtype=np.uint64)
+        _check(self.lib.rbk_boot_export(self.h, P.ctypes.data_as(u64p), S.ctypes.data_as(u64p)))
+        plains, scal, o = [], [], 0
+        for l in pl:
+            plains.append(P[o: o + (l + 1) * self.N].reshape(l + 1, self.N))
+            o += (l + 1) * self.N
+        o = 0
+        for l in sl:
+            scal.append(S[o: o + l + 1])
+            o += l + 1
+        return plains, scal
+
+    def boot_import(self, plains, scalars):
+        P = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.uint64).ravel() for p in plains]))
+        S = np.ascontiguousarray(np.concatenate([np.asarray(s, dtype=np.uint64).ravel() for s in scalars]))
+        _check(self.lib.rbk_boot_import(self.h, P.ctypes.data_as(u64p), S.ctypes.data_as(u64p)))
+
+    def bootstrap_batch(self, cts, scales, out=None):
+        """cts: [count][2][1][N] level-0 ciphertexts; returns (outputs, scales)."""
+        count = cts.shape[0]
+        lo = self.boot_levels[3]
+        out = self.empty_ct(lo, count) if out is None else out
+        sc = np.ascontiguousarray(scales, dtype=np.float64)
+        so = np.zeros(count)
+        _check(self.lib.rbk_bootstrap_batch(self.h, _ptr(cts), sc.ctypes.data_as(dblp), _ptr(out),
+                                            so.ctypes.data_as(dblp), count))
+        return out, so
+
+    def bootstrap(self, ct, scale):
+        lo = self.boot_levels[3]
+        out = self.empty_ct(lo)
+        so = ctypes.c_double()
+        _check(self.lib.rbk_bootstrap(self.h, _ptr(ct), float(scale), _ptr(out), ctypes.byref(so)))
+        return out, so.value
 
     # ---------------------------------------------------------------- timers
     def timer_enable(self, on=True):

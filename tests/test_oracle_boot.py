@@ -1,0 +1,96 @@
+"""Pins of the oracle's bootstrapping pieces against plain mathematics:
+the butterfly factorisation equals the decoding map (direct evaluation of the
+canonical embedding), the Chebyshev split is an identity, the interpolant
+error is within its expected bound, and a full encrypted bootstrap at
+N = 2^11 decrypts within 2^-12 of the input slots.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth_inputs as S
+from oracle import boot as B
+from oracle import encoding as ENC
+
+
+def _brv(j, bits):
+    return int(format(j, "0%db" % bits)[::-1], 2)
+
+
+@pytest.mark.parametrize("logN,levels", [(5, 2), (7, 3), (9, 3), (11, 3)])
+def test_butterfly_factorisation_is_the_decoding_map(logN, levels):
+    N = 1 << logN
+    n, M = N // 2, 2 * N
+    logn = logN - 1
+    g = S.rng(40, logN)
+    t = g.uniform(-1, 1, N)                       # a real polynomial
+    w = t[:n] + 1j * t[n:]
+    v = w[[_brv(j, logn) for j in range(n)]]      # bit-reversed w
+    # SlotToCoeff direction: groups innermost first
+    x = v.copy()
+    for grp in B.stage_groups(logn, levels)[::-1]:
+        x = B.apply_diag(B.group_matrix(n, M, grp, False), x)
+    want = ENC.embed(t, N)                        # z_j = t(zeta^(5^j))
+    assert np.max(np.abs(x - want)) < 1e-9 * n
+    # CoeffToSlot direction recovers the bit-reversed coefficients
+    y = want.copy()
+    for grp in B.stage_groups(logn, levels):
+        y = B.apply_diag(B.group_matrix(n, M, grp, True), y)
+    assert np.max(np.abs(y - v)) < 1e-9
+    # every diagonal offset lies in the planned set
+    for grp in B.stage_groups(logn, levels):
+        h0, kks = B.group_offsets(n, grp)
+        offs = {(k * h0) % n for k in kks}
+        assert set(B.group_matrix(n, M, grp, False)) <= offs
+
+
+def test_decoding_map_direct_definition_small():
+    N = 16
+    n, M = 8, 32
+    t = np.arange(N, dtype=float) - 7.5
+    zeta = np.exp(2j * np.pi / M)
+    direct = np.array([sum(t[k] * zeta ** (pow(5, j, M) * k) for k in range(N)) for j in range(n)])
+    assert np.max(np.abs(ENC.embed(t, N) - direct)) < 1e-12
+
+
+def test_chebyshev_split_identity_and_error():
+    K, deg, r = 23, 59, 2
+    c = B.cheb_coeffs(B.evalmod_function(K, r), deg)
+    u = np.linspace(-1, 1, 4001)
+    T = np.polynomial.chebyshev
+    for m, cc in ((32, c), (16, c[:31]), (8, c[:12])):
+        q, rr = B.cheb_split(cc, m)
+        lhs = T.chebval(u, cc)
+        rhs = T.chebval(u, q) * T.chebval(u, np.eye(m + 1)[m]) + T.chebval(u, rr)
+        assert np.max(np.abs(lhs - rhs)) < 1e-12
+    err = np.max(np.abs(T.chebval(u, c) - B.evalmod_function(K, r)(u)))
+    assert err < 2.0 ** -24        # degree 59 on [-(K+1), K+1]
+    # after r double angles the result approximates sin(2 pi x) near integers
+    x = np.concatenate([I + np.linspace(-1e-3, 1e-3, 101) for I in range(-K, K + 1)])
+    y = T.chebval(x / (K + 1), c)
+    for _ in range(r):
+        y = 2 * y * y - 1
+    assert np.max(np.abs(y - np.sin(2 * np.pi * x))) < 2.0 ** -20
+
+
+def test_oracle_bootstrap_precision():
+    logN = 11
+    orc = O.Oracle(logN, [60] + [50] * 17, [60] * 6, 6)
+    N = orc.N
+    g = S.rng(41, logN)
+    plan = B.Plan(N, orc.Q, B.BootParams(log2_rho=4))
+    assert plan.level_out == 3      # 17 - 3 (CoeffToSlot) - 8 (EvalMod) - 3 (SlotToCoeff)
+    s = S.ternary_hw(g, N, 192)
+    pk = orc.keygen_public(s, S.uniform_residues(g, orc.Q, N), S.gaussian(g, N))
+    rlk = orc.keygen_relin(s, *S.key_randomness(g, orc.beta, orc.moduli, N))
+    keys = {}
+    for k in plan.rotations() + ["conj"]:
+        gal = 2 * N - 1 if k == "conj" else orc.galois_rot(k)
+        keys[gal] = orc.keygen_galois(s, gal, *S.key_randomness(g, orc.beta, orc.moduli, N))
+    z = S.uniform_slots(g, N // 2)
+    scale = 2.0 ** 38.3
+    ct = orc.encrypt(0, pk, O.encode(z, N, scale, orc.Q[:1]), *S.encryption_randomness(g, N))
+    out, so = B.Evaluator(orc, plan, rlk, keys).bootstrap(ct, scale)
+    back = O.decode(orc.decrypt(plan.level_out, s, out), N, so, orc.Q[: plan.level_out + 1])
+    assert math.log2(np.max(np.abs(back - z))) < -12
