@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--rots", type=int, default=32, help="hoisted rotations per ciphertext")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-boot", action="store_true", help="skip the bootstrap throughput part")
     return ap.parse_args()
 
 
@@ -99,6 +100,75 @@ def plain_ct(ctx, a, b, ks):
     m = ctx.mult_relin(a, b, L)
     r = ctx.rescale(m, L)
     return ctx.rotate_hoisted(r, ks, L - 1)
+
+
+BOOT_Q_BITS = [60] + [50] * 25
+BOOT_P_BITS = [60] * 9
+BOOT_ALPHA = 9
+
+
+def bench_bootstrap(args, torch):
+    """16 level-0 ciphertexts at scales 2^(35 + 10 i / 15), N = 2^16, full
+    slots, HW-192 secret: batched (one call) vs plain (one call each)."""
+    import numpy as np
+
+    import synth_inputs as S
+    from paper_2506_19693_amd import Context
+
+    ctx = Context(LOG_N, BOOT_Q_BITS, BOOT_P_BITS, BOOT_ALPHA)
+    ctx.boot_setup(K=23, degree=59, double_angle=2, cts_levels=3, stc_levels=3, log2_rho=2)
+    N = ctx.N
+    g = S.rng(3, 16)
+    s = S.ternary_hw(g, N, 192)
+    ctx.set_secret(s)
+    ctx.keygen_public(S.uniform_residues(g, ctx.moduli[: ctx.nQ], N), S.gaussian(g, N))
+    ctx.keygen_relin(*S.key_randomness(g, ctx.beta, ctx.moduli, N))
+    for k in ctx.boot_rotations() + ["conj"]:
+        gal = 2 * N - 1 if k == "conj" else ctx.galois_elt(k)
+        ctx.keygen_galois(gal, *S.key_randomness(g, ctx.beta, ctx.moduli, N))
+    count = 16
+    scales = [2.0 ** (35 + 10 * i / 15) for i in range(count)]
+    zs = [S.uniform_slots(g, N // 2) for _ in range(count)]
+    cts = ctx.empty(count, 2, 1, N)
+    for i in range(count):
+        cts[i].copy_(ctx.encrypt(ctx.encode(zs[i], 0, scales[i]), 0, *S.encryption_randomness(g, N)))
+    lo = ctx.boot_levels[3]
+    out = ctx.empty_ct(lo, count)
+    for _ in range(args.warmup):
+        ctx.bootstrap_batch(cts, scales, out=out)
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, so = ctx.bootstrap_batch(cts, scales, out=out)
+    ctx.sync()
+    t_b = (time.perf_counter() - t0) / args.steps
+    err = max(float(np.max(np.abs(ctx.decode(ctx.decrypt(out[i], lo), lo, so[i]).real - zs[i]))) for i in range(count))
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(count):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.bootstrap(cts[i], scales[i])
+        e1.record()
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    t_p = time.perf_counter() - t0
+    res = {
+        "workload": "bootstrap: 16 level-0 ciphertexts at scales 2^35..2^45, N=2^16, full 2^15 slots, HW-192 secret, "
+                    "CtS/StC 3-level BSGS, EvalMod Chebyshev degree 59 + 2 double angles, 26 primes (60 + 25x50), "
+                    "9 special primes",
+        "bootstraps_per_s_batched": count / t_b,
+        "bootstraps_per_s_plain": count / t_p,
+        "batched_vs_plain": t_p / t_b,
+        "ms_per_batch": t_b * 1e3,
+        "plain_latency_ms_p50": percentile(lat, 50),
+        "plain_latency_ms_p99": percentile(lat, 99),
+        "output_level": lo,
+        "max_slot_error_log2": float(np.log2(err)),
+    }
+    ctx.close()
+    return res
 
 
 def cpu_baseline():
@@ -229,6 +299,17 @@ def main():
         "share_of_step": round(ms / (t_batched * 1e3 * args.steps), 3),
     }
 
+    boot = None
+    if not args.no_boot:
+        del out_m, out_r, out_h, A, B
+        ctx.close()
+        torch.cuda.empty_cache()
+        log("bootstrap: 16 ciphertexts, N=2^16 ...")
+        boot = bench_bootstrap(args, torch)
+        log("bootstrap: %.2f/s batched, %.2f/s plain, p99 %.1f ms, max error 2^%.2f" % (
+            boot["bootstraps_per_s_batched"], boot["bootstraps_per_s_plain"], boot["plain_latency_ms_p99"],
+            boot["max_slot_error_log2"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample) ...")
@@ -258,6 +339,7 @@ def main():
         "batched_vs_plain": round(plain["ms_per_step"] / (t_batched * 1e3), 3) if plain else None,
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
+        "bootstrap": boot,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

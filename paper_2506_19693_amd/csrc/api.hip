@@ -1039,7 +1039,7 @@ extern "C" int rbk_rotate_hoisted(rbk_ctx *c, const uint64_t *ct, const int64_t 
 static const char *kc_names[KC_COUNT] = {
     "ntt_cols_fwd",      "ntt_rows_fwd",      "ntt_rows_inv",     "ntt_cols_inv",      "k_bconv_modup",
     "k_bconv_moddown",   "k_ip",              "k_moddown_finish", "k_tensor",          "k_rescale_lift+finish",
-    "elementwise",
+    "elementwise",       "k_ip_p",            "k_moddown_ip",
 };
 
 static hipEvent_t take_event(const rbk_ctx_impl *c)

@@ -185,7 +185,7 @@ void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly,
 // extended-basis position outside the digit (written into ext).
 // ModDown (MODUP = false): inputs are the nP special-prime limbs of one
 // polynomial, outputs the l+1 Q limbs.
-template <bool MODUP>
+template <bool MODUP, int MAXIN>
 __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_stride, u64 *out, long out_stride, int logN,
                                                       int L1, int E, int alpha, int nP, int nQ, const u64 *A,
                                                       const u64 *Ash, const u64 *M, long m_stride, const PrimeC *pc)
@@ -221,9 +221,9 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
     for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS) tab[w] = Mj[(size_t)(w / n_out) * m_stride + (w % n_out)];
     __syncthreads();
     if (k >= N) return;
-    u64 y[BCONV_MAX_IN];
+    u64 y[MAXIN];
 #pragma unroll
-    for (int i = 0; i < BCONV_MAX_IN; i++)
+    for (int i = 0; i < MAXIN; i++)
         if (i < n_in) {
             const int pi = MODUP ? lo + i : nQ + i;
             y[i] = shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[pi].q);
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
         const PrimeC p = pc[pr];
         u128w acc = {0, 0};
 #pragma unroll
-        for (int i = 0; i < BCONV_MAX_IN; i++)
+        for (int i = 0; i < MAXIN; i++)
             if (i < n_in) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
         dst[(size_t)pos * N + k] = redc_any(acc, p.q, p.qneg, p.one_sh);
     }
@@ -253,8 +253,15 @@ void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride
     int L1 = level + 1, E = L1 + c->nP;
     dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), T.beta, count);
     kt_begin(c, KC_BCONV_UP, st);
-    hipLaunchKernelGGL(k_bconv<true>, grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1, E,
-                       c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
+    if (c->alpha <= 4)
+        hipLaunchKernelGGL((k_bconv<true, 4>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
+                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
+    else if (c->alpha <= 8)
+        hipLaunchKernelGGL((k_bconv<true, 8>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
+                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
+    else
+        hipLaunchKernelGGL((k_bconv<true, 16>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
+                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
     kt_end(c, KC_BCONV_UP, (double)count * T.beta * E * c->N * sizeof(u64), st);
 }
 
@@ -264,8 +271,15 @@ void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride
     int L1 = level + 1;
     dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), 1, count);
     kt_begin(c, KC_BCONV_DOWN, st);
-    hipLaunchKernelGGL(k_bconv<false>, grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
-                       L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
+    if (c->nP <= 4)
+        hipLaunchKernelGGL((k_bconv<false, 4>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
+                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
+    else if (c->nP <= 8)
+        hipLaunchKernelGGL((k_bconv<false, 8>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
+                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
+    else
+        hipLaunchKernelGGL((k_bconv<false, 16>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN,
+                           L1, L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
     kt_end(c, KC_BCONV_DOWN, (double)count * (c->nP + L1) * c->N * sizeof(u64), st);
 }
 
@@ -366,39 +380,73 @@ void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, c
 
 // ---------------------------------------------------------------- key switching with a fused ModDown epilogue
 
+// ciphertexts handled by one thread of the fused inner-product kernels: the
+// key words are loaded once per thread, the grid's z dimension covers the rest
+#define IP_CTS_PER_THREAD 8
+
+// Two adjacent NTT-domain coefficients (o, o+1), o even, are the values at
+// psi^(2k+1) and psi^(2k+1+N) (bit reversal); an automorphism maps them to the
+// two halves of one aligned pair, possibly swapped: auto_src(o+1) = auto_src(o) ^ 1.
+// So every kernel below moves 16-byte pairs.
+struct __attribute__((aligned(16))) u64x2 {
+    u64 x, y;
+};
+
+__device__ __forceinline__ u64x2 ld2(const u64 *p) { return *reinterpret_cast<const u64x2 *>(p); }
+__device__ __forceinline__ void st2(u64 *p, u64 a, u64 b)
+{
+    u64x2 v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<u64x2 *>(p) = v;
+}
+// the pair at source index src (even-aligned load, swapped when src is odd)
+__device__ __forceinline__ u64x2 ld2_perm(const u64 *base, size_t src)
+{
+    u64x2 v = ld2(base + (src & ~(size_t)1));
+    if (src & 1) {
+        u64 t = v.x;
+        v.x = v.y;
+        v.y = t;
+    }
+    return v;
+}
+
 // Inner product restricted to the special-prime positions, written to
 // tp[count][2][nP][N] (the input of the ModDown inverse NTT).
+template <int BETA>
 __global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int logN,
-                                                     int L1, int E, int beta, int nT, int nQ, int nP, int count, u64 g,
+                                                     int L1, int E, int nT, int nQ, int nP, int count, int cpc, u64 g,
                                                      const PrimeC *pc)
 {
     const size_t N = (size_t)1 << logN;
-    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const size_t k = 2 * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
     const int t = blockIdx.y;
+    const int ct0 = blockIdx.z * cpc, ct1 = min(count, ct0 + cpc);
     if (k >= N) return;
     const int pos = L1 + t, pr = nQ + t;
     const PrimeC p = pc[pr];
-    u64 kb[IP_MAX_BETA], ka[IP_MAX_BETA];
+    u64x2 kb[BETA], ka[BETA];
 #pragma unroll
-    for (int j = 0; j < IP_MAX_BETA; j++)
-        if (j < beta) {
-            kb[j] = key[(((size_t)j * 2 + 0) * nT + pr) * N + k];
-            ka[j] = key[(((size_t)j * 2 + 1) * nT + pr) * N + k];
+    for (int j = 0; j < BETA; j++) {
+            kb[j] = ld2(key + (((size_t)j * 2 + 0) * nT + pr) * N + k);
+            ka[j] = ld2(key + (((size_t)j * 2 + 1) * nT + pr) * N + k);
         }
     const size_t src = g ? auto_src((u32)k, g, logN) : k;
-    for (int ct = 0; ct < count; ct++) {
-        const u64 *x = ext + ct * ext_stride + (size_t)pos * N + src;
-        u128w s0 = {0, 0}, s1 = {0, 0};
+    for (int ct = ct0; ct < ct1; ct++) {
+        const u64 *x = ext + ct * ext_stride + (size_t)pos * N;
+        u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
 #pragma unroll
-        for (int j = 0; j < IP_MAX_BETA; j++)
-            if (j < beta) {
-                u64 d = x[(size_t)j * E * N];
-                acc_wide(s0, mul_wide(d, kb[j]));
-                acc_wide(s1, mul_wide(d, ka[j]));
+        for (int j = 0; j < BETA; j++) {
+                u64x2 d = ld2_perm(x + (size_t)j * E * N, src);
+                acc_wide(s0, mul_wide(d.x, kb[j].x));
+                acc_wide(t0, mul_wide(d.y, kb[j].y));
+                acc_wide(s1, mul_wide(d.x, ka[j].x));
+                acc_wide(t1, mul_wide(d.y, ka[j].y));
             }
         u64 *o = tp + ((size_t)ct * 2 * nP + t) * N + k;
-        o[0] = redc_any(s0, p.q, p.qneg, p.one_sh);
-        o[(size_t)nP * N] = redc_any(s1, p.q, p.qneg, p.one_sh);
+        st2(o, redc_any(s0, p.q, p.qneg, p.one_sh), redc_any(t0, p.q, p.qneg, p.one_sh));
+        st2(o + (size_t)nP * N, redc_any(s1, p.q, p.qneg, p.one_sh), redc_any(t1, p.q, p.qneg, p.one_sh));
     }
 }
 
@@ -406,49 +454,60 @@ __global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *ext, long ext_st
 //   out[h][i] = (sum_j ext_j[i] key_j[h][i] - conv[h][i]) * P^-1 mod q_i (+ add_h[i]).
 // add (through sigma_{add_g} when add_g != 0) goes to poly 0, and to poly 1
 // when add_both != 0.
+template <int BETA>
 __global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
                                                            long conv_stride, const u64 *add, long add_stride, u64 add_g,
                                                            int add_both, u64 *out, long out_stride, int logN, int L1, int E,
-                                                           int beta, int nT, int count, u64 g, const u64 *Pinv,
+                                                           int nT, int count, int cpc, u64 g, const u64 *Pinv,
                                                            const u64 *Pinv_sh, const PrimeC *pc)
 {
     const size_t N = (size_t)1 << logN;
-    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const size_t k = 2 * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
     const int i = blockIdx.y;
+    const int ct0 = blockIdx.z * cpc, ct1 = min(count, ct0 + cpc);
     if (k >= N) return;
     const PrimeC p = pc[i];
     const u64 pinv = Pinv[i], pinv_sh = Pinv_sh[i];
-    u64 kb[IP_MAX_BETA], ka[IP_MAX_BETA];
+    u64x2 kb[BETA], ka[BETA];
 #pragma unroll
-    for (int j = 0; j < IP_MAX_BETA; j++)
-        if (j < beta) {
-            kb[j] = key[(((size_t)j * 2 + 0) * nT + i) * N + k];
-            ka[j] = key[(((size_t)j * 2 + 1) * nT + i) * N + k];
+    for (int j = 0; j < BETA; j++) {
+            kb[j] = ld2(key + (((size_t)j * 2 + 0) * nT + i) * N + k);
+            ka[j] = ld2(key + (((size_t)j * 2 + 1) * nT + i) * N + k);
         }
     const size_t src = g ? auto_src((u32)k, g, logN) : k;
     const size_t asrc = add_g ? auto_src((u32)k, add_g, logN) : k;
     const size_t per = (size_t)L1 * N, li = (size_t)i * N;
-    for (int ct = 0; ct < count; ct++) {
-        const u64 *x = ext + ct * ext_stride + li + src;
-        u128w s0 = {0, 0}, s1 = {0, 0};
+    for (int ct = ct0; ct < ct1; ct++) {
+        const u64 *x = ext + ct * ext_stride + li;
+        u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
 #pragma unroll
-        for (int j = 0; j < IP_MAX_BETA; j++)
-            if (j < beta) {
-                u64 d = x[(size_t)j * E * N];
-                acc_wide(s0, mul_wide(d, kb[j]));
-                acc_wide(s1, mul_wide(d, ka[j]));
+        for (int j = 0; j < BETA; j++) {
+                u64x2 d = ld2_perm(x + (size_t)j * E * N, src);
+                acc_wide(s0, mul_wide(d.x, kb[j].x));
+                acc_wide(t0, mul_wide(d.y, kb[j].y));
+                acc_wide(s1, mul_wide(d.x, ka[j].x));
+                acc_wide(t1, mul_wide(d.y, ka[j].y));
             }
         const u64 *cv = conv + ct * conv_stride + li + k;
-        u64 v0 = shoup(sub_mod(redc_any(s0, p.q, p.qneg, p.one_sh), cv[0], p.q), pinv, pinv_sh, p.q);
-        u64 v1 = shoup(sub_mod(redc_any(s1, p.q, p.qneg, p.one_sh), cv[per], p.q), pinv, pinv_sh, p.q);
+        u64x2 c0 = ld2(cv), c1 = ld2(cv + per);
+        u64 v0 = shoup(sub_mod(redc_any(s0, p.q, p.qneg, p.one_sh), c0.x, p.q), pinv, pinv_sh, p.q);
+        u64 w0 = shoup(sub_mod(redc_any(t0, p.q, p.qneg, p.one_sh), c0.y, p.q), pinv, pinv_sh, p.q);
+        u64 v1 = shoup(sub_mod(redc_any(s1, p.q, p.qneg, p.one_sh), c1.x, p.q), pinv, pinv_sh, p.q);
+        u64 w1 = shoup(sub_mod(redc_any(t1, p.q, p.qneg, p.one_sh), c1.y, p.q), pinv, pinv_sh, p.q);
         if (add) {
             const u64 *ad = add + ct * add_stride + li;
-            v0 = add_mod(v0, ad[asrc], p.q);
-            if (add_both) v1 = add_mod(v1, ad[per + asrc], p.q);
+            u64x2 a0 = ld2_perm(ad, asrc);
+            v0 = add_mod(v0, a0.x, p.q);
+            w0 = add_mod(w0, a0.y, p.q);
+            if (add_both) {
+                u64x2 a1 = ld2_perm(ad + per, asrc);
+                v1 = add_mod(v1, a1.x, p.q);
+                w1 = add_mod(w1, a1.y, p.q);
+            }
         }
         u64 *o = out + ct * out_stride + li + k;
-        o[0] = v0;
-        o[per] = v1;
+        st2(o, v0, w0);
+        st2(o + per, v1, w1);
     }
 }
 
@@ -458,11 +517,17 @@ void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u
     int L1 = level + 1, E = L1 + c->nP;
     int beta_l = (L1 + c->alpha - 1) / c->alpha;
     if (c->nP == 0) return;
-    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), c->nP, 1);
-    kt_begin(c, KC_IP, st);
-    hipLaunchKernelGGL(k_ip_p, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, tp, c->logN, L1, E, beta_l, c->nT, c->nQ,
-                       c->nP, count, g, c->d_pc);
-    kt_end(c, KC_IP, ((double)count * beta_l * c->nP + 2.0 * beta_l * c->nP + 2.0 * count * c->nP) * c->N * sizeof(u64),
+    const int cpc = IP_CTS_PER_THREAD;
+    dim3 grid((unsigned)((c->N / 2 + EW_THREADS - 1) / EW_THREADS), c->nP, (count + cpc - 1) / cpc);
+    kt_begin(c, KC_IP_P, st);
+#define IPP_CASE(B)                                                                                          \
+    case B:                                                                                                   \
+        hipLaunchKernelGGL(k_ip_p<B>, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, tp, c->logN, L1, E, c->nT, \
+                           c->nQ, c->nP, count, cpc, g, c->d_pc);                                             \
+        break;
+    switch (beta_l) { IPP_CASE(1) IPP_CASE(2) IPP_CASE(3) IPP_CASE(4) IPP_CASE(5) IPP_CASE(6) IPP_CASE(7) default: IPP_CASE(8) }
+#undef IPP_CASE
+    kt_end(c, KC_IP_P, ((double)count * beta_l * c->nP + 2.0 * beta_l * c->nP + 2.0 * count * c->nP) * c->N * sizeof(u64),
            st);
 }
 
@@ -472,13 +537,19 @@ void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, c
 {
     int L1 = level + 1, E = L1 + c->nP;
     int beta_l = (L1 + c->alpha - 1) / c->alpha;
-    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), L1, 1);
-    kt_begin(c, KC_MODDOWN_FIN, st);
-    hipLaunchKernelGGL(k_moddown_ip, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, conv, conv_stride, add,
-                       add_stride, add_g, add_both, out, out_stride, c->logN, L1, E, beta_l, c->nT, count, g, c->d_Pinv,
-                       c->d_Pinv_sh, c->d_pc);
+    const int cpc = IP_CTS_PER_THREAD;
+    dim3 grid((unsigned)((c->N / 2 + EW_THREADS - 1) / EW_THREADS), L1, (count + cpc - 1) / cpc);
+    kt_begin(c, KC_MODDOWN_IP, st);
+#define MDI_CASE(B)                                                                                           \
+    case B:                                                                                                    \
+        hipLaunchKernelGGL(k_moddown_ip<B>, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, conv, conv_stride, add, \
+                           add_stride, add_g, add_both, out, out_stride, c->logN, L1, E, c->nT, count, cpc, g, c->d_Pinv, \
+                           c->d_Pinv_sh, c->d_pc);                                                             \
+        break;
+    switch (beta_l) { MDI_CASE(1) MDI_CASE(2) MDI_CASE(3) MDI_CASE(4) MDI_CASE(5) MDI_CASE(6) MDI_CASE(7) default: MDI_CASE(8) }
+#undef MDI_CASE
     double words = (double)count * L1 * (beta_l + 2 + 2 + (add ? (add_both ? 2 : 1) : 0)) + 2.0 * beta_l * L1;
-    kt_end(c, KC_MODDOWN_FIN, words * c->N * sizeof(u64), st);
+    kt_end(c, KC_MODDOWN_IP, words * c->N * sizeof(u64), st);
 }
 
 // ---------------------------------------------------------------- rescale

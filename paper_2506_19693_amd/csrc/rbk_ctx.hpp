@@ -35,6 +35,8 @@ enum KClass {
     KC_TENSOR,
     KC_RESCALE,
     KC_ELEMENTWISE,
+    KC_IP_P,
+    KC_MODDOWN_IP,
     KC_COUNT
 };
 
