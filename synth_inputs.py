@@ -61,3 +61,17 @@ def key_randomness(g, beta, moduli, N):
 def encryption_randomness(g, N):
     """(v, e0, e1) of one public-key encryption."""
     return ternary(g, N), gaussian(g, N), gaussian(g, N)
+
+
+def mlp_batch(g, b, k0, o):
+    """A synthetic classification batch: features uniform in [0, 1), one-hot
+    labels of classes drawn uniformly from o."""
+    X = g.uniform(0.0, 1.0, size=(b, k0))
+    Y = np.zeros((b, o))
+    Y[np.arange(b), g.integers(0, o, size=b)] = 1.0
+    return X, Y
+
+
+def mlp_weights(g, dims):
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) matrices of the given (fan_in, fan_out) shapes."""
+    return [g.uniform(-1.0, 1.0, size=(d, k)) / np.sqrt(d) for d, k in dims]
