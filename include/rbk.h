@@ -48,6 +48,7 @@ extern "C" {
 #define RBK_EDEVICE (-5)     /* HIP runtime error */
 #define RBK_ESTATE (-6)      /* operation needs state that is not set up */
 #define RBK_EUNSUPPORTED (-7)
+#define RBK_ESCALE (-8)      /* operands of an addition at different scales */
 
 typedef struct rbk_ctx rbk_ctx;
 
@@ -251,6 +252,99 @@ int rbk_boot_import(rbk_ctx *ctx, const uint64_t *plains, const uint64_t *scalar
 int rbk_bootstrap_batch(rbk_ctx *ctx, const uint64_t *d_in, const double *scales_in, uint64_t *d_out, double *scales_out,
                         int count);
 int rbk_bootstrap(rbk_ctx *ctx, const uint64_t *d_in, double scale_in, uint64_t *d_out, double *scale_out);
+
+/* ---- packed MLP training step (paper Section 4; Algorithms 1 and 2) ------ */
+
+/* An MLP of H encrypted local-loss blocks packed into r x c slot matrices
+ * (Section 4.1, r c = N/2, slot (i, j) at index i c + j).  Block h (1-based)
+ * is an RE-block for odd h (RE-FC layer in the row-wise format, CE-FC local
+ * classifier in the column-wise format) and a CE-block for even h.  Its
+ * forward pass, RSS gradient, backward pass and NAG-style update follow
+ * Algorithm 1 and Algorithm 2; the products are RE-Matmul / CE-Matmul
+ * (SumRows / SumCols of Section 3).
+ *
+ *  k0        input width; wider than r means ceil(k0 / r) row tiles of the
+ *            first layer (its input, weights, gradients and velocities are
+ *            one ciphertext per tile, and RE-Matmul sums the tiles first)
+ *  widths    k_1..k_H; odd layers k_h <= c, even layers k_h <= r, and the
+ *            input of every layer but the first fits its side (r or c)
+ *  n_out     o, the outputs of every local classifier (o <= r and o <= c)
+ *  act       f(z) = act[0] z + act[1] z^2 + act[2] z^3; the leading non-zero
+ *            coefficient (act[2], else act[1]) must be positive.  The paper's
+ *            activation z + z^2 is {1, 1, 0}
+ *  gamma, eta, mu   learning rate, decay rate, momentum of Algorithm 2
+ *  log2_scale       the scale 2^log2_scale of the updated W and V
+ *  flags     RBK_MLP_LITERAL_DERIV: dZ = 1 + 2 dA as printed in Section
+ *            4.3.3 instead of the chain rule dZ = dA (.) f'(Z);
+ *            RBK_MLP_L2_DECAY: decay dW + eta W instead of (1 + eta) dW
+ *
+ * The batch gradient is the mean over the b samples.  The update folds the
+ * decay and the constants gamma, gamma mu, gamma mu^2 into one scalar per
+ * operand: W' = W - c_w dW - c_wv V and V' = c_v dW + c_vv V, one level each.
+ * Every ciphertext carries an exact float64 scale: a product of ciphertexts
+ * has scale s_a s_b / q_l, a product with a constant c uses the integer
+ * round(c q_l T / s) so that the rescaled result has the scale T it must
+ * meet, the SumCols mask is encoded at scale q_l, and an affine map a x + b
+ * (a > 0) of one ciphertext only changes its scale to s / a and adds
+ * round(b s / a).  Additions then always meet equal scales (RBK_ESCALE
+ * otherwise). */
+#define RBK_MLP_LITERAL_DERIV 1u
+#define RBK_MLP_L2_DECAY 2u
+
+typedef struct rbk_mlp rbk_mlp;
+
+typedef struct {
+    uint32_t k0;
+    uint32_t n_layers;
+    const uint32_t *widths;
+    uint32_t n_out;
+    uint32_t r, c;
+    double act[3];
+    double gamma, eta, mu;
+    double log2_scale;
+    uint32_t flags;
+} rbk_mlp_desc;
+
+/* Validate the description against the context's N and create the step's
+ * runner (device memory is taken on the first step and kept).  *out owned by
+ * the caller; destroy it before its context. */
+int rbk_mlp_create(rbk_ctx *ctx, const rbk_mlp_desc *desc, rbk_mlp **out);
+int rbk_mlp_destroy(rbk_mlp *mlp);
+/* info[0] = input tiles, info[1] = state ciphertexts, info[2] = levels one
+ * step consumes below the level of the weights (Table 1's depth) */
+int rbk_mlp_info(const rbk_mlp *mlp, int *info);
+/* rotation indices (both signs) the step needs Galois keys for; writes at
+ * most max, returns the count */
+int rbk_mlp_rotations(const rbk_mlp *mlp, int64_t *ks, int max);
+/* The state is, per block h: the W tiles (one ciphertext each), W*, the V
+ * tiles, V*.  set_state copies d_ct[2][level+1][N] (NTT domain) with its
+ * scale into slot idx; get_state returns level and scale and, if d_ct is not
+ * NULL, copies the ciphertext out.  V slots are not read at t = 1. */
+int rbk_mlp_set_state(rbk_mlp *mlp, int idx, const uint64_t *d_ct, int level, double scale);
+int rbk_mlp_get_state(rbk_mlp *mlp, int idx, uint64_t *d_ct, int *level, double *scale);
+/* Use d_pt[level+1][N] (NTT domain, encoded at scale q_level) as the SumCols
+ * mask plaintext at `level` instead of the library's own encoding. */
+int rbk_mlp_set_mask(rbk_mlp *mlp, int level, const uint64_t *d_pt);
+
+/* One training step t >= 1 on b samples, all at `level` and `scale`:
+ *   d_x     [b][tiles][2][level+1][N]  inputs in the expanded format
+ *   d_y_exp [b][2][level+1][N]         one-hot labels, expanded format
+ *   d_y_rep [b][2][level+1][N]         the same labels, repeated format
+ * Afterwards every state ciphertext is bootstrapped (one batched call; the
+ * context needs rbk_boot_setup and its keys) unless RBK_MLP_NO_BOOTSTRAP.
+ * RBK_MLP_PER_SAMPLE runs the samples one at a time (the plain form; the
+ * default processes the b samples of every operation in one launch set);
+ * the residues are the same either way.  Needs the relinearisation key and
+ * the keys of rbk_mlp_rotations.  RBK_ELEVEL if a product would go below
+ * level 0. */
+#define RBK_MLP_NO_BOOTSTRAP 1u
+#define RBK_MLP_PER_SAMPLE 2u
+int rbk_mlp_train_step(rbk_mlp *mlp, const uint64_t *d_x, const uint64_t *d_y_exp, const uint64_t *d_y_rep, int b,
+                       int level, double scale, int t, uint32_t step_flags);
+/* The integer constants the last step multiplied or added, in evaluation
+ * order (with RBK_MLP_PER_SAMPLE: sample by sample, block by block, then
+ * the updates).  Writes at most max, returns the count. */
+int rbk_mlp_scalars(const rbk_mlp *mlp, int64_t *out, int max);
 
 /* ---- per-kernel timers -------------------------------------------------- */
 /* With timers on, every kernel launch on the context stream is bracketed by

@@ -471,6 +471,8 @@ class EncOps:
         return np.array([k % q for q in self.q[: lv + 1]], dtype=np.uint64)
 
     def _int(self, v):
+        if not abs(v) < 2.0 ** 62:
+            raise ValueError("constant out of range (|k| >= 2^62): the scales do not fit the primes")
         k = int(np.rint(v))
         self.scalars.append(k)
         return k

@@ -2,7 +2,8 @@
 
 Every .hip file under csrc/ is compiled for gfx950 only and linked into one
 shared library next to this file.  Packed FP32 instructions are disabled for
-all device code.
+all device code, and floating-point contraction is off so that host-side
+constants round exactly as in plain IEEE double arithmetic.
 """
 import os
 import subprocess
@@ -21,6 +22,7 @@ FLAGS = [
     "-fPIC",
     "--offload-arch=" + ARCH,
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=off",
     "-Wall",
     "-Wno-unused-result",
     "-Wno-unused-function",

@@ -436,7 +436,7 @@ static int check_level(const rbk_ctx *c, int level, int min_level = 0)
 }
 
 // workspace words of the key-switching pipeline for `count` ciphertexts at level l
-static size_t ks_words(const rbk_ctx *c, int level, int count)
+size_t ks_words(const rbk_ctx *c, int level, int count)
 {
     size_t L1 = level + 1, E = L1 + c->nP, beta = (L1 + c->alpha - 1) / c->alpha, N = c->N;
     size_t ext = count * beta * E * N, u = count * 2 * E * N, coef = count * L1 * N, tp = count * 2 * c->nP * N,
@@ -888,7 +888,7 @@ extern "C" int rbk_moddown(rbk_ctx *c, const uint64_t *u, uint64_t *out, int lev
 
 // key switch of count polynomials d (at d_stride) with key g (0 = relin),
 // results into out (count x [2][l+1][N] at out_stride) plus `add`.
-static int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d, long d_stride, const u64 *add,
+int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d, long d_stride, const u64 *add,
                          long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count, u64 *base)
 {
     const size_t N = c->N, L1 = level + 1, E = L1 + c->nP, beta = (L1 + c->alpha - 1) / c->alpha;

@@ -158,3 +158,15 @@ void mac_plain_launch(const rbk_ctx_impl *c, u64 *acc, const u64 *ct, long ct_st
 void add_scalar_batch_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int level, int count, const ScalArg &s,
                              hipStream_t st);
 void boot_free(rbk_ctx_impl *c);
+
+// ---- pieces of api.hip shared with the bootstrap and MLP runners ----
+// workspace words of the key-switching pipeline for `count` ciphertexts at level l
+size_t ks_words(const rbk_ctx *c, int level, int count);
+// KS of count polynomials d (d_stride apart) with `key`: out = KS(d) + add
+// (add_both: both polynomials of add, else c0 only; perm_g: automorphism of
+// the digits first, 0 for none); base: ks_words() of workspace
+int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d, long d_stride, const u64 *add,
+                  long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count, u64 *base);
+// out = Rot_g of count contiguous ciphertexts [count][2][l+1][N]
+int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g);
+int rbk_set_error(int code, const char *msg);

@@ -5,8 +5,10 @@ librbk.so.  PyTorch supplies device memory (int64 tensors that hold the
 uint64 residues bit for bit) and the current stream.  If the library is not
 built, or no GPU is visible, calls fail loudly: there is no fallback.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -30,6 +32,29 @@ class RbkParams(ctypes.Structure):
         ("p_bits", ctypes.POINTER(ctypes.c_uint32)),
         ("alpha", ctypes.c_uint32),
     ]
+
+
+class RbkMlpDesc(ctypes.Structure):
+    _fields_ = [
+        ("k0", ctypes.c_uint32),
+        ("n_layers", ctypes.c_uint32),
+        ("widths", ctypes.POINTER(ctypes.c_uint32)),
+        ("n_out", ctypes.c_uint32),
+        ("r", ctypes.c_uint32),
+        ("c", ctypes.c_uint32),
+        ("act", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("log2_scale", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+MLP_LITERAL_DERIV = 1
+MLP_L2_DECAY = 2
+MLP_NO_BOOTSTRAP = 1
+MLP_PER_SAMPLE = 2
 
 
 class RbkBootParams(ctypes.Structure):
@@ -95,6 +120,15 @@ SIGNATURES = {
     "rbk_boot_import": (ci, [vp, u64p, u64p]),
     "rbk_bootstrap_batch": (ci, [vp, vp, dblp, vp, dblp, ci]),
     "rbk_bootstrap": (ci, [vp, vp, ctypes.c_double, vp, dblp]),
+    "rbk_mlp_create": (ci, [vp, ctypes.POINTER(RbkMlpDesc), ctypes.POINTER(vp)]),
+    "rbk_mlp_destroy": (ci, [vp]),
+    "rbk_mlp_info": (ci, [vp, ctypes.POINTER(ci)]),
+    "rbk_mlp_rotations": (ci, [vp, i64p, ci]),
+    "rbk_mlp_set_state": (ci, [vp, ci, vp, ci, ctypes.c_double]),
+    "rbk_mlp_get_state": (ci, [vp, ci, vp, ctypes.POINTER(ci), dblp]),
+    "rbk_mlp_set_mask": (ci, [vp, ci, vp]),
+    "rbk_mlp_train_step": (ci, [vp, vp, vp, vp, ci, ci, ctypes.c_double, ci, ctypes.c_uint32]),
+    "rbk_mlp_scalars": (ci, [vp, i64p, ci]),
     "rbk_timer_enable": (ci, [vp, ci]),
     "rbk_timer_read": (ci, [vp, ci, dblp, u64p, dblp]),
     "rbk_timer_name": (ctypes.c_char_p, [ci]),
@@ -162,6 +196,20 @@ def to_host(t):
     return t.detach().cpu().numpy().view(np.uint64)
 
 
+_LIVE_MLPS = weakref.WeakSet()
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Release library objects while the HIP runtime is still up (objects that
+    survive until interpreter teardown would otherwise be freed after it)."""
+    for m in list(_LIVE_MLPS):
+        m.close()
+    for c in list(_LIVE_CONTEXTS):
+        c.close()
+
+
 class Context:
     """One librbk context: ring degree 2^log_n, Q chain of sizes q_bits,
     special primes p_bits, alpha primes per key-switching digit."""
@@ -189,6 +237,7 @@ class Context:
         _check(self.lib.rbk_psi(self.h, p.ctypes.data_as(u64p)))
         self.psi = [int(x) for x in p]
         self.beta = self.num_digits(self.L)
+        _LIVE_CONTEXTS.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -512,3 +561,74 @@ class Context:
         out = self.empty(count, len(ks), 2, level + 1, self.N) if out is None else out
         _check(self.lib.rbk_rotate_hoisted_batch(self.h, _ptr(ct), pk, len(ks), _ptr(out), level, count))
         return out
+
+
+class Mlp:
+    """The packed MLP training step of one context (rbk_mlp_* of rbk.h).
+
+    widths: hidden widths k_1..k_H; act: (a1, a2, a3) of
+    f(z) = a1 z + a2 z^2 + a3 z^3."""
+
+    def __init__(self, ctx, k0, widths, n_out, r, c, act=(1.0, 1.0, 0.0), gamma=0.001, eta=0.001, mu=0.9,
+                 log2_scale=50.0, literal_deriv=False, l2_decay=False):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        w = (ctypes.c_uint32 * len(widths))(*widths)
+        flags = (MLP_LITERAL_DERIV if literal_deriv else 0) | (MLP_L2_DECAY if l2_decay else 0)
+        self._w = w
+        d = RbkMlpDesc(k0, len(widths), w, n_out, r, c, (ctypes.c_double * 3)(*act), gamma, eta, mu, log2_scale,
+                       flags)
+        h = vp()
+        _check(self.lib.rbk_mlp_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        info = (ci * 3)()
+        _check(self.lib.rbk_mlp_info(self.h, info))
+        self.tiles, self.n_state, self.depth = list(info)
+        _LIVE_MLPS.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbk_mlp_destroy(self.h)
+            self.h = None
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rotations(self):
+        n = _check(self.lib.rbk_mlp_rotations(self.h, None, 0))
+        ks = np.zeros(max(n, 1), dtype=np.int64)
+        _check(self.lib.rbk_mlp_rotations(self.h, ks.ctypes.data_as(i64p), n))
+        return [int(k) for k in ks[:n]]
+
+    def set_state(self, idx, ct, level, scale):
+        _check(self.lib.rbk_mlp_set_state(self.h, idx, _ptr(ct), level, float(scale)))
+
+    def get_state(self, idx, copy=True):
+        """(ciphertext tensor or None, level, scale) of state slot idx."""
+        lv, sc = ci(), ctypes.c_double()
+        _check(self.lib.rbk_mlp_get_state(self.h, idx, None, ctypes.byref(lv), ctypes.byref(sc)))
+        if not copy:
+            return None, lv.value, sc.value
+        out = self.ctx.empty_ct(lv.value)
+        _check(self.lib.rbk_mlp_get_state(self.h, idx, _ptr(out), ctypes.byref(lv), ctypes.byref(sc)))
+        return out, lv.value, sc.value
+
+    def set_mask(self, level, pt):
+        _check(self.lib.rbk_mlp_set_mask(self.h, level, _ptr(pt)))
+
+    def train_step(self, x, y_exp, y_rep, level, scale, t, bootstrap=True, per_sample=False):
+        """x: [b][tiles][2][level+1][N], y_exp / y_rep: [b][2][level+1][N] device tensors."""
+        b = x.shape[0]
+        flags = (0 if bootstrap else MLP_NO_BOOTSTRAP) | (MLP_PER_SAMPLE if per_sample else 0)
+        _check(self.lib.rbk_mlp_train_step(self.h, _ptr(x), _ptr(y_exp), _ptr(y_rep), b, level, float(scale), t,
+                                           flags))
+
+    def scalars(self):
+        n = _check(self.lib.rbk_mlp_scalars(self.h, None, 0))
+        out = np.zeros(max(n, 1), dtype=np.int64)
+        _check(self.lib.rbk_mlp_scalars(self.h, out.ctypes.data_as(i64p), n))
+        return [int(v) for v in out[:n]]
