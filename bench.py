@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-boot", action="store_true", help="skip the bootstrap throughput part")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the MLP train_step part")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device to device before the timed region (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -169,6 +170,135 @@ def bench_bootstrap(args, torch):
         "output_level": lo,
         "max_slot_error_log2": float(np.log2(err)),
     }
+    ctx.close()
+    return res
+
+
+MLP_Q_BITS = [60] + [50] * 27
+MLP_P_BITS = [60] * 10
+MLP_ALPHA = 10
+
+
+def bench_train_step(args, torch):
+    """The packed MLP training step at N = 2^16: 64 samples x 784 features
+    uniform in [0, 1], one-hot labels over 10 classes; 784 -> 128 (RE block)
+    -> 128 (CE block), each with a 10-way local classifier; degree-3
+    activation z + z^2 + z^3/3; r = 256, c = 128, four input tiles; gamma =
+    eta = 0.001, mu = 0.9; every W and V bootstrapped each step (14
+    ciphertexts).  Batched (every operation on the 64 samples at once) vs
+    plain (one sample at a time)."""
+    import numpy as np
+
+    import synth_inputs as S
+    from paper_2506_19693_amd import Context, Mlp
+
+    k0, widths, o, r, c = 784, [128, 128], 10, 256, 128
+    act = (1.0, 1.0, 1.0 / 3.0)
+    b = 64
+    ctx = Context(LOG_N, MLP_Q_BITS, MLP_P_BITS, MLP_ALPHA)
+    ctx.boot_setup(K=23, degree=59, double_angle=2, cts_levels=3, stc_levels=3, log2_rho=2)
+    mlp = Mlp(ctx, k0, widths, o, r, c, act=act, gamma=0.001, eta=0.001, mu=0.9, log2_scale=50.0)
+    N = ctx.N
+    g = S.rng(4, 16)
+    ctx.set_secret(S.ternary_hw(g, N, 192))
+    ctx.keygen_public(S.uniform_residues(g, ctx.moduli[: ctx.nQ], N), S.gaussian(g, N))
+    ctx.keygen_relin(*S.key_randomness(g, ctx.beta, ctx.moduli, N))
+    gals = sorted({ctx.galois_elt(k) for k in mlp.rotations() + ctx.boot_rotations()} | {2 * N - 1})
+    for gal in gals:
+        ctx.keygen_galois(gal, *S.key_randomness(g, ctx.beta, ctx.moduli, N))
+    lo = ctx.boot_levels[3]
+    T = 2.0 ** 50
+    tiles = mlp.tiles
+
+    def enc(v):
+        return ctx.encrypt(ctx.encode(v, lo, T), lo, *S.encryption_randomness(g, N))
+
+    dims = [(k0, widths[0]), (widths[0], widths[1])]
+    Ws = S.mlp_weights(g, dims)
+    Wst = S.mlp_weights(g, [(k, o) for _, k in dims])
+    # the state in the order W tiles, W*, V tiles, V* per block (V set by step 1)
+    st = []
+    for h, (W, Wsh) in enumerate(zip(Ws, Wst), start=1):
+        M = np.zeros((r, c))
+        if h == 1:
+            for t in range(tiles):
+                M[:] = 0.0
+                blk = W[t * r: (t + 1) * r]
+                M[: blk.shape[0], : blk.shape[1]] = blk
+                st.append(M.ravel().copy())
+            M[:] = 0.0
+            M[:o, : Wsh.shape[0]] = Wsh.T
+            st.append(M.ravel().copy())
+            st += [None] * (tiles + 1)
+        else:
+            M[:] = 0.0
+            M[: W.shape[1], : W.shape[0]] = W.T
+            st.append(M.ravel().copy())
+            M[:] = 0.0
+            M[: Wsh.shape[0], : Wsh.shape[1]] = Wsh
+            st.append(M.ravel().copy())
+            st += [None, None]
+    assert len(st) == mlp.n_state
+    for i, v in enumerate(st):
+        if v is not None:
+            mlp.set_state(i, enc(v), lo, T)
+    X, Y = S.mlp_batch(g, b, k0, o)
+    x = ctx.empty(b, tiles, 2, lo + 1, N)
+    ye = ctx.empty(b, 2, lo + 1, N)
+    yr = ctx.empty(b, 2, lo + 1, N)
+    for i in range(b):
+        for t in range(tiles):
+            M = np.zeros((r, c))
+            seg = X[i, t * r: (t + 1) * r]
+            M[: len(seg), :] = seg[:, None]
+            x[i, t].copy_(enc(M.ravel()))
+        M = np.zeros((r, c))
+        M[:o, :] = Y[i][:, None]
+        ye[i].copy_(enc(M.ravel()))
+        M = np.zeros((r, c))
+        M[:, :o] = Y[i]
+        yr[i].copy_(enc(M.ravel()))
+    ctx.sync()
+    step = [1]
+
+    def run(**kw):
+        mlp.train_step(x, ye, yr, lo, T, step[0], **kw)
+        step[0] += 1
+
+    for _ in range(max(1, args.warmup)):
+        run()
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    ctx.sync()
+    t_b = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    run(per_sample=True)
+    ctx.sync()
+    t_p = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    run(bootstrap=False)                  # the same step without its bootstrap: the bootstrap's share
+    ctx.sync()
+    t_nb = time.perf_counter() - t0
+    lr, lc = int(np.log2(r)), int(np.log2(c))
+    rot_per_sample = (lr + 2 * lc + lr) + (2 * lc + lr + 2 * lc)
+    res = {
+        "workload": "packed MLP train_step: 64 samples x 784 features, 784->128 (RE)->128 (CE), 10-way local "
+                    "classifiers, degree-3 activation, r=256 c=128 (4 input tiles), N=2^16, 28 primes (60 + 27x50), "
+                    "10 special primes, HW-192 secret, bootstrap of all 14 W/V ciphertexts per step",
+        "train_steps_per_s_batched": 1.0 / t_b,
+        "train_steps_per_s_plain": 1.0 / t_p,
+        "batched_vs_plain": t_p / t_b,
+        "ms_per_step_batched": t_b * 1e3,
+        "ms_per_step_plain": t_p * 1e3,
+        "bootstrap_share_of_step": max(0.0, 1.0 - t_nb / t_b),
+        "rotations_per_step": b * rot_per_sample,
+        "bootstraps_per_step": mlp.n_state,
+        "weight_level": lo,
+        "depth": mlp.depth,
+    }
+    mlp.close()
     ctx.close()
     return res
 
@@ -333,6 +463,15 @@ def main():
             boot["bootstraps_per_s_batched"], boot["bootstraps_per_s_plain"], boot["plain_latency_ms_p99"],
             boot["max_slot_error_log2"]))
 
+    mlp = None
+    if not args.no_mlp:
+        torch.cuda.empty_cache()
+        log("train_step: 784-128-128, 64 samples, N=2^16 ...")
+        mlp = bench_train_step(args, torch)
+        log("train_step: %.3f steps/s batched (%.0f ms), %.3f plain, bootstrap share %.2f" % (
+            mlp["train_steps_per_s_batched"], mlp["ms_per_step_batched"], mlp["train_steps_per_s_plain"],
+            mlp["bootstrap_share_of_step"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample) ...")
@@ -363,6 +502,7 @@ def main():
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
         "bootstrap": boot,
+        "train_step": mlp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
