@@ -346,6 +346,80 @@ int rbk_mlp_train_step(rbk_mlp *mlp, const uint64_t *d_x, const uint64_t *d_y_ex
  * the updates).  Writes at most max, returns the count. */
 int rbk_mlp_scalars(const rbk_mlp *mlp, int64_t *out, int max);
 
+/* ---- serving loop ---------------------------------------------------------- */
+
+/* Encrypted-training jobs of several tenants on one GPU.  A tenant is a
+ * context with its keys (and bootstrap plan) set up; from rbk_server_add_tenant
+ * until rbk_server_destroy the server owns it: it gets a stream of its own and
+ * a worker thread of its own, and the caller must not call into it (the
+ * device memory a job names stays the caller's).  Work of different tenants
+ * overlaps on the device.
+ *
+ * Admission: an HBM ledger starts with every tenant's resident bytes (its
+ * evaluation keys and bootstrap diagonals); a job is admitted, in arrival
+ * order, once its footprint fits the budget next to the ledger (later jobs
+ * may pass a job that does not fit, at most 8 times in a row).  Footprints
+ * are working-set estimates: mult count x 6.5 ciphertexts + key-switch
+ * workspace; bootstrap count x 32 top-level ciphertexts; training step
+ * b x 24 ciphertexts + workspace.
+ *
+ * Batching: whenever a tenant's stream is free, its oldest admitted job runs
+ * together with every later admitted job of the same kind and level, up to
+ * max_batch ciphertexts (training steps run alone).  Results do not depend
+ * on the batching: the batched operations are the per-ciphertext ones. */
+#define RBK_JOB_MULT_RESCALE 1  /* out = Rescale(mult_relin(a_i, b_i)), i < count */
+#define RBK_JOB_BOOTSTRAP 2     /* out_i = Bootstrap(a_i) (level-0 part of a_i) */
+#define RBK_JOB_TRAIN_STEP 3    /* `count` steps t0, t0+1, ... of an MLP */
+
+typedef struct rbk_server rbk_server;
+
+typedef struct {
+    int kind;
+    int tenant;
+    int count;            /* ciphertexts (mult, bootstrap) or steps (train) */
+    int level;            /* mult: operation level l >= 1; train: level of x and y */
+    int in_level;         /* layout level of d_a / d_b: [count][2][in_level+1][N], in_level >= level */
+    const uint64_t *d_a;  /* mult, bootstrap inputs (NTT domain) */
+    const uint64_t *d_b;  /* mult second inputs */
+    uint64_t *d_out;      /* mult: [count][2][l][N]; bootstrap: [count][2][out+1][N] */
+    const double *scales_in;  /* bootstrap: host [count], copied at submission */
+    double *scales_out;       /* bootstrap: host [count], written before the job completes (may be NULL) */
+    rbk_mlp *mlp;             /* train: an MLP of this tenant's context */
+    const uint64_t *d_x, *d_y_exp, *d_y_rep;  /* train: as rbk_mlp_train_step */
+    int b;
+    double scale;
+    int t0;
+} rbk_job;
+
+typedef struct {
+    int status;         /* 0 or the job's RBK_E* code */
+    double latency_ms;  /* submission to completion */
+    double queue_ms;    /* submission to start on the device */
+    double run_ms;      /* start to completion of its batch */
+    int batch_cts;      /* ciphertexts (or 1 step) in the batch it ran in */
+} rbk_job_result;
+
+/* budget: HBM bytes the ledger may hold; max_batch: ciphertexts per merged launch */
+int rbk_server_create(uint64_t hbm_budget, int max_batch, rbk_server **out);
+/* RBK_ENOMEM if the tenant's resident bytes do not fit; before rbk_server_start */
+int rbk_server_add_tenant(rbk_server *srv, rbk_ctx *ctx, int *tenant);
+int rbk_server_start(rbk_server *srv);
+/* Thread-safe; returns at once with the job's id.  RBK_ENOMEM if the job can
+ * never fit the budget.  Inputs must be ready on the device (the caller's
+ * stream synchronised) and stay valid until the job completes. */
+int rbk_server_submit(rbk_server *srv, const rbk_job *job, uint64_t *id);
+/* Block until job id completes, fill *res and forget the job.  Returns the
+ * job's status (its message through rbk_last_error). */
+int rbk_server_wait(rbk_server *srv, uint64_t id, rbk_job_result *res);
+/* Block until every submitted job has completed. */
+int rbk_server_drain(rbk_server *srv);
+/* stats[6] = {jobs completed, batches run, jobs that ran merged with others,
+ * peak ledger bytes, ledger bytes now, budget} */
+int rbk_server_stats(rbk_server *srv, uint64_t *stats);
+/* Run what was submitted, stop the workers, give the contexts their streams
+ * back, free the server. */
+int rbk_server_destroy(rbk_server *srv);
+
 /* ---- per-kernel timers -------------------------------------------------- */
 /* With timers on, every kernel launch on the context stream is bracketed by
  * HIP events.  Class `cls` = 0, 1, ... names one kernel (rbk_timer_name);

@@ -918,3 +918,13 @@ extern "C" int rbk_bootstrap(rbk_ctx *c, const uint64_t *d_in, double scale_in, 
 
 int rbk_set_error(int code, const char *msg);
 static int boot_fail(int code, const char *msg) { return rbk_set_error(code, msg); }
+
+// bytes of the plan's encoded diagonals (resident while the plan exists)
+size_t boot_resident_bytes(const rbk_ctx_impl *ci)
+{
+    const BootPlan *P = ci->boot;
+    if (!P) return 0;
+    size_t w = 0;
+    for (int lv : P->plain_level) w += (size_t)(lv + 1) * ci->N;
+    return w * sizeof(u64);
+}

@@ -158,6 +158,7 @@ void mac_plain_launch(const rbk_ctx_impl *c, u64 *acc, const u64 *ct, long ct_st
 void add_scalar_batch_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int level, int count, const ScalArg &s,
                              hipStream_t st);
 void boot_free(rbk_ctx_impl *c);
+size_t boot_resident_bytes(const rbk_ctx_impl *c);
 
 // ---- pieces of api.hip shared with the bootstrap and MLP runners ----
 // workspace words of the key-switching pipeline for `count` ciphertexts at level l

@@ -1,0 +1,417 @@
+// Serving loop: encrypted-training jobs of several tenants on one GPU.
+//
+// Each tenant is a context (its parameters and evaluation keys, resident in
+// HBM) that the server drives from a worker thread of its own, on a HIP
+// stream of its own, so the work of different tenants overlaps on the
+// device.  Jobs are admitted by memory footprint against an HBM ledger that
+// starts with every tenant's resident bytes (serve_sched.hpp).  Each time a
+// tenant's stream is free, its worker takes the oldest admitted job plus every
+// queued job it can merge with (same kind and level, up to max_batch
+// ciphertexts) and runs them as one batched launch set: inputs are gathered
+// into a staging batch, the batched entry point runs once, results are
+// scattered back.  The batched entry points compute exactly what the
+// per-ciphertext ones do, so a job's result does not depend on what it was
+// batched with.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/rbk.h"
+#include "rbk_ctx.hpp"
+#include "serve_sched.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct SJob {
+    rbk_job j{};
+    std::vector<double> scales_in;
+    Clock::time_point t_submit, t_admit, t_start, t_end;
+    int status = 0;
+    std::string msg;
+    int batch_cts = 0;
+    bool admitted = false, done = false;
+};
+
+struct Tenant {
+    int id = 0;
+    rbk_ctx *c = nullptr;
+    hipStream_t st = nullptr;
+    hipStream_t old_stream = nullptr;
+    uint64_t resident = 0;
+    std::thread th;
+    u64 *stage = nullptr;
+    size_t stage_words = 0;
+};
+
+size_t ct_words(const rbk_ctx *c, int level) { return (size_t)2 * (level + 1) * c->N; }
+
+uint64_t key_bytes(const rbk_ctx *c)
+{
+    const uint64_t one = (uint64_t)c->beta * 2 * c->nT * c->N * sizeof(u64);
+    uint64_t n = c->relin.data ? 1 : 0;
+    for (auto &kv : c->gal)
+        if (kv.second.data) n++;
+    return n * one;
+}
+
+}  // namespace
+
+struct rbk_server {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    rbk_sched::Scheduler sched;
+    std::map<uint64_t, SJob> jobs;
+    std::vector<Tenant *> tenants;
+    uint64_t next_id = 1;
+    bool running = false, stopping = false;
+    uint64_t n_batches = 0, n_jobs_done = 0, n_merged = 0, n_outstanding = 0;
+    int max_batch;
+
+    rbk_server(uint64_t budget, int mb) : sched(budget, mb), max_batch(mb) {}
+};
+
+namespace {
+
+// working-set estimate of a job, bytes (admission only; see rbk.h)
+uint64_t footprint(const rbk_ctx *c, const rbk_job &j)
+{
+    const uint64_t w8 = sizeof(u64);
+    switch (j.kind) {
+    case RBK_JOB_MULT_RESCALE: {
+        const uint64_t ct = ct_words(c, j.level);
+        return w8 * ((uint64_t)j.count * (2 * ct + 3 * ct / 2 + ct + ct) + ks_words(c, j.level, j.count));
+    }
+    case RBK_JOB_BOOTSTRAP:
+        return w8 * (uint64_t)j.count * 32 * ct_words(c, c->nQ - 1);
+    case RBK_JOB_TRAIN_STEP:
+        return w8 * (uint64_t)j.b * 24 * ct_words(c, j.level) + w8 * ks_words(c, j.level, j.b);
+    default:
+        return 0;
+    }
+}
+
+u64 *stage_reserve(Tenant *t, size_t words)
+{
+    if (words <= t->stage_words) return t->stage;
+    if (t->stage) {
+        (void)hipStreamSynchronize(t->st);
+        (void)hipFree(t->stage);
+        t->stage = nullptr;
+        t->stage_words = 0;
+    }
+    if (hipMalloc((void **)&t->stage, words * sizeof(u64)) != hipSuccess) return nullptr;
+    t->stage_words = words;
+    return t->stage;
+}
+
+// copy limbs 0..level of every polynomial of count ciphertexts laid out at
+// in_level into a contiguous batch at level
+int gather(Tenant *t, const uint64_t *src, int in_level, int level, int count, u64 *dst)
+{
+    const rbk_ctx *c = t->c;
+    const size_t N = c->N, w = (size_t)(level + 1) * N, sp = (size_t)(in_level + 1) * N;
+    if (hipMemcpy2DAsync(dst, w * sizeof(u64), src, sp * sizeof(u64), w * sizeof(u64), (size_t)2 * count,
+                         hipMemcpyDeviceToDevice, t->st) != hipSuccess)
+        return rbk_set_error(RBK_EDEVICE, "gather copy failed");
+    return RBK_OK;
+}
+
+int run_mult(Tenant *t, std::vector<SJob *> &b)
+{
+    rbk_ctx *c = t->c;
+    const int lv = b[0]->j.level;
+    int total = 0;
+    for (SJob *s : b) total += s->j.count;
+    const size_t ct = ct_words(c, lv), ct_out = ct_words(c, lv - 1);
+    u64 *A = stage_reserve(t, (size_t)total * (3 * ct) + (size_t)total * ct_out);
+    if (!A) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
+    u64 *B = A + (size_t)total * ct, *M = B + (size_t)total * ct, *R = M + (size_t)total * ct;
+    int off = 0, rc;
+    for (SJob *s : b) {
+        if ((rc = gather(t, s->j.d_a, s->j.in_level, lv, s->j.count, A + (size_t)off * ct))) return rc;
+        if ((rc = gather(t, s->j.d_b, s->j.in_level, lv, s->j.count, B + (size_t)off * ct))) return rc;
+        off += s->j.count;
+    }
+    if ((rc = rbk_mult_relin_batch(c, A, B, M, lv, total))) return rc;
+    if ((rc = rbk_rescale_batch(c, M, R, lv, total))) return rc;
+    off = 0;
+    for (SJob *s : b) {
+        if (hipMemcpyAsync(s->j.d_out, R + (size_t)off * ct_out, (size_t)s->j.count * ct_out * sizeof(u64),
+                           hipMemcpyDeviceToDevice, t->st) != hipSuccess)
+            return rbk_set_error(RBK_EDEVICE, "scatter copy failed");
+        off += s->j.count;
+    }
+    return RBK_OK;
+}
+
+int run_boot(Tenant *t, std::vector<SJob *> &b)
+{
+    rbk_ctx *c = t->c;
+    int levels[4], np = 0, ns = 0, rc;
+    if ((rc = rbk_boot_info(c, levels, &np, &ns))) return rc;
+    const int lo = levels[3];
+    int total = 0;
+    for (SJob *s : b) total += s->j.count;
+    const size_t ci = ct_words(c, 0), co = ct_words(c, lo);
+    u64 *I = stage_reserve(t, (size_t)total * (ci + co));
+    if (!I) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
+    u64 *O = I + (size_t)total * ci;
+    std::vector<double> sin, sout(total);
+    int off = 0;
+    for (SJob *s : b) {
+        if ((rc = gather(t, s->j.d_a, s->j.in_level, 0, s->j.count, I + (size_t)off * ci))) return rc;
+        sin.insert(sin.end(), s->scales_in.begin(), s->scales_in.end());
+        off += s->j.count;
+    }
+    if ((rc = rbk_bootstrap_batch(c, I, sin.data(), O, sout.data(), total))) return rc;
+    off = 0;
+    for (SJob *s : b) {
+        if (hipMemcpyAsync(s->j.d_out, O + (size_t)off * co, (size_t)s->j.count * co * sizeof(u64),
+                           hipMemcpyDeviceToDevice, t->st) != hipSuccess)
+            return rbk_set_error(RBK_EDEVICE, "scatter copy failed");
+        if (s->j.scales_out)
+            for (int i = 0; i < s->j.count; i++) s->j.scales_out[i] = sout[off + i];
+        off += s->j.count;
+    }
+    return RBK_OK;
+}
+
+int run_train(Tenant *, std::vector<SJob *> &b)
+{
+    const rbk_job &j = b[0]->j;
+    for (int s = 0; s < j.count; s++) {
+        int rc = rbk_mlp_train_step(j.mlp, j.d_x, j.d_y_exp, j.d_y_rep, j.b, j.level, j.scale, j.t0 + s, 0);
+        if (rc) return rc;
+    }
+    return RBK_OK;
+}
+
+void worker(rbk_server *S, Tenant *t)
+{
+    hipSetDevice(t->c->device);
+    for (;;) {
+        std::vector<rbk_sched::Job> batch;
+        std::vector<SJob *> sj;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            // a stopping server still runs every job already submitted
+            S->cv_work.wait(lk, [&] {
+                return S->sched.ready(t->id) > 0 || (S->stopping && S->sched.pending() == 0);
+            });
+            if (S->sched.ready(t->id) == 0) return;
+            batch = S->sched.next_batch(t->id);
+            const auto now = Clock::now();
+            int cts = 0;
+            for (auto &x : batch) cts += x.count;
+            for (auto &x : batch) {
+                SJob &s = S->jobs[x.id];
+                s.t_start = now;
+                s.batch_cts = cts;
+                sj.push_back(&s);
+            }
+        }
+        int rc;
+        switch (sj[0]->j.kind) {
+        case RBK_JOB_MULT_RESCALE: rc = run_mult(t, sj); break;
+        case RBK_JOB_BOOTSTRAP: rc = run_boot(t, sj); break;
+        default: rc = run_train(t, sj); break;
+        }
+        if (hipStreamSynchronize(t->st) != hipSuccess && !rc) rc = rbk_set_error(RBK_EDEVICE, "stream failed");
+        const std::string msg = rc ? rbk_last_error() : "";
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            const auto now = Clock::now();
+            for (SJob *s : sj) {
+                s->status = rc;
+                s->msg = msg;
+                s->t_end = now;
+                s->done = true;
+            }
+            S->n_outstanding -= sj.size();
+            S->sched.complete(batch);
+            S->n_batches++;
+            S->n_jobs_done += batch.size();
+            if (batch.size() > 1) S->n_merged += batch.size();
+            for (auto &x : S->sched.admit()) {
+                S->jobs[x.id].admitted = true;
+                S->jobs[x.id].t_admit = now;
+            }
+        }
+        S->cv_work.notify_all();
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" int rbk_server_create(uint64_t hbm_budget, int max_batch, rbk_server **out)
+{
+    if (!out || hbm_budget == 0 || max_batch < 1) return rbk_set_error(RBK_EINVAL, "bad argument");
+    *out = new (std::nothrow) rbk_server(hbm_budget, max_batch);
+    return *out ? RBK_OK : rbk_set_error(RBK_ENOMEM, "host allocation failed");
+}
+
+extern "C" int rbk_server_add_tenant(rbk_server *S, rbk_ctx *c, int *tenant)
+{
+    if (!S || !c || !tenant) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->running) return rbk_set_error(RBK_ESTATE, "tenants are added before rbk_server_start");
+    for (Tenant *t : S->tenants)
+        if (t->c == c) return rbk_set_error(RBK_EINVAL, "context already registered");
+    Tenant *t = new Tenant;
+    t->id = (int)S->tenants.size();
+    t->c = c;
+    t->resident = key_bytes(c) + boot_resident_bytes(c);
+    if (!S->sched.add_tenant(t->id, t->resident)) {
+        delete t;
+        return rbk_set_error(RBK_ENOMEM, "the tenant's resident keys do not fit the HBM budget");
+    }
+    if (hipSetDevice(c->device) != hipSuccess || hipStreamCreateWithFlags(&t->st, hipStreamNonBlocking) != hipSuccess) {
+        delete t;
+        return rbk_set_error(RBK_EDEVICE, "stream creation failed");
+    }
+    t->old_stream = c->stream;
+    c->stream = t->st;
+    S->tenants.push_back(t);
+    *tenant = t->id;
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_start(rbk_server *S)
+{
+    if (!S) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->running) return RBK_OK;
+    S->running = true;
+    for (Tenant *t : S->tenants) t->th = std::thread(worker, S, t);
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_submit(rbk_server *S, const rbk_job *j, uint64_t *id)
+{
+    if (!S || !j || !id) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (!S->running || S->stopping) return rbk_set_error(RBK_ESTATE, "server not running");
+    if (j->tenant < 0 || j->tenant >= (int)S->tenants.size()) return rbk_set_error(RBK_EINVAL, "unknown tenant");
+    const rbk_ctx *c = S->tenants[j->tenant]->c;
+    int kind;
+    switch (j->kind) {
+    case RBK_JOB_MULT_RESCALE:
+        if (j->count < 1 || !j->d_a || !j->d_b || !j->d_out) return rbk_set_error(RBK_EINVAL, "bad mult job");
+        if (j->level < 1 || j->in_level < j->level || j->in_level >= c->nQ)
+            return rbk_set_error(RBK_ELEVEL, "bad mult job levels");
+        kind = rbk_sched::KIND_MULT;
+        break;
+    case RBK_JOB_BOOTSTRAP:
+        if (j->count < 1 || !j->d_a || !j->d_out || !j->scales_in) return rbk_set_error(RBK_EINVAL, "bad bootstrap job");
+        if (!c->boot) return rbk_set_error(RBK_ESTATE, "tenant has no bootstrap plan");
+        if (j->in_level < 0 || j->in_level >= c->nQ) return rbk_set_error(RBK_ELEVEL, "bad bootstrap input level");
+        kind = rbk_sched::KIND_BOOT;
+        break;
+    case RBK_JOB_TRAIN_STEP:
+        if (j->count < 1 || !j->mlp || !j->d_x || !j->d_y_exp || !j->d_y_rep || j->b < 1 || j->t0 < 1)
+            return rbk_set_error(RBK_EINVAL, "bad train job");
+        if (j->level < 0 || j->level >= c->nQ) return rbk_set_error(RBK_ELEVEL, "bad train job level");
+        kind = rbk_sched::KIND_SOLO;
+        break;
+    default:
+        return rbk_set_error(RBK_EINVAL, "unknown job kind");
+    }
+    rbk_sched::Job sj;
+    sj.id = S->next_id++;
+    sj.tenant = j->tenant;
+    sj.kind = kind;
+    sj.level = j->kind == RBK_JOB_BOOTSTRAP ? 0 : j->level;
+    sj.count = j->kind == RBK_JOB_TRAIN_STEP ? 1 : j->count;
+    sj.footprint = footprint(c, *j);
+    if (!S->sched.submit(sj)) return rbk_set_error(RBK_ENOMEM, "job footprint exceeds the HBM budget");
+    SJob &s = S->jobs[sj.id];
+    s.j = *j;
+    if (j->kind == RBK_JOB_BOOTSTRAP) s.scales_in.assign(j->scales_in, j->scales_in + j->count);
+    s.t_submit = Clock::now();
+    S->n_outstanding++;
+    for (auto &x : S->sched.admit()) {
+        S->jobs[x.id].admitted = true;
+        S->jobs[x.id].t_admit = s.t_submit;
+    }
+    *id = sj.id;
+    lk.unlock();
+    S->cv_work.notify_all();
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_wait(rbk_server *S, uint64_t id, rbk_job_result *res)
+{
+    if (!S || !res) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(id);
+    if (it == S->jobs.end()) return rbk_set_error(RBK_EINVAL, "unknown job id");
+    S->cv_done.wait(lk, [&] { return it->second.done; });
+    const SJob &s = it->second;
+    res->status = s.status;
+    res->latency_ms = ms_between(s.t_submit, s.t_end);
+    res->queue_ms = ms_between(s.t_submit, s.t_start);
+    res->run_ms = ms_between(s.t_start, s.t_end);
+    res->batch_cts = s.batch_cts;
+    const int st = s.status;
+    const std::string msg = s.msg;
+    S->jobs.erase(it);
+    if (st) return rbk_set_error(st, msg.c_str());
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_drain(rbk_server *S)
+{
+    if (!S) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->n_outstanding == 0; });
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_stats(rbk_server *S, uint64_t *stats)
+{
+    if (!S || !stats) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    stats[0] = S->n_jobs_done;
+    stats[1] = S->n_batches;
+    stats[2] = S->n_merged;
+    stats[3] = S->sched.peak();
+    stats[4] = S->sched.ledger();
+    stats[5] = S->sched.budget();
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_destroy(rbk_server *S)
+{
+    if (!S) return RBK_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stopping = true;
+    }
+    S->cv_work.notify_all();
+    for (Tenant *t : S->tenants) {
+        if (t->th.joinable()) t->th.join();
+        (void)hipStreamSynchronize(t->st);
+        if (t->stage) (void)hipFree(t->stage);
+        t->c->stream = t->old_stream;
+        (void)hipStreamDestroy(t->st);
+        delete t;
+    }
+    delete S;
+    return RBK_OK;
+}

@@ -57,6 +57,43 @@ MLP_NO_BOOTSTRAP = 1
 MLP_PER_SAMPLE = 2
 
 
+class RbkJob(ctypes.Structure):
+    _fields_ = [
+        ("kind", ci),
+        ("tenant", ci),
+        ("count", ci),
+        ("level", ci),
+        ("in_level", ci),
+        ("d_a", vp),
+        ("d_b", vp),
+        ("d_out", vp),
+        ("scales_in", dblp),
+        ("scales_out", dblp),
+        ("mlp", vp),
+        ("d_x", vp),
+        ("d_y_exp", vp),
+        ("d_y_rep", vp),
+        ("b", ci),
+        ("scale", ctypes.c_double),
+        ("t0", ci),
+    ]
+
+
+class RbkJobResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ci),
+        ("latency_ms", ctypes.c_double),
+        ("queue_ms", ctypes.c_double),
+        ("run_ms", ctypes.c_double),
+        ("batch_cts", ci),
+    ]
+
+
+JOB_MULT_RESCALE = 1
+JOB_BOOTSTRAP = 2
+JOB_TRAIN_STEP = 3
+
+
 class RbkBootParams(ctypes.Structure):
     _fields_ = [
         ("K", ctypes.c_uint32),
@@ -129,6 +166,14 @@ SIGNATURES = {
     "rbk_mlp_set_mask": (ci, [vp, ci, vp]),
     "rbk_mlp_train_step": (ci, [vp, vp, vp, vp, ci, ci, ctypes.c_double, ci, ctypes.c_uint32]),
     "rbk_mlp_scalars": (ci, [vp, i64p, ci]),
+    "rbk_server_create": (ci, [ctypes.c_uint64, ci, ctypes.POINTER(vp)]),
+    "rbk_server_add_tenant": (ci, [vp, vp, ctypes.POINTER(ci)]),
+    "rbk_server_start": (ci, [vp]),
+    "rbk_server_submit": (ci, [vp, ctypes.POINTER(RbkJob), u64p]),
+    "rbk_server_wait": (ci, [vp, ctypes.c_uint64, ctypes.POINTER(RbkJobResult)]),
+    "rbk_server_drain": (ci, [vp]),
+    "rbk_server_stats": (ci, [vp, u64p]),
+    "rbk_server_destroy": (ci, [vp]),
     "rbk_timer_enable": (ci, [vp, ci]),
     "rbk_timer_read": (ci, [vp, ci, dblp, u64p, dblp]),
     "rbk_timer_name": (ctypes.c_char_p, [ci]),
@@ -196,6 +241,7 @@ def to_host(t):
     return t.detach().cpu().numpy().view(np.uint64)
 
 
+_LIVE_SERVERS = weakref.WeakSet()
 _LIVE_MLPS = weakref.WeakSet()
 _LIVE_CONTEXTS = weakref.WeakSet()
 
@@ -204,6 +250,8 @@ _LIVE_CONTEXTS = weakref.WeakSet()
 def _close_all():
     """Release library objects while the HIP runtime is still up (objects that
     survive until interpreter teardown would otherwise be freed after it)."""
+    for v in list(_LIVE_SERVERS):
+        v.close()
     for m in list(_LIVE_MLPS):
         m.close()
     for c in list(_LIVE_CONTEXTS):
@@ -632,3 +680,82 @@ class Mlp:
         out = np.zeros(max(n, 1), dtype=np.int64)
         _check(self.lib.rbk_mlp_scalars(self.h, out.ctypes.data_as(i64p), n))
         return [int(v) for v in out[:n]]
+
+
+class Server:
+    """The serving loop of rbk.h (rbk_server_*).  Tensors named by a job are
+    kept referenced here until the job is waited for."""
+
+    def __init__(self, hbm_budget, max_batch=64):
+        self.lib = load()
+        h = vp()
+        _check(self.lib.rbk_server_create(int(hbm_budget), int(max_batch), ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+        self.tenants = []
+        _LIVE_SERVERS.add(self)
+
+    def add_tenant(self, ctx):
+        t = ci()
+        _check(self.lib.rbk_server_add_tenant(self.h, ctx.h, ctypes.byref(t)))
+        self.tenants.append(ctx)
+        return t.value
+
+    def start(self):
+        _check(self.lib.rbk_server_start(self.h))
+
+    def _submit(self, job, keep):
+        jid = ctypes.c_uint64()
+        _check(self.lib.rbk_server_submit(self.h, ctypes.byref(job), ctypes.byref(jid)))
+        self._keep[jid.value] = keep
+        return jid.value
+
+    def submit_mult(self, tenant, a, b, level, out, in_level=None):
+        """out[i] = Rescale(mult_relin(a[i], b[i])) at `level`; a, b: [count][2][in_level+1][N]."""
+        in_level = level if in_level is None else in_level
+        j = RbkJob(kind=JOB_MULT_RESCALE, tenant=tenant, count=a.shape[0], level=level, in_level=in_level,
+                   d_a=a.data_ptr(), d_b=b.data_ptr(), d_out=out.data_ptr())
+        return self._submit(j, (a, b, out))
+
+    def submit_bootstrap(self, tenant, cts, scales, out, in_level=0):
+        """out[i] = Bootstrap(cts[i]); returns (id, host array the output scales are written to)."""
+        sc = np.ascontiguousarray(scales, dtype=np.float64)
+        so = np.zeros(len(sc))
+        j = RbkJob(kind=JOB_BOOTSTRAP, tenant=tenant, count=len(sc), level=0, in_level=in_level,
+                   d_a=cts.data_ptr(), d_out=out.data_ptr(), scales_in=sc.ctypes.data_as(dblp),
+                   scales_out=so.ctypes.data_as(dblp))
+        return self._submit(j, (cts, out, sc, so)), so
+
+    def submit_train(self, tenant, mlp, x, y_exp, y_rep, level, scale, t0, steps=1):
+        j = RbkJob(kind=JOB_TRAIN_STEP, tenant=tenant, count=steps, level=level, in_level=level, mlp=mlp.h,
+                   d_x=x.data_ptr(), d_y_exp=y_exp.data_ptr(), d_y_rep=y_rep.data_ptr(), b=x.shape[0],
+                   scale=float(scale), t0=t0)
+        return self._submit(j, (mlp, x, y_exp, y_rep))
+
+    def wait(self, jid):
+        r = RbkJobResult()
+        rc = self.lib.rbk_server_wait(self.h, jid, ctypes.byref(r))
+        self._keep.pop(jid, None)
+        _check(rc)
+        return {"latency_ms": r.latency_ms, "queue_ms": r.queue_ms, "run_ms": r.run_ms, "batch_cts": r.batch_cts}
+
+    def drain(self):
+        _check(self.lib.rbk_server_drain(self.h))
+
+    def stats(self):
+        st = np.zeros(6, dtype=np.uint64)
+        _check(self.lib.rbk_server_stats(self.h, st.ctypes.data_as(u64p)))
+        keys = ["jobs_done", "batches", "jobs_merged", "ledger_peak", "ledger_now", "budget"]
+        return {k: int(v) for k, v in zip(keys, st)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbk_server_destroy(self.h)
+            self.h = None
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
