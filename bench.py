@@ -51,6 +51,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-boot", action="store_true", help="skip the bootstrap throughput part")
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP train_step part")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving part")
+    ap.add_argument("--serve-jobs", type=int, default=200)
+    ap.add_argument("--serve-lambda", type=float, default=SERVE_LAMBDA, help="Poisson arrival rate, jobs/s")
+    ap.add_argument("--serve-calibrate", action="store_true",
+                    help="submit every job at once and report the capacity (0.8 x it is the frozen arrival rate)")
+    ap.add_argument("--serve-budget-gib", type=float, default=160.0)
+    ap.add_argument("--serve-max-batch", type=int, default=32)
+    ap.add_argument("--serve-max-boot", type=int, default=8)
+    ap.add_argument("--serve-mlp-b", type=int, default=16, help="samples per training step of serving jobs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device to device before the timed region (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -303,6 +312,258 @@ def bench_train_step(args, torch):
     return res
 
 
+SERVE_Q_BITS = [60] + [50] * 30
+SERVE_P_BITS = [60] * 11
+SERVE_ALPHA = 11
+SERVE_LOG_NS = [14, 14, 14, 15, 15, 15, 16, 16]
+# Poisson arrival rate of the serving workload, jobs/s: 0.8 x the batched
+# capacity measured by `--serve-calibrate` (all 200 jobs submitted at once),
+# then frozen here.
+SERVE_LAMBDA = 3.0
+
+
+def _dev_residues(ctx, gen, lead, level):
+    """uniform residues [*lead][level+1][N] drawn on the device (inputs whose
+    values do not matter to the cost of the operations)"""
+    import torch
+
+    t = torch.empty(*lead, level + 1, ctx.N, dtype=torch.int64, device="cuda")
+    for i in range(level + 1):
+        t[..., i, :] = torch.randint(0, ctx.moduli[i], (*lead, ctx.N), generator=gen, device="cuda",
+                                     dtype=torch.int64)
+    return t
+
+
+class _Tenant:
+    """A serving tenant: context with resident keys (relinearisation,
+    bootstrap, MLP rotations at N = 2^16), input pools, MLPs."""
+
+    def __init__(self, log_n, idx, rand_cache, mlp_b):
+        import numpy as np
+
+        import synth_inputs as S
+        from paper_2506_19693_amd import Context, Mlp
+
+        self.ctx = ctx = Context(log_n, SERVE_Q_BITS, SERVE_P_BITS, SERVE_ALPHA)
+        ctx.boot_setup(K=23, degree=59, double_angle=2, cts_levels=3, stc_levels=3, log2_rho=2)
+        N = ctx.N
+        self.log_n = log_n
+        g = S.rng(5, 100 + idx)
+        ctx.set_secret(S.ternary_hw(g, N, 192))
+        ctx.keygen_public(S.uniform_residues(g, ctx.moduli[: ctx.nQ], N), S.gaussian(g, N))
+        self.mlps = {}
+        if log_n == 16:
+            for w in (64, 128, 256):
+                widths = [w, w] if w <= 128 else [w]
+                r, c = (256, 128) if w <= 128 else (128, 256)
+                self.mlps[w] = Mlp(ctx, 784, widths, 10, r, c, act=(1.0, 1.0, 1.0 / 3.0), gamma=0.001, eta=0.001,
+                                   mu=0.9, log2_scale=50.0)
+        rots = set(ctx.boot_rotations())
+        for m in self.mlps.values():
+            rots |= set(m.rotations())
+        gals = [0] + sorted({ctx.galois_elt(k) for k in rots} | {2 * N - 1})
+        for i, gal in enumerate(gals):
+            # the uniform part of a key is shared by the tenants of one ring degree (their secrets differ)
+            key = (log_n, i)
+            if key not in rand_cache:
+                rand_cache[key] = S.key_randomness(S.rng(6, log_n, i), ctx.beta, ctx.moduli, N)
+            a, e = rand_cache[key]
+            if gal == 0:
+                ctx.keygen_relin(a, e)
+            else:
+                ctx.keygen_galois(gal, a, e)
+        L = ctx.L
+        self.lo = ctx.boot_levels[3]
+        T = 2.0 ** 50
+        self.T = T
+        # input pools: 64 ciphertext pairs at the top level (mult jobs read limbs 0..l),
+        # 16 level-0 ciphertexts (bootstrap jobs)
+        import torch
+
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1000 + idx)
+        self.A = _dev_residues(ctx, gen, (64, 2), L)
+        self.B = _dev_residues(ctx, gen, (64, 2), L)
+        self.C0 = _dev_residues(ctx, gen, (16, 2), 0)
+        self.mlp_in = {}
+        lo = self.lo
+        for w, m in self.mlps.items():
+            r, c = (256, 128) if w <= 128 else (128, 256)
+            X, Y = S.mlp_batch(g, mlp_b, 784, 10)
+            enc = lambda v: ctx.encrypt(ctx.encode(v, lo, T), lo, *S.encryption_randomness(g, N))
+            x = ctx.empty(mlp_b, m.tiles, 2, lo + 1, N)
+            ye = ctx.empty(mlp_b, 2, lo + 1, N)
+            yr = ctx.empty(mlp_b, 2, lo + 1, N)
+            for i in range(mlp_b):
+                for t in range(m.tiles):
+                    M = np.zeros((r, c))
+                    seg = X[i, t * r: (t + 1) * r]
+                    M[: len(seg), :] = seg[:, None]
+                    x[i, t].copy_(enc(M.ravel()))
+                M = np.zeros((r, c))
+                M[:10, :] = Y[i][:, None]
+                ye[i].copy_(enc(M.ravel()))
+                M = np.zeros((r, c))
+                M[:, :10] = Y[i]
+                yr[i].copy_(enc(M.ravel()))
+            self.mlp_in[w] = (x, ye, yr)
+            # random state at the weights' level and scale (the step's cost does not depend on the values)
+            for i in range(m.n_state):
+                m.set_state(i, _dev_residues(ctx, gen, (2,), lo), lo, T)
+        ctx.sync()
+
+
+def _serve_jobs(n_jobs, tenants, lam):
+    """The job list: (arrival s, tenant, kind, params).  Types: mult+rescale
+    batches (8..64 ciphertexts, levels 8..30), bootstraps (1..16), 1..3
+    training steps (N = 2^16 tenants, widths 64 / 128 / 256)."""
+    import numpy as np
+
+    import synth_inputs as S
+
+    g = S.rng(7, n_jobs)
+    t = 0.0
+    jobs = []
+    mlp_tenants = [i for i, tn in enumerate(tenants) if tn.mlps]
+    for _ in range(n_jobs):
+        t += float(g.exponential(1.0 / lam)) if lam > 0 else 0.0
+        u = g.uniform()
+        if u < 0.55:
+            ten = int(g.integers(0, len(tenants)))
+            jobs.append((t, ten, "mult", dict(count=int(g.integers(8, 65)), level=int(g.integers(8, 31)))))
+        elif u < 0.85:
+            ten = int(g.integers(0, len(tenants)))
+            n = int(g.integers(1, 17))
+            jobs.append((t, ten, "boot", dict(count=n, scales=[2.0 ** float(g.uniform(35, 45)) for _ in range(n)])))
+        else:
+            ten = mlp_tenants[int(g.integers(0, len(mlp_tenants)))]
+            jobs.append((t, ten, "train", dict(steps=int(g.integers(1, 4)), width=int((64, 128, 256)[g.integers(0, 3)]))))
+    return jobs
+
+
+def _serve_run(tenants, jobs, budget, max_batch, max_boot, torch):
+    """Submit at the arrival times; returns (makespan s, per-job latency ms, stats)."""
+    import threading
+
+    from paper_2506_19693_amd import Server
+
+    srv = Server(budget, max_batch, max_boot)
+    for tn in tenants:
+        srv.add_tenant(tn.ctx)
+    srv.start()
+    step = {id(tn): {w: 1 for w in tn.mlps} for tn in tenants}
+    ids = []
+    lock = threading.Lock()
+    t0 = time.perf_counter()
+    for (t_arr, ti, kind, p) in jobs:
+        now = time.perf_counter() - t0
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        tn = tenants[ti]
+        ctx = tn.ctx
+        if kind == "mult":
+            n, lv = p["count"], p["level"]
+            out = ctx.empty_ct(lv - 1, n)
+            ids.append(srv.submit_mult(ti, tn.A[:n], tn.B[:n], lv, out, in_level=ctx.L))
+        elif kind == "boot":
+            n = p["count"]
+            out = ctx.empty_ct(tn.lo, n)
+            ids.append(srv.submit_bootstrap(ti, tn.C0[:n], p["scales"], out)[0])
+        else:
+            w = p["width"]
+            x, ye, yr = tn.mlp_in[w]
+            with lock:
+                t_first = step[id(tn)][w]
+                step[id(tn)][w] += p["steps"]
+            ids.append(srv.submit_train(ti, tn.mlps[w], x, ye, yr, tn.lo, tn.T, t_first, steps=p["steps"]))
+    res = [srv.wait(j) for j in ids]
+    srv.drain()
+    makespan = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    return makespan, [r["latency_ms"] for r in res], stats
+
+
+def _serial_run(tenants, jobs, torch):
+    """Serial plain FIFO: one job at a time in arrival order, one ciphertext
+    (or one sample) per call."""
+    t0 = time.perf_counter()
+    lat = []
+    step = {id(tn): {w: 10 ** 6 for w in tn.mlps} for tn in tenants}
+    for (t_arr, ti, kind, p) in jobs:
+        now = time.perf_counter() - t0
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        tn = tenants[ti]
+        ctx = tn.ctx
+        if kind == "mult":
+            lv = p["level"]
+            for i in range(p["count"]):
+                a = tn.A[i][:, : lv + 1].contiguous()
+                b = tn.B[i][:, : lv + 1].contiguous()
+                ctx.rescale(ctx.mult_relin(a, b, lv), lv)
+        elif kind == "boot":
+            for i in range(p["count"]):
+                ctx.bootstrap(tn.C0[i], p["scales"][i])
+        else:
+            w = p["width"]
+            x, ye, yr = tn.mlp_in[w]
+            for _ in range(p["steps"]):
+                tn.mlps[w].train_step(x, ye, yr, tn.lo, tn.T, step[id(tn)][w], per_sample=True)
+                step[id(tn)][w] += 1
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0 - t_arr) * 1e3)
+    return time.perf_counter() - t0, lat
+
+
+def bench_serve(args, torch):
+    """Serving workload: 8 tenants (N = 2^14 x 3, 2^15 x 3, 2^16 x 2; 31
+    primes, 11 special; HW-192 secrets; resident relinearisation, bootstrap
+    and MLP keys), Poisson arrivals of mixed jobs, served (continuous batching,
+    HBM-ledger admission, per-tenant streams) vs serial plain FIFO."""
+    rand_cache = {}
+    tenants = [_Tenant(ln, i, rand_cache, args.serve_mlp_b) for i, ln in enumerate(SERVE_LOG_NS)]
+    rand_cache.clear()
+    budget = int(args.serve_budget_gib * (1 << 30))
+    lam = 0.0 if args.serve_calibrate else args.serve_lambda
+    jobs = _serve_jobs(args.serve_jobs, tenants, lam)
+    # warm every tenant's workspaces and pools with one of each job kind
+    _serve_run(tenants, [(0.0, i, "mult", dict(count=8, level=30)) for i in range(len(tenants))]
+               + [(0.0, i, "boot", dict(count=2, scales=[2.0 ** 40] * 2)) for i in range(len(tenants))],
+               budget, args.serve_max_batch, args.serve_max_boot, torch)
+    mk, lat, stats = _serve_run(tenants, jobs, budget, args.serve_max_batch, args.serve_max_boot, torch)
+    out = {
+        "workload": "serving: %d jobs, Poisson arrivals at %.2f jobs/s, 8 tenants (N=2^14 x3, 2^15 x3, 2^16 x2), "
+                    "31 primes (60 + 30x50) + 11 special, HW-192 secrets; jobs: 55%% mult+rescale batches (8-64 "
+                    "ciphertexts, levels 8-30), 30%% bootstraps (1-16), 15%% 1-3 train_steps (784-w-w-10, w in "
+                    "64/128; 784-256-10; %d samples) on the N=2^16 tenants" % (len(jobs), lam, args.serve_mlp_b),
+        "jobs_per_s": len(jobs) / mk,
+        "makespan_s": mk,
+        "latency_ms_p50": percentile(lat, 50),
+        "latency_ms_p99": percentile(lat, 99),
+        "batches": stats["batches"],
+        "jobs_merged": stats["jobs_merged"],
+        "ledger_peak_gib": stats["ledger_peak"] / 2.0 ** 30,
+        "budget_gib": stats["budget"] / 2.0 ** 30,
+    }
+    if args.serve_calibrate:
+        out["calibration_capacity_jobs_per_s"] = len(jobs) / mk
+        out["lambda_for_0.8"] = 0.8 * len(jobs) / mk
+    elif not args.no_plain:
+        mk_s, lat_s = _serial_run(tenants, jobs, torch)
+        out["serial_plain"] = {
+            "jobs_per_s": len(jobs) / mk_s,
+            "makespan_s": mk_s,
+            "latency_ms_p50": percentile(lat_s, 50),
+            "latency_ms_p99": percentile(lat_s, 99),
+        }
+    for tn in tenants:
+        for m in tn.mlps.values():
+            m.close()
+        tn.ctx.close()
+    return out
+
+
 def cpu_baseline():
     """The oracle, single-threaded, on one ciphertext of the same workload:
     mult_relin + rescale + one hoisted rotation (2 key switches)."""
@@ -452,11 +713,13 @@ def main():
         "share_of_step": round(ms / (t_batched * 1e3 * args.steps), 3),
     }
 
+    # release the key-switch workload before the next parts
+    del out_m, out_r, out_h, A, B
+    ctx.close()
+    torch.cuda.empty_cache()
+
     boot = None
     if not args.no_boot:
-        del out_m, out_r, out_h, A, B
-        ctx.close()
-        torch.cuda.empty_cache()
         log("bootstrap: 16 ciphertexts, N=2^16 ...")
         boot = bench_bootstrap(args, torch)
         log("bootstrap: %.2f/s batched, %.2f/s plain, p99 %.1f ms, max error 2^%.2f" % (
@@ -471,6 +734,17 @@ def main():
         log("train_step: %.3f steps/s batched (%.0f ms), %.3f plain, bootstrap share %.2f" % (
             mlp["train_steps_per_s_batched"], mlp["ms_per_step_batched"], mlp["train_steps_per_s_plain"],
             mlp["bootstrap_share_of_step"]))
+
+    serve = None
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        log("serving: %d jobs, 8 tenants ..." % args.serve_jobs)
+        serve = bench_serve(args, torch)
+        log("serving: %.2f jobs/s, p50 %.0f ms, p99 %.0f ms%s" % (
+            serve["jobs_per_s"], serve["latency_ms_p50"], serve["latency_ms_p99"],
+            "" if "serial_plain" not in serve else "; serial plain %.2f jobs/s, p50 %.0f ms, p99 %.0f ms" % (
+                serve["serial_plain"]["jobs_per_s"], serve["serial_plain"]["latency_ms_p50"],
+                serve["serial_plain"]["latency_ms_p99"])))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -503,6 +777,7 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
         "bootstrap": boot,
         "train_step": mlp,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -359,14 +359,16 @@ int rbk_mlp_scalars(const rbk_mlp *mlp, int64_t *out, int max);
  * evaluation keys and bootstrap diagonals); a job is admitted, in arrival
  * order, once its footprint fits the budget next to the ledger (later jobs
  * may pass a job that does not fit, at most 8 times in a row).  Footprints
- * are working-set estimates: mult count x 6.5 ciphertexts + key-switch
- * workspace; bootstrap count x 32 top-level ciphertexts; training step
- * b x 24 ciphertexts + workspace.
+ * are working-set estimates, with n = min(count, chunk cap): mult
+ * count + 5.5 n ciphertexts + key-switch workspace of n; bootstrap n x 48
+ * top-level ciphertexts; training step b x 24 ciphertexts + workspace.
  *
  * Batching: whenever a tenant's stream is free, its oldest admitted job runs
  * together with every later admitted job of the same kind and level, up to
- * max_batch ciphertexts (training steps run alone).  Results do not depend
- * on the batching: the batched operations are the per-ciphertext ones. */
+ * max_batch ciphertexts (max_boot_batch for bootstraps; training steps run
+ * alone).  A batch runs in chunks of at most that many ciphertexts, which
+ * bounds each tenant's workspace.  Results do not depend on the batching:
+ * the batched operations are the per-ciphertext ones. */
 #define RBK_JOB_MULT_RESCALE 1  /* out = Rescale(mult_relin(a_i, b_i)), i < count */
 #define RBK_JOB_BOOTSTRAP 2     /* out_i = Bootstrap(a_i) (level-0 part of a_i) */
 #define RBK_JOB_TRAIN_STEP 3    /* `count` steps t0, t0+1, ... of an MLP */
@@ -399,8 +401,9 @@ typedef struct {
     int batch_cts;      /* ciphertexts (or 1 step) in the batch it ran in */
 } rbk_job_result;
 
-/* budget: HBM bytes the ledger may hold; max_batch: ciphertexts per merged launch */
-int rbk_server_create(uint64_t hbm_budget, int max_batch, rbk_server **out);
+/* budget: HBM bytes the ledger may hold; max_batch / max_boot_batch:
+ * ciphertexts per launch of mult+rescale / bootstrap work */
+int rbk_server_create(uint64_t hbm_budget, int max_batch, int max_boot_batch, rbk_server **out);
 /* RBK_ENOMEM if the tenant's resident bytes do not fit; before rbk_server_start */
 int rbk_server_add_tenant(rbk_server *srv, rbk_ctx *ctx, int *tenant);
 int rbk_server_start(rbk_server *srv);

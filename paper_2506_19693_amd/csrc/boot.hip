@@ -528,7 +528,7 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
         rots = P.rot_area;
     }
     u64 *inner = take(), *irot = take(), *total = take();
-    if (!inner || !irot || !total) return RBK_ENOMEM;
+    if (!inner || !irot || !total) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
     bool have_total = false;
     std::vector<int> gs;
     for (auto &e : L.ents)
@@ -583,7 +583,7 @@ int Runner::evalmod(Reg &x, int n_ct)
     std::map<std::string, Reg> regs;
     int rc = RBK_OK;
     u64 *tmp = take(), *tmp2 = take();
-    if (!tmp || !tmp2) return RBK_ENOMEM;
+    if (!tmp || !tmp2) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
     // operand at level lv: the register itself, or a dropped copy in dst
     auto at = [&](const Reg &r, int lv, u64 *dst) -> const u64 * {
         if (r.level == lv) return r.d;
@@ -594,7 +594,7 @@ int Runner::evalmod(Reg &x, int n_ct)
         if (st.kind == ST_PROD) {
             const int lv = st.lv;
             u64 *A = take(), *B = take(), *X = take();
-            if (!A || !B || !X) return RBK_ENOMEM;
+            if (!A || !B || !X) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             const u64 *pa = at(T[st.a], lv, A), *pb = at(T[st.b], lv, B);
             rc = rbk_mult_relin_batch(c, pa, pb, X, lv, n_ct);
             if (rc) return rc;
@@ -607,6 +607,7 @@ int Runner::evalmod(Reg &x, int n_ct)
                 ew_launch(c, EW_SUB, X, B, X, 2 * n_ct, lv + 1, qm, c->stream);
             }
             u64 *out = take();
+            if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             rc = rbk_rescale_batch(c, X, out, lv, n_ct);
             if (rc) return rc;
             T[st.k] = Reg{out, lv - 1};
@@ -616,6 +617,7 @@ int Runner::evalmod(Reg &x, int n_ct)
         } else if (st.kind == ST_LEAF) {
             const int lv = st.lv;
             u64 *acc = take(), *D = take();
+            if (!acc || !D) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             bool first = true;
             for (auto &t : st.terms) {
                 const u64 *pk = at(T[t.first], lv, D);
@@ -629,6 +631,7 @@ int Runner::evalmod(Reg &x, int n_ct)
             }
             add_scalar_batch_launch(c, acc, acc, lv, n_ct, scal(st.cidx, lv), c->stream);
             u64 *out = take();
+            if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             rc = rbk_rescale_batch(c, acc, out, lv, n_ct);
             if (rc) return rc;
             regs[st.reg] = Reg{out, lv - 1};
@@ -640,6 +643,7 @@ int Runner::evalmod(Reg &x, int n_ct)
             regs.erase(st.reg + "r");
             const int lp = st.lp;
             u64 *A = take(), *B = take(), *X = take(), *Y = take();
+            if (!A || !B || !X || !Y) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             const u64 *pq = at(q, lp, A), *pm = at(T[st.m], lp, B);
             rc = rbk_mult_relin_batch(c, pq, pm, X, lp, n_ct);
             if (rc) return rc;
@@ -648,6 +652,7 @@ int Runner::evalmod(Reg &x, int n_ct)
             const u64 *py = at(Reg{Y, lp - 1}, st.out, A);
             const u64 *pr = at(r, st.out, B);
             u64 *out = take();
+            if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             ew_launch(c, EW_ADD, py, pr, out, 2 * n_ct, st.out + 1, qm, c->stream);
             regs[st.reg] = Reg{out, st.out};
             give(q.d);
@@ -660,12 +665,14 @@ int Runner::evalmod(Reg &x, int n_ct)
             Reg y = regs["p"];
             const int lv = st.lv;
             u64 *A = take(), *X = take();
+            if (!A || !X) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             const u64 *py = at(y, lv, A);
             rc = rbk_mult_relin_batch(c, py, py, X, lv, n_ct);
             if (rc) return rc;
             ew_launch(c, EW_ADD, X, X, X, 2 * n_ct, lv + 1, qm, c->stream);
             add_scalar_batch_launch(c, X, X, lv, n_ct, scal(st.sidx, lv), c->stream);
             u64 *out = take();
+            if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             rc = rbk_rescale_batch(c, X, out, lv, n_ct);
             if (rc) return rc;
             give(y.d);
@@ -839,9 +846,11 @@ extern "C" int rbk_bootstrap_batch(rbk_ctx *c, const uint64_t *d_in, const doubl
     }
     // EvalMod runs the real and imaginary halves of the batch together
     Runner R{c, P, count, (size_t)2 * count * 2 * (P.L + 1) * N, {}};
-    // reuse pooled buffers of the right size from earlier runs
-    if (P.pool_words == R.reg_words) R.free_ = P.pool;
-    else {
+    // reuse the pooled registers of earlier runs when they are large enough
+    if (P.pool_words >= R.reg_words) {
+        R.reg_words = P.pool_words;
+        R.free_ = P.pool;
+    } else {
         (void)hipStreamSynchronize(c->stream);
         for (u64 *d : P.pool) (void)hipFree(d);
         P.pool.clear();
@@ -878,6 +887,7 @@ extern "C" int rbk_bootstrap_batch(rbk_ctx *c, const uint64_t *d_in, const doubl
     const int lv = P.level_evalmod;
     const size_t ctw = 2 * R.per(lv);
     u64 *conj = R.take(), *both = R.take();
+    if (!conj || !both) return boot_fail(RBK_ENOMEM, "bootstrapping registers");
     rc = rotate_batch_g(c, x.d, conj, lv, count, 2 * c->N - 1);
     if (rc) return rc;
     ew_launch(c, EW_ADD, x.d, conj, both, 2 * count, lv + 1, qm, c->stream);

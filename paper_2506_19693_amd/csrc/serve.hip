@@ -14,6 +14,7 @@
 // batched with.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <map>
@@ -78,24 +79,25 @@ struct rbk_server {
     uint64_t next_id = 1;
     bool running = false, stopping = false;
     uint64_t n_batches = 0, n_jobs_done = 0, n_merged = 0, n_outstanding = 0;
-    int max_batch;
+    int max_batch, max_boot;
 
-    rbk_server(uint64_t budget, int mb) : sched(budget, mb), max_batch(mb) {}
+    rbk_server(uint64_t budget, int mb, int mbb) : sched(budget, mb, mbb), max_batch(mb), max_boot(mbb) {}
 };
 
 namespace {
 
-// working-set estimate of a job, bytes (admission only; see rbk.h)
-uint64_t footprint(const rbk_ctx *c, const rbk_job &j)
+// working-set estimate of a job, bytes (admission only; see rbk.h).  Jobs run
+// in chunks of at most max_batch (mult) / max_boot (bootstrap) ciphertexts.
+uint64_t footprint(const rbk_ctx *c, const rbk_job &j, int max_batch, int max_boot)
 {
     const uint64_t w8 = sizeof(u64);
     switch (j.kind) {
     case RBK_JOB_MULT_RESCALE: {
-        const uint64_t ct = ct_words(c, j.level);
-        return w8 * ((uint64_t)j.count * (2 * ct + 3 * ct / 2 + ct + ct) + ks_words(c, j.level, j.count));
+        const uint64_t ct = ct_words(c, j.level), n = (uint64_t)std::min(j.count, max_batch);
+        return w8 * ((uint64_t)j.count * ct + n * (2 * ct + 3 * ct / 2 + ct + ct) + ks_words(c, j.level, (int)n));
     }
     case RBK_JOB_BOOTSTRAP:
-        return w8 * (uint64_t)j.count * 32 * ct_words(c, c->nQ - 1);
+        return w8 * (uint64_t)std::min(j.count, max_boot) * 48 * ct_words(c, c->nQ - 1);
     case RBK_JOB_TRAIN_STEP:
         return w8 * (uint64_t)j.b * 24 * ct_words(c, j.level) + w8 * ks_words(c, j.level, j.b);
     default:
@@ -129,62 +131,96 @@ int gather(Tenant *t, const uint64_t *src, int in_level, int level, int count, u
     return RBK_OK;
 }
 
-int run_mult(Tenant *t, std::vector<SJob *> &b)
+// the ciphertexts of a batch, job by job, as (job, first index, count) pieces
+// of chunks of at most `cap`
+struct Piece {
+    SJob *s;
+    int first, n;
+};
+
+std::vector<std::vector<Piece>> chunks(std::vector<SJob *> &b, int cap)
+{
+    std::vector<std::vector<Piece>> out(1);
+    int fill = 0;
+    for (SJob *s : b) {
+        for (int i = 0; i < s->j.count;) {
+            if (fill == cap) {
+                out.emplace_back();
+                fill = 0;
+            }
+            const int n = std::min(s->j.count - i, cap - fill);
+            out.back().push_back(Piece{s, i, n});
+            fill += n;
+            i += n;
+        }
+    }
+    return out;
+}
+
+int run_mult(Tenant *t, std::vector<SJob *> &b, int cap)
 {
     rbk_ctx *c = t->c;
     const int lv = b[0]->j.level;
-    int total = 0;
-    for (SJob *s : b) total += s->j.count;
     const size_t ct = ct_words(c, lv), ct_out = ct_words(c, lv - 1);
-    u64 *A = stage_reserve(t, (size_t)total * (3 * ct) + (size_t)total * ct_out);
-    if (!A) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
-    u64 *B = A + (size_t)total * ct, *M = B + (size_t)total * ct, *R = M + (size_t)total * ct;
-    int off = 0, rc;
-    for (SJob *s : b) {
-        if ((rc = gather(t, s->j.d_a, s->j.in_level, lv, s->j.count, A + (size_t)off * ct))) return rc;
-        if ((rc = gather(t, s->j.d_b, s->j.in_level, lv, s->j.count, B + (size_t)off * ct))) return rc;
-        off += s->j.count;
-    }
-    if ((rc = rbk_mult_relin_batch(c, A, B, M, lv, total))) return rc;
-    if ((rc = rbk_rescale_batch(c, M, R, lv, total))) return rc;
-    off = 0;
-    for (SJob *s : b) {
-        if (hipMemcpyAsync(s->j.d_out, R + (size_t)off * ct_out, (size_t)s->j.count * ct_out * sizeof(u64),
-                           hipMemcpyDeviceToDevice, t->st) != hipSuccess)
-            return rbk_set_error(RBK_EDEVICE, "scatter copy failed");
-        off += s->j.count;
+    for (auto &ch : chunks(b, cap)) {
+        int total = 0, rc;
+        for (auto &p : ch) total += p.n;
+        u64 *A = stage_reserve(t, (size_t)total * (3 * ct) + (size_t)total * ct_out);
+        if (!A) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
+        u64 *B = A + (size_t)total * ct, *M = B + (size_t)total * ct, *R = M + (size_t)total * ct;
+        int off = 0;
+        for (auto &p : ch) {
+            const rbk_job &j = p.s->j;
+            const size_t in_ct = ct_words(c, j.in_level);
+            if ((rc = gather(t, j.d_a + p.first * in_ct, j.in_level, lv, p.n, A + (size_t)off * ct))) return rc;
+            if ((rc = gather(t, j.d_b + p.first * in_ct, j.in_level, lv, p.n, B + (size_t)off * ct))) return rc;
+            off += p.n;
+        }
+        if ((rc = rbk_mult_relin_batch(c, A, B, M, lv, total))) return rc;
+        if ((rc = rbk_rescale_batch(c, M, R, lv, total))) return rc;
+        off = 0;
+        for (auto &p : ch) {
+            if (hipMemcpyAsync(p.s->j.d_out + p.first * ct_out, R + (size_t)off * ct_out, (size_t)p.n * ct_out * sizeof(u64),
+                               hipMemcpyDeviceToDevice, t->st) != hipSuccess)
+                return rbk_set_error(RBK_EDEVICE, "scatter copy failed");
+            off += p.n;
+        }
     }
     return RBK_OK;
 }
 
-int run_boot(Tenant *t, std::vector<SJob *> &b)
+int run_boot(Tenant *t, std::vector<SJob *> &b, int cap)
 {
     rbk_ctx *c = t->c;
     int levels[4], np = 0, ns = 0, rc;
     if ((rc = rbk_boot_info(c, levels, &np, &ns))) return rc;
     const int lo = levels[3];
-    int total = 0;
-    for (SJob *s : b) total += s->j.count;
     const size_t ci = ct_words(c, 0), co = ct_words(c, lo);
-    u64 *I = stage_reserve(t, (size_t)total * (ci + co));
-    if (!I) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
-    u64 *O = I + (size_t)total * ci;
-    std::vector<double> sin, sout(total);
-    int off = 0;
-    for (SJob *s : b) {
-        if ((rc = gather(t, s->j.d_a, s->j.in_level, 0, s->j.count, I + (size_t)off * ci))) return rc;
-        sin.insert(sin.end(), s->scales_in.begin(), s->scales_in.end());
-        off += s->j.count;
-    }
-    if ((rc = rbk_bootstrap_batch(c, I, sin.data(), O, sout.data(), total))) return rc;
-    off = 0;
-    for (SJob *s : b) {
-        if (hipMemcpyAsync(s->j.d_out, O + (size_t)off * co, (size_t)s->j.count * co * sizeof(u64),
-                           hipMemcpyDeviceToDevice, t->st) != hipSuccess)
-            return rbk_set_error(RBK_EDEVICE, "scatter copy failed");
-        if (s->j.scales_out)
-            for (int i = 0; i < s->j.count; i++) s->j.scales_out[i] = sout[off + i];
-        off += s->j.count;
+    for (auto &ch : chunks(b, cap)) {
+        int total = 0;
+        for (auto &p : ch) total += p.n;
+        u64 *I = stage_reserve(t, (size_t)total * (ci + co));
+        if (!I) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
+        u64 *O = I + (size_t)total * ci;
+        std::vector<double> sin, sout(total);
+        int off = 0;
+        for (auto &p : ch) {
+            const rbk_job &j = p.s->j;
+            const size_t in_ct = ct_words(c, j.in_level);
+            if ((rc = gather(t, j.d_a + p.first * in_ct, j.in_level, 0, p.n, I + (size_t)off * ci))) return rc;
+            sin.insert(sin.end(), p.s->scales_in.begin() + p.first, p.s->scales_in.begin() + p.first + p.n);
+            off += p.n;
+        }
+        if ((rc = rbk_bootstrap_batch(c, I, sin.data(), O, sout.data(), total))) return rc;
+        off = 0;
+        for (auto &p : ch) {
+            if (hipMemcpyAsync(p.s->j.d_out + p.first * co, O + (size_t)off * co, (size_t)p.n * co * sizeof(u64),
+                               hipMemcpyDeviceToDevice, t->st) != hipSuccess)
+                return rbk_set_error(RBK_EDEVICE, "scatter copy failed");
+            if (p.s->j.scales_out)
+                for (int i = 0; i < p.n; i++) p.s->j.scales_out[p.first + i] = sout[off + i];
+            off += p.n;
+        }
     }
     return RBK_OK;
 }
@@ -225,8 +261,8 @@ void worker(rbk_server *S, Tenant *t)
         }
         int rc;
         switch (sj[0]->j.kind) {
-        case RBK_JOB_MULT_RESCALE: rc = run_mult(t, sj); break;
-        case RBK_JOB_BOOTSTRAP: rc = run_boot(t, sj); break;
+        case RBK_JOB_MULT_RESCALE: rc = run_mult(t, sj, S->max_batch); break;
+        case RBK_JOB_BOOTSTRAP: rc = run_boot(t, sj, S->max_boot); break;
         default: rc = run_train(t, sj); break;
         }
         if (hipStreamSynchronize(t->st) != hipSuccess && !rc) rc = rbk_set_error(RBK_EDEVICE, "stream failed");
@@ -259,10 +295,10 @@ void worker(rbk_server *S, Tenant *t)
 
 // ---------------------------------------------------------------- C ABI
 
-extern "C" int rbk_server_create(uint64_t hbm_budget, int max_batch, rbk_server **out)
+extern "C" int rbk_server_create(uint64_t hbm_budget, int max_batch, int max_boot_batch, rbk_server **out)
 {
-    if (!out || hbm_budget == 0 || max_batch < 1) return rbk_set_error(RBK_EINVAL, "bad argument");
-    *out = new (std::nothrow) rbk_server(hbm_budget, max_batch);
+    if (!out || hbm_budget == 0 || max_batch < 1 || max_boot_batch < 1) return rbk_set_error(RBK_EINVAL, "bad argument");
+    *out = new (std::nothrow) rbk_server(hbm_budget, max_batch, max_boot_batch);
     return *out ? RBK_OK : rbk_set_error(RBK_ENOMEM, "host allocation failed");
 }
 
@@ -338,7 +374,7 @@ extern "C" int rbk_server_submit(rbk_server *S, const rbk_job *j, uint64_t *id)
     sj.kind = kind;
     sj.level = j->kind == RBK_JOB_BOOTSTRAP ? 0 : j->level;
     sj.count = j->kind == RBK_JOB_TRAIN_STEP ? 1 : j->count;
-    sj.footprint = footprint(c, *j);
+    sj.footprint = footprint(c, *j, S->max_batch, S->max_boot);
     if (!S->sched.submit(sj)) return rbk_set_error(RBK_ENOMEM, "job footprint exceeds the HBM budget");
     SJob &s = S->jobs[sj.id];
     s.j = *j;

@@ -10,8 +10,9 @@
 //   `max_skips` times, after which admission waits for it.
 // * A tenant's next batch is its oldest admitted job plus every later admitted
 //   job of the same kind and level, while the ciphertext total stays within
-//   max_batch (a first job larger than max_batch runs alone).  Jobs of kind
-//   KIND_SOLO (a training step) are never merged.
+//   the kind's cap (max_boot_batch for bootstraps, max_batch otherwise; a first
+//   job above the cap runs alone).  Jobs of kind KIND_SOLO (a training step)
+//   are never merged.
 // * Completing a batch releases its footprints.
 #pragma once
 #include <cstddef>
@@ -35,8 +36,11 @@ struct Job {
 
 class Scheduler {
 public:
-    Scheduler(uint64_t budget, int max_batch, int max_skips = 8)
-        : budget_(budget), max_batch_(max_batch < 1 ? 1 : max_batch), max_skips_(max_skips)
+    Scheduler(uint64_t budget, int max_batch, int max_boot_batch, int max_skips = 8)
+        : budget_(budget),
+          max_batch_(max_batch < 1 ? 1 : max_batch),
+          max_boot_(max_boot_batch < 1 ? 1 : max_boot_batch),
+          max_skips_(max_skips)
     {
     }
 
@@ -97,10 +101,11 @@ public:
         b.push_back(q.front());
         q.pop_front();
         if (b[0].kind == KIND_SOLO) return b;
+        const int cap = b[0].kind == KIND_BOOT ? max_boot_ : max_batch_;
         int total = b[0].count;
         for (size_t k = 0; k < q.size();) {
             const Job &x = q[k];
-            if (x.kind == b[0].kind && x.level == b[0].level && total + x.count <= max_batch_) {
+            if (x.kind == b[0].kind && x.level == b[0].level && total + x.count <= cap) {
                 total += x.count;
                 b.push_back(x);
                 q.erase(q.begin() + (long)k);
@@ -128,7 +133,7 @@ public:
 
 private:
     uint64_t budget_, resident_ = 0, ledger_ = 0, peak_ = 0;
-    int max_batch_, max_skips_, head_skips_ = 0;
+    int max_batch_, max_boot_, max_skips_, head_skips_ = 0;
     std::deque<Job> pending_;
     std::map<int, std::deque<Job>> ready_;
 };

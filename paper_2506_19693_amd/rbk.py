@@ -166,7 +166,7 @@ SIGNATURES = {
     "rbk_mlp_set_mask": (ci, [vp, ci, vp]),
     "rbk_mlp_train_step": (ci, [vp, vp, vp, vp, ci, ci, ctypes.c_double, ci, ctypes.c_uint32]),
     "rbk_mlp_scalars": (ci, [vp, i64p, ci]),
-    "rbk_server_create": (ci, [ctypes.c_uint64, ci, ctypes.POINTER(vp)]),
+    "rbk_server_create": (ci, [ctypes.c_uint64, ci, ci, ctypes.POINTER(vp)]),
     "rbk_server_add_tenant": (ci, [vp, vp, ctypes.POINTER(ci)]),
     "rbk_server_start": (ci, [vp]),
     "rbk_server_submit": (ci, [vp, ctypes.POINTER(RbkJob), u64p]),
@@ -686,10 +686,10 @@ class Server:
     """The serving loop of rbk.h (rbk_server_*).  Tensors named by a job are
     kept referenced here until the job is waited for."""
 
-    def __init__(self, hbm_budget, max_batch=64):
+    def __init__(self, hbm_budget, max_batch=64, max_boot_batch=16):
         self.lib = load()
         h = vp()
-        _check(self.lib.rbk_server_create(int(hbm_budget), int(max_batch), ctypes.byref(h)))
+        _check(self.lib.rbk_server_create(int(hbm_budget), int(max_batch), int(max_boot_batch), ctypes.byref(h)))
         self.h = h
         self._keep = {}
         self.tenants = []

@@ -43,7 +43,7 @@ int main()
 {
     // resident bytes count against the budget; a tenant that does not fit is refused
     {
-        Scheduler s(1000, 64);
+        Scheduler s(1000, 64, 16);
         CHECK(s.add_tenant(0, 300));
         CHECK(!s.add_tenant(0, 10));  // twice
         CHECK(!s.add_tenant(1, 800));
@@ -54,7 +54,7 @@ int main()
     }
     // admission in arrival order within the budget
     {
-        Scheduler s(100, 64);
+        Scheduler s(100, 64, 16);
         CHECK(s.add_tenant(0, 10));
         for (uint64_t i = 1; i <= 4; i++) CHECK(s.submit(job(i, 0, KIND_MULT, 5, 8, 30)));
         auto a = s.admit();
@@ -70,7 +70,7 @@ int main()
     // batches: same kind and level only, at most max_batch ciphertexts, solo jobs alone,
     // a first job above max_batch alone
     {
-        Scheduler s(1 << 30, 16);
+        Scheduler s(1 << 30, 16, 8);
         CHECK(s.add_tenant(0, 0));
         CHECK(s.add_tenant(1, 0));
         CHECK(s.submit(job(1, 0, KIND_MULT, 5, 8, 1)));
@@ -86,7 +86,7 @@ int main()
         CHECK(s.admit().size() == 10);
         CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{1, 4}));     // 8 + 8 = 16, job 5 no longer fits
         CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{2}));
-        CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{3, 10}));    // 4 + 2; job 9 (20) does not fit
+        CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{3, 10}));    // 4 + 2 <= 8; job 9 (20) does not fit
         CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{5}));
         CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{7}));
         CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{8}));
@@ -96,7 +96,7 @@ int main()
     }
     // backfill past a head that does not fit, bounded by max_skips
     {
-        Scheduler s(100, 64, 3);
+        Scheduler s(100, 64, 16, 3);
         CHECK(s.add_tenant(0, 0));
         CHECK(s.submit(job(1, 0, KIND_MULT, 5, 1, 60)));
         CHECK((ids(s.admit()) == std::vector<uint64_t>{1}));
@@ -117,8 +117,8 @@ int main()
     {
         std::mt19937_64 rng(7);
         const uint64_t budget = 5000;
-        const int max_batch = 32;
-        Scheduler s(budget, max_batch, 4);
+        const int max_batch = 32, max_boot = 12;
+        Scheduler s(budget, max_batch, max_boot, 4);
         const int tenants = 4;
         for (int t = 0; t < tenants; t++) CHECK(s.add_tenant(t, 200));
         std::set<uint64_t> submitted, admitted, completed;
@@ -143,7 +143,7 @@ int main()
                         CHECK(admitted.count(x.id));
                         total += x.count;
                     }
-                    CHECK(b.size() == 1 || total <= max_batch);
+                    CHECK(b.size() == 1 || total <= (b[0].kind == KIND_BOOT ? max_boot : max_batch));
                     CHECK(b[0].kind != KIND_SOLO || b.size() == 1);
                     running.push_back(b);
                 }

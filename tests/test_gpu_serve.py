@@ -1,8 +1,9 @@
 """The serving loop on the GPU: a mix of jobs from three tenants (two ring
 degrees, mult+rescale batches at several levels, bootstraps, MLP training
 steps) gives every job exactly the result it gets alone, whether jobs are
-merged freely (large budget) or queued by a tight HBM budget; the ledger stays
-within the budget and jobs do get merged."""
+merged freely (large budget) or queued by a tight HBM budget with small chunk
+caps (jobs split across launches); the ledger stays within the budget and
+jobs do get merged."""
 import pytest
 
 import synth_inputs as S
@@ -113,7 +114,7 @@ class World:
         ctx.sync()
         return want
 
-    def served(self, budget, max_batch):
+    def served(self, budget, max_batch, max_boot_batch=16):
         import torch
 
         from paper_2506_19693_amd import Server
@@ -121,7 +122,7 @@ class World:
         mlp = self.mk_mlp()
         self.reset_mlp(mlp)
         torch.cuda.synchronize()
-        srv = Server(budget, max_batch)
+        srv = Server(budget, max_batch, max_boot_batch)
         for c in self.ctxs:
             srv.add_tenant(c)
         srv.start()
@@ -200,14 +201,15 @@ def test_mix_equals_alone_tight_budget():
     # room for the resident keys plus roughly one large job at a time
     from paper_2506_19693_amd import Server
 
-    probe = Server(1 << 60, 8)
+    probe = Server(1 << 60, 8, 2)
     for c in w.ctxs:
         probe.add_tenant(c)
     resident = probe.stats()["ledger_now"]
     probe.close()
-    # the largest job (a 3-ciphertext bootstrap) needs about 72 MiB: at most one at a time
+    # bootstraps run in chunks of 2 ciphertexts (about 72 MiB of estimated
+    # working set), mult batches in chunks of at most 8: one bootstrap at a time
     budget = resident + (100 << 20)
-    got, final, res, stats = w.served(budget=budget, max_batch=8)
+    got, final, res, stats = w.served(budget=budget, max_batch=8, max_boot_batch=2)
     _compare(w, want, got, final)
     assert resident < stats["ledger_peak"] <= budget
     assert stats["jobs_done"] == len(w.jobs)
