@@ -423,6 +423,31 @@ int rbk_server_stats(rbk_server *srv, uint64_t *stats);
  * back, free the server. */
 int rbk_server_destroy(rbk_server *srv);
 
+/* ---- graph capture ---------------------------------------------------------- */
+
+/* Record the device work of a sequence of calls on the context's stream into
+ * a HIP graph and replay it with one launch.  Between rbk_capture_begin and
+ * rbk_capture_end nothing executes: the calls enqueue their kernels and
+ * copies into the graph (host-side results such as bootstrap output scales
+ * are those computed while capturing).  Requirements:
+ *  - the context is on a stream other than the default one (rbk_set_stream);
+ *  - the same sequence ran once before, so that every workspace, register
+ *    pool and mask is already sized: a call that would grow one fails with
+ *    RBK_ESTATE instead (the capture must then be ended and discarded);
+ *  - calls that transfer host data or synchronise (keygen, encode, decode,
+ *    encrypt, bootstrap setup/import/export, timers, set_state) are refused;
+ *  - the graph reads and writes the device addresses named while capturing:
+ *    replays recompute from whatever those buffers hold at launch time
+ *    (an MLP's state buffers keep their addresses across steps, so replaying
+ *    a captured step t >= 2 runs the following steps).
+ * No memset node is recorded (buffers are cleared by kernels). */
+typedef struct rbk_graph rbk_graph;
+int rbk_capture_begin(rbk_ctx *ctx);
+int rbk_capture_end(rbk_ctx *ctx, rbk_graph **out);
+/* enqueue the captured work on the context's current stream */
+int rbk_graph_launch(rbk_graph *graph);
+int rbk_graph_destroy(rbk_graph *graph);
+
 /* ---- per-kernel timers -------------------------------------------------- */
 /* With timers on, every kernel launch on the context stream is bracketed by
  * HIP events.  Class `cls` = 0, 1, ... names one kernel (rbk_timer_name);

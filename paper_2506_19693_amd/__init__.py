@@ -4,6 +4,6 @@ The arithmetic lives in librbk.so (HIP kernels behind the C ABI of
 include/rbk.h); ``rbk`` is its ctypes binding.
 """
 from . import rbk  # noqa: F401
-from .rbk import Context, Mlp, RbkError, Server, load, to_device, to_host  # noqa: F401
+from .rbk import Context, Graph, Mlp, RbkError, Server, load, to_device, to_host  # noqa: F401
 
-__all__ = ["rbk", "Context", "Mlp", "RbkError", "Server", "load", "to_device", "to_host"]
+__all__ = ["rbk", "Context", "Graph", "Mlp", "RbkError", "Server", "load", "to_device", "to_host"]

@@ -161,12 +161,27 @@ static void dev_release(rbk_ctx *c, void *p)
     (void)hipFree(p);
 }
 
+void release_buffer(rbk_ctx_impl *c, void *p)
+{
+    if (!p) return;
+    if (c->live_graphs > 0) {
+        c->retired.push_back(p);
+        return;
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(p);
+}
+
 u64 *ws_reserve(rbk_ctx_impl *c, size_t words)
 {
     if (words <= c->ws_words) return c->ws;
+    if (c->capturing) {
+        // the captured work already points into the current workspace
+        rbk_set_error(RBK_ESTATE, "workspace too small during graph capture: run the sequence once before capturing");
+        return nullptr;
+    }
     if (c->ws) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->ws);
+        release_buffer(c, c->ws);
         c->ws = nullptr;
         c->ws_words = 0;
     }
@@ -180,7 +195,7 @@ u64 *ws_reserve(rbk_ctx_impl *c, size_t words)
 
 #define WS(ptr, words)                                                                         \
     u64 *ptr = ws_reserve(c, (words));                                                          \
-    if (!ptr) return fail(RBK_ENOMEM, "device workspace allocation failed");
+    if (!ptr) return c->capturing ? RBK_ESTATE : fail(RBK_ENOMEM, "device workspace allocation failed");
 
 // ---------------------------------------------------------------- tables
 
@@ -380,6 +395,7 @@ extern "C" int rbk_ctx_create(const rbk_params *p, rbk_ctx **out)
 
 extern "C" int rbk_ctx_destroy(rbk_ctx *c)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c) return RBK_OK;
     (void)hipStreamSynchronize(c->stream);
     boot_free(c);
@@ -387,6 +403,7 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
         for (hipEvent_t e : c->timers[k].pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     for (void *p : c->owned) (void)hipFree(p);
+    for (void *p : c->retired) (void)hipFree(p);
     if (c->ws) (void)hipFree(c->ws);
     delete c;
     return RBK_OK;
@@ -446,6 +463,7 @@ size_t ks_words(const rbk_ctx *c, int level, int count)
 
 extern "C" int rbk_reserve(rbk_ctx *c, int level, int count)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || count < 1) return fail(RBK_EINVAL, "bad argument");
     if (check_level(c, level)) return RBK_ELEVEL;
     size_t L1 = level + 1, N = c->N;
@@ -477,6 +495,7 @@ static LimbMap allmap(const rbk_ctx *c) { return LimbMap{0, c->nQ, c->nQ}; }  //
 
 extern "C" int rbk_set_secret(rbk_ctx *c, const int64_t *s)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !s) return fail(RBK_EINVAL, "null argument");
     const size_t N = c->N;
     if (!c->d_s && dev_alloc(c, &c->d_s, c->nT * N)) return RBK_ENOMEM;
@@ -491,6 +510,7 @@ extern "C" int rbk_set_secret(rbk_ctx *c, const int64_t *s)
 
 extern "C" int rbk_keygen_public(rbk_ctx *c, const uint64_t *a, const int64_t *e)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
     if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
     const size_t N = c->N, nQ = c->nQ;
@@ -534,6 +554,7 @@ static int keygen_switch(rbk_ctx *c, DevKey &k, const u64 *s_from, const uint64_
 
 extern "C" int rbk_keygen_relin(rbk_ctx *c, const uint64_t *a, const int64_t *e)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
     if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
     u64 *s2 = nullptr;
@@ -556,6 +577,7 @@ extern "C" uint64_t rbk_galois_elt(const rbk_ctx *c, int64_t k)
 
 extern "C" int rbk_keygen_galois(rbk_ctx *c, uint64_t g, const uint64_t *a, const int64_t *e)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
     if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
     if (g % 2 == 0 || g >= 2 * c->N || g == 1) return fail(RBK_EINVAL, "Galois element must be odd, in (1, 2N)");
@@ -579,6 +601,7 @@ static const DevKey *find_key(const rbk_ctx *c, u64 g)
 
 extern "C" int rbk_key_export(rbk_ctx *c, uint64_t g, uint64_t *out)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !out) return fail(RBK_EINVAL, "null argument");
     const DevKey *k = find_key(c, g);
     if (!k) return fail(RBK_ENOKEY, "no such key");
@@ -597,6 +620,7 @@ extern "C" int rbk_key_export(rbk_ctx *c, uint64_t g, uint64_t *out)
 
 extern "C" int rbk_encode(rbk_ctx *c, const double *re, const double *im, size_t n, int level, double scale, uint64_t *d_pt)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || (!re && n) || !d_pt) return fail(RBK_EINVAL, "null argument");
     if (check_level(c, level)) return RBK_ELEVEL;
     if (n > c->N / 2) return fail(RBK_EINVAL, "more slots than N/2");
@@ -621,6 +645,7 @@ extern "C" int rbk_encode(rbk_ctx *c, const double *re, const double *im, size_t
 
 extern "C" int rbk_decode(rbk_ctx *c, const uint64_t *d_pt, int level, double scale, double *re, double *im, size_t n)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !d_pt || (!re && n)) return fail(RBK_EINVAL, "null argument");
     if (check_level(c, level)) return RBK_ELEVEL;
     if (n > c->N / 2) return fail(RBK_EINVAL, "more slots than N/2");
@@ -643,6 +668,7 @@ extern "C" int rbk_decode(rbk_ctx *c, const uint64_t *d_pt, int level, double sc
 extern "C" int rbk_encrypt(rbk_ctx *c, const uint64_t *d_pt, int level, const int64_t *v, const int64_t *e0,
                            const int64_t *e1, uint64_t *d_ct)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !d_pt || !v || !e0 || !e1 || !d_ct) return fail(RBK_EINVAL, "null argument");
     if (check_level(c, level)) return RBK_ELEVEL;
     if (!c->d_pk) return fail(RBK_ENOKEY, "public key not generated");
@@ -803,7 +829,7 @@ static int moddown_run(rbk_ctx *c, u64 *u, const u64 *add, long add_stride, u64 
         bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, c->stream);
         ntt_launch(c, conv, (long)L1 * N, 2 * count, L1, qmap(c), false, c->stream);
     } else {
-        HIPCK(hipMemsetAsync(conv, 0, 2 * count * L1 * N * sizeof(u64), c->stream));
+        ew_launch(c, EW_ZERO, conv, nullptr, conv, 2 * count, L1, qmap(c), c->stream);
     }
     moddown_finish_launch(c, u, (long)2 * E * N, conv, (long)2 * L1 * N, add, add_stride, add_g, add_both, out, out_stride,
                           level, count, c->stream);
@@ -825,7 +851,7 @@ static int moddown_fused_run(rbk_ctx *c, const u64 *ext, long ext_stride, const 
         bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, c->stream);
         ntt_launch(c, conv, (long)L1 * N, 2 * count, L1, qmap(c), false, c->stream);
     } else {
-        HIPCK(hipMemsetAsync(conv, 0, 2 * count * L1 * N * sizeof(u64), c->stream));
+        ew_launch(c, EW_ZERO, conv, nullptr, conv, 2 * count, L1, qmap(c), c->stream);
     }
     moddown_ip_launch(c, ext, ext_stride, key->data, conv, (long)2 * L1 * N, add, add_stride, add_g, add_both, out,
                       out_stride, level, count, perm_g, c->stream);
@@ -879,7 +905,7 @@ extern "C" int rbk_moddown(rbk_ctx *c, const uint64_t *u, uint64_t *out, int lev
     WS(ws, pairs * 2 * E * N + pairs * 2 * c->nP * N + pairs * 2 * L1 * N + pairs * 2 * L1 * N);
     u64 *uu = ws, *tp = uu + pairs * 2 * E * N, *conv = tp + pairs * 2 * c->nP * N, *o = conv + pairs * 2 * L1 * N;
     HIPCK(hipMemcpyAsync(uu, u, npoly * E * N * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
-    if (npoly & 1) HIPCK(hipMemsetAsync(uu + npoly * E * N, 0, E * N * sizeof(u64), c->stream));
+    if (npoly & 1) ew_launch(c, EW_ZERO, uu + npoly * E * N, nullptr, uu + npoly * E * N, 1, (int)E, qmap(c), c->stream);
     int rc = moddown_run(c, uu, nullptr, 0, 0, 0, o, (long)2 * L1 * N, level, pairs, tp, conv);
     if (rc) return rc;
     HIPCK(hipMemcpyAsync(out, o, npoly * L1 * N * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
@@ -1091,6 +1117,7 @@ static int kt_collect(rbk_ctx *c)
 
 extern "C" int rbk_timer_enable(rbk_ctx *c, int on)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c) return fail(RBK_EINVAL, "null context");
     int rc = kt_collect(c);
     if (rc) return rc;
@@ -1101,6 +1128,7 @@ extern "C" int rbk_timer_enable(rbk_ctx *c, int on)
 
 extern "C" int rbk_timer_read(rbk_ctx *c, int cls, double *ms, uint64_t *launches, double *bytes)
 {
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || cls < 0 || cls >= KC_COUNT) return fail(RBK_EINVAL, "bad argument");
     int rc = kt_collect(c);
     if (rc) return rc;
@@ -1111,3 +1139,74 @@ extern "C" int rbk_timer_read(rbk_ctx *c, int cls, double *ms, uint64_t *launche
 }
 
 extern "C" const char *rbk_timer_name(int cls) { return (cls >= 0 && cls < KC_COUNT) ? kc_names[cls] : nullptr; }
+
+// ---------------------------------------------------------------- graph capture
+
+struct rbk_graph {
+    rbk_ctx *c = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+};
+
+extern "C" int rbk_capture_begin(rbk_ctx *c)
+{
+    if (!c) return fail(RBK_EINVAL, "null argument");
+    if (c->capturing) return fail(RBK_ESTATE, "already capturing");
+    if (c->timing) return fail(RBK_ESTATE, "disable the kernel timers before capturing");
+    if (!c->stream) return fail(RBK_ESTATE, "capture needs a non-default stream (rbk_set_stream)");
+    HIPCK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    c->capturing = true;
+    return RBK_OK;
+}
+
+extern "C" int rbk_capture_end(rbk_ctx *c, rbk_graph **out)
+{
+    if (!c || !out) return fail(RBK_EINVAL, "null argument");
+    if (!c->capturing) return fail(RBK_ESTATE, "not capturing");
+    c->capturing = false;
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || !g) return fail(RBK_EDEVICE, std::string("capture failed: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(RBK_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+    }
+    rbk_graph *r = new (std::nothrow) rbk_graph;
+    if (!r) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
+        return fail(RBK_ENOMEM, "host allocation failed");
+    }
+    c->live_graphs++;
+    r->c = c;
+    r->g = g;
+    r->e = ex;
+    *out = r;
+    return RBK_OK;
+}
+
+extern "C" int rbk_graph_launch(rbk_graph *g)
+{
+    if (!g) return fail(RBK_EINVAL, "null argument");
+    if (g->c->capturing) return fail(RBK_ESTATE, "cannot launch while capturing");
+    HIPCK(hipGraphLaunch(g->e, g->c->stream));
+    return RBK_OK;
+}
+
+extern "C" int rbk_graph_destroy(rbk_graph *g)
+{
+    if (!g) return RBK_OK;
+    rbk_ctx *c = g->c;
+    (void)hipStreamSynchronize(c->stream);
+    if (g->e) (void)hipGraphExecDestroy(g->e);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    delete g;
+    if (--c->live_graphs == 0) {
+        for (void *p : c->retired) (void)hipFree(p);
+        c->retired.clear();
+    }
+    return RBK_OK;
+}

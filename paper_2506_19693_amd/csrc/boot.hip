@@ -365,9 +365,9 @@ void boot_free(rbk_ctx_impl *ci)
 {
     BootPlan *P = ci->boot;
     if (!P) return;
-    for (u64 *d : P->d_plain) (void)hipFree(d);
-    for (u64 *d : P->pool) (void)hipFree(d);
-    if (P->rot_area) (void)hipFree(P->rot_area);
+    for (u64 *d : P->d_plain) release_buffer(ci, d);
+    for (u64 *d : P->pool) release_buffer(ci, d);
+    release_buffer(ci, P->rot_area);
     delete P;
     ci->boot = nullptr;
 }
@@ -514,11 +514,12 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
     if (nb) {
         const size_t need = (size_t)n_ct * nb * ctw;
         if (need > P.rot_words) {
-            (void)hipStreamSynchronize(c->stream);
-            if (P.rot_area) (void)hipFree(P.rot_area);
+            if (c->capturing) return rbk_set_error(RBK_ESTATE, "rotation area too small during graph capture");
+            release_buffer(c, P.rot_area);
             P.rot_area = nullptr;
             P.rot_words = 0;
-            if (hipMalloc((void **)&P.rot_area, need * sizeof(u64)) != hipSuccess) return RBK_ENOMEM;
+            if (hipMalloc((void **)&P.rot_area, need * sizeof(u64)) != hipSuccess)
+                return rbk_set_error(RBK_ENOMEM, "rotation area");
             P.rot_words = need;
         }
         std::vector<int64_t> ks;
@@ -701,6 +702,7 @@ static int boot_fail(int code, const char *msg);
 
 extern "C" int rbk_boot_setup(rbk_ctx *c, const rbk_boot_params *prm)
 {
+    if (c && c->capturing) return boot_fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !prm) return boot_fail(RBK_EINVAL, "null argument");
     if (prm->degree < 8 || prm->degree > 255 || prm->cts_levels < 1 || prm->stc_levels < 1 || prm->K < 1 ||
         prm->cts_levels > (unsigned)(c->logN - 1) || prm->stc_levels > (unsigned)(c->logN - 1) || prm->double_angle > 8 ||
@@ -754,6 +756,7 @@ extern "C" int rbk_boot_constant_levels(const rbk_ctx *c, int *plain_levels, int
 
 extern "C" int rbk_boot_export(rbk_ctx *c, uint64_t *plains, uint64_t *scalars)
 {
+    if (c && c->capturing) return boot_fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !c->boot) return boot_fail(RBK_ESTATE, "bootstrapping not set up");
     BootPlan &P = *c->boot;
     const size_t N = c->N;
@@ -789,6 +792,7 @@ extern "C" int rbk_boot_export(rbk_ctx *c, uint64_t *plains, uint64_t *scalars)
 
 extern "C" int rbk_boot_import(rbk_ctx *c, const uint64_t *plains, const uint64_t *scalars)
 {
+    if (c && c->capturing) return boot_fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !c->boot) return boot_fail(RBK_ESTATE, "bootstrapping not set up");
     BootPlan &P = *c->boot;
     const size_t N = c->N;
@@ -851,8 +855,8 @@ extern "C" int rbk_bootstrap_batch(rbk_ctx *c, const uint64_t *d_in, const doubl
         R.reg_words = P.pool_words;
         R.free_ = P.pool;
     } else {
-        (void)hipStreamSynchronize(c->stream);
-        for (u64 *d : P.pool) (void)hipFree(d);
+        if (c->capturing) return boot_fail(RBK_ESTATE, "bootstrap registers too small during graph capture: run the call once before capturing");
+        for (u64 *d : P.pool) release_buffer(c, d);
         P.pool.clear();
         P.pool_words = R.reg_words;
     }

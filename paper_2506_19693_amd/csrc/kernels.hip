@@ -28,6 +28,10 @@ __global__ void k_ew(const u64 *a, const u64 *b, u64 *out, size_t total, int log
 {
     size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (i >= total) return;
+    if (OP == EW_ZERO) {
+        out[i] = 0;
+        return;
+    }
     int limb = (int)((i >> logN) % nlimbs);
     u64 q = pc[map.prime(limb)].q;
     u64 x = a[i];
@@ -50,6 +54,7 @@ void ew_launch(const rbk_ctx_impl *c, EwOp op, const u64 *a, const u64 *b, u64 *
     case EW_SUB: hipLaunchKernelGGL(k_ew<EW_SUB>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
     case EW_NEG: hipLaunchKernelGGL(k_ew<EW_NEG>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
     case EW_MUL: hipLaunchKernelGGL(k_ew<EW_MUL>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
+    case EW_ZERO: hipLaunchKernelGGL(k_ew<EW_ZERO>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
     default: hipLaunchKernelGGL(k_ew<EW_COPY>, grid, dim3(EW_THREADS), 0, st, a, b, out, total, c->logN, nlimbs, map, c->d_pc); break;
     }
     kt_end(c, KC_ELEMENTWISE, (op == EW_NEG || op == EW_COPY ? 2.0 : 3.0) * total * sizeof(u64), st);

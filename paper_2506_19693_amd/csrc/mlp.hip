@@ -402,6 +402,11 @@ struct rbk_mlp {
     rbk_ctx *c = nullptr;
     Shape sh;
     Pool pool;
+    // every state ciphertext lives in a buffer of its own ("home", sized for
+    // the top level): a step reads the homes and copies its results into them
+    // last, so the same device addresses serve every step (and the replays of
+    // a captured step)
+    std::vector<u64 *> home;
     std::vector<Vec> state;
     std::map<int, u64 *> masks;
     std::vector<int64_t> scalars;
@@ -411,6 +416,7 @@ struct rbk_mlp {
     {
         if (c) (void)hipStreamSynchronize(c->stream);
         state.clear();
+        for (u64 *h : home) (void)hipFree(h);
         for (auto &kv : masks) (void)hipFree(kv.second);
     }
 };
@@ -682,6 +688,7 @@ extern "C" int rbk_mlp_create(rbk_ctx *c, const rbk_mlp_desc *d, rbk_mlp **out)
     m->c = c;
     m->sh = sh;
     m->state.resize(sh.layout.size());
+    m->home.assign(sh.layout.size(), nullptr);
     m->depth = step_depth(sh);
     *out = m;
     return RBK_OK;
@@ -725,16 +732,23 @@ extern "C" int rbk_mlp_set_state(rbk_mlp *m, int idx, const uint64_t *d_ct, int 
     if (idx < 0 || idx >= (int)m->state.size()) return rbk_set_error(RBK_EINVAL, "state index out of range");
     if (level < 0 || level >= m->c->nQ) return rbk_set_error(RBK_ELEVEL, "level out of range");
     if (!(scale > 0.0)) return rbk_set_error(RBK_EINVAL, "scale must be positive");
-    try {
-        GpuOps ops(m);
-        Vec v = ops.alloc(level, 1);
-        hck(hipMemcpyAsync((u64 *)v.d, d_ct, 2 * ops.per(level) * sizeof(u64), hipMemcpyDeviceToDevice, m->c->stream),
-            "copy");
-        v.s = scale;
-        m->state[idx] = v;
-    } catch (const MlpError &e) {
-        return mfail(e);
+    if (m->c->capturing) return rbk_set_error(RBK_ESTATE, "not allowed during graph capture");
+    const size_t N = m->c->N, P = (size_t)(level + 1) * N;
+    u64 *&h = m->home[idx];
+    if (!h && hipMalloc((void **)&h, (size_t)2 * m->c->nQ * N * sizeof(u64)) != hipSuccess) {
+        h = nullptr;
+        return rbk_set_error(RBK_ENOMEM, "state allocation failed");
     }
+    if (hipMemcpyAsync(h, d_ct, 2 * P * sizeof(u64), hipMemcpyDeviceToDevice, m->c->stream) != hipSuccess)
+        return rbk_set_error(RBK_EDEVICE, "copy failed");
+    Vec v;
+    v.d = h;
+    v.lv = level;
+    v.ps = (long)P;
+    v.cs = 2 * v.ps;
+    v.count = 1;
+    v.s = scale;
+    m->state[idx] = v;
     return RBK_OK;
 }
 
@@ -816,7 +830,28 @@ extern "C" int rbk_mlp_train_step(rbk_mlp *m, const uint64_t *d_x, const uint64_
         Step<GpuOps> st{ops, sh};
         std::vector<Vec> next = st.run(m->state, samples, b, t, (flags & RBK_MLP_NO_BOOTSTRAP) == 0);
         samples.clear();
-        m->state = next;
+        // the new state goes into the homes (V homes may be new at t = 1)
+        const size_t N = m->c->N;
+        for (size_t i = 0; i < next.size(); i++) {
+            const Vec &x = next[i];
+            u64 *&h = m->home[i];
+            if (!h) {
+                if (m->c->capturing) mthrow(RBK_ESTATE, "state slot without storage during graph capture");
+                hck(hipMalloc((void **)&h, (size_t)2 * m->c->nQ * N * sizeof(u64)), "state allocation");
+            }
+            const size_t P = (size_t)(x.lv + 1) * N;
+            hck(hipMemcpy2DAsync(h, P * sizeof(u64), x.d, x.ps * sizeof(u64), P * sizeof(u64), 2,
+                                 hipMemcpyDeviceToDevice, m->c->stream),
+                "copy");
+            Vec v;
+            v.d = h;
+            v.lv = x.lv;
+            v.ps = (long)P;
+            v.cs = 2 * v.ps;
+            v.count = 1;
+            v.s = x.s;
+            m->state[i] = v;
+        }
     } catch (const MlpError &e) {
         return mfail(e);
     } catch (const std::bad_alloc &) {

@@ -92,6 +92,12 @@ struct rbk_ctx_impl {
     struct BootPlan *boot = nullptr;   // bootstrapping plan (boot.hip)
 
     bool timing = false;
+    // the stream is being captured into a graph: nothing may grow, free or wait
+    bool capturing = false;
+    // graphs recorded on this context reference its workspaces: while any is
+    // alive, a buffer that is replaced is retired instead of freed
+    int live_graphs = 0;
+    std::vector<void *> retired;
     mutable KTimer timers[KC_COUNT];
     mutable std::vector<hipEvent_t> event_pool;
 };
@@ -105,10 +111,12 @@ void kt_end(const rbk_ctx_impl *c, int cls, double bytes, hipStream_t st);
 
 // ---- helpers implemented in api.hip ----
 u64 *ws_reserve(rbk_ctx_impl *c, size_t words);
+// free a replaced device buffer, or keep it until the last graph is destroyed
+void release_buffer(rbk_ctx_impl *c, void *p);
 const ModUpTables &modup_tables(rbk_ctx_impl *c, int level);
 
 // ---- kernel launchers implemented in kernels.hip ----
-enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_MUL = 3, EW_COPY = 4 };
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_NEG = 2, EW_MUL = 3, EW_COPY = 4, EW_ZERO = 5 };
 
 struct ScalArg {
     u64 w[RBK_MAX_PRIMES];

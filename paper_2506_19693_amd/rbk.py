@@ -174,6 +174,10 @@ SIGNATURES = {
     "rbk_server_drain": (ci, [vp]),
     "rbk_server_stats": (ci, [vp, u64p]),
     "rbk_server_destroy": (ci, [vp]),
+    "rbk_capture_begin": (ci, [vp]),
+    "rbk_capture_end": (ci, [vp, ctypes.POINTER(vp)]),
+    "rbk_graph_launch": (ci, [vp]),
+    "rbk_graph_destroy": (ci, [vp]),
     "rbk_timer_enable": (ci, [vp, ci]),
     "rbk_timer_read": (ci, [vp, ci, dblp, u64p, dblp]),
     "rbk_timer_name": (ctypes.c_char_p, [ci]),
@@ -242,6 +246,7 @@ def to_host(t):
 
 
 _LIVE_SERVERS = weakref.WeakSet()
+_LIVE_GRAPHS = weakref.WeakSet()
 _LIVE_MLPS = weakref.WeakSet()
 _LIVE_CONTEXTS = weakref.WeakSet()
 
@@ -251,6 +256,8 @@ def _close_all():
     """Release library objects while the HIP runtime is still up (objects that
     survive until interpreter teardown would otherwise be freed after it)."""
     for v in list(_LIVE_SERVERS):
+        v.close()
+    for v in list(_LIVE_GRAPHS):
         v.close()
     for m in list(_LIVE_MLPS):
         m.close()
@@ -570,6 +577,29 @@ class Context:
         _check(self.lib.rbk_bootstrap(self.h, _ptr(ct), float(scale), _ptr(out), ctypes.byref(so)))
         return out, so.value
 
+    # ---------------------------------------------------------------- graph capture
+    def capture(self, fn):
+        """Capture the library work of fn() into a Graph.  fn must have run
+        once eagerly before (buffers sized); it runs on a side stream while
+        capturing, and nothing executes until the graph is launched."""
+        torch = _torch()
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        self.set_stream(side)
+        h = vp()
+        try:
+            _check(self.lib.rbk_capture_begin(self.h))
+            try:
+                fn()
+            except BaseException:
+                if self.lib.rbk_capture_end(self.h, ctypes.byref(h)) == 0 and h:
+                    self.lib.rbk_graph_destroy(h)
+                raise
+            _check(self.lib.rbk_capture_end(self.h, ctypes.byref(h)))
+        finally:
+            self.set_stream(torch.cuda.current_stream())
+        return Graph(self, h, side)
+
     # ---------------------------------------------------------------- timers
     def timer_enable(self, on=True):
         _check(self.lib.rbk_timer_enable(self.h, 1 if on else 0))
@@ -609,6 +639,32 @@ class Context:
         out = self.empty(count, len(ks), 2, level + 1, self.N) if out is None else out
         _check(self.lib.rbk_rotate_hoisted_batch(self.h, _ptr(ct), pk, len(ks), _ptr(out), level, count))
         return out
+
+
+class Graph:
+    """A captured sequence of library calls (rbk_capture_*); launch() replays
+    it on the context's current stream."""
+
+    def __init__(self, ctx, h, side):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.h = h
+        self._side = side
+        _LIVE_GRAPHS.add(self)
+
+    def launch(self):
+        _check(self.lib.rbk_graph_launch(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbk_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Mlp:
