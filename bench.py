@@ -155,6 +155,18 @@ def bench_bootstrap(args, torch):
     ctx.sync()
     t_b = (time.perf_counter() - t0) / args.steps
     err = max(float(np.max(np.abs(ctx.decode(ctx.decrypt(out[i], lo), lo, so[i]).real - zs[i]))) for i in range(count))
+    # the same batch captured once into a HIP graph and replayed
+    out_g = ctx.empty_ct(lo, count)
+    graph = ctx.capture(lambda: ctx.bootstrap_batch(cts, scales, out=out_g))
+    graph.launch()
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.launch()
+    ctx.sync()
+    t_g = (time.perf_counter() - t0) / args.steps
+    graph_equal = bool(torch.equal(out_g, out))
+    graph.close()
     lat = []
     t0 = time.perf_counter()
     for i in range(count):
@@ -172,6 +184,8 @@ def bench_bootstrap(args, torch):
                     "9 special primes",
         "bootstraps_per_s_batched": count / t_b,
         "bootstraps_per_s_plain": count / t_p,
+        "bootstraps_per_s_graph": count / t_g,
+        "graph_equals_eager": graph_equal,
         "batched_vs_plain": t_p / t_b,
         "ms_per_batch": t_b * 1e3,
         "plain_latency_ms_p50": percentile(lat, 50),
@@ -282,6 +296,16 @@ def bench_train_step(args, torch):
         run()
     ctx.sync()
     t_b = (time.perf_counter() - t0) / args.steps
+    # one step captured into a HIP graph; each replay runs the next step
+    graph = ctx.capture(lambda: mlp.train_step(x, ye, yr, lo, T, 2))
+    graph.launch()
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.launch()
+    ctx.sync()
+    t_g = (time.perf_counter() - t0) / args.steps
+    graph.close()
     t0 = time.perf_counter()
     run(per_sample=True)
     ctx.sync()
@@ -298,6 +322,7 @@ def bench_train_step(args, torch):
                     "10 special primes, HW-192 secret, bootstrap of all 14 W/V ciphertexts per step",
         "train_steps_per_s_batched": 1.0 / t_b,
         "train_steps_per_s_plain": 1.0 / t_p,
+        "train_steps_per_s_graph": 1.0 / t_g,
         "batched_vs_plain": t_p / t_b,
         "ms_per_step_batched": t_b * 1e3,
         "ms_per_step_plain": t_p * 1e3,
@@ -729,18 +754,18 @@ def main():
     if not args.no_boot:
         log("bootstrap: 16 ciphertexts, N=2^16 ...")
         boot = bench_bootstrap(args, torch)
-        log("bootstrap: %.2f/s batched, %.2f/s plain, p99 %.1f ms, max error 2^%.2f" % (
-            boot["bootstraps_per_s_batched"], boot["bootstraps_per_s_plain"], boot["plain_latency_ms_p99"],
-            boot["max_slot_error_log2"]))
+        log("bootstrap: %.2f/s batched, %.2f/s graph, %.2f/s plain, p99 %.1f ms, max error 2^%.2f" % (
+            boot["bootstraps_per_s_batched"], boot["bootstraps_per_s_graph"], boot["bootstraps_per_s_plain"],
+            boot["plain_latency_ms_p99"], boot["max_slot_error_log2"]))
 
     mlp = None
     if not args.no_mlp:
         torch.cuda.empty_cache()
         log("train_step: 784-128-128, 64 samples, N=2^16 ...")
         mlp = bench_train_step(args, torch)
-        log("train_step: %.3f steps/s batched (%.0f ms), %.3f plain, bootstrap share %.2f" % (
-            mlp["train_steps_per_s_batched"], mlp["ms_per_step_batched"], mlp["train_steps_per_s_plain"],
-            mlp["bootstrap_share_of_step"]))
+        log("train_step: %.3f steps/s batched (%.0f ms), %.3f graph, %.3f plain, bootstrap share %.2f" % (
+            mlp["train_steps_per_s_batched"], mlp["ms_per_step_batched"], mlp["train_steps_per_s_graph"],
+            mlp["train_steps_per_s_plain"], mlp["bootstrap_share_of_step"]))
 
     serve = None
     if not args.no_serve:
