@@ -650,6 +650,9 @@ def main():
     s, A, B = setup(ctx, count, ks)
     L = ctx.L
     ctx.reserve(L, count)
+    tuned = ctx.autotune(L - 1, count, os.path.join(os.path.expanduser("~"), ".cache", "rbk_tune.txt")
+                         if os.path.isdir(os.path.join(os.path.expanduser("~"), ".cache")) else None)
+    log("autotuned: NTT split 2^%d columns, %d ciphertexts per inner-product thread" % (tuned["logC"], tuned["cpc"]))
     out_m = ctx.empty_ct(L, count)
     out_r = ctx.empty_ct(L - 1, count)
     out_h = ctx.empty(count, len(ks), 2, L, ctx.N)
@@ -802,6 +805,7 @@ def main():
                         "N=2^16, 24 primes (60 + 23x50 bits), 8 special 60-bit primes, dnum=3" % (count, len(ks)),
             "key_switches_per_step": ks_per_step,
             "path": "batched",
+            "autotuned": tuned,
         },
         "plain": plain,
         "batched_vs_plain": round(plain["ms_per_step"] / (t_batched * 1e3), 3) if plain else None,

@@ -423,6 +423,21 @@ int rbk_server_stats(rbk_server *srv, uint64_t *stats);
  * back, free the server. */
 int rbk_server_destroy(rbk_server *srv);
 
+/* ---- autotuner -------------------------------------------------------------- */
+
+/* Launch parameters that change speed but never a residue:
+ *   cfg[0] = logC, the NTT split (a limb is a 2^(logN-logC) x 2^logC matrix;
+ *            for 13 <= logN <= 16 both sides must be 2^6 .. 2^8);
+ *   cfg[1] = ciphertexts per thread of the fused key inner products (1..64).
+ * rbk_autotune times every candidate on the batched key-switching shape
+ * (level, count) with HIP events on the context stream and keeps the
+ * fastest.  With cache_path (a text file) it first looks up the GPU
+ * architecture and shape there and appends what it measured.  cfg (may be
+ * NULL) receives the configuration in force. */
+int rbk_autotune(rbk_ctx *ctx, int level, int count, const char *cache_path, int *cfg);
+int rbk_tune_get(const rbk_ctx *ctx, int *cfg);
+int rbk_tune_set(rbk_ctx *ctx, const int *cfg);
+
 /* ---- graph capture ---------------------------------------------------------- */
 
 /* Record the device work of a sequence of calls on the context's stream into

@@ -387,7 +387,6 @@ void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, c
 
 // ciphertexts handled by one thread of the fused inner-product kernels: the
 // key words are loaded once per thread, the grid's z dimension covers the rest
-#define IP_CTS_PER_THREAD 8
 
 // Two adjacent NTT-domain coefficients (o, o+1), o even, are the values at
 // psi^(2k+1) and psi^(2k+1+N) (bit reversal); an automorphism maps them to the
@@ -522,7 +521,7 @@ void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u
     int L1 = level + 1, E = L1 + c->nP;
     int beta_l = (L1 + c->alpha - 1) / c->alpha;
     if (c->nP == 0) return;
-    const int cpc = IP_CTS_PER_THREAD;
+    const int cpc = c->ip_cpc;
     dim3 grid((unsigned)((c->N / 2 + EW_THREADS - 1) / EW_THREADS), c->nP, (count + cpc - 1) / cpc);
     kt_begin(c, KC_IP_P, st);
 #define IPP_CASE(B)                                                                                          \
@@ -542,7 +541,7 @@ void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, c
 {
     int L1 = level + 1, E = L1 + c->nP;
     int beta_l = (L1 + c->alpha - 1) / c->alpha;
-    const int cpc = IP_CTS_PER_THREAD;
+    const int cpc = c->ip_cpc;
     dim3 grid((unsigned)((c->N / 2 + EW_THREADS - 1) / EW_THREADS), L1, (count + cpc - 1) / cpc);
     kt_begin(c, KC_MODDOWN_IP, st);
 #define MDI_CASE(B)                                                                                           \

@@ -52,7 +52,8 @@ struct rbk_ctx_impl {
     int logN = 0;
     size_t N = 0;
     int nQ = 0, nP = 0, nT = 0, alpha = 1, beta = 1;
-    int ntt_logC = 0;
+    int ntt_logC = 0;   // NTT split: a limb is a 2^(logN - ntt_logC) x 2^ntt_logC matrix
+    int ip_cpc = 8;     // ciphertexts per thread of the fused key inner products
     std::vector<u64> mod, psi;
     std::vector<PrimeC> h_pc;
 

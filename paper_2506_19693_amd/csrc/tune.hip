@@ -1,0 +1,192 @@
+// Autotuner of the batched key-switching path.
+//
+// Two launch parameters leave every residue unchanged but move the speed:
+//  * the NTT split: a limb of N = 2^logN residues is transformed as an
+//    R x C matrix, C = 2^logC (column pass, then row pass); the register
+//    kernels support R, C in 2^6 .. 2^8;
+//  * the ciphertexts per thread of the fused key inner products (ip_p and
+//    moddown_ip): more share each key word among more ciphertexts, fewer
+//    give more workgroups.
+// rbk_autotune times each candidate on the shape it is asked about (level,
+// batch) with HIP events on the context stream, keeps the fastest, and
+// records the choice in a text cache keyed by the GPU architecture and the
+// shape, so later processes read it instead of measuring again.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/rbk.h"
+#include "rbk_ctx.hpp"
+
+namespace {
+
+std::string tune_key(const rbk_ctx *c, int level, int count)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "gfx";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    std::ostringstream os;
+    os << arch << " logN=" << c->logN << " nQ=" << c->nQ << " nP=" << c->nP << " alpha=" << c->alpha
+       << " level=" << level << " count=" << count;
+    return os.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, int &logC, int &cpc)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const size_t bar = line.find(" : ");
+        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        int a = 0, b = 0;
+        if (std::sscanf(line.c_str() + bar + 3, "logC=%d cpc=%d", &a, &b) == 2) {
+            logC = a;
+            cpc = b;
+            found = true;  // the last entry of a key wins
+        }
+    }
+    return found;
+}
+
+// mean ms of `reps` runs of fn after one warm-up run
+template <class F>
+double time_ms(rbk_ctx *c, F fn, int reps)
+{
+    fn();
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1;
+    }
+    (void)hipEventRecord(e0, c->stream);
+    for (int i = 0; i < reps; i++) fn();
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = -1;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+
+bool split_ok(int logN, int logC)
+{
+    const int r = logN - logC;
+    return logN >= 13 && logN <= 16 && r >= 6 && r <= 8 && logC >= 6 && logC <= 8;
+}
+
+}  // namespace
+
+extern "C" int rbk_tune_get(const rbk_ctx *c, int *cfg)
+{
+    if (!c || !cfg) return rbk_set_error(RBK_EINVAL, "null argument");
+    cfg[0] = c->ntt_logC;
+    cfg[1] = c->ip_cpc;
+    return RBK_OK;
+}
+
+extern "C" int rbk_tune_set(rbk_ctx *c, const int *cfg)
+{
+    if (!c || !cfg) return rbk_set_error(RBK_EINVAL, "null argument");
+    if (c->capturing) return rbk_set_error(RBK_ESTATE, "not allowed during graph capture");
+    if (cfg[0] != c->ntt_logC && !split_ok(c->logN, cfg[0]))
+        return rbk_set_error(RBK_EINVAL, "NTT split not supported for this ring degree");
+    if (cfg[1] < 1 || cfg[1] > 64) return rbk_set_error(RBK_EINVAL, "ciphertexts per thread out of 1..64");
+    c->ntt_logC = cfg[0];
+    c->ip_cpc = cfg[1];
+    return RBK_OK;
+}
+
+extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_path, int *cfg)
+{
+    if (!c || count < 1) return rbk_set_error(RBK_EINVAL, "bad argument");
+    if (c->capturing) return rbk_set_error(RBK_ESTATE, "not allowed during graph capture");
+    if (level < 0 || level >= c->nQ) return rbk_set_error(RBK_ELEVEL, "level out of range");
+    const std::string key = tune_key(c, level, count);
+    int logC = c->ntt_logC, cpc = c->ip_cpc;
+    if (!cache_lookup(cache_path, key, logC, cpc)) {
+        const size_t N = c->N, L1 = level + 1, E = L1 + c->nP, beta = (L1 + c->alpha - 1) / c->alpha;
+        // scratch: the NTT batch (count x 2 polynomials) or the key-switch buffers
+        const size_t ntt_words = (size_t)count * 2 * L1 * N;
+        const size_t ext_words = (size_t)count * beta * E * N, conv_words = (size_t)count * 2 * L1 * N;
+        const size_t tp_words = (size_t)count * 2 * c->nP * N, out_words = (size_t)count * 2 * L1 * N;
+        u64 *ws = ws_reserve(c, std::max(ntt_words, ext_words + conv_words + tp_words + out_words));
+        if (!ws) return RBK_ENOMEM;
+        const LimbMap qm{0, c->nQ, c->nQ};
+        ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)(ntt_words / N), 1, qm, c->stream);
+        // NTT split
+        double best = 1e30;
+        int best_logC = logC;
+        for (int cand = 6; cand <= 8; cand++) {
+            if (!split_ok(c->logN, cand)) continue;
+            c->ntt_logC = cand;
+            double ms = time_ms(c, [&] {
+                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, false, c->stream);
+                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, true, c->stream);
+            }, 3);
+            if (ms >= 0 && ms < best) {
+                best = ms;
+                best_logC = cand;
+            }
+        }
+        c->ntt_logC = best_logC;
+        logC = best_logC;
+        // ciphertexts per thread of the fused inner products (needs a key)
+        const DevKey *key_d = c->relin.data ? &c->relin : nullptr;
+        if (!key_d)
+            for (auto &kv : c->gal)
+                if (kv.second.data) {
+                    key_d = &kv.second;
+                    break;
+                }
+        if (key_d && c->nP > 0) {
+            u64 *ext = ws, *conv = ext + ext_words, *tp = conv + conv_words, *out = tp + tp_words;
+            ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)((ext_words + conv_words + tp_words + out_words) / N), 1, qm,
+                      c->stream);
+            const u64 g = key_d->g ? key_d->g : 0;
+            best = 1e30;
+            int best_cpc = cpc;
+            for (int cand : {2, 4, 8, 16}) {
+                c->ip_cpc = cand;
+                double ms = time_ms(c, [&] {
+                    ip_p_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);
+                    moddown_ip_launch(c, ext, (long)(beta * E * N), key_d->data, conv, (long)(2 * L1 * N), nullptr, 0, 0,
+                                      0, out, (long)(2 * L1 * N), level, count, g, c->stream);
+                }, 3);
+                if (ms >= 0 && ms < best) {
+                    best = ms;
+                    best_cpc = cand;
+                }
+            }
+            c->ip_cpc = best_cpc;
+            cpc = best_cpc;
+        }
+        if (hipGetLastError() != hipSuccess) return rbk_set_error(RBK_EDEVICE, "autotune launch failed");
+        if (cache_path) {
+            std::ofstream f(cache_path, std::ios::app);
+            if (f) f << key << " : logC=" << logC << " cpc=" << cpc << "\n";
+        }
+    } else {
+        int cfgv[2] = {logC, cpc};
+        int rc = rbk_tune_set(c, cfgv);
+        if (rc) return rc;
+    }
+    if (cfg) {
+        cfg[0] = c->ntt_logC;
+        cfg[1] = c->ip_cpc;
+    }
+    return RBK_OK;
+}

@@ -174,6 +174,9 @@ SIGNATURES = {
     "rbk_server_drain": (ci, [vp]),
     "rbk_server_stats": (ci, [vp, u64p]),
     "rbk_server_destroy": (ci, [vp]),
+    "rbk_autotune": (ci, [vp, ci, ci, ctypes.c_char_p, ctypes.POINTER(ci)]),
+    "rbk_tune_get": (ci, [vp, ctypes.POINTER(ci)]),
+    "rbk_tune_set": (ci, [vp, ctypes.POINTER(ci)]),
     "rbk_capture_begin": (ci, [vp]),
     "rbk_capture_end": (ci, [vp, ctypes.POINTER(vp)]),
     "rbk_graph_launch": (ci, [vp]),
@@ -576,6 +579,23 @@ class Context:
         so = ctypes.c_double()
         _check(self.lib.rbk_bootstrap(self.h, _ptr(ct), float(scale), _ptr(out), ctypes.byref(so)))
         return out, so.value
+
+    # ---------------------------------------------------------------- autotuner
+    def autotune(self, level, count, cache_path=None):
+        """Time the NTT split and the inner-product chunk on (level, count);
+        returns {"logC": .., "cpc": ..} now in force."""
+        cfg = (ci * 2)()
+        path = cache_path.encode() if cache_path else None
+        _check(self.lib.rbk_autotune(self.h, level, count, path, cfg))
+        return {"logC": cfg[0], "cpc": cfg[1]}
+
+    def tune_get(self):
+        cfg = (ci * 2)()
+        _check(self.lib.rbk_tune_get(self.h, cfg))
+        return {"logC": cfg[0], "cpc": cfg[1]}
+
+    def tune_set(self, logC, cpc):
+        _check(self.lib.rbk_tune_set(self.h, (ci * 2)(logC, cpc)))
 
     # ---------------------------------------------------------------- graph capture
     def capture(self, fn):

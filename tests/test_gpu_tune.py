@@ -1,0 +1,61 @@
+"""The autotuner: it picks a supported configuration, records it in its cache
+and reads it back instead of measuring again; and every configuration it can
+choose (NTT split x inner-product chunk) gives the same residues for
+batched mult_relin, rescale and hoisted rotations."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(log_n):
+    from paper_2506_19693_amd import Context
+
+    d = Context(log_n, [60] + [50] * 7, [60] * 3, 3)
+    g = S.rng(51, log_n)
+    N = d.N
+    d.set_secret(S.ternary(g, N))
+    d.keygen_relin(*S.key_randomness(g, d.beta, d.moduli, N))
+    for k in (1, 5, -3):
+        d.keygen_galois(d.galois_elt(k), *S.key_randomness(g, d.beta, d.moduli, N))
+    return d, g
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    path = str(tmp_path / "tune.txt")
+    d, _ = _ctx(14)
+    cfg = d.autotune(7, 8, path)
+    assert cfg["logC"] in (6, 7, 8) and cfg["cpc"] in (2, 4, 8, 16)
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].endswith("logC=%d cpc=%d" % (cfg["logC"], cfg["cpc"]))
+    d2, _ = _ctx(14)
+    assert d2.autotune(7, 8, path) == cfg
+    assert len(open(path).read().splitlines()) == 1          # read, not measured again
+    assert d2.tune_get() == cfg
+
+
+@pytest.mark.parametrize("log_n", [13, 14, 15])
+def test_every_configuration_gives_the_same_residues(log_n):
+    from paper_2506_19693_amd import RbkError
+
+    d, g = _ctx(log_n)
+    L = d.L
+    A = d.to_ntt(S.uniform_residues(g, d.moduli[: L + 1], d.N, lead=(5, 2)), L)
+    B = d.to_ntt(S.uniform_residues(g, d.moduli[: L + 1], d.N, lead=(5, 2)), L)
+    splits = [c for c in (6, 7, 8) if 6 <= log_n - c <= 8]
+    ref = None
+    for logC, cpc in itertools.product(splits, (1, 3, 8, 16)):
+        d.tune_set(logC, cpc)
+        m = d.rescale_batch(d.mult_relin_batch(A, B, L), L)
+        h = d.rotate_hoisted_batch(m, [1, 5, -3], L - 1)
+        got = (d.to_coef(m, L - 1), d.to_coef(h, L - 1))
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (logC, cpc)
+    with pytest.raises(RbkError):
+        d.tune_set(log_n - 9, 8)                              # unsupported split
