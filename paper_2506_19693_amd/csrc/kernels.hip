@@ -247,7 +247,9 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
             if (i < n_in) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
-        dst[(size_t)pos * N + k] = redc_any(acc, p.q, p.qneg, p.one_sh);
+        // n_in <= 16 terms, each y (< 2^60) times a table entry (< p): the sum
+        // stays below p 2^64, so a plain REDC reduces it
+        dst[(size_t)pos * N + k] = redc(acc, p.q, p.qneg);
     }
 }
 
@@ -324,8 +326,8 @@ __global__ __launch_bounds__(EW_THREADS) void k_ip(const u64 *ext, long ext_stri
                 acc_wide(s1, mul_wide(d, ka[j]));
             }
         u64 *o = u + ct * u_stride + (size_t)e * N + k;
-        o[0] = redc_any(s0, p.q, p.qneg, p.one_sh);
-        o[(size_t)E * N] = redc_any(s1, p.q, p.qneg, p.one_sh);
+        o[0] = redc(s0, p.q, p.qneg);  // beta <= 8 products below p^2: the sum is below p 2^64
+        o[(size_t)E * N] = redc(s1, p.q, p.qneg);
     }
 }
 
@@ -419,7 +421,8 @@ __device__ __forceinline__ u64x2 ld2_perm(const u64 *base, size_t src)
 // Inner product restricted to the special-prime positions, written to
 // tp[count][2][nP][N] (the input of the ModDown inverse NTT).
 template <int BETA>
-__global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int logN,
+__global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *__restrict__ ext, long ext_stride,
+                                                     const u64 *__restrict__ key, u64 *__restrict__ tp, int logN,
                                                      int L1, int E, int nT, int nQ, int nP, int count, int cpc, u64 g,
                                                      const PrimeC *pc)
 {
@@ -437,6 +440,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *ext, long ext_st
             ka[j] = ld2(key + (((size_t)j * 2 + 1) * nT + pr) * N + k);
         }
     const size_t src = g ? auto_src((u32)k, g, logN) : k;
+#pragma unroll 2
     for (int ct = ct0; ct < ct1; ct++) {
         const u64 *x = ext + ct * ext_stride + (size_t)pos * N;
         u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
@@ -449,8 +453,9 @@ __global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *ext, long ext_st
                 acc_wide(t1, mul_wide(d.y, ka[j].y));
             }
         u64 *o = tp + ((size_t)ct * 2 * nP + t) * N + k;
-        st2(o, redc_any(s0, p.q, p.qneg, p.one_sh), redc_any(t0, p.q, p.qneg, p.one_sh));
-        st2(o + (size_t)nP * N, redc_any(s1, p.q, p.qneg, p.one_sh), redc_any(t1, p.q, p.qneg, p.one_sh));
+        // beta <= 8 products below p^2: every sum is below p 2^64, a plain REDC suffices
+        st2(o, redc(s0, p.q, p.qneg), redc(t0, p.q, p.qneg));
+        st2(o + (size_t)nP * N, redc(s1, p.q, p.qneg), redc(t1, p.q, p.qneg));
     }
 }
 
@@ -459,9 +464,11 @@ __global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *ext, long ext_st
 // add (through sigma_{add_g} when add_g != 0) goes to poly 0, and to poly 1
 // when add_both != 0.
 template <int BETA>
-__global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
-                                                           long conv_stride, const u64 *add, long add_stride, u64 add_g,
-                                                           int add_both, u64 *out, long out_stride, int logN, int L1, int E,
+__global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *__restrict__ ext, long ext_stride,
+                                                           const u64 *__restrict__ key, const u64 *__restrict__ conv,
+                                                           long conv_stride, const u64 *__restrict__ add, long add_stride,
+                                                           u64 add_g, int add_both, u64 *__restrict__ out,
+                                                           long out_stride, int logN, int L1, int E,
                                                            int nT, int count, int cpc, u64 g, const u64 *Pinv,
                                                            const u64 *Pinv_sh, const PrimeC *pc)
 {
@@ -481,6 +488,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *ext, long 
     const size_t src = g ? auto_src((u32)k, g, logN) : k;
     const size_t asrc = add_g ? auto_src((u32)k, add_g, logN) : k;
     const size_t per = (size_t)L1 * N, li = (size_t)i * N;
+#pragma unroll 2
     for (int ct = ct0; ct < ct1; ct++) {
         const u64 *x = ext + ct * ext_stride + li;
         u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
@@ -494,10 +502,11 @@ __global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *ext, long 
             }
         const u64 *cv = conv + ct * conv_stride + li + k;
         u64x2 c0 = ld2(cv), c1 = ld2(cv + per);
-        u64 v0 = shoup(sub_mod(redc_any(s0, p.q, p.qneg, p.one_sh), c0.x, p.q), pinv, pinv_sh, p.q);
-        u64 w0 = shoup(sub_mod(redc_any(t0, p.q, p.qneg, p.one_sh), c0.y, p.q), pinv, pinv_sh, p.q);
-        u64 v1 = shoup(sub_mod(redc_any(s1, p.q, p.qneg, p.one_sh), c1.x, p.q), pinv, pinv_sh, p.q);
-        u64 w1 = shoup(sub_mod(redc_any(t1, p.q, p.qneg, p.one_sh), c1.y, p.q), pinv, pinv_sh, p.q);
+        // beta <= 8 products below q^2: every sum is below q 2^64, a plain REDC suffices
+        u64 v0 = shoup(sub_mod(redc(s0, p.q, p.qneg), c0.x, p.q), pinv, pinv_sh, p.q);
+        u64 w0 = shoup(sub_mod(redc(t0, p.q, p.qneg), c0.y, p.q), pinv, pinv_sh, p.q);
+        u64 v1 = shoup(sub_mod(redc(s1, p.q, p.qneg), c1.x, p.q), pinv, pinv_sh, p.q);
+        u64 w1 = shoup(sub_mod(redc(t1, p.q, p.qneg), c1.y, p.q), pinv, pinv_sh, p.q);
         if (add) {
             const u64 *ad = add + ct * add_stride + li;
             u64x2 a0 = ld2_perm(ad, asrc);

@@ -145,13 +145,14 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         c->ntt_logC = best_logC;
         logC = best_logC;
         // ciphertexts per thread of the fused inner products (needs a key)
-        const DevKey *key_d = c->relin.data ? &c->relin : nullptr;
-        if (!key_d)
-            for (auto &kv : c->gal)
-                if (kv.second.data) {
-                    key_d = &kv.second;
-                    break;
-                }
+        // a Galois key when there is one (rotations read the digits through the automorphism)
+        const DevKey *key_d = nullptr;
+        for (auto &kv : c->gal)
+            if (kv.second.data) {
+                key_d = &kv.second;
+                break;
+            }
+        if (!key_d && c->relin.data) key_d = &c->relin;
         if (key_d && c->nP > 0) {
             u64 *ext = ws, *conv = ext + ext_words, *tp = conv + conv_words, *out = tp + tp_words;
             ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)((ext_words + conv_words + tp_words + out_words) / N), 1, qm,
@@ -159,7 +160,7 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
             const u64 g = key_d->g ? key_d->g : 0;
             best = 1e30;
             int best_cpc = cpc;
-            for (int cand : {2, 4, 8, 16}) {
+            for (int cand : {4, 8, 16}) {
                 c->ip_cpc = cand;
                 double ms = time_ms(c, [&] {
                     ip_p_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);

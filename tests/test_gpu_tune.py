@@ -29,7 +29,7 @@ def test_autotune_cache_roundtrip(tmp_path):
     path = str(tmp_path / "tune.txt")
     d, _ = _ctx(14)
     cfg = d.autotune(7, 8, path)
-    assert cfg["logC"] in (6, 7, 8) and cfg["cpc"] in (2, 4, 8, 16)
+    assert cfg["logC"] in (6, 7, 8) and cfg["cpc"] in (4, 8, 16)
     lines = open(path).read().splitlines()
     assert len(lines) == 1 and lines[0].endswith("logC=%d cpc=%d" % (cfg["logC"], cfg["cpc"]))
     d2, _ = _ctx(14)
