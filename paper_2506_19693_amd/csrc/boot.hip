@@ -535,22 +535,27 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
     for (auto &e : L.ents)
         if (std::find(gs.begin(), gs.end(), e.g) == gs.end()) gs.push_back(e.g);
     for (int g : gs) {
+        // the giant step's diagonal products, up to MAC_MAX_TERMS per pass
+        MacTerms T{};
         bool first = true;
         for (auto &e : L.ents) {
             if (e.g != g) continue;
-            const u64 *src;
-            long stride;
             if (e.b == 0) {
-                src = x.d;
-                stride = (long)ctw;
+                T.src[T.n] = x.d;
+                T.stride[T.n] = (long)ctw;
             } else {
                 int bi = (int)(std::find(babies.begin(), babies.end(), e.b) - babies.begin());
-                src = rots + (size_t)bi * ctw;
-                stride = (long)(nb * ctw);
+                T.src[T.n] = rots + (size_t)bi * ctw;
+                T.stride[T.n] = (long)(nb * ctw);
             }
-            mac_plain_launch(c, inner, src, stride, P.d_plain[e.plain], lvl, n_ct, first ? 1 : 0, c->stream);
-            first = false;
+            T.pt[T.n] = P.d_plain[e.plain];
+            if (++T.n == MAC_MAX_TERMS) {
+                mac_multi_launch(c, T, inner, lvl, n_ct, first ? 0 : 1, c->stream);
+                first = false;
+                T.n = 0;
+            }
         }
+        if (T.n) mac_multi_launch(c, T, inner, lvl, n_ct, first ? 0 : 1, c->stream);
         u64 *term = inner;
         if (g) {
             rc = rotate(inner, irot, lvl, n_ct, (int64_t)g * L.n1 * L.h0);

@@ -707,6 +707,45 @@ void mac_plain_launch(const rbk_ctx_impl *c, u64 *acc, const u64 *ct, long ct_st
     kt_end(c, KC_ELEMENTWISE, (first ? 2.0 : 3.0) * total * sizeof(u64) + (double)(level + 1) * c->N * sizeof(u64), st);
 }
 
+// out = sum_t src_t (.) pt_t (+ out when add): a BSGS giant step's diagonal
+// products in one pass.  Each thread keeps its plaintext residues in
+// registers and walks the ciphertexts of the batch; every product is below
+// q^2 and at most MAC_MAX_TERMS of them stay below q 2^64, so one REDC (and
+// one more to undo its 2^-64) ends the lazy 128-bit sum.
+__global__ __launch_bounds__(EW_THREADS) void k_mac_multi(MacTerms T, u64 *out, int logN, int L1, int count, int add,
+                                                          const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t n = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (n >= N) return;
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    const PrimeC p = pc[limb];
+    const size_t per = (size_t)L1 * N, off = (size_t)poly * per + ((size_t)limb << logN) + n;
+    u64 w[MAC_MAX_TERMS];
+#pragma unroll
+    for (int t = 0; t < MAC_MAX_TERMS; t++)
+        if (t < T.n) w[t] = T.pt[t][((size_t)limb << logN) + n];
+    for (int c = 0; c < count; c++) {
+        u128w acc = {0, 0};
+#pragma unroll
+        for (int t = 0; t < MAC_MAX_TERMS; t++)
+            if (t < T.n) acc_wide(acc, mul_wide(T.src[t][(size_t)c * T.stride[t] + off], w[t]));
+        const u64 r = redc(mul_wide(redc(acc, p.q, p.qneg), p.r2), p.q, p.qneg);
+        u64 *o = out + (size_t)c * 2 * per + off;
+        *o = add ? add_mod(*o, r, p.q) : r;
+    }
+}
+
+void mac_multi_launch(const rbk_ctx_impl *c, const MacTerms &T, u64 *out, int level, int count, int add, hipStream_t st)
+{
+    if (T.n <= 0) return;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), level + 1, 2);
+    kt_begin(c, KC_ELEMENTWISE, st);
+    hipLaunchKernelGGL(k_mac_multi, grid, dim3(EW_THREADS), 0, st, T, out, c->logN, level + 1, count, add, c->d_pc);
+    const double ct = 2.0 * (level + 1) * c->N * sizeof(u64);
+    kt_end(c, KC_ELEMENTWISE, ct * count * (T.n + (add ? 2 : 1)) + ct / 2 * T.n, st);
+}
+
 // ct + constant for count ciphertexts (the constant goes to every NTT point of c0)
 __global__ void k_add_scalar_batch(const u64 *a, u64 *out, size_t per, int logN, int count, const PrimeC *pc, ScalArg s)
 {
