@@ -67,6 +67,9 @@ struct BootPlan {
     size_t pool_words = 0;
     u64 *rot_area = nullptr;  // hoisted baby rotations of a transform
     size_t rot_words = 0;
+    // the scalars with Shoup quotients, [n_scalars][nQ][2], uploaded when they change
+    u64 *d_scal = nullptr;
+    bool scal_dirty = true;
 };
 
 // ---------------------------------------------------------------- host arithmetic
@@ -368,6 +371,7 @@ void boot_free(rbk_ctx_impl *ci)
     for (u64 *d : P->d_plain) release_buffer(ci, d);
     for (u64 *d : P->pool) release_buffer(ci, d);
     release_buffer(ci, P->rot_area);
+    release_buffer(ci, P->d_scal);
     delete P;
     ci->boot = nullptr;
 }
@@ -441,6 +445,68 @@ struct Reg {
     int level = 0;
 };
 
+// out = (2 x if x) + sum_t (+-) s_t v_t + (constant on c0): the elementwise part
+// of an EvalMod step in one pass.  Terms are views (ciphertext c, polynomial
+// p of term t at v[t] + c vcs[t] + p vps[t]), read at the output level, so a
+// power kept at a higher level needs no dropped copy.  A scalar index of -1
+// is the coefficient 1.
+constexpr int COMB_MAX = 8;
+struct CombArgs {
+    const u64 *x;
+    const u64 *v[COMB_MAX];
+    long vcs[COMB_MAX], vps[COMB_MAX];
+    int vs[COMB_MAX], vneg[COMB_MAX];
+    int n;
+    int cidx;
+};
+
+__global__ __launch_bounds__(256) void k_boot_comb(CombArgs A, u64 *out, const u64 *scal, int nQ, int logN, int L1,
+                                                    const PrimeC *pc)
+{
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ((size_t)1 << logN)) return;
+    const int limb = blockIdx.y;
+    const unsigned ct = blockIdx.z >> 1, poly = blockIdx.z & 1;
+    const u64 q = pc[limb].q;
+    const size_t per = (size_t)L1 << logN;
+    const size_t o = (size_t)ct * 2 * per + poly * per + ((size_t)limb << logN) + n;
+    u64 r = 0;
+    if (A.x) r = add_mod(A.x[o], A.x[o], q);
+#pragma unroll
+    for (int t = 0; t < COMB_MAX; t++) {
+        if (t >= A.n) break;
+        u64 v = A.v[t][(size_t)ct * A.vcs[t] + poly * A.vps[t] + ((size_t)limb << logN) + n];
+        if (A.vs[t] >= 0) {
+            const u64 *w = scal + ((size_t)A.vs[t] * nQ + limb) * 2;
+            v = shoup(v, w[0], w[1], q);
+        }
+        r = A.vneg[t] ? sub_mod(r, v, q) : add_mod(r, v, q);
+    }
+    if (poly == 0 && A.cidx >= 0) r = add_mod(r, scal[((size_t)A.cidx * nQ + limb) * 2], q);
+    out[o] = r;
+}
+
+static int upload_scalars(rbk_ctx *c, BootPlan &P)
+{
+    if (!P.scal_dirty && P.d_scal) return RBK_OK;
+    if (c->capturing) return rbk_set_error(RBK_ESTATE, "bootstrap scalars changed during graph capture");
+    const size_t nQ = c->nQ, n = std::max<size_t>(P.scalars.size(), 1);
+    std::vector<u64> h(n * nQ * 2, 0);
+    for (size_t i = 0; i < P.scalars.size(); i++)
+        for (size_t k = 0; k < P.scalars[i].size() && k < nQ; k++) {
+            h[(i * nQ + k) * 2] = P.scalars[i][k];
+            h[(i * nQ + k) * 2 + 1] = b_shoup(P.scalars[i][k], c->mod[k]);
+        }
+    if (!P.d_scal && hipMalloc((void **)&P.d_scal, h.size() * sizeof(u64)) != hipSuccess) {
+        P.d_scal = nullptr;
+        return rbk_set_error(RBK_ENOMEM, "bootstrap scalar table");
+    }
+    if (hipMemcpy(P.d_scal, h.data(), h.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess)
+        return rbk_set_error(RBK_EDEVICE, "bootstrap scalar upload");
+    P.scal_dirty = false;
+    return RBK_OK;
+}
+
 struct Runner {
     rbk_ctx *c;
     BootPlan &P;
@@ -489,6 +555,25 @@ struct Runner {
     }
 
     int rotate(const u64 *in, u64 *out, int level, int n_ct, int64_t k);
+    // one elementwise pass at level lv over n_ct ciphertexts (see k_boot_comb)
+    void comb(CombArgs &A, u64 *out, int lv, int n_ct)
+    {
+        const unsigned thr = (unsigned)std::min<size_t>(256, c->N);
+        dim3 grid((unsigned)(c->N / thr), lv + 1, 2 * n_ct);
+        kt_begin(c, KC_ELEMENTWISE, c->stream);
+        hipLaunchKernelGGL(k_boot_comb, grid, dim3(thr), 0, c->stream, A, out, P.d_scal, c->nQ, c->logN, lv + 1, c->d_pc);
+        kt_end(c, KC_ELEMENTWISE, (double)n_ct * 2 * (lv + 1) * c->N * sizeof(u64) * (A.n + (A.x ? 2 : 1)), c->stream);
+    }
+    // a register seen as a view: ciphertexts 2 (level+1) N apart
+    static void term(CombArgs &A, const Reg &r, size_t N, int sidx, int neg)
+    {
+        const int t = A.n++;
+        A.v[t] = r.d;
+        A.vps[t] = (long)((size_t)(r.level + 1) * N);
+        A.vcs[t] = 2 * A.vps[t];
+        A.vs[t] = sidx;
+        A.vneg[t] = neg;
+    }
     int lt(Reg &x, const BootLT &lt, int n_ct);
     int evalmod(Reg &x, int n_ct);
 };
@@ -588,8 +673,6 @@ int Runner::evalmod(Reg &x, int n_ct)
     T[1] = x;
     std::map<std::string, Reg> regs;
     int rc = RBK_OK;
-    u64 *tmp = take(), *tmp2 = take();
-    if (!tmp || !tmp2) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
     // operand at level lv: the register itself, or a dropped copy in dst
     auto at = [&](const Reg &r, int lv, u64 *dst) -> const u64 * {
         if (r.level == lv) return r.d;
@@ -598,20 +681,19 @@ int Runner::evalmod(Reg &x, int n_ct)
     };
     for (const BootStep &st : P.prog) {
         if (st.kind == ST_PROD) {
+            // T_k = 2 T_a T_b - T_c (or + constant when c = 0), exact scale via the scalar
             const int lv = st.lv;
             u64 *A = take(), *B = take(), *X = take();
             if (!A || !B || !X) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             const u64 *pa = at(T[st.a], lv, A), *pb = at(T[st.b], lv, B);
             rc = rbk_mult_relin_batch(c, pa, pb, X, lv, n_ct);
             if (rc) return rc;
-            ew_launch(c, EW_ADD, X, X, X, 2 * n_ct, lv + 1, qm, c->stream);
-            if (st.cc == 0) {
-                add_scalar_batch_launch(c, X, X, lv, n_ct, scal(st.sidx, lv), c->stream);
-            } else {
-                const u64 *pc = at(T[st.cc], lv, A);
-                mul_scalar_launch(c, pc, B, 2 * n_ct, lv + 1, qm, scal(st.sidx, lv), c->stream);
-                ew_launch(c, EW_SUB, X, B, X, 2 * n_ct, lv + 1, qm, c->stream);
-            }
+            CombArgs C{};
+            C.x = X;
+            C.cidx = -1;
+            if (st.cc == 0) C.cidx = st.sidx;
+            else term(C, T[st.cc], c->N, st.sidx, 1);
+            comb(C, X, lv, n_ct);
             u64 *out = take();
             if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             rc = rbk_rescale_batch(c, X, out, lv, n_ct);
@@ -621,28 +703,22 @@ int Runner::evalmod(Reg &x, int n_ct)
             give(B);
             give(X);
         } else if (st.kind == ST_LEAF) {
+            // sum_k s_k T_k + constant, the powers read in place at level lv
             const int lv = st.lv;
-            u64 *acc = take(), *D = take();
-            if (!acc || !D) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
-            bool first = true;
-            for (auto &t : st.terms) {
-                const u64 *pk = at(T[t.first], lv, D);
-                if (first) {
-                    mul_scalar_launch(c, pk, acc, 2 * n_ct, lv + 1, qm, scal(t.second, lv), c->stream);
-                    first = false;
-                } else {
-                    mul_scalar_launch(c, pk, tmp, 2 * n_ct, lv + 1, qm, scal(t.second, lv), c->stream);
-                    ew_launch(c, EW_ADD, acc, tmp, acc, 2 * n_ct, lv + 1, qm, c->stream);
-                }
-            }
-            add_scalar_batch_launch(c, acc, acc, lv, n_ct, scal(st.cidx, lv), c->stream);
+            u64 *acc = take();
+            if (!acc) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+            if (st.terms.size() > (size_t)COMB_MAX) return rbk_set_error(RBK_EUNSUPPORTED, "leaf with too many terms");
+            CombArgs C{};
+            C.x = nullptr;
+            for (auto &t : st.terms) term(C, T[t.first], c->N, t.second, 0);
+            C.cidx = st.cidx;
+            comb(C, acc, lv, n_ct);
             u64 *out = take();
             if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             rc = rbk_rescale_batch(c, acc, out, lv, n_ct);
             if (rc) return rc;
             regs[st.reg] = Reg{out, lv - 1};
             give(acc);
-            give(D);
         } else if (st.kind == ST_GIANT) {
             Reg q = regs[st.reg + "q"], r = regs[st.reg + "r"];
             regs.erase(st.reg + "q");
@@ -655,11 +731,14 @@ int Runner::evalmod(Reg &x, int n_ct)
             if (rc) return rc;
             rc = rbk_rescale_batch(c, X, Y, lp, n_ct);
             if (rc) return rc;
-            const u64 *py = at(Reg{Y, lp - 1}, st.out, A);
-            const u64 *pr = at(r, st.out, B);
             u64 *out = take();
             if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
-            ew_launch(c, EW_ADD, py, pr, out, 2 * n_ct, st.out + 1, qm, c->stream);
+            CombArgs C{};
+            C.x = nullptr;
+            C.cidx = -1;
+            term(C, Reg{Y, lp - 1}, c->N, -1, 0);
+            term(C, r, c->N, -1, 0);
+            comb(C, out, st.out, n_ct);
             regs[st.reg] = Reg{out, st.out};
             give(q.d);
             give(r.d);
@@ -667,7 +746,7 @@ int Runner::evalmod(Reg &x, int n_ct)
             give(B);
             give(X);
             give(Y);
-        } else {  // ST_DBL
+        } else {  // ST_DBL: y = 2 y^2 - 1 with the scale folded into the constant
             Reg y = regs["p"];
             const int lv = st.lv;
             u64 *A = take(), *X = take();
@@ -675,8 +754,10 @@ int Runner::evalmod(Reg &x, int n_ct)
             const u64 *py = at(y, lv, A);
             rc = rbk_mult_relin_batch(c, py, py, X, lv, n_ct);
             if (rc) return rc;
-            ew_launch(c, EW_ADD, X, X, X, 2 * n_ct, lv + 1, qm, c->stream);
-            add_scalar_batch_launch(c, X, X, lv, n_ct, scal(st.sidx, lv), c->stream);
+            CombArgs C{};
+            C.x = X;
+            C.cidx = st.sidx;
+            comb(C, X, lv, n_ct);
             u64 *out = take();
             if (!out) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
             rc = rbk_rescale_batch(c, X, out, lv, n_ct);
@@ -696,8 +777,6 @@ int Runner::evalmod(Reg &x, int n_ct)
         return RBK_EDEVICE;
     x.level = res.level;
     give(res.d);
-    give(tmp);
-    give(tmp2);
     return RBK_OK;
 }
 
@@ -823,6 +902,7 @@ extern "C" int rbk_boot_import(rbk_ctx *c, const uint64_t *plains, const uint64_
             for (size_t k = 0; k < P.scalars[i].size(); k++) {
                 if (scalars[off + k] >= c->mod[k]) return boot_fail(RBK_EINVAL, "imported scalar not below its prime");
                 P.scalars[i][k] = scalars[off + k];
+                P.scal_dirty = true;
             }
             off += P.scalars[i].size();
         }
@@ -854,6 +934,7 @@ extern "C" int rbk_bootstrap_batch(rbk_ctx *c, const uint64_t *d_in, const doubl
         dprime[i] = std::ldexp(scales_in[i], ex[i]);
     }
     // EvalMod runs the real and imaginary halves of the batch together
+    if (int rc0 = upload_scalars(c, P)) return rc0;
     Runner R{c, P, count, (size_t)2 * count * 2 * (P.L + 1) * N, {}};
     // reuse the pooled registers of earlier runs when they are large enough
     if (P.pool_words >= R.reg_words) {
