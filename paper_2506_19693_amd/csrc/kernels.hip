@@ -406,6 +406,12 @@ __device__ __forceinline__ void st2(u64 *p, u64 a, u64 b)
     v.y = b;
     *reinterpret_cast<u64x2 *>(p) = v;
 }
+// the same, streamed: the data is not read again soon, so it bypasses the caches' retention
+__device__ __forceinline__ void st2_nt(u64 *p, u64 a, u64 b)
+{
+    __builtin_nontemporal_store(a, p);
+    __builtin_nontemporal_store(b, p + 1);
+}
 // the pair at source index src (even-aligned load, swapped when src is odd)
 __device__ __forceinline__ u64x2 ld2_perm(const u64 *base, size_t src)
 {
@@ -519,8 +525,8 @@ __global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *__restrict
             }
         }
         u64 *o = out + ct * out_stride + li + k;
-        st2(o, v0, w0);
-        st2(o + per, v1, w1);
+        st2_nt(o, v0, w0);
+        st2_nt(o + per, v1, w1);
     }
 }
 
