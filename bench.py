@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--rots", type=int, default=32, help="hoisted rotations per ciphertext")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ks", action="store_true", help="skip the key-switch part (the headline value is then null)")
     ap.add_argument("--no-boot", action="store_true", help="skip the bootstrap throughput part")
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP train_step part")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving part")
@@ -596,52 +597,62 @@ def bench_serve(args, torch):
     return out
 
 
-def cpu_baseline():
-    """The oracle, single-threaded, on one ciphertext of the same workload:
-    mult_relin + rescale + one hoisted rotation (2 key switches)."""
+def _oracle_worker(idx, barrier, out):
+    """One ciphertext of the key-switch workload on the oracle: mult_relin +
+    rescale + one hoisted rotation (2 key switches); the timed region starts
+    when every worker is ready."""
     import oracle as O
     import synth_inputs as S
 
     orc = O.Oracle(LOG_N, Q_BITS, P_BITS, ALPHA)
     N, L = orc.N, orc.L
-    g = S.rng(2, 16)
+    g = S.rng(2, 16, idx)
     s = S.ternary(g, N)
-    a, e = S.key_randomness(g, orc.beta, orc.moduli, N)
-    rlk = orc.keygen_relin(s, a, e)
+    rlk = orc.keygen_relin(s, *S.key_randomness(g, orc.beta, orc.moduli, N))
     gal = orc.galois_rot(1)
-    a, e = S.key_randomness(g, orc.beta, orc.moduli, N)
-    gk = orc.keygen_galois(s, gal, a, e)
+    gk = orc.keygen_galois(s, gal, *S.key_randomness(g, orc.beta, orc.moduli, N))
     x = S.uniform_residues(g, orc.Q, N, lead=(2,))
     y = S.uniform_residues(g, orc.Q, N, lead=(2,))
+    barrier.wait()
     t0 = time.perf_counter()
     m = orc.mult_relin(L, rlk, x, y)
     r = orc.rescale(L, m)
     orc.rotate_hoisted(L - 1, [gk], [gal], r)
-    dt = time.perf_counter() - t0
+    out.put(time.perf_counter() - t0)
+
+
+def cpu_baseline():
+    """The oracle (plain C, one thread per process) on independent ciphertexts
+    of the key-switch workload, one process per host core (at most 16): each
+    does mult_relin + rescale + one hoisted rotation (2 key switches)."""
+    import multiprocessing as mp
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    ctxm = mp.get_context("fork")
+    barrier = ctxm.Barrier(workers)
+    q = ctxm.Queue()
+    procs = [ctxm.Process(target=_oracle_worker, args=(i, barrier, q)) for i in range(workers)]
+    for p_ in procs:
+        p_.start()
+    dts = [q.get() for _ in procs]
+    for p_ in procs:
+        p_.join()
+    wall = max(dts)
     return {
-        "value": 2.0 / dt,
+        "value": 2.0 * workers / wall,
         "unit": "key-switches/s",
-        "cores": 1,
+        "cores": workers,
         "kind": "oracle",
-        "sample": "1 ciphertext at N=2^16, 24 limbs: mult_relin + rescale + 1 hoisted rotation "
-                  "(2 key switches) in %.1f s, single thread" % dt,
+        "sample": "%d independent ciphertexts at N=2^16, 24 limbs, one oracle process per core: mult_relin + rescale "
+                  "+ 1 hoisted rotation each (2 key switches), %.1f s wall (single-process time %.1f s)" % (
+                      workers, wall, min(dts)),
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-
+def bench_keyswitch(args, torch):
+    """The key-switch workload (module docstring): batched and plain, kernel timers, roofline."""
     from paper_2506_19693_amd import Context
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a ROCm GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
     count, ks = args.count, ROTS[: args.rots]
     log("setup: N=2^16, %d limbs, %d special, alpha %d, %d ciphertexts, %d rotations" % (
         len(Q_BITS), len(P_BITS), ALPHA, count, len(ks)))
@@ -752,6 +763,35 @@ def main():
     del out_m, out_r, out_h, A, B
     ctx.close()
     torch.cuda.empty_cache()
+    return {
+        "value": ks_per_step / t_batched,
+        "ms_per_step": t_batched * 1e3,
+        "count": count,
+        "rots": len(ks),
+        "ks_per_step": ks_per_step,
+        "tuned": tuned,
+        "plain": plain,
+        "roofline": roofline,
+        "kernels": kern,
+    }
+
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    ksw = None
+    if not args.no_ks:
+        ksw = bench_keyswitch(args, torch)
 
     boot = None
     if not args.no_boot:
@@ -789,28 +829,29 @@ def main():
 
     line = {
         "metric": "bootstraps/s + key-switches/s at N=2^16, batched vs plain; p99 latency",
-        "value": round(ks_per_step / t_batched, 1),
+        "value": round(ksw["value"], 1) if ksw else None,
         "unit": "key-switches/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_batched * 1e3, 3),
+        "ms_per_step": round(ksw["ms_per_step"], 3) if ksw else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
         "config": {
-            "workload": "key-switch throughput: %d ciphertexts x (mult_relin + rescale + %d hoisted rotations), "
-                        "N=2^16, 24 primes (60 + 23x50 bits), 8 special 60-bit primes, dnum=3" % (count, len(ks)),
-            "key_switches_per_step": ks_per_step,
+            "workload": ("key-switch throughput: %d ciphertexts x (mult_relin + rescale + %d hoisted rotations), "
+                         "N=2^16, 24 primes (60 + 23x50 bits), 8 special 60-bit primes, dnum=3" % (
+                             ksw["count"], ksw["rots"])) if ksw else None,
+            "key_switches_per_step": ksw["ks_per_step"] if ksw else None,
             "path": "batched",
-            "autotuned": tuned,
+            "autotuned": ksw["tuned"] if ksw else None,
         },
-        "plain": plain,
-        "batched_vs_plain": round(plain["ms_per_step"] / (t_batched * 1e3), 3) if plain else None,
-        "roofline": roofline,
-        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
+        "plain": ksw["plain"] if ksw else None,
+        "batched_vs_plain": round(ksw["plain"]["ms_per_step"] / ksw["ms_per_step"], 3) if ksw and ksw["plain"] else None,
+        "roofline": ksw["roofline"] if ksw else None,
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in ksw["kernels"].items()} if ksw else None,
         "bootstrap": boot,
         "train_step": mlp,
         "serving": serve,
