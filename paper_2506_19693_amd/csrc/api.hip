@@ -244,6 +244,8 @@ static int build_tables(rbk_ctx *c)
     const int nT = c->nT;
     c->h_pc.resize(nT);
     std::vector<u64> tw(nT * N), tws(nT * N), itw(nT * N), itws(nT * N), last(nT), lasts(nT);
+    std::vector<double2> twf(nT * N, make_double2(0, 0)), itwf(nT * N, make_double2(0, 0));
+    std::vector<FpC> fc(nT, FpC{0, 0, 0, 0, 0, 0, 0, 0});
     for (int p = 0; p < nT; p++) {
         u64 q = c->mod[p], psi = c->psi[p], ipsi = h_inv(psi, q);
         PrimeC &pc = c->h_pc[p];
@@ -269,6 +271,15 @@ static int build_tables(rbk_ctx *c)
         }
         last[p] = h_mul(itw[p * N + 1], pc.ninv, q);
         lasts[p] = h_shoup(last[p], q);
+        if (q < ((u64)1 << 50)) {
+            // integers below 2^50 are exact doubles; quotients are correctly rounded divisions
+            const double qd = (double)q;
+            for (size_t k = 0; k < N; k++) {
+                twf[p * N + k] = make_double2((double)tw[p * N + k], (double)tw[p * N + k] / qd);
+                itwf[p * N + k] = make_double2((double)itw[p * N + k], (double)itw[p * N + k] / qd);
+            }
+            fc[p] = FpC{qd, 1.0 / qd, (double)pc.ninv, (double)pc.ninv / qd, (double)last[p], (double)last[p] / qd, 1, 0};
+        }
     }
     int rc = 0;
     rc |= dev_upload(c, &c->d_pc, c->h_pc);
@@ -278,8 +289,12 @@ static int build_tables(rbk_ctx *c)
     rc |= dev_upload(c, &c->d_itw_sh, itws);
     rc |= dev_upload(c, &c->d_last, last);
     rc |= dev_upload(c, &c->d_last_sh, lasts);
+    rc |= dev_upload(c, &c->d_twf, twf);
+    rc |= dev_upload(c, &c->d_itwf, itwf);
+    rc |= dev_upload(c, &c->d_fc, fc);
     if (rc) return RBK_ENOMEM;
-    c->tabs = NttTables{c->d_tw, c->d_tw_sh, c->d_itw, c->d_itw_sh, c->d_last, c->d_last_sh, c->d_pc};
+    c->tabs = NttTables{c->d_tw, c->d_tw_sh, c->d_itw, c->d_itw_sh, c->d_last, c->d_last_sh, c->d_pc,
+                        c->d_twf, c->d_itwf, c->d_fc};
 
     // ModDown P -> Q, P^-1, P mod q
     const int nQ = c->nQ, nP = c->nP;

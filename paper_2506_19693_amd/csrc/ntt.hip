@@ -242,19 +242,179 @@ __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride
     }
 }
 
+// ---------------------------------------------------------------- FP64 butterflies (primes below 2^50)
+//
+// For p < 2^50 the pass runs on the FP64 pipes: residues are integers held
+// exactly in doubles and may be negative.  A product a * w mod p (w in [0, p),
+// wp = fl(w / p)) is computed exactly: h = fl(a w) and l = a w - h (one FMA)
+// split the product, qq = rint(fl(a wp)) estimates the quotient, and
+// (h - qq p) + l is the exact integer a w - qq p (both steps are exact because
+// the values are integers below 2^53).  With |a| <= k p the estimate is off by
+// at most 1/2 + k/4, so the result t satisfies |t| <= (1/2 + k/4) p.
+// Bounds, in units of p, for the stage sequences used here:
+//  * forward (CT: x' = x + t, y' = x - t): from |x| <= 2 the next four stages
+//    stay below 2 -> 3 -> 4.25 -> 5.8 -> 7.7;
+//  * inverse (GS: x' = x + y, y' = (x - y) w): from |x| <= 1/2 four stages
+//    stay below 1 -> 2 -> 4 -> 8;
+// so every round of at most four stages starts with a reduction of its 16
+// registers to |x| <= (p-1)/2 (x - rint(x / p) p, exact), and every value
+// stays below 8 p < 2^53.  Between the two passes of a transform the limb is
+// kept in HBM as raw double bits; the first pass reads canonical residues and
+// the last one writes them back canonical in [0, p).
+
+__device__ __forceinline__ double fp_mul(double a, double w, double wp, double p)
+{
+    const double h = a * w;
+    const double l = __fma_rn(a, w, -h);
+    const double qq = rint(a * wp);
+    return __fma_rn(-qq, p, h) + l;
+}
+
+__device__ __forceinline__ double fp_red(double x, double p, double pinv) { return __fma_rn(-rint(x * pinv), p, x); }
+
+// canonical residue (< 2^52) -> double
+__device__ __forceinline__ double fp_from_u64(u64 v)
+{
+    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+
+// any exact integer |x| < 2^53 -> canonical residue in [0, p)
+__device__ __forceinline__ u64 fp_to_u64(double x, double p, double pinv)
+{
+    double r = fp_red(x, p, pinv);
+    r = r < 0 ? r + p : r;
+    return (u64)__double_as_longlong(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+
+template <int LOGS, int NST, int RD0, bool INV>
+__device__ __forceinline__ void fp_round16(double (&x)[16], int ebase, int estride, int s0, int off, int line_id, int logN,
+                                           const double2 *twf, double p, bool fold, const FpC &fc)
+{
+#pragma unroll
+    for (int k = 0; k < NST; k++) {
+        const int d = INV ? (RD0 << k) : (RD0 >> k);
+        const int s = s0 + k;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int i0 = (j / d) * 2 * d + (j % d), i1 = i0 + d;
+            const int e = ebase + estride * i0;
+            if (!INV) {
+                const int ti = (1 << (off + s)) + (line_id << s) + (e >> (LOGS - s));
+                const double2 w = twf[ti];
+                const double t = fp_mul(x[i1], w.x, w.y, p);
+                const double u = x[i0];
+                x[i0] = u + t;
+                x[i1] = u - t;
+            } else if (fold && k == NST - 1) {
+                const double u = x[i0], v = x[i1];
+                x[i0] = fp_mul(u + v, fc.ninv, fc.ninv_p, p);
+                x[i1] = fp_mul(u - v, fc.lw, fc.lw_p, p);
+            } else {
+                const int ti = (1 << (logN - 1 - off - s)) + (line_id << (LOGS - s - 1)) + (e >> (s + 1));
+                const double2 w = twf[ti];
+                const double u = x[i0], v = x[i1];
+                x[i0] = u + v;
+                x[i1] = fp_mul(u - v, w.x, w.y, p);
+            }
+        }
+    }
+}
+
+template <int LOGS>
+__device__ __forceinline__ void fp_reduce16(double (&x)[16], double p, double pinv)
+{
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = fp_red(x[i], p, pinv);
+}
+
+// One pass of the register NTT in FP64 (same geometry and twiddle indexing as
+// the integer pass in k_ntt16).
+template <int LOGS, bool INV, bool COLS>
+__device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, int t, int gl,
+                                         int logN)
+{
+    typedef Geo<LOGS> G;
+    constexpr int NST2 = LOGS - 4;
+    const size_t N = (size_t)1 << logN;
+    const size_t C = COLS ? (N >> LOGS) : (size_t)G::S;
+    auto addr = [&](int e) -> size_t { return COLS ? (size_t)e * C + gl : (size_t)gl * G::S + e; };
+    const int off_f = COLS ? 0 : logN - LOGS;
+    const int off_i = COLS ? logN - LOGS : 0;
+    const int lid = COLS ? 0 : gl;
+    const double p = fc.p, pinv = fc.pinv;
+    double *sl = reinterpret_cast<double *>(sm_line);
+    double x[16];
+
+    if (!INV) {
+        if (COLS) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) x[i] = fp_from_u64(base[addr(t + G::TPL * i)]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; i++) x[i] = __longlong_as_double((long long)base[addr(t + G::TPL * i)]);
+        }
+        fp_reduce16<LOGS>(x, p, pinv);
+        fp_round16<LOGS, 4, 8, false>(x, t, G::TPL, 0, off_f, lid, logN, twf, p, false, fc);
+#pragma unroll
+        for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = x[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
+        fp_reduce16<LOGS>(x, p, pinv);
+        fp_round16<LOGS, NST2, (1 << (NST2 - 1)), false>(x, 16 * t, 1, 4, off_f, lid, logN, twf, p, false, fc);
+        if (COLS) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(16 * t + i)] = (u64)__double_as_longlong(x[i]);
+        } else {
+            u64 *su = sm_line;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; i++) su[lidx(16 * t + i)] = fp_to_u64(x[i], p, pinv);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = su[lidx(t + G::TPL * i)];
+        }
+    } else {
+        if (COLS) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) x[i] = __longlong_as_double((long long)base[addr(16 * t + i)]);
+        } else {
+            u64 *su = sm_line;
+#pragma unroll
+            for (int i = 0; i < 16; i++) su[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; i++) x[i] = fp_from_u64(su[lidx(16 * t + i)]);
+            __syncthreads();
+        }
+        fp_reduce16<LOGS>(x, p, pinv);
+        fp_round16<LOGS, 4, 1, true>(x, 16 * t, 1, 0, off_i, lid, logN, twf, p, false, fc);
+#pragma unroll
+        for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = x[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; i++) x[i] = sl[lidx(t + G::TPL * i)];
+        fp_reduce16<LOGS>(x, p, pinv);
+        fp_round16<LOGS, NST2, (16 >> NST2), true>(x, t, G::TPL, 4, off_i, lid, logN, twf, p, COLS, fc);
+        if (COLS) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = fp_to_u64(x[i], p, pinv);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = (u64)__double_as_longlong(x[i]);
+        }
+    }
+}
+
 template <int LOGS, bool INV, bool COLS>
 __global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN)
 {
     typedef Geo<LOGS> G;
     constexpr int NST2 = LOGS - 4;
     __shared__ u64 sm[G::LINES * G::LS];
-    const int limb = blockIdx.y, poly = blockIdx.z;
+    const int limb = blockIdx.z, poly = blockIdx.y;
     const int pr = map.prime(limb);
     const size_t N = (size_t)1 << logN;
-    const PrimeC pc = T.pc[pr];
-    const u64 q = pc.q, q2 = 2 * q;
-    const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
-    const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
     u64 *base = data + (size_t)poly * poly_stride + (size_t)limb * N;
     const int tid = threadIdx.x;
     int line, t;
@@ -266,6 +426,15 @@ __global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, Limb
         line = tid / G::TPL;
     }
     const int gl = blockIdx.x * G::LINES + line;          // column (COLS) or row index
+    const FpC fc = T.fc[pr];
+    if (fc.use) {
+        ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, (INV ? T.itwf : T.twf) + (size_t)pr * N, t, gl, logN);
+        return;
+    }
+    const PrimeC pc = T.pc[pr];
+    const u64 q = pc.q, q2 = 2 * q;
+    const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
+    const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
     const size_t C = COLS ? (N >> LOGS) : (size_t)G::S;   // row length of the R x C view
     u64 *sl = sm + line * G::LS;
     auto addr = [&](int e) -> size_t { return COLS ? (size_t)e * C + gl : (size_t)gl * G::S + e; };
@@ -330,7 +499,8 @@ template <int LOGS, bool INV, bool COLS>
 static void launch16(u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, const NttTables &T, int logN,
                      hipStream_t st)
 {
-    dim3 grid((unsigned)(((size_t)1 << logN) / 4096), nlimbs, npoly);
+    // limbs outermost: the blocks in flight share one prime's twiddles
+    dim3 grid((unsigned)(((size_t)1 << logN) / 4096), npoly, nlimbs);
     hipLaunchKernelGGL((k_ntt16<LOGS, INV, COLS>), grid, dim3(256), 0, st, data, poly_stride, map, T, logN);
 }
 

@@ -61,6 +61,8 @@ struct rbk_ctx_impl {
     PrimeC *d_pc = nullptr;
     u64 *d_tw = nullptr, *d_tw_sh = nullptr, *d_itw = nullptr, *d_itw_sh = nullptr;
     u64 *d_last = nullptr, *d_last_sh = nullptr;
+    double2 *d_twf = nullptr, *d_itwf = nullptr;
+    FpC *d_fc = nullptr;
     NttTables tabs{};
 
     // ModDown P -> Q (level independent, indexed by Q prime)

@@ -27,11 +27,23 @@ struct LimbMap {
     }
 };
 
+// Per-prime constants of the floating-point butterflies (primes below 2^50):
+// every value is an integer held exactly in a double, wp = fl(w / p).
+struct FpC {
+    double p, pinv;       // p and fl(1 / p)
+    double ninv, ninv_p;  // N^-1 mod p and its quotient
+    double lw, lw_p;      // psi^-brv(1) * N^-1 mod p and its quotient
+    int use;              // 1 if p < 2^50 (the transform runs in FP64 for this prime)
+    int pad;
+};
+
 struct NttTables {
     const u64 *tw, *tw_sh;    // [nprimes][N], psi^brv(k) and Shoup quotients
     const u64 *itw, *itw_sh;  // [nprimes][N], psi^-brv(k)
     const u64 *last, *last_sh;  // [nprimes], psi^-brv(1) * N^-1
     const PrimeC *pc;
+    const double2 *twf, *itwf;  // [nprimes][N], (w, fl(w / p)) of tw / itw (FP primes only)
+    const FpC *fc;              // [nprimes]
 };
 
 // A switching key on the device: beta digits of (b, a) over every prime,

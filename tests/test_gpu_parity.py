@@ -97,6 +97,17 @@ def test_ntt_matches_oracle(logN):
             assert np.array_equal(got[c][l], orc.limb_ntt(l, a[c][l])), (c, l)
     ctx.ntt(t, idx, inverse=True)
     assert np.array_equal(to_host(t), a)
+    # extreme inputs: every residue q - 1, and alternating 0 / q - 1
+    for pat in ("max", "alt"):
+        m = np.array([[[(q - 1) if (pat == "max" or i % 2) else 0 for i in range(N)] for q in orc.moduli]],
+                     dtype=np.uint64)
+        t = to_device(m)
+        ctx.ntt(t, idx)
+        got = to_host(t)
+        for l in range(5):
+            assert np.array_equal(got[0][l], orc.limb_ntt(l, m[0][l])), (pat, l)
+        ctx.ntt(t, idx, inverse=True)
+        assert np.array_equal(to_host(t), m), pat
     # special primes alone (as in ModDown)
     b = S.uniform_residues(g, orc.P, N)
     tb = to_device(b)
