@@ -206,6 +206,36 @@ int rbk_rescale_batch(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int l
 int rbk_rotate_hoisted_batch(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, int n, uint64_t *d_outs, int level,
                              int count);
 
+/* ---- descriptor lists: uneven level and ring degree per launch ---------- */
+/* Work whose shapes differ goes through one set of launches: the transforms
+ * run on a persistent grid that walks a list of descriptors, the other
+ * kernels read a per-ciphertext level table.  Descriptors are packed on the
+ * host and uploaded on the context stream, so list calls are refused
+ * (RBK_ESTATE) during graph capture.  Ring degrees up to 2^16. */
+
+/* one limb of one polynomial: N residues of ctx's ring at d_limb (device),
+ * modulo prime index `prime` of ctx (Q primes, then special primes) */
+typedef struct {
+    const rbk_ctx *ctx;
+    uint64_t *d_limb;
+    int prime;
+    int pad;
+} rbk_ntt_item;
+/* In-place forward (inverse = 0) or inverse NTT of every limb of the list,
+ * each in its own context's ring (contexts on the device of ctx), launched
+ * on ctx's stream.  The same results as per-context rbk_ntt calls.
+ * RBK_EUNSUPPORTED for a ring degree above 2^16. */
+int rbk_ntt_list(rbk_ctx *ctx, const rbk_ntt_item *items, int n, int inverse);
+/* out_i = rescale(mult_relin(a_i, b_i)) for count ciphertexts of ctx at the
+ * uneven levels levels[i] (host array, 1 <= levels[i] <= L).  With Lm the
+ * largest level: d_a, d_b: [count][2][Lm+1][N], ciphertext i in limbs
+ * 0..levels[i] of its slot; d_out: [count][2][Lm][N], ciphertext i written
+ * to limbs 0..levels[i]-1 (the rest of its slot is left as it was).  The
+ * same residues as rbk_mult_relin_batch followed by rbk_rescale_batch at
+ * each ciphertext's level. */
+int rbk_mult_relin_rescale_list(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out,
+                                const int *levels, int count);
+
 /* ---- approximate bootstrapping (Section 3: encoding step, scaled-sine
  *      modular reduction, decoding step; Cheon et al. 2018, Bossuat et al.
  *      2021) ------------------------------------------------------------- */

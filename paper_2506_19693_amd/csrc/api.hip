@@ -193,6 +193,59 @@ u64 *ws_reserve(rbk_ctx_impl *c, size_t words)
     return c->ws;
 }
 
+char *desc_upload(rbk_ctx_impl *c, const DescBlob &b, int *rc)
+{
+    *rc = RBK_OK;
+    if (c->capturing) {
+        *rc = rbk_set_error(RBK_ESTATE, "list calls upload descriptors and cannot be captured");
+        return nullptr;
+    }
+    const size_t n = std::max(b.h.size(), (size_t)16);
+    const int k = c->desc_turn;
+    c->desc_turn ^= 1;
+    if (!c->desc_evt[k]) {
+        if (hipEventCreateWithFlags(&c->desc_evt[k], hipEventDisableTiming) != hipSuccess) {
+            c->desc_evt[k] = nullptr;
+            *rc = rbk_set_error(RBK_EDEVICE, "event creation failed");
+            return nullptr;
+        }
+    } else if (hipEventSynchronize(c->desc_evt[k]) != hipSuccess) {
+        *rc = rbk_set_error(RBK_EDEVICE, "descriptor staging wait failed");
+        return nullptr;
+    }
+    if (n > c->desc_host_bytes[k]) {
+        if (c->desc_host[k]) (void)hipHostFree(c->desc_host[k]);
+        c->desc_host[k] = nullptr;
+        c->desc_host_bytes[k] = 0;
+        const size_t w = std::max(n, (size_t)1 << 16);
+        if (hipHostMalloc(&c->desc_host[k], w, hipHostMallocDefault) != hipSuccess) {
+            c->desc_host[k] = nullptr;
+            *rc = rbk_set_error(RBK_ENOMEM, "pinned descriptor staging allocation failed");
+            return nullptr;
+        }
+        c->desc_host_bytes[k] = w;
+    }
+    if (n > c->desc_dev_bytes) {
+        release_buffer(c, c->desc_dev);
+        c->desc_dev = nullptr;
+        c->desc_dev_bytes = 0;
+        const size_t w = std::max(n, (size_t)1 << 16);
+        if (hipMalloc(&c->desc_dev, w) != hipSuccess) {
+            c->desc_dev = nullptr;
+            *rc = rbk_set_error(RBK_ENOMEM, "descriptor arena allocation failed");
+            return nullptr;
+        }
+        c->desc_dev_bytes = w;
+    }
+    std::memcpy(c->desc_host[k], b.h.data(), b.h.size());
+    if (hipMemcpyAsync(c->desc_dev, c->desc_host[k], n, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipEventRecord(c->desc_evt[k], c->stream) != hipSuccess) {
+        *rc = rbk_set_error(RBK_EDEVICE, "descriptor upload failed");
+        return nullptr;
+    }
+    return (char *)c->desc_dev;
+}
+
 #define WS(ptr, words)                                                                         \
     u64 *ptr = ws_reserve(c, (words));                                                          \
     if (!ptr) return c->capturing ? RBK_ESTATE : fail(RBK_ENOMEM, "device workspace allocation failed");
@@ -295,6 +348,7 @@ static int build_tables(rbk_ctx *c)
     if (rc) return RBK_ENOMEM;
     c->tabs = NttTables{c->d_tw, c->d_tw_sh, c->d_itw, c->d_itw_sh, c->d_last, c->d_last_sh, c->d_pc,
                         c->d_twf, c->d_itwf, c->d_fc};
+    if (dev_upload(c, &c->d_tabs, std::vector<NttTables>{c->tabs})) return RBK_ENOMEM;
 
     // ModDown P -> Q, P^-1, P mod q
     const int nQ = c->nQ, nP = c->nP;
@@ -420,6 +474,11 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
     for (void *p : c->owned) (void)hipFree(p);
     for (void *p : c->retired) (void)hipFree(p);
     if (c->ws) (void)hipFree(c->ws);
+    if (c->desc_dev) (void)hipFree(c->desc_dev);
+    for (int k = 0; k < 2; k++) {
+        if (c->desc_host[k]) (void)hipHostFree(c->desc_host[k]);
+        if (c->desc_evt[k]) (void)hipEventDestroy(c->desc_evt[k]);
+    }
     delete c;
     return RBK_OK;
 }

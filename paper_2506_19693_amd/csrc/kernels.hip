@@ -866,3 +866,352 @@ void decrypt_launch(const rbk_ctx_impl *c, const u64 *ct, u64 *pt, int level, hi
     dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
     hipLaunchKernelGGL(k_decrypt, grid, dim3(EW_THREADS), 0, st, ct, c->d_s, pt, c->logN, level + 1, c->d_pc);
 }
+
+// ---------------------------------------------------------------- batches of uneven level
+//
+// A batch of `count` ciphertexts whose levels differ.  Every buffer is laid
+// out at the strides of the largest level Lm (L1m = Lm + 1 limbs per
+// polynomial, Em = L1m + nP extended positions per ModUp digit, betam digits
+// per ciphertext); ciphertext i uses the first level_i + 1 limbs (and E_i =
+// level_i + 1 + nP positions, beta_i digits) of its slot.  Grids cover the
+// largest shape and work outside a ciphertext's own shape returns at once.
+// The arithmetic of every element is that of the uniform kernels above.
+
+__global__ void k_tensor_list(const u64 *a, const u64 *b, u64 *out, int logN, int L1m, int count, const ListCt *cts,
+                              const PrimeC *pc)
+{
+    const size_t per = (size_t)L1m << logN;
+    const size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= per * count) return;
+    const size_t ct = i / per, r = i % per;
+    const int limb = (int)(r >> logN);
+    if (limb > cts[ct].level) return;
+    const PrimeC p = pc[limb];
+    const u64 *A = a + ct * 2 * per, *B = b + ct * 2 * per;
+    const u64 a0 = A[r], a1 = A[per + r], b0 = B[r], b1 = B[per + r];
+    u64 *O = out + ct * 3 * per;
+    O[r] = mul_mod(a0, b0, p);
+    u128w s = mul_wide(a0, b1);
+    acc_wide(s, mul_wide(a1, b0));
+    const u64 t = redc(s, p.q, p.qneg);
+    O[per + r] = redc(mul_wide(t, p.r2), p.q, p.qneg);
+    O[2 * per + r] = mul_mod(a1, b1, p);
+}
+
+// ModUp base conversion of digit blockIdx.y of ciphertext blockIdx.z, with the
+// digit's own limbs (NTT domain, from d) copied into their positions.
+template <int MAXIN>
+__global__ __launch_bounds__(EW_THREADS) void k_bconv_up_list(const u64 *coef, long coef_stride, const u64 *d, long d_stride,
+                                                              u64 *ext, long ext_stride, long dig_stride, int logN,
+                                                              int alpha, int nP, int nQ, const ListCt *cts,
+                                                              const PrimeC *pc)
+{
+    __shared__ u64 tab[BCONV_MAX_TAB];
+    const size_t N = (size_t)1 << logN;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int ct = blockIdx.z, j = blockIdx.y;
+    const ListCt C = cts[ct];
+    const int L1 = C.level + 1, E = L1 + nP, beta = (L1 + alpha - 1) / alpha;
+    if (j >= beta) return;
+    const int lo = j * alpha, n_in = min(alpha, L1 - lo), n_out = E - n_in;
+    const u64 *Aj = C.A + j * alpha, *Ashj = C.Ash + j * alpha, *Mj = C.M + (size_t)j * alpha * E;
+    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS) tab[w] = Mj[(size_t)(w / n_out) * E + (w % n_out)];
+    __syncthreads();
+    if (k >= N) return;
+    const u64 *x = coef + ct * coef_stride + (size_t)lo * N;
+    const u64 *own = d + ct * d_stride + (size_t)lo * N;
+    u64 *dst = ext + ct * ext_stride + (size_t)j * dig_stride;
+    u64 y[MAXIN];
+#pragma unroll
+    for (int i = 0; i < MAXIN; i++)
+        if (i < n_in) {
+            y[i] = shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[lo + i].q);
+            dst[(size_t)(lo + i) * N + k] = own[(size_t)i * N + k];
+        }
+    for (int o = 0; o < n_out; o++) {
+        const int pos = o < lo ? o : o + n_in;
+        const int pr = pos < L1 ? pos : nQ + pos - L1;
+        const PrimeC p = pc[pr];
+        u128w acc = {0, 0};
+#pragma unroll
+        for (int i = 0; i < MAXIN; i++)
+            if (i < n_in) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
+        dst[(size_t)pos * N + k] = redc(acc, p.q, p.qneg);
+    }
+}
+
+// ModDown base conversion P -> Q_l of polynomial blockIdx.z (ciphertext z / 2);
+// tp: [2 count][nP][N], conv: polynomial stride conv_stride.
+template <int MAXIN>
+__global__ __launch_bounds__(EW_THREADS) void k_bconv_down_list(const u64 *tp, u64 *conv, long conv_stride, int logN,
+                                                                int nP, int nQ, const ListCt *cts, const u64 *A,
+                                                                const u64 *Ash, const u64 *M, const PrimeC *pc)
+{
+    __shared__ u64 tab[BCONV_MAX_TAB];
+    const size_t N = (size_t)1 << logN;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int poly = blockIdx.z;
+    const int n_out = cts[poly / 2].level + 1;
+    for (int w = threadIdx.x; w < nP * n_out; w += EW_THREADS) tab[w] = M[(size_t)(w / n_out) * nQ + (w % n_out)];
+    __syncthreads();
+    if (k >= N) return;
+    const u64 *x = tp + (size_t)poly * nP * N;
+    u64 *dst = conv + poly * conv_stride;
+    u64 y[MAXIN];
+#pragma unroll
+    for (int i = 0; i < MAXIN; i++)
+        if (i < nP) y[i] = shoup(x[(size_t)i * N + k], A[i], Ash[i], pc[nQ + i].q);
+    for (int o = 0; o < n_out; o++) {
+        const PrimeC p = pc[o];
+        u128w acc = {0, 0};
+#pragma unroll
+        for (int i = 0; i < MAXIN; i++)
+            if (i < nP) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
+        dst[(size_t)o * N + k] = redc(acc, p.q, p.qneg);
+    }
+}
+
+// Special-prime part of the relinearisation inner product (no automorphism).
+template <int BETA>
+__global__ __launch_bounds__(EW_THREADS) void k_ip_p_list(const u64 *__restrict__ ext, long ext_stride, long dig_stride,
+                                                          const u64 *__restrict__ key, u64 *__restrict__ tp, int logN,
+                                                          int alpha, int nT, int nQ, int nP, int count, int cpc,
+                                                          const ListCt *cts, const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t k = 2 * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
+    const int t = blockIdx.y;
+    const int ct0 = blockIdx.z * cpc, ct1 = min(count, ct0 + cpc);
+    if (k >= N) return;
+    const int pr = nQ + t;
+    const PrimeC p = pc[pr];
+    u64x2 kb[BETA], ka[BETA];
+#pragma unroll
+    for (int j = 0; j < BETA; j++) {
+        kb[j] = ld2(key + (((size_t)j * 2 + 0) * nT + pr) * N + k);
+        ka[j] = ld2(key + (((size_t)j * 2 + 1) * nT + pr) * N + k);
+    }
+    for (int ct = ct0; ct < ct1; ct++) {
+        const int L1 = cts[ct].level + 1, beta = (L1 + alpha - 1) / alpha;
+        const u64 *x = ext + ct * ext_stride + (size_t)(L1 + t) * N + k;
+        u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < BETA; j++)
+            if (j < beta) {
+                const u64x2 dd = ld2(x + (size_t)j * dig_stride);
+                acc_wide(s0, mul_wide(dd.x, kb[j].x));
+                acc_wide(t0, mul_wide(dd.y, kb[j].y));
+                acc_wide(s1, mul_wide(dd.x, ka[j].x));
+                acc_wide(t1, mul_wide(dd.y, ka[j].y));
+            }
+        u64 *o = tp + ((size_t)ct * 2 * nP + t) * N + k;
+        st2(o, redc(s0, p.q, p.qneg), redc(t0, p.q, p.qneg));
+        st2(o + (size_t)nP * N, redc(s1, p.q, p.qneg), redc(t1, p.q, p.qneg));
+    }
+}
+
+// Q positions of the relinearisation: out = (IP - conv) * P^-1 + (d0, d1);
+// conv, add and out have polynomial stride `per` inside a ciphertext.
+template <int BETA>
+__global__ __launch_bounds__(EW_THREADS) void k_moddown_ip_list(const u64 *__restrict__ ext, long ext_stride,
+                                                                long dig_stride, const u64 *__restrict__ key,
+                                                                const u64 *__restrict__ conv, long conv_stride, long per,
+                                                                const u64 *__restrict__ add, long add_stride,
+                                                                u64 *__restrict__ out, long out_stride, int logN,
+                                                                int alpha, int nT, int count, int cpc,
+                                                                const ListCt *cts, const u64 *Pinv, const u64 *Pinv_sh,
+                                                                const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t k = 2 * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
+    const int i = blockIdx.y;
+    const int ct0 = blockIdx.z * cpc, ct1 = min(count, ct0 + cpc);
+    if (k >= N) return;
+    const PrimeC p = pc[i];
+    const u64 pinv = Pinv[i], pinv_sh = Pinv_sh[i];
+    u64x2 kb[BETA], ka[BETA];
+#pragma unroll
+    for (int j = 0; j < BETA; j++) {
+        kb[j] = ld2(key + (((size_t)j * 2 + 0) * nT + i) * N + k);
+        ka[j] = ld2(key + (((size_t)j * 2 + 1) * nT + i) * N + k);
+    }
+    const size_t li = (size_t)i * N + k;
+    for (int ct = ct0; ct < ct1; ct++) {
+        const int L1 = cts[ct].level + 1;
+        if (i >= L1) continue;
+        const int beta = (L1 + alpha - 1) / alpha;
+        const u64 *x = ext + ct * ext_stride + li;
+        u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < BETA; j++)
+            if (j < beta) {
+                const u64x2 dd = ld2(x + (size_t)j * dig_stride);
+                acc_wide(s0, mul_wide(dd.x, kb[j].x));
+                acc_wide(t0, mul_wide(dd.y, kb[j].y));
+                acc_wide(s1, mul_wide(dd.x, ka[j].x));
+                acc_wide(t1, mul_wide(dd.y, ka[j].y));
+            }
+        const u64 *cv = conv + ct * conv_stride + li;
+        const u64x2 c0 = ld2(cv), c1 = ld2(cv + per);
+        const u64 *ad = add + ct * add_stride + li;
+        const u64x2 a0 = ld2(ad), a1 = ld2(ad + per);
+        const u64 v0 = add_mod(shoup(sub_mod(redc(s0, p.q, p.qneg), c0.x, p.q), pinv, pinv_sh, p.q), a0.x, p.q);
+        const u64 w0 = add_mod(shoup(sub_mod(redc(t0, p.q, p.qneg), c0.y, p.q), pinv, pinv_sh, p.q), a0.y, p.q);
+        const u64 v1 = add_mod(shoup(sub_mod(redc(s1, p.q, p.qneg), c1.x, p.q), pinv, pinv_sh, p.q), a1.x, p.q);
+        const u64 w1 = add_mod(shoup(sub_mod(redc(t1, p.q, p.qneg), c1.y, p.q), pinv, pinv_sh, p.q), a1.y, p.q);
+        u64 *o = out + ct * out_stride + li;
+        st2(o, v0, w0);
+        st2(o + per, v1, w1);
+    }
+}
+
+// rescale: last[poly] = limb level_i of polynomial poly (coefficient pass follows)
+__global__ void k_rescale_last_list(const u64 *in, long in_poly_stride, u64 *last, int logN, int count,
+                                    const ListCt *cts)
+{
+    const size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= ((size_t)2 * count << logN)) return;
+    const size_t poly = i >> logN, k = i & (((size_t)1 << logN) - 1);
+    last[i] = in[poly * in_poly_stride + ((size_t)cts[poly / 2].level << logN) + k];
+}
+
+// lifted[poly][limb] for limb < level_i (layout [2 count][Lm][N])
+__global__ void k_rescale_lift_list(const u64 *last, u64 *lifted, int logN, int Lm, int count, const ListCt *cts,
+                                    const PrimeC *pc, const u64 *rs_qmod, int nQ)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t per = (size_t)Lm * N;
+    const size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= per * 2 * count) return;
+    const size_t poly = i / per, r = i % per;
+    const int limb = (int)(r >> logN), l = cts[poly / 2].level;
+    if (limb >= l) return;
+    const size_t k = r & (N - 1);
+    const PrimeC p = pc[limb];
+    const u64 ql = pc[l].q;
+    const u64 x = last[poly * N + k];
+    const u64 xm = shoup(x, 1, p.one_sh, p.q);
+    lifted[i] = (x <= (ql - 1) / 2) ? xm : sub_mod(xm, rs_qmod[(size_t)l * nQ + limb], p.q);
+}
+
+// out[poly][limb] = (in - lifted) * q_l^-1 for limb < level_i
+__global__ void k_rescale_finish_list(const u64 *in, long in_poly_stride, const u64 *lifted, u64 *out,
+                                      long out_poly_stride, int logN, int Lm, int count, const ListCt *cts,
+                                      const PrimeC *pc, const u64 *rs_inv, const u64 *rs_inv_sh, int nQ)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t per = (size_t)Lm * N;
+    const size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= per * 2 * count) return;
+    const size_t poly = i / per, r = i % per;
+    const int limb = (int)(r >> logN), l = cts[poly / 2].level;
+    if (limb >= l) return;
+    const u64 q = pc[limb].q;
+    const u64 x = in[poly * in_poly_stride + r];
+    const size_t ti = (size_t)l * nQ + limb;
+    out[poly * out_poly_stride + r] = shoup(sub_mod(x, lifted[i], q), rs_inv[ti], rs_inv_sh[ti], q);
+}
+
+void tensor_list_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, int Lm, int count,
+                        const ListCt *cts, hipStream_t st)
+{
+    const size_t total = (size_t)count * (Lm + 1) * c->N;
+    kt_begin(c, KC_TENSOR, st);
+    hipLaunchKernelGGL(k_tensor_list, dim3((unsigned)((total + EW_THREADS - 1) / EW_THREADS)), dim3(EW_THREADS), 0, st, a,
+                       b, out, c->logN, Lm + 1, count, cts, c->d_pc);
+    kt_end(c, KC_TENSOR, 7.0 * total * sizeof(u64), st);
+}
+
+void bconv_up_list_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, const u64 *d, long d_stride, u64 *ext,
+                          long ext_stride, long dig_stride, int Lm, int count, const ListCt *cts, hipStream_t st)
+{
+    const int betam = (Lm + 1 + c->alpha - 1) / c->alpha;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), betam, count);
+    kt_begin(c, KC_BCONV_UP, st);
+    if (c->alpha <= 4)
+        hipLaunchKernelGGL((k_bconv_up_list<4>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, d, d_stride, ext,
+                           ext_stride, dig_stride, c->logN, c->alpha, c->nP, c->nQ, cts, c->d_pc);
+    else if (c->alpha <= 8)
+        hipLaunchKernelGGL((k_bconv_up_list<8>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, d, d_stride, ext,
+                           ext_stride, dig_stride, c->logN, c->alpha, c->nP, c->nQ, cts, c->d_pc);
+    else
+        hipLaunchKernelGGL((k_bconv_up_list<16>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, d, d_stride, ext,
+                           ext_stride, dig_stride, c->logN, c->alpha, c->nP, c->nQ, cts, c->d_pc);
+    kt_end(c, KC_BCONV_UP, (double)count * betam * (Lm + 1 + c->nP) * c->N * sizeof(u64), st);
+}
+
+void bconv_down_list_launch(const rbk_ctx_impl *c, const u64 *tp, u64 *conv, long conv_stride, int Lm, int count,
+                            const ListCt *cts, hipStream_t st)
+{
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), 1, 2 * count);
+    kt_begin(c, KC_BCONV_DOWN, st);
+    if (c->nP <= 4)
+        hipLaunchKernelGGL((k_bconv_down_list<4>), grid, dim3(EW_THREADS), 0, st, tp, conv, conv_stride, c->logN, c->nP,
+                           c->nQ, cts, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
+    else if (c->nP <= 8)
+        hipLaunchKernelGGL((k_bconv_down_list<8>), grid, dim3(EW_THREADS), 0, st, tp, conv, conv_stride, c->logN, c->nP,
+                           c->nQ, cts, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
+    else
+        hipLaunchKernelGGL((k_bconv_down_list<16>), grid, dim3(EW_THREADS), 0, st, tp, conv, conv_stride, c->logN, c->nP,
+                           c->nQ, cts, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
+    kt_end(c, KC_BCONV_DOWN, 2.0 * count * (c->nP + Lm + 1) * c->N * sizeof(u64), st);
+}
+
+void ip_p_list_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, long dig_stride, const u64 *key, u64 *tp,
+                      int Lm, int count, const ListCt *cts, hipStream_t st)
+{
+    const int betam = (Lm + 1 + c->alpha - 1) / c->alpha;
+    const int cpc = c->ip_cpc;
+    dim3 grid((unsigned)((c->N / 2 + EW_THREADS - 1) / EW_THREADS), c->nP, (count + cpc - 1) / cpc);
+    kt_begin(c, KC_IP_P, st);
+#define IPL_CASE(B)                                                                                                \
+    case B:                                                                                                         \
+        hipLaunchKernelGGL(k_ip_p_list<B>, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, dig_stride, key, tp, c->logN, \
+                           c->alpha, c->nT, c->nQ, c->nP, count, cpc, cts, c->d_pc);                               \
+        break;
+    switch (betam) { IPL_CASE(1) IPL_CASE(2) IPL_CASE(3) IPL_CASE(4) IPL_CASE(5) IPL_CASE(6) IPL_CASE(7) default: IPL_CASE(8) }
+#undef IPL_CASE
+    kt_end(c, KC_IP_P, ((double)count * betam * c->nP + 2.0 * betam * c->nP + 2.0 * count * c->nP) * c->N * sizeof(u64), st);
+}
+
+void moddown_ip_list_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, long dig_stride, const u64 *key,
+                            const u64 *conv, long conv_stride, long per, const u64 *add, long add_stride, u64 *out,
+                            long out_stride, int Lm, int count, const ListCt *cts, hipStream_t st)
+{
+    const int betam = (Lm + 1 + c->alpha - 1) / c->alpha;
+    const int cpc = c->ip_cpc;
+    dim3 grid((unsigned)((c->N / 2 + EW_THREADS - 1) / EW_THREADS), Lm + 1, (count + cpc - 1) / cpc);
+    kt_begin(c, KC_MODDOWN_IP, st);
+#define MDL_CASE(B)                                                                                                   \
+    case B:                                                                                                            \
+        hipLaunchKernelGGL(k_moddown_ip_list<B>, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, dig_stride, key, conv,   \
+                           conv_stride, per, add, add_stride, out, out_stride, c->logN, c->alpha, c->nT, count, cpc, cts, \
+                           c->d_Pinv, c->d_Pinv_sh, c->d_pc);                                                          \
+        break;
+    switch (betam) { MDL_CASE(1) MDL_CASE(2) MDL_CASE(3) MDL_CASE(4) MDL_CASE(5) MDL_CASE(6) MDL_CASE(7) default: MDL_CASE(8) }
+#undef MDL_CASE
+    kt_end(c, KC_MODDOWN_IP, ((double)count * (Lm + 1) * (betam + 6) + 2.0 * betam * (Lm + 1)) * c->N * sizeof(u64), st);
+}
+
+void rescale_list_launch(const rbk_ctx_impl *c, int step, const u64 *in, long in_poly_stride, u64 *last, u64 *lifted,
+                         u64 *out, long out_poly_stride, int Lm, int count, const ListCt *cts, hipStream_t st)
+{
+    const size_t N = c->N;
+    if (step == 0) {
+        const size_t total = (size_t)2 * count * N;
+        hipLaunchKernelGGL(k_rescale_last_list, dim3((unsigned)((total + EW_THREADS - 1) / EW_THREADS)), dim3(EW_THREADS),
+                           0, st, in, in_poly_stride, last, c->logN, count, cts);
+        return;
+    }
+    const size_t total = (size_t)2 * count * Lm * N;
+    if (total == 0) return;
+    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    kt_begin(c, KC_RESCALE, st);
+    if (step == 1)
+        hipLaunchKernelGGL(k_rescale_lift_list, grid, dim3(EW_THREADS), 0, st, last, lifted, c->logN, Lm, count, cts,
+                           c->d_pc, c->d_rs_qmod, c->nQ);
+    else
+        hipLaunchKernelGGL(k_rescale_finish_list, grid, dim3(EW_THREADS), 0, st, in, in_poly_stride, lifted, out,
+                           out_poly_stride, c->logN, Lm, count, cts, c->d_pc, c->d_rs_inv, c->d_rs_inv_sh, c->nQ);
+    kt_end(c, KC_RESCALE, 3.0 * total * sizeof(u64), st);
+}

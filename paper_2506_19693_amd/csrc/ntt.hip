@@ -42,22 +42,20 @@ __device__ __forceinline__ void bfly_gs(u64 &x, u64 &y, u64 w, u64 wsh, u64 q, u
 // Row pass.  Forward: stages (logN-logC) .. logN-1, output reduced to [0, q).
 // Inverse: distances 1 .. C/2; if logC == logN this is the whole inverse
 // (N^-1 folded into the last stage, output in [0, q)), else output in [0, 2q).
+// body of one row tile; limb: the limb's first element, s: NTT_TILE words of LDS
 template <bool INV>
-__global__ __launch_bounds__(NTT_THREADS) void k_ntt_rows(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN,
-                                                          int logC, int rows_per_tile)
+__device__ __forceinline__ void ntt_rows_tile(u64 *limb_base, u64 *s, const NttTables &T, int pr, int logN, int logC,
+                                              int rows_per_tile, int tile)
 {
-    __shared__ u64 s[NTT_TILE];
-    const int limb = blockIdx.y, poly = blockIdx.z;
-    const int pr = map.prime(limb);
     const size_t N = (size_t)1 << logN;
     const PrimeC pc = T.pc[pr];
     const u64 q = pc.q, q2 = 2 * q;
     const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
     const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
     const int C = 1 << logC;
-    const int row0 = blockIdx.x * rows_per_tile;
+    const int row0 = tile * rows_per_tile;
     const int nel = rows_per_tile * C;
-    u64 *g = data + (size_t)poly * poly_stride + (size_t)limb * N + (size_t)row0 * C;
+    u64 *g = limb_base + (size_t)row0 * C;
 
     for (int i = threadIdx.x; i < nel; i += NTT_THREADS) s[i] = g[i];
     __syncthreads();
@@ -108,6 +106,16 @@ __global__ __launch_bounds__(NTT_THREADS) void k_ntt_rows(u64 *data, long poly_s
         else
             for (int i = threadIdx.x; i < nel; i += NTT_THREADS) g[i] = s[i];
     }
+}
+
+template <bool INV>
+__global__ __launch_bounds__(NTT_THREADS) void k_ntt_rows(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN,
+                                                          int logC, int rows_per_tile)
+{
+    __shared__ u64 s[NTT_TILE];
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    u64 *base = data + (size_t)poly * poly_stride + ((size_t)limb << logN);
+    ntt_rows_tile<INV>(base, s, T, map.prime(limb), logN, logC, rows_per_tile, blockIdx.x);
 }
 
 // Column pass over R = 2^(logN-logC) rows and 'cols' adjacent columns.
@@ -406,16 +414,14 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
     }
 }
 
+// One tile (4096 elements: LINES lines of S) of one pass over the limb at
+// base (prime pr of the tables T).  sm: LINES * LS words of LDS.
 template <int LOGS, bool INV, bool COLS>
-__global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN)
+__device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, const NttTables &T, int pr, int tile, int logN)
 {
     typedef Geo<LOGS> G;
     constexpr int NST2 = LOGS - 4;
-    __shared__ u64 sm[G::LINES * G::LS];
-    const int limb = blockIdx.z, poly = blockIdx.y;
-    const int pr = map.prime(limb);
     const size_t N = (size_t)1 << logN;
-    u64 *base = data + (size_t)poly * poly_stride + (size_t)limb * N;
     const int tid = threadIdx.x;
     int line, t;
     if (COLS) {
@@ -425,7 +431,7 @@ __global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, Limb
         t = tid % G::TPL;
         line = tid / G::TPL;
     }
-    const int gl = blockIdx.x * G::LINES + line;          // column (COLS) or row index
+    const int gl = tile * G::LINES + line;                // column (COLS) or row index
     const FpC fc = T.fc[pr];
     if (fc.use) {
         ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, (INV ? T.itwf : T.twf) + (size_t)pr * N, t, gl, logN);
@@ -492,6 +498,52 @@ __global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, Limb
 #pragma unroll
             for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = x[i];
         }
+    }
+}
+
+template <int LOGS, bool INV, bool COLS>
+__global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN)
+{
+    __shared__ u64 sm[Geo<LOGS>::LINES * Geo<LOGS>::LS];
+    const int limb = blockIdx.z, poly = blockIdx.y;
+    u64 *base = data + (size_t)poly * poly_stride + ((size_t)limb << logN);
+    ntt16_tile<LOGS, INV, COLS>(base, sm, T, map.prime(limb), blockIdx.x, logN);
+}
+
+// Descriptor-list form: a persistent grid walks the (item, tile) units of a
+// list of limbs that may belong to different ring degrees, primes and
+// contexts.  FIRST selects the first pass of the transform (the column pass
+// of a forward transform, the row pass of an inverse one); the caller
+// launches FIRST, then the second pass, over the same list.
+// Items with N <= 4096 take one row pass over the whole limb (in the first
+// launch); they have no units in the second.
+template <bool INV, bool FIRST>
+__global__ __launch_bounds__(256) void k_ntt16_list(const NttItem *items, const int *prefix, int n_items, int total)
+{
+    __shared__ u64 sm[Geo<8>::LINES * Geo<8>::LS > NTT_TILE ? Geo<8>::LINES * Geo<8>::LS : NTT_TILE];
+    constexpr bool COLS = INV ? !FIRST : FIRST;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        // the item holding unit u: prefix[it] <= u < prefix[it + 1]
+        int lo = 0, hi = n_items - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        const NttItem it = items[lo];
+        const int tile = u - prefix[lo];
+        if (it.logN <= 12) {
+            ntt_rows_tile<INV>(it.data, sm, *it.tabs, it.prime, it.logN, it.logN, 1, 0);
+            __syncthreads();
+            continue;
+        }
+        const int logs = COLS ? it.logN - it.logC : it.logC;
+        switch (logs) {
+        case 6: ntt16_tile<6, INV, COLS>(it.data, sm, *it.tabs, it.prime, tile, it.logN); break;
+        case 7: ntt16_tile<7, INV, COLS>(it.data, sm, *it.tabs, it.prime, tile, it.logN); break;
+        default: ntt16_tile<8, INV, COLS>(it.data, sm, *it.tabs, it.prime, tile, it.logN); break;
+        }
+        __syncthreads();  // the next unit reuses the LDS tile
     }
 }
 
@@ -572,5 +624,29 @@ void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, i
         kt_begin(c, KC_NTT_COLS_INV, st);
         hipLaunchKernelGGL(k_ntt_cols<true>, gcol, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, logCt);
         kt_end(c, KC_NTT_COLS_INV, bytes, st);
+    }
+}
+
+// units of an item in the first / second launch of a list transform
+int ntt_item_units(int logN, bool first)
+{
+    if (logN <= 12) return first ? 1 : 0;
+    return 1 << (logN - 12);
+}
+
+void ntt_list_launch(const NttItem *d_items, const int *d_prefix1, const int *d_prefix2, int n_items, int total1,
+                     int total2, bool inverse, hipStream_t st)
+{
+    // persistent grid: four resident blocks per compute unit
+    const int cap = 4 * 256;
+    if (total1 > 0) {
+        dim3 g1(std::min(total1, cap));
+        if (inverse) hipLaunchKernelGGL((k_ntt16_list<true, true>), g1, dim3(256), 0, st, d_items, d_prefix1, n_items, total1);
+        else hipLaunchKernelGGL((k_ntt16_list<false, true>), g1, dim3(256), 0, st, d_items, d_prefix1, n_items, total1);
+    }
+    if (total2 > 0) {
+        dim3 g2(std::min(total2, cap));
+        if (inverse) hipLaunchKernelGGL((k_ntt16_list<true, false>), g2, dim3(256), 0, st, d_items, d_prefix2, n_items, total2);
+        else hipLaunchKernelGGL((k_ntt16_list<false, false>), g2, dim3(256), 0, st, d_items, d_prefix2, n_items, total2);
     }
 }

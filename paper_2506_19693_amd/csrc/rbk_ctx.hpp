@@ -5,6 +5,7 @@
 
 #include <map>
 #include <string>
+#include <cstring>
 #include <vector>
 
 #include "rbk_internal.hpp"
@@ -63,6 +64,7 @@ struct rbk_ctx_impl {
     u64 *d_last = nullptr, *d_last_sh = nullptr;
     double2 *d_twf = nullptr, *d_itwf = nullptr;
     FpC *d_fc = nullptr;
+    NttTables *d_tabs = nullptr;  // device copy of tabs, for descriptor-list transforms
     NttTables tabs{};
 
     // ModDown P -> Q (level independent, indexed by Q prime)
@@ -101,12 +103,38 @@ struct rbk_ctx_impl {
     // alive, a buffer that is replaced is retired instead of freed
     int live_graphs = 0;
     std::vector<void *> retired;
+    // descriptor uploads of the list entry points: one device arena reused by
+    // every call (stream order protects it) and two pinned host arenas used
+    // in turn, each reusable once the event after its last copy has passed
+    void *desc_dev = nullptr;
+    size_t desc_dev_bytes = 0;
+    void *desc_host[2] = {nullptr, nullptr};
+    size_t desc_host_bytes[2] = {0, 0};
+    hipEvent_t desc_evt[2] = {nullptr, nullptr};
+    int desc_turn = 0;
     mutable KTimer timers[KC_COUNT];
     mutable std::vector<hipEvent_t> event_pool;
 };
 
 // the opaque handle of the C ABI
 struct rbk_ctx : rbk_ctx_impl {};
+
+// Host-side packing of the descriptor arrays of one list call; every part is
+// 16-byte aligned.  desc_upload copies the blob to the context's device
+// arena on its stream and returns the device address (null on failure, with
+// the error set and its code in *rc).
+struct DescBlob {
+    std::vector<char> h;
+    template <class T>
+    size_t put(const T *p, size_t n)
+    {
+        const size_t off = (h.size() + 15) & ~(size_t)15;
+        h.resize(off + n * sizeof(T));
+        if (n) std::memcpy(h.data() + off, p, n * sizeof(T));
+        return off;
+    }
+};
+char *desc_upload(rbk_ctx_impl *c, const DescBlob &b, int *rc);
 
 // timer hooks around a launch (no-ops unless timing is enabled)
 void kt_begin(const rbk_ctx_impl *c, int cls, hipStream_t st);
@@ -192,3 +220,26 @@ int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d, long 
 // out = Rot_g of count contiguous ciphertexts [count][2][l+1][N]
 int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g);
 int rbk_set_error(int code, const char *msg);
+
+// ---- batches of uneven level (kernels.hip, list.hip) ----
+// Per-ciphertext entry of a batch whose ciphertexts differ in level: the
+// level and the ModUp tables of that level.
+struct ListCt {
+    int level;
+    int pad;
+    const u64 *A, *Ash, *M;
+};
+void tensor_list_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, int Lm, int count,
+                        const ListCt *cts, hipStream_t st);
+void bconv_up_list_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, const u64 *d, long d_stride, u64 *ext,
+                          long ext_stride, long dig_stride, int Lm, int count, const ListCt *cts, hipStream_t st);
+void bconv_down_list_launch(const rbk_ctx_impl *c, const u64 *tp, u64 *conv, long conv_stride, int Lm, int count,
+                            const ListCt *cts, hipStream_t st);
+void ip_p_list_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, long dig_stride, const u64 *key, u64 *tp,
+                      int Lm, int count, const ListCt *cts, hipStream_t st);
+void moddown_ip_list_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, long dig_stride, const u64 *key,
+                            const u64 *conv, long conv_stride, long per, const u64 *add, long add_stride, u64 *out,
+                            long out_stride, int Lm, int count, const ListCt *cts, hipStream_t st);
+// step 0: gather the last limbs; 1: lift; 2: finish
+void rescale_list_launch(const rbk_ctx_impl *c, int step, const u64 *in, long in_poly_stride, u64 *last, u64 *lifted,
+                         u64 *out, long out_poly_stride, int Lm, int count, const ListCt *cts, hipStream_t st);

@@ -53,8 +53,23 @@ struct DevKey {
     u64 g = 0;            // Galois element, 0 for the relinearisation key
 };
 
+// One limb of one polynomial for the descriptor-list NTT: N = 2^logN
+// residues at data, modulo prime `prime` of the tables at tabs (a device
+// copy of a context's NttTables); logC is that context's NTT split.
+struct NttItem {
+    u64 *data;
+    const NttTables *tabs;
+    int prime;
+    int logN;
+    int logC;
+    int pad;
+};
+
 struct rbk_ctx_impl;
 
 // ---- launchers (defined in the .hip files) ----
 void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, bool inverse,
                 hipStream_t st);
+int ntt_item_units(int logN, bool first);
+void ntt_list_launch(const NttItem *d_items, const int *d_prefix1, const int *d_prefix2, int n_items, int total1,
+                     int total2, bool inverse, hipStream_t st);

@@ -105,6 +105,15 @@ class RbkBootParams(ctypes.Structure):
     ]
 
 
+class RbkNttItem(ctypes.Structure):
+    _fields_ = [
+        ("ctx", ctypes.c_void_p),
+        ("d_limb", ctypes.c_void_p),
+        ("prime", ctypes.c_int),
+        ("pad", ctypes.c_int),
+    ]
+
+
 # name -> (restype, argtypes); the declarations of include/rbk.h
 SIGNATURES = {
     "rbk_ctx_create": (ci, [ctypes.POINTER(RbkParams), ctypes.POINTER(vp)]),
@@ -148,6 +157,8 @@ SIGNATURES = {
     "rbk_rotate_hoisted": (ci, [vp, vp, i64p, ci, vp, ci]),
     "rbk_mult_relin_batch": (ci, [vp, vp, vp, vp, ci, ci]),
     "rbk_rescale_batch": (ci, [vp, vp, vp, ci, ci]),
+    "rbk_ntt_list": (ci, [vp, ctypes.POINTER(RbkNttItem), ci, ci]),
+    "rbk_mult_relin_rescale_list": (ci, [vp, vp, vp, vp, ctypes.POINTER(ci), ci]),
     "rbk_rotate_hoisted_batch": (ci, [vp, vp, i64p, ci, vp, ci, ci]),
     "rbk_boot_setup": (ci, [vp, ctypes.POINTER(RbkBootParams)]),
     "rbk_boot_rotations": (ci, [vp, i64p, ci]),
@@ -652,6 +663,30 @@ class Context:
         out = self.empty_ct(level - 1, count) if out is None else out
         _check(self.lib.rbk_rescale_batch(self.h, _ptr(ct), _ptr(out), level, count))
         return out
+
+    def mult_relin_rescale_list(self, a, b, levels, out=None):
+        """Uneven levels in one batch: a, b [count][2][Lm+1][N] with ciphertext
+        i in limbs 0..levels[i]; returns [count][2][Lm][N] with ciphertext i's
+        rescaled product in limbs 0..levels[i]-1."""
+        count = a.shape[0]
+        Lm = max(levels)
+        if len(levels) != count or a.shape[2] != Lm + 1 or b.shape != a.shape:
+            raise ValueError("a, b must be [count][2][max(levels)+1][N]")
+        out = self.empty_ct(Lm - 1, count) if out is None else out
+        lv = (ci * count)(*[int(x) for x in levels])
+        _check(self.lib.rbk_mult_relin_rescale_list(self.h, _ptr(a), _ptr(b), _ptr(out), lv, count))
+        return out
+
+    def ntt_list(self, items, inverse=False):
+        """In-place NTT of a list of limbs: items = [(ctx, tensor, offset, prime)],
+        the limb being the N residues of ctx's ring at tensor's element offset;
+        launched on this context's stream."""
+        arr = (RbkNttItem * len(items))()
+        for k, (ctx, t, off, prime) in enumerate(items):
+            if t.dtype.itemsize != 8 or off < 0 or off + ctx.N > t.numel():
+                raise ValueError("limb outside its tensor")
+            arr[k] = RbkNttItem(ctx.h, t.data_ptr() + 8 * off, int(prime), 0)
+        _check(self.lib.rbk_ntt_list(self.h, arr, len(items), 1 if inverse else 0))
 
     def rotate_hoisted_batch(self, ct, ks, level, out=None):
         count = ct.shape[0]

@@ -235,6 +235,37 @@ def test_batched_equals_plain(name):
         assert np.array_equal(down(p, hb[c], level), down(p, d.rotate_hoisted(A[c], ks, level), level))
 
 
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_uneven_level_list_bit_exact(name):
+    """Ciphertexts at uneven levels in one list call: each equals the
+    oracle's rescale(mult_relin) at its own level; limbs outside a
+    ciphertext's level are neither read (junk there) nor written."""
+    import torch
+
+    p = pair(name)
+    o, d = p.orc, p.gpu
+    L = o.L
+    levels = [L, 1, max(1, L - 1), min(2, L), L, 1]
+    Lm, cnt = max(levels), len(levels)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    junk = lambda *sh: torch.randint(-(2 ** 62), 2 ** 62, sh, generator=gen, dtype=torch.int64).cuda()
+    A, B = junk(cnt, 2, Lm + 1, p.N), junk(cnt, 2, Lm + 1, p.N)
+    host = []
+    for i, l in enumerate(levels):
+        a, b = p.rand_ct(l), p.rand_ct(l)
+        A[i, :, : l + 1] = up(p, a, l)
+        B[i, :, : l + 1] = up(p, b, l)
+        host.append((a, b))
+    sentinel = 0x5A5A5A5A5A5A5A5
+    out = d.empty_ct(Lm - 1, cnt).fill_(sentinel)
+    d.mult_relin_rescale_list(A, B, levels, out)
+    for i, l in enumerate(levels):
+        a, b = host[i]
+        want = o.rescale(l, o.mult_relin(l, p.rlk, a, b))
+        assert np.array_equal(down(p, out[i, :, :l].contiguous(), l - 1), want), (i, l)
+        assert bool((out[i, :, l:] == sentinel).all()), (i, l)
+
+
 # ---------------------------------------------------------------- encoding and end to end
 
 @pytest.mark.parametrize("name", list(PARAMS))
