@@ -582,7 +582,21 @@ def bench_serve(args, torch):
     if args.serve_calibrate:
         out["calibration_capacity_jobs_per_s"] = len(jobs) / mk
         out["lambda_for_0.8"] = 0.8 * len(jobs) / mk
-    elif not args.no_plain:
+    else:
+        # the same jobs submitted at once: the queue builds up, so batches merge
+        # (mult jobs of any level through the uneven-level list path)
+        burst = [(0.0, i, k, p) for (_, i, k, p) in jobs]
+        mk_b, lat_b, st_b = _serve_run(tenants, burst, budget, args.serve_max_batch, args.serve_max_boot, torch)
+        log("serving: burst of %d jobs done in %.1f s, %d batches" % (len(burst), mk_b, st_b["batches"]))
+        out["burst"] = {
+            "jobs_per_s": len(burst) / mk_b,
+            "makespan_s": mk_b,
+            "latency_ms_p50": percentile(lat_b, 50),
+            "latency_ms_p99": percentile(lat_b, 99),
+            "batches": st_b["batches"],
+            "jobs_merged": st_b["jobs_merged"],
+        }
+    if not args.serve_calibrate and not args.no_plain:
         mk_s, lat_s = _serial_run(tenants, jobs, torch)
         out["serial_plain"] = {
             "jobs_per_s": len(jobs) / mk_s,

@@ -86,15 +86,29 @@ struct rbk_server {
 
 namespace {
 
+// mult jobs of any level share batches (the uneven-level list path) when the
+// context supports it: hybrid key switching and a ring degree up to 2^16
+bool mixed_levels(const rbk_ctx *c)
+{
+    if (c->nP < 1) return false;
+    if (c->logN <= 12) return true;
+    const int r = c->logN - c->ntt_logC;
+    return c->logN <= 16 && r >= 6 && r <= 8 && c->ntt_logC >= 6 && c->ntt_logC <= 8;
+}
+
 // working-set estimate of a job, bytes (admission only; see rbk.h).  Jobs run
 // in chunks of at most max_batch (mult) / max_boot (bootstrap) ciphertexts.
+// A mult job of a mixed-level tenant may share a chunk with ciphertexts of
+// the top level, whose slot strides the whole chunk then uses: its working
+// set is counted at the top level.
 uint64_t footprint(const rbk_ctx *c, const rbk_job &j, int max_batch, int max_boot)
 {
     const uint64_t w8 = sizeof(u64);
     switch (j.kind) {
     case RBK_JOB_MULT_RESCALE: {
-        const uint64_t ct = ct_words(c, j.level), n = (uint64_t)std::min(j.count, max_batch);
-        return w8 * ((uint64_t)j.count * ct + n * (2 * ct + 3 * ct / 2 + ct + ct) + ks_words(c, j.level, (int)n));
+        const int wl = mixed_levels(c) ? c->nQ - 1 : j.level;
+        const uint64_t ct = ct_words(c, j.level), cw = ct_words(c, wl), n = (uint64_t)std::min(j.count, max_batch);
+        return w8 * ((uint64_t)j.count * ct + n * (2 * cw + 3 * cw / 2 + cw + cw) + ks_words(c, wl, (int)n));
     }
     case RBK_JOB_BOOTSTRAP:
         return w8 * (uint64_t)std::min(j.count, max_boot) * 48 * ct_words(c, c->nQ - 1);
@@ -120,12 +134,14 @@ u64 *stage_reserve(Tenant *t, size_t words)
 }
 
 // copy limbs 0..level of every polynomial of count ciphertexts laid out at
-// in_level into a contiguous batch at level
-int gather(Tenant *t, const uint64_t *src, int in_level, int level, int count, u64 *dst)
+// in_level into a batch whose slots are laid out at slot_level (default: level)
+int gather(Tenant *t, const uint64_t *src, int in_level, int level, int count, u64 *dst, int slot_level = -1)
 {
     const rbk_ctx *c = t->c;
+    if (slot_level < 0) slot_level = level;
     const size_t N = c->N, w = (size_t)(level + 1) * N, sp = (size_t)(in_level + 1) * N;
-    if (hipMemcpy2DAsync(dst, w * sizeof(u64), src, sp * sizeof(u64), w * sizeof(u64), (size_t)2 * count,
+    const size_t dp = (size_t)(slot_level + 1) * N;
+    if (hipMemcpy2DAsync(dst, dp * sizeof(u64), src, sp * sizeof(u64), w * sizeof(u64), (size_t)2 * count,
                          hipMemcpyDeviceToDevice, t->st) != hipSuccess)
         return rbk_set_error(RBK_EDEVICE, "gather copy failed");
     return RBK_OK;
@@ -157,9 +173,53 @@ std::vector<std::vector<Piece>> chunks(std::vector<SJob *> &b, int cap)
     return out;
 }
 
+// a batch of mult jobs at uneven levels: slots at the chunk's largest level,
+// one uneven-level list call per chunk
+int run_mult_list(Tenant *t, std::vector<SJob *> &b, int cap)
+{
+    rbk_ctx *c = t->c;
+    const size_t N = c->N;
+    for (auto &ch : chunks(b, cap)) {
+        int total = 0, Lm = 0, rc;
+        std::vector<int> levels;
+        for (auto &p : ch) {
+            total += p.n;
+            Lm = std::max(Lm, p.s->j.level);
+            levels.insert(levels.end(), (size_t)p.n, p.s->j.level);
+        }
+        const size_t ct = ct_words(c, Lm), ct_out = ct_words(c, Lm - 1);
+        u64 *A = stage_reserve(t, (size_t)total * (2 * ct + ct_out));
+        if (!A) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
+        u64 *B = A + (size_t)total * ct, *R = B + (size_t)total * ct;
+        int off = 0;
+        for (auto &p : ch) {
+            const rbk_job &j = p.s->j;
+            const size_t in_ct = ct_words(c, j.in_level);
+            if ((rc = gather(t, j.d_a + p.first * in_ct, j.in_level, j.level, p.n, A + (size_t)off * ct, Lm))) return rc;
+            if ((rc = gather(t, j.d_b + p.first * in_ct, j.in_level, j.level, p.n, B + (size_t)off * ct, Lm))) return rc;
+            off += p.n;
+        }
+        if ((rc = rbk_mult_relin_rescale_list(c, A, B, R, levels.data(), total))) return rc;
+        off = 0;
+        for (auto &p : ch) {
+            // limbs 0..l-1 of each polynomial from slots of Lm limbs
+            const int l = p.s->j.level;
+            const size_t w = (size_t)l * N;
+            if (hipMemcpy2DAsync(p.s->j.d_out + p.first * ct_words(c, l - 1), w * sizeof(u64),
+                                 R + (size_t)off * ct_out, (size_t)Lm * N * sizeof(u64), w * sizeof(u64),
+                                 (size_t)2 * p.n, hipMemcpyDeviceToDevice, t->st) != hipSuccess)
+                return rbk_set_error(RBK_EDEVICE, "scatter copy failed");
+            off += p.n;
+        }
+    }
+    return RBK_OK;
+}
+
 int run_mult(Tenant *t, std::vector<SJob *> &b, int cap)
 {
     rbk_ctx *c = t->c;
+    for (SJob *s : b)
+        if (s->j.level != b[0]->j.level) return run_mult_list(t, b, cap);
     const int lv = b[0]->j.level;
     const size_t ct = ct_words(c, lv), ct_out = ct_words(c, lv - 1);
     for (auto &ch : chunks(b, cap)) {
@@ -313,7 +373,7 @@ extern "C" int rbk_server_add_tenant(rbk_server *S, rbk_ctx *c, int *tenant)
     t->id = (int)S->tenants.size();
     t->c = c;
     t->resident = key_bytes(c) + boot_resident_bytes(c);
-    if (!S->sched.add_tenant(t->id, t->resident)) {
+    if (!S->sched.add_tenant(t->id, t->resident, mixed_levels(c))) {
         delete t;
         return rbk_set_error(RBK_ENOMEM, "the tenant's resident keys do not fit the HBM budget");
     }

@@ -11,8 +11,10 @@
 // * A tenant's next batch is its oldest admitted job plus every later admitted
 //   job of the same kind and level, while the ciphertext total stays within
 //   the kind's cap (max_boot_batch for bootstraps, max_batch otherwise; a first
-//   job above the cap runs alone).  Jobs of kind KIND_SOLO (a training step)
-//   are never merged.
+//   job above the cap runs alone).  For a tenant registered with mixed_levels,
+//   KIND_MULT jobs merge whatever their level (the server runs such batches
+//   through the uneven-level list path).  Jobs of kind KIND_SOLO (a training
+//   step) are never merged.
 // * Completing a batch releases its footprints.
 #pragma once
 #include <cstddef>
@@ -45,7 +47,7 @@ public:
     }
 
     // false if the resident bytes do not fit next to what is already resident
-    bool add_tenant(int tenant, uint64_t resident)
+    bool add_tenant(int tenant, uint64_t resident, bool mixed_levels = false)
     {
         if (ready_.count(tenant)) return false;
         if (resident_ + resident > budget_) return false;
@@ -53,6 +55,7 @@ public:
         ledger_ += resident;
         peak_ = ledger_ > peak_ ? ledger_ : peak_;
         ready_[tenant];
+        mixed_[tenant] = mixed_levels;
         return true;
     }
 
@@ -102,10 +105,11 @@ public:
         q.pop_front();
         if (b[0].kind == KIND_SOLO) return b;
         const int cap = b[0].kind == KIND_BOOT ? max_boot_ : max_batch_;
+        const bool any_level = b[0].kind == KIND_MULT && mixed_[tenant];
         int total = b[0].count;
         for (size_t k = 0; k < q.size();) {
             const Job &x = q[k];
-            if (x.kind == b[0].kind && x.level == b[0].level && total + x.count <= cap) {
+            if (x.kind == b[0].kind && (any_level || x.level == b[0].level) && total + x.count <= cap) {
                 total += x.count;
                 b.push_back(x);
                 q.erase(q.begin() + (long)k);
@@ -136,6 +140,7 @@ private:
     int max_batch_, max_boot_, max_skips_, head_skips_ = 0;
     std::deque<Job> pending_;
     std::map<int, std::deque<Job>> ready_;
+    std::map<int, bool> mixed_;
 };
 
 }  // namespace rbk_sched

@@ -94,6 +94,26 @@ int main()
         CHECK(s.next_batch(0).empty());
         CHECK((ids(s.next_batch(1)) == std::vector<uint64_t>{6}));        // other tenant, own queue
     }
+    // a mixed-level tenant merges mult jobs of any level (bootstraps still by level)
+    {
+        Scheduler s(1 << 30, 16, 8);
+        CHECK(s.add_tenant(0, 0, true));
+        CHECK(s.add_tenant(1, 0, false));
+        CHECK(s.submit(job(1, 0, KIND_MULT, 5, 4, 1)));
+        CHECK(s.submit(job(2, 0, KIND_MULT, 9, 4, 1)));
+        CHECK(s.submit(job(3, 0, KIND_BOOT, 0, 2, 1)));
+        CHECK(s.submit(job(4, 0, KIND_BOOT, 1, 2, 1)));
+        CHECK(s.submit(job(5, 0, KIND_MULT, 2, 10, 1)));
+        CHECK(s.submit(job(6, 1, KIND_MULT, 5, 4, 1)));
+        CHECK(s.submit(job(7, 1, KIND_MULT, 9, 4, 1)));
+        CHECK(s.admit().size() == 7);
+        CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{1, 2}));     // levels 5 and 9 together; 18 > 16
+        CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{3}));        // bootstraps: same level only
+        CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{4}));
+        CHECK((ids(s.next_batch(0)) == std::vector<uint64_t>{5}));
+        CHECK((ids(s.next_batch(1)) == std::vector<uint64_t>{6}));        // not mixed: by level
+        CHECK((ids(s.next_batch(1)) == std::vector<uint64_t>{7}));
+    }
     // backfill past a head that does not fit, bounded by max_skips
     {
         Scheduler s(100, 64, 16, 3);
