@@ -677,7 +677,8 @@ def bench_keyswitch(args, torch):
     ctx.reserve(L, count)
     tuned = ctx.autotune(L - 1, count, os.path.join(os.path.expanduser("~"), ".cache", "rbk_tune.txt")
                          if os.path.isdir(os.path.join(os.path.expanduser("~"), ".cache")) else None)
-    log("autotuned: NTT split 2^%d columns, %d ciphertexts per inner-product thread" % (tuned["logC"], tuned["cpc"]))
+    log("autotuned: NTT split 2^%d columns, NTT chunk %d limbs, %d ciphertexts per inner-product thread" % (
+        tuned["logC"], tuned["chunk"], tuned["cpc"]))
     out_m = ctx.empty_ct(L, count)
     out_r = ctx.empty_ct(L - 1, count)
     out_h = ctx.empty(count, len(ks), 2, L, ctx.N)

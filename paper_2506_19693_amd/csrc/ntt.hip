@@ -17,6 +17,8 @@
 //
 // Value ranges follow Harvey: forward butterflies keep [0, 4q), inverse
 // butterflies [0, 2q); each pass that ends a transform reduces to [0, q).
+#include <algorithm>
+
 #include "rbk_internal.hpp"
 #include "rbk_ctx.hpp"
 
@@ -587,20 +589,28 @@ void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, i
         return;
     }
     if (logN >= 13 && logN <= 16 && r >= 6 && r <= 8 && logC >= 6 && logC <= 8) {
-        if (!inverse) {
-            kt_begin(c, KC_NTT_COLS_FWD, st);
-            launch16_logs<false, true>(r, data, poly_stride, npoly, nlimbs, map, T, logN, st);
-            kt_end(c, KC_NTT_COLS_FWD, bytes, st);
-            kt_begin(c, KC_NTT_ROWS_FWD, st);
-            launch16_logs<false, false>(logC, data, poly_stride, npoly, nlimbs, map, T, logN, st);
-            kt_end(c, KC_NTT_ROWS_FWD, bytes, st);
-        } else {
-            kt_begin(c, KC_NTT_ROWS_INV, st);
-            launch16_logs<true, false>(logC, data, poly_stride, npoly, nlimbs, map, T, logN, st);
-            kt_end(c, KC_NTT_ROWS_INV, bytes, st);
-            kt_begin(c, KC_NTT_COLS_INV, st);
-            launch16_logs<true, true>(r, data, poly_stride, npoly, nlimbs, map, T, logN, st);
-            kt_end(c, KC_NTT_COLS_INV, bytes, st);
+        // chunks of whole polynomials, both passes per chunk
+        int ppc = npoly;
+        if (c->ntt_chunk > 0 && (long)npoly * nlimbs > c->ntt_chunk) ppc = std::max(1, c->ntt_chunk / nlimbs);
+        for (int p0 = 0; p0 < npoly; p0 += ppc) {
+            const int np = std::min(ppc, npoly - p0);
+            u64 *d = data + (size_t)p0 * poly_stride;
+            const double cb = bytes * np / npoly;
+            if (!inverse) {
+                kt_begin(c, KC_NTT_COLS_FWD, st);
+                launch16_logs<false, true>(r, d, poly_stride, np, nlimbs, map, T, logN, st);
+                kt_end(c, KC_NTT_COLS_FWD, cb, st);
+                kt_begin(c, KC_NTT_ROWS_FWD, st);
+                launch16_logs<false, false>(logC, d, poly_stride, np, nlimbs, map, T, logN, st);
+                kt_end(c, KC_NTT_ROWS_FWD, cb, st);
+            } else {
+                kt_begin(c, KC_NTT_ROWS_INV, st);
+                launch16_logs<true, false>(logC, d, poly_stride, np, nlimbs, map, T, logN, st);
+                kt_end(c, KC_NTT_ROWS_INV, cb, st);
+                kt_begin(c, KC_NTT_COLS_INV, st);
+                launch16_logs<true, true>(r, d, poly_stride, np, nlimbs, map, T, logN, st);
+                kt_end(c, KC_NTT_COLS_INV, cb, st);
+            }
         }
         return;
     }

@@ -55,6 +55,10 @@ struct rbk_ctx_impl {
     int nQ = 0, nP = 0, nT = 0, alpha = 1, beta = 1;
     int ntt_logC = 0;   // NTT split: a limb is a 2^(logN - ntt_logC) x 2^ntt_logC matrix
     int ip_cpc = 8;     // ciphertexts per thread of the fused key inner products
+    // limbs per chunk of a two-pass NTT launch: both passes run over one chunk
+    // before the next, so the intermediate can stay in the memory-side cache
+    // (0: one pair of launches over the whole batch)
+    int ntt_chunk = 512;
     std::vector<u64> mod, psi;
     std::vector<PrimeC> h_pc;
 

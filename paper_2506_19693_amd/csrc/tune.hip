@@ -1,9 +1,12 @@
 // Autotuner of the batched key-switching path.
 //
-// Two launch parameters leave every residue unchanged but move the speed:
+// Three launch parameters leave every residue unchanged but move the speed:
 //  * the NTT split: a limb of N = 2^logN residues is transformed as an
 //    R x C matrix, C = 2^logC (column pass, then row pass); the register
 //    kernels support R, C in 2^6 .. 2^8;
+//  * the NTT chunk: how many limbs one pair of pass launches covers before
+//    the next chunk starts (the intermediate of a chunk the size of the
+//    memory-side cache is read back from it rather than from HBM);
 //  * the ciphertexts per thread of the fused key inner products (ip_p and
 //    moddown_ip): more share each key word among more ciphertexts, fewer
 //    give more workgroups.
@@ -41,7 +44,7 @@ std::string tune_key(const rbk_ctx *c, int level, int count)
     return os.str();
 }
 
-bool cache_lookup(const char *path, const std::string &key, int &logC, int &cpc)
+bool cache_lookup(const char *path, const std::string &key, int &logC, int &cpc, int &chunk)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -50,10 +53,11 @@ bool cache_lookup(const char *path, const std::string &key, int &logC, int &cpc)
     while (std::getline(f, line)) {
         const size_t bar = line.find(" : ");
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
-        int a = 0, b = 0;
-        if (std::sscanf(line.c_str() + bar + 3, "logC=%d cpc=%d", &a, &b) == 2) {
+        int a = 0, b = 0, k = 0;
+        if (std::sscanf(line.c_str() + bar + 3, "logC=%d cpc=%d chunk=%d", &a, &b, &k) == 3) {
             logC = a;
             cpc = b;
+            chunk = k;
             found = true;  // the last entry of a key wins
         }
     }
@@ -95,6 +99,7 @@ extern "C" int rbk_tune_get(const rbk_ctx *c, int *cfg)
     if (!c || !cfg) return rbk_set_error(RBK_EINVAL, "null argument");
     cfg[0] = c->ntt_logC;
     cfg[1] = c->ip_cpc;
+    cfg[2] = c->ntt_chunk;
     return RBK_OK;
 }
 
@@ -105,8 +110,10 @@ extern "C" int rbk_tune_set(rbk_ctx *c, const int *cfg)
     if (cfg[0] != c->ntt_logC && !split_ok(c->logN, cfg[0]))
         return rbk_set_error(RBK_EINVAL, "NTT split not supported for this ring degree");
     if (cfg[1] < 1 || cfg[1] > 64) return rbk_set_error(RBK_EINVAL, "ciphertexts per thread out of 1..64");
+    if (cfg[2] < 0) return rbk_set_error(RBK_EINVAL, "negative NTT chunk");
     c->ntt_logC = cfg[0];
     c->ip_cpc = cfg[1];
+    c->ntt_chunk = cfg[2];
     return RBK_OK;
 }
 
@@ -116,8 +123,8 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
     if (c->capturing) return rbk_set_error(RBK_ESTATE, "not allowed during graph capture");
     if (level < 0 || level >= c->nQ) return rbk_set_error(RBK_ELEVEL, "level out of range");
     const std::string key = tune_key(c, level, count);
-    int logC = c->ntt_logC, cpc = c->ip_cpc;
-    if (!cache_lookup(cache_path, key, logC, cpc)) {
+    int logC = c->ntt_logC, cpc = c->ip_cpc, chunk = c->ntt_chunk;
+    if (!cache_lookup(cache_path, key, logC, cpc, chunk)) {
         const size_t N = c->N, L1 = level + 1, E = L1 + c->nP, beta = (L1 + c->alpha - 1) / c->alpha;
         // scratch: the NTT batch (count x 2 polynomials) or the key-switch buffers
         const size_t ntt_words = (size_t)count * 2 * L1 * N;
@@ -144,6 +151,22 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         }
         c->ntt_logC = best_logC;
         logC = best_logC;
+        // NTT chunk (whole batch, or chunks around the memory-side cache size)
+        best = 1e30;
+        int best_chunk = chunk;
+        for (int cand : {0, 256, 512, 1024}) {
+            c->ntt_chunk = cand;
+            double ms = time_ms(c, [&] {
+                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, false, c->stream);
+                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, true, c->stream);
+            }, 3);
+            if (ms >= 0 && ms < best) {
+                best = ms;
+                best_chunk = cand;
+            }
+        }
+        c->ntt_chunk = best_chunk;
+        chunk = best_chunk;
         // ciphertexts per thread of the fused inner products (needs a key)
         // a Galois key when there is one (rotations read the digits through the automorphism)
         const DevKey *key_d = nullptr;
@@ -178,16 +201,17 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         if (hipGetLastError() != hipSuccess) return rbk_set_error(RBK_EDEVICE, "autotune launch failed");
         if (cache_path) {
             std::ofstream f(cache_path, std::ios::app);
-            if (f) f << key << " : logC=" << logC << " cpc=" << cpc << "\n";
+            if (f) f << key << " : logC=" << logC << " cpc=" << cpc << " chunk=" << chunk << "\n";
         }
     } else {
-        int cfgv[2] = {logC, cpc};
+        int cfgv[3] = {logC, cpc, chunk};
         int rc = rbk_tune_set(c, cfgv);
         if (rc) return rc;
     }
     if (cfg) {
         cfg[0] = c->ntt_logC;
         cfg[1] = c->ip_cpc;
+        cfg[2] = c->ntt_chunk;
     }
     return RBK_OK;
 }

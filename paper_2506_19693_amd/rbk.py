@@ -593,20 +593,22 @@ class Context:
 
     # ---------------------------------------------------------------- autotuner
     def autotune(self, level, count, cache_path=None):
-        """Time the NTT split and the inner-product chunk on (level, count);
-        returns {"logC": .., "cpc": ..} now in force."""
-        cfg = (ci * 2)()
+        """Time the NTT split, the NTT chunk and the inner-product chunk on
+        (level, count); returns {"logC": .., "cpc": .., "chunk": ..} now in force."""
+        cfg = (ci * 3)()
         path = cache_path.encode() if cache_path else None
         _check(self.lib.rbk_autotune(self.h, level, count, path, cfg))
-        return {"logC": cfg[0], "cpc": cfg[1]}
+        return {"logC": cfg[0], "cpc": cfg[1], "chunk": cfg[2]}
 
     def tune_get(self):
-        cfg = (ci * 2)()
+        cfg = (ci * 3)()
         _check(self.lib.rbk_tune_get(self.h, cfg))
-        return {"logC": cfg[0], "cpc": cfg[1]}
+        return {"logC": cfg[0], "cpc": cfg[1], "chunk": cfg[2]}
 
-    def tune_set(self, logC, cpc):
-        _check(self.lib.rbk_tune_set(self.h, (ci * 2)(logC, cpc)))
+    def tune_set(self, logC, cpc, chunk=None):
+        if chunk is None:
+            chunk = self.tune_get()["chunk"]
+        _check(self.lib.rbk_tune_set(self.h, (ci * 3)(logC, cpc, chunk)))
 
     # ---------------------------------------------------------------- graph capture
     def capture(self, fn):

@@ -1,6 +1,6 @@
 """The autotuner: it picks a supported configuration, records it in its cache
 and reads it back instead of measuring again; and every configuration it can
-choose (NTT split x inner-product chunk) gives the same residues for
+choose (NTT split x NTT chunk x inner-product chunk) gives the same residues for
 batched mult_relin, rescale and hoisted rotations."""
 import itertools
 
@@ -29,9 +29,9 @@ def test_autotune_cache_roundtrip(tmp_path):
     path = str(tmp_path / "tune.txt")
     d, _ = _ctx(14)
     cfg = d.autotune(7, 8, path)
-    assert cfg["logC"] in (6, 7, 8) and cfg["cpc"] in (4, 8, 16)
+    assert cfg["logC"] in (6, 7, 8) and cfg["cpc"] in (4, 8, 16) and cfg["chunk"] in (0, 256, 512, 1024)
     lines = open(path).read().splitlines()
-    assert len(lines) == 1 and lines[0].endswith("logC=%d cpc=%d" % (cfg["logC"], cfg["cpc"]))
+    assert len(lines) == 1 and lines[0].endswith("logC=%d cpc=%d chunk=%d" % (cfg["logC"], cfg["cpc"], cfg["chunk"]))
     d2, _ = _ctx(14)
     assert d2.autotune(7, 8, path) == cfg
     assert len(open(path).read().splitlines()) == 1          # read, not measured again
@@ -48,14 +48,17 @@ def test_every_configuration_gives_the_same_residues(log_n):
     B = d.to_ntt(S.uniform_residues(g, d.moduli[: L + 1], d.N, lead=(5, 2)), L)
     splits = [c for c in (6, 7, 8) if 6 <= log_n - c <= 8]
     ref = None
-    for logC, cpc in itertools.product(splits, (1, 3, 8, 16)):
-        d.tune_set(logC, cpc)
+    # chunks of 1, 7 and 40 limbs split the 10-polynomial batches unevenly
+    for logC, cpc, chunk in itertools.product(splits, (1, 3, 8, 16), (0, 1, 7, 40)):
+        d.tune_set(logC, cpc, chunk)
         m = d.rescale_batch(d.mult_relin_batch(A, B, L), L)
         h = d.rotate_hoisted_batch(m, [1, 5, -3], L - 1)
         got = (d.to_coef(m, L - 1), d.to_coef(h, L - 1))
         if ref is None:
             ref = got
         else:
-            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (logC, cpc)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (logC, cpc, chunk)
     with pytest.raises(RbkError):
         d.tune_set(log_n - 9, 8)                              # unsupported split
+    with pytest.raises(RbkError):
+        d.tune_set(splits[0], 8, -1)                          # negative chunk
