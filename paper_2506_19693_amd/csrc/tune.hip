@@ -86,6 +86,25 @@ double time_ms(rbk_ctx *c, F fn, int reps)
     return ms / reps;
 }
 
+// index of the fastest candidate: every candidate is timed in each of
+// `rounds` interleaved rounds (mean of `reps` runs) and keeps its best round,
+// so a slow first measurement or a passing disturbance does not decide
+template <class Set, class Run>
+int pick_fastest(rbk_ctx *c, int n, Set set, Run run, int rounds = 3, int reps = 4)
+{
+    std::vector<double> best(n, 1e30);
+    for (int r = 0; r < rounds; r++)
+        for (int i = 0; i < n; i++) {
+            set(i);
+            const double ms = time_ms(c, run, reps);
+            if (ms >= 0 && ms < best[i]) best[i] = ms;
+        }
+    int k = 0;
+    for (int i = 1; i < n; i++)
+        if (best[i] < best[k]) k = i;
+    return k;
+}
+
 bool split_ok(int logN, int logC)
 {
     const int r = logN - logC;
@@ -134,39 +153,22 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         if (!ws) return RBK_ENOMEM;
         const LimbMap qm{0, c->nQ, c->nQ};
         ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)(ntt_words / N), 1, qm, c->stream);
+        auto ntt_pair = [&] {
+            ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, false, c->stream);
+            ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, true, c->stream);
+        };
         // NTT split
-        double best = 1e30;
-        int best_logC = logC;
-        for (int cand = 6; cand <= 8; cand++) {
-            if (!split_ok(c->logN, cand)) continue;
-            c->ntt_logC = cand;
-            double ms = time_ms(c, [&] {
-                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, false, c->stream);
-                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, true, c->stream);
-            }, 3);
-            if (ms >= 0 && ms < best) {
-                best = ms;
-                best_logC = cand;
-            }
+        std::vector<int> splits;
+        for (int cand = 6; cand <= 8; cand++)
+            if (split_ok(c->logN, cand)) splits.push_back(cand);
+        if (!splits.empty()) {
+            const int k = pick_fastest(c, (int)splits.size(), [&](int i) { c->ntt_logC = splits[i]; }, ntt_pair);
+            c->ntt_logC = logC = splits[k];
         }
-        c->ntt_logC = best_logC;
-        logC = best_logC;
         // NTT chunk (whole batch, or chunks around the memory-side cache size)
-        best = 1e30;
-        int best_chunk = chunk;
-        for (int cand : {0, 256, 512, 1024}) {
-            c->ntt_chunk = cand;
-            double ms = time_ms(c, [&] {
-                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, false, c->stream);
-                ntt_launch(c, ws, (long)(L1 * N), 2 * count, (int)L1, qm, true, c->stream);
-            }, 3);
-            if (ms >= 0 && ms < best) {
-                best = ms;
-                best_chunk = cand;
-            }
-        }
-        c->ntt_chunk = best_chunk;
-        chunk = best_chunk;
+        const int chunks[4] = {0, 256, 512, 1024};
+        const int kc = pick_fastest(c, 4, [&](int i) { c->ntt_chunk = chunks[i]; }, ntt_pair);
+        c->ntt_chunk = chunk = chunks[kc];
         // ciphertexts per thread of the fused inner products (needs a key)
         // a Galois key when there is one (rotations read the digits through the automorphism)
         const DevKey *key_d = nullptr;
@@ -181,22 +183,13 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
             ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)((ext_words + conv_words + tp_words + out_words) / N), 1, qm,
                       c->stream);
             const u64 g = key_d->g ? key_d->g : 0;
-            best = 1e30;
-            int best_cpc = cpc;
-            for (int cand : {4, 8, 16}) {
-                c->ip_cpc = cand;
-                double ms = time_ms(c, [&] {
-                    ip_p_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);
-                    moddown_ip_launch(c, ext, (long)(beta * E * N), key_d->data, conv, (long)(2 * L1 * N), nullptr, 0, 0,
-                                      0, out, (long)(2 * L1 * N), level, count, g, c->stream);
-                }, 3);
-                if (ms >= 0 && ms < best) {
-                    best = ms;
-                    best_cpc = cand;
-                }
-            }
-            c->ip_cpc = best_cpc;
-            cpc = best_cpc;
+            const int cpcs[3] = {4, 8, 16};
+            const int k = pick_fastest(c, 3, [&](int i) { c->ip_cpc = cpcs[i]; }, [&] {
+                ip_p_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);
+                moddown_ip_launch(c, ext, (long)(beta * E * N), key_d->data, conv, (long)(2 * L1 * N), nullptr, 0, 0, 0,
+                                  out, (long)(2 * L1 * N), level, count, g, c->stream);
+            });
+            c->ip_cpc = cpc = cpcs[k];
         }
         if (hipGetLastError() != hipSuccess) return rbk_set_error(RBK_EDEVICE, "autotune launch failed");
         if (cache_path) {
