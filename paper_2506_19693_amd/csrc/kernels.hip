@@ -6,6 +6,7 @@
 // ModUp output [beta_l][E][N] with E = l+1+nP positions (q_0..q_l, p_0..);
 // inner-product output [2][E][N].
 #include "rbk_ctx.hpp"
+#include "wide_arith.hpp"
 
 #define EW_THREADS 256
 
@@ -180,22 +181,26 @@ void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly,
 #define BCONV_MAX_IN 16
 #define BCONV_MAX_TAB 1024   // n_in * n_out words staged in LDS
 
-// Fast base conversion, one thread per coefficient, all outputs in one pass:
-//   y_i = x_i * A_i mod b_i,   out_o = sum_i y_i * M[i][o] mod t_o
-// M (stored times 2^64) is staged in LDS once per block and read as a
-// broadcast; the sum is a lazy 128-bit accumulation with one REDC per output.
-//
-// ModUp (MODUP = true): block row blockIdx.y = digit j, inputs are the digit's
-// limbs [lo, lo+n_in) of the coefficient-domain copy, outputs every
-// extended-basis position outside the digit (written into ext).
-// ModDown (MODUP = false): inputs are the nP special-prime limbs of one
-// polynomial, outputs the l+1 Q limbs.
+// Base-conversion sums use the carry-free 30-bit split accumulation of
+// wide_arith.hpp (at most 16 terms of residues and table entries below 2^60).
+using wa::Acc4;
+using wa::Half30;
+using wa::split30;
+__device__ __forceinline__ u128w acc4_sum(const Acc4 &a)
+{
+    const wa::Wide w = wa::acc4_value(a);
+    u128w t;
+    t.lo = w.lo;
+    t.hi = w.hi;
+    return t;
+}
+
 template <bool MODUP, int MAXIN>
 __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_stride, u64 *out, long out_stride, int logN,
                                                       int L1, int E, int alpha, int nP, int nQ, const u64 *A,
                                                       const u64 *Ash, const u64 *M, long m_stride, const PrimeC *pc)
 {
-    __shared__ u64 tab[BCONV_MAX_TAB];
+    __shared__ Half30 tab[BCONV_MAX_TAB];
     const size_t N = (size_t)1 << logN;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     const int poly = blockIdx.z;
@@ -223,15 +228,17 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
         x = in + poly * in_stride;
         dst = out + poly * out_stride;
     }
-    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS) tab[w] = Mj[(size_t)(w / n_out) * m_stride + (w % n_out)];
+    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS)
+        tab[w] = split30(Mj[(size_t)(w / n_out) * m_stride + (w % n_out)]);
     __syncthreads();
     if (k >= N) return;
-    u64 y[MAXIN];
+    Half30 yh[MAXIN];
 #pragma unroll
     for (int i = 0; i < MAXIN; i++)
         if (i < n_in) {
             const int pi = MODUP ? lo + i : nQ + i;
-            y[i] = shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[pi].q);
+            const Half30 y = split30(shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[pi].q));
+            yh[i] = y;
         }
     for (int o = 0; o < n_out; o++) {
         int pos, pr;
@@ -243,13 +250,13 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
             pr = o;
         }
         const PrimeC p = pc[pr];
-        u128w acc = {0, 0};
+        Acc4 acc;
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
-            if (i < n_in) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
+            if (i < n_in) wa::acc4(acc, yh[i], tab[i * n_out + o]);
         // n_in <= 16 terms, each y (< 2^60) times a table entry (< p): the sum
         // stays below p 2^64, so a plain REDC reduces it
-        dst[(size_t)pos * N + k] = redc(acc, p.q, p.qneg);
+        dst[(size_t)pos * N + k] = redc(acc4_sum(acc), p.q, p.qneg);
     }
 }
 
@@ -906,7 +913,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_up_list(const u64 *coef, l
                                                               int alpha, int nP, int nQ, const ListCt *cts,
                                                               const PrimeC *pc)
 {
-    __shared__ u64 tab[BCONV_MAX_TAB];
+    __shared__ Half30 tab[BCONV_MAX_TAB];
     const size_t N = (size_t)1 << logN;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     const int ct = blockIdx.z, j = blockIdx.y;
@@ -915,28 +922,29 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_up_list(const u64 *coef, l
     if (j >= beta) return;
     const int lo = j * alpha, n_in = min(alpha, L1 - lo), n_out = E - n_in;
     const u64 *Aj = C.A + j * alpha, *Ashj = C.Ash + j * alpha, *Mj = C.M + (size_t)j * alpha * E;
-    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS) tab[w] = Mj[(size_t)(w / n_out) * E + (w % n_out)];
+    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS) tab[w] = split30(Mj[(size_t)(w / n_out) * E + (w % n_out)]);
     __syncthreads();
     if (k >= N) return;
     const u64 *x = coef + ct * coef_stride + (size_t)lo * N;
     const u64 *own = d + ct * d_stride + (size_t)lo * N;
     u64 *dst = ext + ct * ext_stride + (size_t)j * dig_stride;
-    u64 y[MAXIN];
+    Half30 yh[MAXIN];
 #pragma unroll
     for (int i = 0; i < MAXIN; i++)
         if (i < n_in) {
-            y[i] = shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[lo + i].q);
+            const Half30 y = split30(shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[lo + i].q));
+            yh[i] = y;
             dst[(size_t)(lo + i) * N + k] = own[(size_t)i * N + k];
         }
     for (int o = 0; o < n_out; o++) {
         const int pos = o < lo ? o : o + n_in;
         const int pr = pos < L1 ? pos : nQ + pos - L1;
         const PrimeC p = pc[pr];
-        u128w acc = {0, 0};
+        Acc4 acc;
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
-            if (i < n_in) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
-        dst[(size_t)pos * N + k] = redc(acc, p.q, p.qneg);
+            if (i < n_in) wa::acc4(acc, yh[i], tab[i * n_out + o]);
+        dst[(size_t)pos * N + k] = redc(acc4_sum(acc), p.q, p.qneg);
     }
 }
 
@@ -947,27 +955,30 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_down_list(const u64 *tp, u
                                                                 int nP, int nQ, const ListCt *cts, const u64 *A,
                                                                 const u64 *Ash, const u64 *M, const PrimeC *pc)
 {
-    __shared__ u64 tab[BCONV_MAX_TAB];
+    __shared__ Half30 tab[BCONV_MAX_TAB];
     const size_t N = (size_t)1 << logN;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     const int poly = blockIdx.z;
     const int n_out = cts[poly / 2].level + 1;
-    for (int w = threadIdx.x; w < nP * n_out; w += EW_THREADS) tab[w] = M[(size_t)(w / n_out) * nQ + (w % n_out)];
+    for (int w = threadIdx.x; w < nP * n_out; w += EW_THREADS) tab[w] = split30(M[(size_t)(w / n_out) * nQ + (w % n_out)]);
     __syncthreads();
     if (k >= N) return;
     const u64 *x = tp + (size_t)poly * nP * N;
     u64 *dst = conv + poly * conv_stride;
-    u64 y[MAXIN];
+    Half30 yh[MAXIN];
 #pragma unroll
     for (int i = 0; i < MAXIN; i++)
-        if (i < nP) y[i] = shoup(x[(size_t)i * N + k], A[i], Ash[i], pc[nQ + i].q);
+        if (i < nP) {
+            const Half30 y = split30(shoup(x[(size_t)i * N + k], A[i], Ash[i], pc[nQ + i].q));
+            yh[i] = y;
+        }
     for (int o = 0; o < n_out; o++) {
         const PrimeC p = pc[o];
-        u128w acc = {0, 0};
+        Acc4 acc;
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
-            if (i < nP) acc_wide(acc, mul_wide(y[i], tab[i * n_out + o]));
-        dst[(size_t)o * N + k] = redc(acc, p.q, p.qneg);
+            if (i < nP) wa::acc4(acc, yh[i], tab[i * n_out + o]);
+        dst[(size_t)o * N + k] = redc(acc4_sum(acc), p.q, p.qneg);
     }
 }
 

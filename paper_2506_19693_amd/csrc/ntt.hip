@@ -17,10 +17,15 @@
 //
 // Value ranges follow Harvey: forward butterflies keep [0, 4q), inverse
 // butterflies [0, 2q); each pass that ends a transform reduces to [0, q).
+// The integer butterflies of the register passes use a quotient that may be
+// up to 2 short (three 32x32 products instead of four), so their Shoup
+// products land in [0, 4q) and the ranges widen to [0, 8q) forward and
+// [0, 4q) inverse; with q < 2^61 every value fits a word.
 #include <algorithm>
 
 #include "rbk_internal.hpp"
 #include "rbk_ctx.hpp"
+#include "wide_arith.hpp"
 
 #define NTT_TILE 4096
 #define NTT_THREADS 256
@@ -40,6 +45,10 @@ __device__ __forceinline__ void bfly_gs(u64 &x, u64 &y, u64 w, u64 wsh, u64 q, u
     x = s;
     y = shoup_lazy(d, w, wsh, q);
 }
+
+using wa::bfly_ct8;
+using wa::bfly_gs4;
+using wa::shoup_lazy4;
 
 // Row pass.  Forward: stages (logN-logC) .. logN-1, output reduced to [0, q).
 // Inverse: distances 1 .. C/2; if logC == logN this is the whole inverse
@@ -225,7 +234,7 @@ __device__ __forceinline__ int lidx(int e) { return e + (e >> 4); }
 // (distance 2^s in the line) uses (1 << (logN-1-off-s)) + (line_id << (LOGS-s-1)) + (e >> (s+1)).
 template <bool INV, int NST, int RD0, int LOGS>
 __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride, int s0, int off, int line_id, int logN,
-                                            const u64 *tw, const u64 *tws, u64 q, u64 q2, bool fold, u64 ninv,
+                                            const u64 *tw, const u64 *tws, u64 q, u64 q4, bool fold, u64 ninv,
                                             u64 ninv_sh, u64 lw, u64 lw_sh)
 {
 #pragma unroll
@@ -238,15 +247,15 @@ __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride
             const int e = ebase + estride * i0;
             if (!INV) {
                 const int ti = (1 << (off + s)) + (line_id << s) + (e >> (LOGS - s));
-                bfly_ct(x[i0], x[i1], tw[ti], tws[ti], q, q2);
+                bfly_ct8(x[i0], x[i1], tw[ti], tws[ti], q, q4);
             } else if (fold && k == NST - 1) {
-                u64 sum = csub(x[i0] + x[i1], q2);
-                u64 dd = x[i0] + q2 - x[i1];
-                x[i0] = shoup_lazy(sum, ninv, ninv_sh, q);
-                x[i1] = shoup_lazy(dd, lw, lw_sh, q);
+                u64 sum = csub(x[i0] + x[i1], q4);
+                u64 dd = x[i0] + q4 - x[i1];
+                x[i0] = shoup_lazy4(sum, ninv, ninv_sh, q);
+                x[i1] = shoup_lazy4(dd, lw, lw_sh, q);
             } else {
                 const int ti = (1 << (logN - 1 - off - s)) + (line_id << (LOGS - s - 1)) + (e >> (s + 1));
-                bfly_gs(x[i0], x[i1], tw[ti], tws[ti], q, q2);
+                bfly_gs4(x[i0], x[i1], tw[ti], tws[ti], q, q4);
             }
         }
     }
@@ -272,29 +281,10 @@ __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride
 // kept in HBM as raw double bits; the first pass reads canonical residues and
 // the last one writes them back canonical in [0, p).
 
-__device__ __forceinline__ double fp_mul(double a, double w, double wp, double p)
-{
-    const double h = a * w;
-    const double l = __fma_rn(a, w, -h);
-    const double qq = rint(a * wp);
-    return __fma_rn(-qq, p, h) + l;
-}
-
-__device__ __forceinline__ double fp_red(double x, double p, double pinv) { return __fma_rn(-rint(x * pinv), p, x); }
-
-// canonical residue (< 2^52) -> double
-__device__ __forceinline__ double fp_from_u64(u64 v)
-{
-    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
-}
-
-// any exact integer |x| < 2^53 -> canonical residue in [0, p)
-__device__ __forceinline__ u64 fp_to_u64(double x, double p, double pinv)
-{
-    double r = fp_red(x, p, pinv);
-    r = r < 0 ? r + p : r;
-    return (u64)__double_as_longlong(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
-}
+using wa::fp_from_u64;
+using wa::fp_mul;
+using wa::fp_red;
+using wa::fp_to_u64;
 
 template <int LOGS, int NST, int RD0, bool INV>
 __device__ __forceinline__ void fp_round16(double (&x)[16], int ebase, int estride, int s0, int off, int line_id, int logN,
@@ -440,7 +430,7 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, const NttTables &
         return;
     }
     const PrimeC pc = T.pc[pr];
-    const u64 q = pc.q, q2 = 2 * q;
+    const u64 q = pc.q, q2 = 2 * q, q4 = 4 * q;
     const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
     const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
     const size_t C = COLS ? (N >> LOGS) : (size_t)G::S;   // row length of the R x C view
@@ -454,13 +444,13 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, const NttTables &
     if (!INV) {
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = base[addr(t + G::TPL * i)];
-        ntt_round16<false, 4, 8, LOGS>(x, t, G::TPL, 0, off_f, lid, logN, tw, tws, q, q2, false, 0, 0, 0, 0);
+        ntt_round16<false, 4, 8, LOGS>(x, t, G::TPL, 0, off_f, lid, logN, tw, tws, q, q4, false, 0, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = x[i];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
-        ntt_round16<false, NST2, (1 << (NST2 - 1)), LOGS>(x, 16 * t, 1, 4, off_f, lid, logN, tw, tws, q, q2, false, 0, 0, 0,
+        ntt_round16<false, NST2, (1 << (NST2 - 1)), LOGS>(x, 16 * t, 1, 4, off_f, lid, logN, tw, tws, q, q4, false, 0, 0, 0,
                                                           0);
         if (COLS) {
 #pragma unroll
@@ -468,7 +458,7 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, const NttTables &
         } else {
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = csub(csub(x[i], q2), q);
+            for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = csub(csub(csub(x[i], q4), q2), q);
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = sl[lidx(t + G::TPL * i)];
@@ -485,17 +475,17 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, const NttTables &
             for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
             __syncthreads();
         }
-        ntt_round16<true, 4, 1, LOGS>(x, 16 * t, 1, 0, off_i, lid, logN, tw, tws, q, q2, false, 0, 0, 0, 0);
+        ntt_round16<true, 4, 1, LOGS>(x, 16 * t, 1, 0, off_i, lid, logN, tw, tws, q, q4, false, 0, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = x[i];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = sl[lidx(t + G::TPL * i)];
-        ntt_round16<true, NST2, (16 >> NST2), LOGS>(x, t, G::TPL, 4, off_i, lid, logN, tw, tws, q, q2, COLS, pc.ninv,
+        ntt_round16<true, NST2, (16 >> NST2), LOGS>(x, t, G::TPL, 4, off_i, lid, logN, tw, tws, q, q4, COLS, pc.ninv,
                                                     pc.ninv_sh, T.last[pr], T.last_sh[pr]);
         if (COLS) {
 #pragma unroll
-            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = csub(x[i], q);
+            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = csub(csub(x[i], q2), q);
         } else {
 #pragma unroll
             for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = x[i];
