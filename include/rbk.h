@@ -99,7 +99,9 @@ int rbk_reserve(rbk_ctx *ctx, int level, int count);
  * limb i of every polynomial uses the prime with table index prime_idx[i]
  * (host array; 0..n_q-1 are Q primes, n_q.. the special primes).  The index
  * list must be a run of Q primes 0..a-1 optionally followed by a run of
- * consecutive special primes starting at p_0, or a run of special primes. */
+ * consecutive special primes starting at p_0, or a run of special primes.
+ * Inputs are residues in [0, q) (as every residue of this API); outputs are
+ * in [0, q).  Residues outside [0, q) give unspecified results. */
 int rbk_ntt(rbk_ctx *ctx, uint64_t *d_data, int count, const int *prime_idx, int n_limbs, int inverse);
 
 /* ---- keys (Section 3: sk/pk; rotation keys, one per index) -------------- */
@@ -223,7 +225,8 @@ typedef struct {
 } rbk_ntt_item;
 /* In-place forward (inverse = 0) or inverse NTT of every limb of the list,
  * each in its own context's ring (contexts on the device of ctx), launched
- * on ctx's stream.  The same results as per-context rbk_ntt calls.
+ * on ctx's stream.  The same results as per-context rbk_ntt calls (inputs
+ * in [0, q), outputs in [0, q)); a limb must not appear twice in one list.
  * RBK_EUNSUPPORTED for a ring degree above 2^16. */
 int rbk_ntt_list(rbk_ctx *ctx, const rbk_ntt_item *items, int n, int inverse);
 /* out_i = rescale(mult_relin(a_i, b_i)) for count ciphertexts of ctx at the
