@@ -875,12 +875,11 @@ static int modup_run(rbk_ctx *c, const u64 *d, long d_stride, u64 *ext, long ext
     HIPCK(hipMemcpy2DAsync(coef, L1 * N * sizeof(u64), d, d_stride * sizeof(u64), L1 * N * sizeof(u64), count,
                            hipMemcpyDeviceToDevice, c->stream));
     ntt_launch(c, coef, (long)L1 * N, count, L1, qmap(c), true, c->stream);
-    bconv_modup_launch(c, coef, (long)L1 * N, ext, ext_stride, level, count, c->stream);
+    // the base conversion also places each digit's own limbs (from d, NTT domain)
+    bconv_modup_launch(c, coef, (long)L1 * N, d, d_stride, ext, ext_stride, level, count, c->stream);
     for (int j = 0; j < T.beta; j++) {
         int lo = T.lo[j], n_in = T.n_in[j];
         u64 *ej = ext + (size_t)j * E * N;
-        HIPCK(hipMemcpy2DAsync(ej + (size_t)lo * N, ext_stride * sizeof(u64), d + (size_t)lo * N, d_stride * sizeof(u64),
-                               n_in * N * sizeof(u64), count, hipMemcpyDeviceToDevice, c->stream));
         if (lo > 0) ntt_launch(c, ej, ext_stride, count, lo, LimbMap{0, L1, c->nQ}, false, c->stream);
         int hi = lo + n_in;
         if (hi < E) ntt_launch(c, ej + (size_t)hi * N, ext_stride, count, E - hi, LimbMap{hi, L1, c->nQ}, false, c->stream);

@@ -195,10 +195,13 @@ __device__ __forceinline__ u128w acc4_sum(const Acc4 &a)
     return t;
 }
 
+// ModUp also copies the digit's own limbs, in the NTT domain (own: the
+// polynomial the coefficient-domain input was made from), into their positions.
 template <bool MODUP, int MAXIN>
 __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_stride, u64 *out, long out_stride, int logN,
                                                       int L1, int E, int alpha, int nP, int nQ, const u64 *A,
-                                                      const u64 *Ash, const u64 *M, long m_stride, const PrimeC *pc)
+                                                      const u64 *Ash, const u64 *M, long m_stride, const PrimeC *pc,
+                                                      const u64 *own, long own_stride)
 {
     __shared__ Half30 tab[BCONV_MAX_TAB];
     const size_t N = (size_t)1 << logN;
@@ -233,12 +236,14 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
     __syncthreads();
     if (k >= N) return;
     Half30 yh[MAXIN];
+    const u64 *ownj = MODUP ? own + poly * own_stride + (size_t)lo * N : nullptr;
 #pragma unroll
     for (int i = 0; i < MAXIN; i++)
         if (i < n_in) {
             const int pi = MODUP ? lo + i : nQ + i;
             const Half30 y = split30(shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[pi].q));
             yh[i] = y;
+            if (MODUP) dst[(size_t)(lo + i) * N + k] = ownj[(size_t)i * N + k];
         }
     for (int o = 0; o < n_out; o++) {
         int pos, pr;
@@ -260,8 +265,8 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
     }
 }
 
-void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, u64 *ext, long ext_stride, int level,
-                        int count, hipStream_t st)
+void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, const u64 *own, long own_stride,
+                        u64 *ext, long ext_stride, int level, int count, hipStream_t st)
 {
     const ModUpTables &T = modup_tables(const_cast<rbk_ctx_impl *>(c), level);
     int L1 = level + 1, E = L1 + c->nP;
@@ -269,13 +274,13 @@ void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride
     kt_begin(c, KC_BCONV_UP, st);
     if (c->alpha <= 4)
         hipLaunchKernelGGL((k_bconv<true, 4>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
-                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
+                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
     else if (c->alpha <= 8)
         hipLaunchKernelGGL((k_bconv<true, 8>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
-                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
+                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
     else
         hipLaunchKernelGGL((k_bconv<true, 16>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
-                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc);
+                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
     kt_end(c, KC_BCONV_UP, (double)count * T.beta * E * c->N * sizeof(u64), st);
 }
 
@@ -287,13 +292,13 @@ void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride
     kt_begin(c, KC_BCONV_DOWN, st);
     if (c->nP <= 4)
         hipLaunchKernelGGL((k_bconv<false, 4>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
-                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
+                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
     else if (c->nP <= 8)
         hipLaunchKernelGGL((k_bconv<false, 8>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
-                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
+                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
     else
         hipLaunchKernelGGL((k_bconv<false, 16>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN,
-                           L1, L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc);
+                           L1, L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
     kt_end(c, KC_BCONV_DOWN, (double)count * (c->nP + L1) * c->N * sizeof(u64), st);
 }
 

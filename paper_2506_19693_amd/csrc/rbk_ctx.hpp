@@ -167,8 +167,8 @@ void signed_to_limbs_launch(const rbk_ctx_impl *c, const i64 *v, u64 *out, int n
                             hipStream_t st);
 void tensor_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, int level, int count, hipStream_t st);
 void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int nlimbs, u64 g, hipStream_t st);
-void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, u64 *ext, long ext_stride, int level,
-                        int count, hipStream_t st);
+void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, const u64 *own, long own_stride,
+                        u64 *ext, long ext_stride, int level, int count, hipStream_t st);
 void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride, u64 *conv, long conv_stride, int level,
                           int count, hipStream_t st);
 void ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *u, long u_stride, int level,
