@@ -11,7 +11,9 @@
 //    moddown_ip): more share each key word among more ciphertexts, fewer
 //    give more workgroups.
 // rbk_autotune times each candidate on the shape it is asked about (level,
-// batch) with HIP events on the context stream, keeps the fastest, and
+// batch) with HIP events on the context stream, each run starting from a
+// cache overwritten by a 512 MiB scrub (as inside a pipeline), keeps the
+// fastest, and
 // records the choice in a text cache keyed by the GPU architecture and the
 // shape, so later processes read it instead of measuring again.
 #include <hip/hip_runtime.h>
@@ -64,9 +66,15 @@ bool cache_lookup(const char *path, const std::string &key, int &logC, int &cpc,
     return found;
 }
 
-// mean ms of `reps` runs of fn after one warm-up run
+// Words written before every timed run, larger than the memory-side cache:
+// in a pipeline the key words and inputs of a kernel arrive from HBM, not
+// from a cache a repeated run kept warm.
+constexpr size_t SCRUB_WORDS = (size_t)1 << 26;  // 512 MiB
+
+// mean ms of `reps` runs of fn after one warm-up run; each run starts after
+// the scrub region has been overwritten (not timed)
 template <class F>
-double time_ms(rbk_ctx *c, F fn, int reps)
+double time_ms(rbk_ctx *c, F fn, int reps, u64 *scrub)
 {
     fn();
     hipEvent_t e0, e1;
@@ -75,28 +83,38 @@ double time_ms(rbk_ctx *c, F fn, int reps)
         (void)hipEventDestroy(e0);
         return -1;
     }
-    (void)hipEventRecord(e0, c->stream);
-    for (int i = 0; i < reps; i++) fn();
-    (void)hipEventRecord(e1, c->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = -1;
-    (void)hipEventElapsedTime(&ms, e0, e1);
+    const LimbMap qm{0, c->nQ, c->nQ};
+    double total = 0;
+    for (int i = 0; i < reps; i++) {
+        ew_launch(c, EW_ZERO, scrub, nullptr, scrub, (int)(SCRUB_WORDS / c->N), 1, qm, c->stream);
+        (void)hipEventRecord(e0, c->stream);
+        fn();
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = -1;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < 0) {
+            total = -1;
+            break;
+        }
+        total += ms;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return ms / reps;
+    return total < 0 ? -1 : total / reps;
 }
 
 // index of the fastest candidate: every candidate is timed in each of
 // `rounds` interleaved rounds (mean of `reps` runs) and keeps its best round,
 // so a slow first measurement or a passing disturbance does not decide
 template <class Set, class Run>
-int pick_fastest(rbk_ctx *c, int n, Set set, Run run, int rounds = 3, int reps = 4)
+int pick_fastest(rbk_ctx *c, int n, Set set, Run run, u64 *scrub, int rounds = 3, int reps = 4)
 {
     std::vector<double> best(n, 1e30);
     for (int r = 0; r < rounds; r++)
         for (int i = 0; i < n; i++) {
             set(i);
-            const double ms = time_ms(c, run, reps);
+            const double ms = time_ms(c, run, reps, scrub);
             if (ms >= 0 && ms < best[i]) best[i] = ms;
         }
     int k = 0;
@@ -149,8 +167,10 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         const size_t ntt_words = (size_t)count * 2 * L1 * N;
         const size_t ext_words = (size_t)count * beta * E * N, conv_words = (size_t)count * 2 * L1 * N;
         const size_t tp_words = (size_t)count * 2 * c->nP * N, out_words = (size_t)count * 2 * L1 * N;
-        u64 *ws = ws_reserve(c, std::max(ntt_words, ext_words + conv_words + tp_words + out_words));
+        const size_t work = std::max(ntt_words, ext_words + conv_words + tp_words + 2 * out_words);
+        u64 *ws = ws_reserve(c, work + SCRUB_WORDS);
         if (!ws) return RBK_ENOMEM;
+        u64 *scrub = ws + work;
         const LimbMap qm{0, c->nQ, c->nQ};
         ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)(ntt_words / N), 1, qm, c->stream);
         auto ntt_pair = [&] {
@@ -162,12 +182,12 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         for (int cand = 6; cand <= 8; cand++)
             if (split_ok(c->logN, cand)) splits.push_back(cand);
         if (!splits.empty()) {
-            const int k = pick_fastest(c, (int)splits.size(), [&](int i) { c->ntt_logC = splits[i]; }, ntt_pair);
+            const int k = pick_fastest(c, (int)splits.size(), [&](int i) { c->ntt_logC = splits[i]; }, ntt_pair, scrub);
             c->ntt_logC = logC = splits[k];
         }
         // NTT chunk (whole batch, or chunks around the memory-side cache size)
         const int chunks[4] = {0, 256, 512, 1024};
-        const int kc = pick_fastest(c, 4, [&](int i) { c->ntt_chunk = chunks[i]; }, ntt_pair);
+        const int kc = pick_fastest(c, 4, [&](int i) { c->ntt_chunk = chunks[i]; }, ntt_pair, scrub);
         c->ntt_chunk = chunk = chunks[kc];
         // ciphertexts per thread of the fused inner products (needs a key)
         // a Galois key when there is one (rotations read the digits through the automorphism)
@@ -180,15 +200,23 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         if (!key_d && c->relin.data) key_d = &c->relin;
         if (key_d && c->nP > 0) {
             u64 *ext = ws, *conv = ext + ext_words, *tp = conv + conv_words, *out = tp + tp_words;
-            ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)((ext_words + conv_words + tp_words + out_words) / N), 1, qm,
+            u64 *c0 = out + out_words;  // the rotated input's c0, added in the epilogue
+            ew_launch(c, EW_ZERO, ws, nullptr, ws, (int)((ext_words + conv_words + tp_words + 2 * out_words) / N), 1, qm,
                       c->stream);
             const u64 g = key_d->g ? key_d->g : 0;
             const int cpcs[3] = {4, 8, 16};
+            // the whole ModDown of a hoisted rotation, with c0 (through the
+            // automorphism) added in the epilogue: the other kernels between the
+            // two inner products decide what is still cached when they run
+            const LimbMap pm{0, 0, c->nQ};
             const int k = pick_fastest(c, 3, [&](int i) { c->ip_cpc = cpcs[i]; }, [&] {
                 ip_p_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);
-                moddown_ip_launch(c, ext, (long)(beta * E * N), key_d->data, conv, (long)(2 * L1 * N), nullptr, 0, 0, 0,
-                                  out, (long)(2 * L1 * N), level, count, g, c->stream);
-            });
+                ntt_launch(c, tp, (long)(c->nP * N), 2 * count, c->nP, pm, true, c->stream);
+                bconv_moddown_launch(c, tp, (long)(c->nP * N), conv, (long)(L1 * N), level, 2 * count, c->stream);
+                ntt_launch(c, conv, (long)(L1 * N), 2 * count, (int)L1, qm, false, c->stream);
+                moddown_ip_launch(c, ext, (long)(beta * E * N), key_d->data, conv, (long)(2 * L1 * N), c0,
+                                  (long)(2 * L1 * N), g, 0, out, (long)(2 * L1 * N), level, count, g, c->stream);
+            }, scrub);
             c->ip_cpc = cpc = cpcs[k];
         }
         if (hipGetLastError() != hipSuccess) return rbk_set_error(RBK_EDEVICE, "autotune launch failed");
