@@ -179,7 +179,10 @@ void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly,
 // ---------------------------------------------------------------- base conversion
 
 #define BCONV_MAX_IN 16
-#define BCONV_MAX_TAB 1024   // n_in * n_out words staged in LDS
+// the table is staged in LDS output-major, entry (i, o) at o * MAXIN + i, so
+// the inputs of one output sit at one address plus immediate offsets; n_out
+// is below the prime count
+#define BCONV_TAB(MAXIN) (RBK_MAX_PRIMES * (MAXIN))
 
 // Base-conversion sums use the carry-free 30-bit split accumulation of
 // wide_arith.hpp (at most 16 terms of residues and table entries below 2^60).
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
                                                       const u64 *Ash, const u64 *M, long m_stride, const PrimeC *pc,
                                                       const u64 *own, long own_stride)
 {
-    __shared__ Half30 tab[BCONV_MAX_TAB];
+    __shared__ Half30 tab[BCONV_TAB(MAXIN)];
     const size_t N = (size_t)1 << logN;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     const int poly = blockIdx.z;
@@ -231,20 +234,24 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
         x = in + poly * in_stride;
         dst = out + poly * out_stride;
     }
-    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS)
-        tab[w] = split30(Mj[(size_t)(w / n_out) * m_stride + (w % n_out)]);
+    // zero columns past n_in: every output sums all MAXIN terms without branches
+    for (int w = threadIdx.x; w < MAXIN * n_out; w += EW_THREADS) {
+        const int o = w / MAXIN, i = w % MAXIN;
+        tab[w] = i < n_in ? split30(Mj[(size_t)i * m_stride + o]) : Half30{0, 0};
+    }
     __syncthreads();
     if (k >= N) return;
     Half30 yh[MAXIN];
     const u64 *ownj = MODUP ? own + poly * own_stride + (size_t)lo * N : nullptr;
 #pragma unroll
-    for (int i = 0; i < MAXIN; i++)
+    for (int i = 0; i < MAXIN; i++) {
+        yh[i] = Half30{0, 0};
         if (i < n_in) {
             const int pi = MODUP ? lo + i : nQ + i;
-            const Half30 y = split30(shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[pi].q));
-            yh[i] = y;
+            yh[i] = split30(shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[pi].q));
             if (MODUP) dst[(size_t)(lo + i) * N + k] = ownj[(size_t)i * N + k];
         }
+    }
     for (int o = 0; o < n_out; o++) {
         int pos, pr;
         if (MODUP) {
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
         Acc4 acc;
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
-            if (i < n_in) wa::acc4(acc, yh[i], tab[i * n_out + o]);
+            wa::acc4(acc, yh[i], tab[o * MAXIN + i]);
         // n_in <= 16 terms, each y (< 2^60) times a table entry (< p): the sum
         // stays below p 2^64, so a plain REDC reduces it
         dst[(size_t)pos * N + k] = redc(acc4_sum(acc), p.q, p.qneg);
@@ -278,6 +285,9 @@ void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride
     else if (c->alpha <= 8)
         hipLaunchKernelGGL((k_bconv<true, 8>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
                            E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
+    else if (c->alpha <= 12)
+        hipLaunchKernelGGL((k_bconv<true, 12>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
+                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
     else
         hipLaunchKernelGGL((k_bconv<true, 16>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
                            E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
@@ -296,6 +306,9 @@ void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride
     else if (c->nP <= 8)
         hipLaunchKernelGGL((k_bconv<false, 8>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
                            L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
+    else if (c->nP <= 12)
+        hipLaunchKernelGGL((k_bconv<false, 12>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN,
+                           L1, L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
     else
         hipLaunchKernelGGL((k_bconv<false, 16>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN,
                            L1, L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
@@ -918,7 +931,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_up_list(const u64 *coef, l
                                                               int alpha, int nP, int nQ, const ListCt *cts,
                                                               const PrimeC *pc)
 {
-    __shared__ Half30 tab[BCONV_MAX_TAB];
+    __shared__ Half30 tab[BCONV_TAB(MAXIN)];
     const size_t N = (size_t)1 << logN;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     const int ct = blockIdx.z, j = blockIdx.y;
@@ -927,7 +940,11 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_up_list(const u64 *coef, l
     if (j >= beta) return;
     const int lo = j * alpha, n_in = min(alpha, L1 - lo), n_out = E - n_in;
     const u64 *Aj = C.A + j * alpha, *Ashj = C.Ash + j * alpha, *Mj = C.M + (size_t)j * alpha * E;
-    for (int w = threadIdx.x; w < n_in * n_out; w += EW_THREADS) tab[w] = split30(Mj[(size_t)(w / n_out) * E + (w % n_out)]);
+    // zero columns past n_in: every output sums all MAXIN terms without branches
+    for (int w = threadIdx.x; w < MAXIN * n_out; w += EW_THREADS) {
+        const int o = w / MAXIN, i = w % MAXIN;
+        tab[w] = i < n_in ? split30(Mj[(size_t)i * E + o]) : Half30{0, 0};
+    }
     __syncthreads();
     if (k >= N) return;
     const u64 *x = coef + ct * coef_stride + (size_t)lo * N;
@@ -935,12 +952,13 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_up_list(const u64 *coef, l
     u64 *dst = ext + ct * ext_stride + (size_t)j * dig_stride;
     Half30 yh[MAXIN];
 #pragma unroll
-    for (int i = 0; i < MAXIN; i++)
+    for (int i = 0; i < MAXIN; i++) {
+        yh[i] = Half30{0, 0};
         if (i < n_in) {
-            const Half30 y = split30(shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[lo + i].q));
-            yh[i] = y;
+            yh[i] = split30(shoup(x[(size_t)i * N + k], Aj[i], Ashj[i], pc[lo + i].q));
             dst[(size_t)(lo + i) * N + k] = own[(size_t)i * N + k];
         }
+    }
     for (int o = 0; o < n_out; o++) {
         const int pos = o < lo ? o : o + n_in;
         const int pr = pos < L1 ? pos : nQ + pos - L1;
@@ -948,7 +966,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_up_list(const u64 *coef, l
         Acc4 acc;
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
-            if (i < n_in) wa::acc4(acc, yh[i], tab[i * n_out + o]);
+            wa::acc4(acc, yh[i], tab[o * MAXIN + i]);
         dst[(size_t)pos * N + k] = redc(acc4_sum(acc), p.q, p.qneg);
     }
 }
@@ -960,29 +978,32 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv_down_list(const u64 *tp, u
                                                                 int nP, int nQ, const ListCt *cts, const u64 *A,
                                                                 const u64 *Ash, const u64 *M, const PrimeC *pc)
 {
-    __shared__ Half30 tab[BCONV_MAX_TAB];
+    __shared__ Half30 tab[BCONV_TAB(MAXIN)];
     const size_t N = (size_t)1 << logN;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     const int poly = blockIdx.z;
     const int n_out = cts[poly / 2].level + 1;
-    for (int w = threadIdx.x; w < nP * n_out; w += EW_THREADS) tab[w] = split30(M[(size_t)(w / n_out) * nQ + (w % n_out)]);
+    // zero columns past nP: every output sums all MAXIN terms without branches
+    for (int w = threadIdx.x; w < MAXIN * n_out; w += EW_THREADS) {
+        const int o = w / MAXIN, i = w % MAXIN;
+        tab[w] = i < nP ? split30(M[(size_t)i * nQ + o]) : Half30{0, 0};
+    }
     __syncthreads();
     if (k >= N) return;
     const u64 *x = tp + (size_t)poly * nP * N;
     u64 *dst = conv + poly * conv_stride;
     Half30 yh[MAXIN];
 #pragma unroll
-    for (int i = 0; i < MAXIN; i++)
-        if (i < nP) {
-            const Half30 y = split30(shoup(x[(size_t)i * N + k], A[i], Ash[i], pc[nQ + i].q));
-            yh[i] = y;
-        }
+    for (int i = 0; i < MAXIN; i++) {
+        yh[i] = Half30{0, 0};
+        if (i < nP) yh[i] = split30(shoup(x[(size_t)i * N + k], A[i], Ash[i], pc[nQ + i].q));
+    }
     for (int o = 0; o < n_out; o++) {
         const PrimeC p = pc[o];
         Acc4 acc;
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
-            if (i < nP) wa::acc4(acc, yh[i], tab[i * n_out + o]);
+            wa::acc4(acc, yh[i], tab[o * MAXIN + i]);
         dst[(size_t)o * N + k] = redc(acc4_sum(acc), p.q, p.qneg);
     }
 }
@@ -1150,6 +1171,9 @@ void bconv_up_list_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stri
     else if (c->alpha <= 8)
         hipLaunchKernelGGL((k_bconv_up_list<8>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, d, d_stride, ext,
                            ext_stride, dig_stride, c->logN, c->alpha, c->nP, c->nQ, cts, c->d_pc);
+    else if (c->alpha <= 12)
+        hipLaunchKernelGGL((k_bconv_up_list<12>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, d, d_stride, ext,
+                           ext_stride, dig_stride, c->logN, c->alpha, c->nP, c->nQ, cts, c->d_pc);
     else
         hipLaunchKernelGGL((k_bconv_up_list<16>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, d, d_stride, ext,
                            ext_stride, dig_stride, c->logN, c->alpha, c->nP, c->nQ, cts, c->d_pc);
@@ -1166,6 +1190,9 @@ void bconv_down_list_launch(const rbk_ctx_impl *c, const u64 *tp, u64 *conv, lon
                            c->nQ, cts, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
     else if (c->nP <= 8)
         hipLaunchKernelGGL((k_bconv_down_list<8>), grid, dim3(EW_THREADS), 0, st, tp, conv, conv_stride, c->logN, c->nP,
+                           c->nQ, cts, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
+    else if (c->nP <= 12)
+        hipLaunchKernelGGL((k_bconv_down_list<12>), grid, dim3(EW_THREADS), 0, st, tp, conv, conv_stride, c->logN, c->nP,
                            c->nQ, cts, c->d_md_A, c->d_md_Ash, c->d_md_M, c->d_pc);
     else
         hipLaunchKernelGGL((k_bconv_down_list<16>), grid, dim3(EW_THREADS), 0, st, tp, conv, conv_stride, c->logN, c->nP,
