@@ -246,6 +246,24 @@ char *desc_upload(rbk_ctx_impl *c, const DescBlob &b, int *rc)
     return (char *)c->desc_dev;
 }
 
+// the two side streams (default priority) and three events of the
+// two-lane ModDown, created on first use on the context's device
+static int side_streams(rbk_ctx_impl *c)
+{
+    if (c->side[0]) return RBK_OK;
+    for (int k = 0; k < 2; k++)
+        if (hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking) != hipSuccess) {
+            c->side[k] = nullptr;
+            return rbk_set_error(RBK_EDEVICE, "side stream creation failed");
+        }
+    for (int k = 0; k < 3; k++)
+        if (hipEventCreateWithFlags(&c->side_ev[k], hipEventDisableTiming) != hipSuccess) {
+            c->side_ev[k] = nullptr;
+            return rbk_set_error(RBK_EDEVICE, "event creation failed");
+        }
+    return RBK_OK;
+}
+
 #define WS(ptr, words)                                                                         \
     u64 *ptr = ws_reserve(c, (words));                                                          \
     if (!ptr) return c->capturing ? RBK_ESTATE : fail(RBK_ENOMEM, "device workspace allocation failed");
@@ -475,6 +493,13 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
     for (void *p : c->retired) (void)hipFree(p);
     if (c->ws) (void)hipFree(c->ws);
     if (c->desc_dev) (void)hipFree(c->desc_dev);
+    for (int k = 0; k < 2; k++)
+        if (c->side[k]) {
+            (void)hipStreamSynchronize(c->side[k]);
+            (void)hipStreamDestroy(c->side[k]);
+        }
+    for (int k = 0; k < 3; k++)
+        if (c->side_ev[k]) (void)hipEventDestroy(c->side_ev[k]);
     for (int k = 0; k < 2; k++) {
         if (c->desc_host[k]) (void)hipHostFree(c->desc_host[k]);
         if (c->desc_evt[k]) (void)hipEventDestroy(c->desc_evt[k]);
@@ -914,20 +939,21 @@ static int moddown_run(rbk_ctx *c, u64 *u, const u64 *add, long add_stride, u64 
 // the inner product is stored; the Q part is recomputed in the final kernel.
 static int moddown_fused_run(rbk_ctx *c, const u64 *ext, long ext_stride, const DevKey *key, u64 perm_g, const u64 *add,
                              long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count,
-                             u64 *tp, u64 *conv)
+                             u64 *tp, u64 *conv, hipStream_t st = nullptr)
 {
     const size_t N = c->N;
     const int L1 = level + 1, nP = c->nP;
+    if (!st) st = c->stream;
     if (nP > 0) {
-        ip_p_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, c->stream);
-        ntt_launch(c, tp, (long)nP * N, 2 * count, nP, LimbMap{0, 0, c->nQ}, true, c->stream);
-        bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, c->stream);
-        ntt_launch(c, conv, (long)L1 * N, 2 * count, L1, qmap(c), false, c->stream);
+        ip_p_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, st);
+        ntt_launch(c, tp, (long)nP * N, 2 * count, nP, LimbMap{0, 0, c->nQ}, true, st);
+        bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, st);
+        ntt_launch(c, conv, (long)L1 * N, 2 * count, L1, qmap(c), false, st);
     } else {
-        ew_launch(c, EW_ZERO, conv, nullptr, conv, 2 * count, L1, qmap(c), c->stream);
+        ew_launch(c, EW_ZERO, conv, nullptr, conv, 2 * count, L1, qmap(c), st);
     }
     moddown_ip_launch(c, ext, ext_stride, key->data, conv, (long)2 * L1 * N, add, add_stride, add_g, add_both, out,
-                      out_stride, level, count, perm_g, c->stream);
+                      out_stride, level, count, perm_g, st);
     HIPCK_LAUNCH();
     return RBK_OK;
 }
@@ -1110,10 +1136,22 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
         keys[r] = gs[r] == 1 ? nullptr : find_key(c, gs[r]);
         if (gs[r] != 1 && !keys[r]) return fail(RBK_ENOKEY, "no Galois key for rotation " + std::to_string(ks[r]));
     }
-    WS(ws, ks_words(c, level, count));
+    // two ModDown lanes: the rotations' independent ModDowns alternate over
+    // two side streams with buffers of their own, so the VALU-bound stages of
+    // one overlap the memory-bound stages of the other (one lane while the
+    // stream is being captured)
+    const size_t tp_words = (size_t)count * 2 * c->nP * N, conv_words = (size_t)count * 2 * L1 * N;
+    WS(ws, ks_words(c, level, count) + tp_words + conv_words);
     KsBufs b = ks_layout(c, ws, level, count);
+    u64 *tp2 = ws + ks_words(c, level, count), *conv2 = tp2 + tp_words;
     int rc = modup_run(c, ct + per, (long)(2 * per), b.ext, (long)(beta * E * N), level, count, b.coef);
     if (rc) return rc;
+    const bool two = !c->capturing && n > 1 && side_streams(c) == RBK_OK;
+    if (two) {
+        HIPCK(hipEventRecord(c->side_ev[2], c->stream));
+        for (int k = 0; k < 2; k++) HIPCK(hipStreamWaitEvent(c->side[k], c->side_ev[2], 0));
+    }
+    int lane = 0;
     for (int r = 0; r < n; r++) {
         u64 *o = outs + (size_t)r * 2 * per;
         if (gs[r] == 1) {
@@ -1121,10 +1159,17 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
                                    hipMemcpyDeviceToDevice, c->stream));
             continue;
         }
+        hipStream_t st = two ? c->side[lane] : c->stream;
         rc = moddown_fused_run(c, b.ext, (long)(beta * E * N), keys[r], gs[r], ct, (long)(2 * per), gs[r], 0, o,
-                               (long)(n * 2 * per), level, count, b.tp, b.conv);
+                               (long)(n * 2 * per), level, count, lane ? tp2 : b.tp, lane ? conv2 : b.conv, st);
         if (rc) return rc;
+        if (two) lane ^= 1;
     }
+    if (two)
+        for (int k = 0; k < 2; k++) {
+            HIPCK(hipEventRecord(c->side_ev[k], c->side[k]));
+            HIPCK(hipStreamWaitEvent(c->stream, c->side_ev[k], 0));
+        }
     return RBK_OK;
 }
 

@@ -116,6 +116,9 @@ struct rbk_ctx_impl {
     size_t desc_host_bytes[2] = {0, 0};
     hipEvent_t desc_evt[2] = {nullptr, nullptr};
     int desc_turn = 0;
+    // side streams of the two-lane ModDown of hoisted rotations (lazily created)
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t side_ev[3] = {nullptr, nullptr, nullptr};
     mutable KTimer timers[KC_COUNT];
     mutable std::vector<hipEvent_t> event_pool;
 };
