@@ -1136,17 +1136,20 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
         keys[r] = gs[r] == 1 ? nullptr : find_key(c, gs[r]);
         if (gs[r] != 1 && !keys[r]) return fail(RBK_ENOKEY, "no Galois key for rotation " + std::to_string(ks[r]));
     }
-    // two ModDown lanes: the rotations' independent ModDowns alternate over
-    // two side streams with buffers of their own, so the VALU-bound stages of
-    // one overlap the memory-bound stages of the other (one lane while the
-    // stream is being captured)
+    // two ModDown lanes for small batches: the rotations' independent
+    // ModDowns alternate over two side streams with buffers of their own, so
+    // kernels too small to fill the GPU overlap (per-ciphertext calls gain
+    // ~20%, a 64-ciphertext batch ~1%).  One lane for large batches, while the
+    // stream is being captured, and while per-kernel timers run (overlapping
+    // kernels would not have durations of their own)
     const size_t tp_words = (size_t)count * 2 * c->nP * N, conv_words = (size_t)count * 2 * L1 * N;
     WS(ws, ks_words(c, level, count) + tp_words + conv_words);
     KsBufs b = ks_layout(c, ws, level, count);
     u64 *tp2 = ws + ks_words(c, level, count), *conv2 = tp2 + tp_words;
     int rc = modup_run(c, ct + per, (long)(2 * per), b.ext, (long)(beta * E * N), level, count, b.coef);
     if (rc) return rc;
-    const bool two = !c->capturing && n > 1 && side_streams(c) == RBK_OK;
+    const bool small = (size_t)2 * count * L1 < 1024;  // limbs of one ModDown transform
+    const bool two = small && !c->capturing && !c->timing && n > 1 && side_streams(c) == RBK_OK;
     if (two) {
         HIPCK(hipEventRecord(c->side_ev[2], c->stream));
         for (int k = 0; k < 2; k++) HIPCK(hipStreamWaitEvent(c->side[k], c->side_ev[2], 0));
