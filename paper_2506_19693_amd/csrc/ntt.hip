@@ -407,9 +407,12 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 }
 
 // One tile (4096 elements: LINES lines of S) of one pass over the limb at
-// base (prime pr of the tables T).  sm: LINES * LS words of LDS.
+// base (prime pr of the tables T).  sm: LINES * LS words of LDS; smtw: 512
+// words of LDS for the column passes.  A column pass uses only the twiddles
+// 1 .. 2^LOGS - 1 (the same for every column of the limb), so the block stages
+// them in LDS once instead of every thread loading them from memory.
 template <int LOGS, bool INV, bool COLS>
-__device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, const NttTables &T, int pr, int tile, int logN)
+__device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const NttTables &T, int pr, int tile, int logN)
 {
     typedef Geo<LOGS> G;
     constexpr int NST2 = LOGS - 4;
@@ -426,13 +429,29 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, const NttTables &
     const int gl = tile * G::LINES + line;                // column (COLS) or row index
     const FpC fc = T.fc[pr];
     if (fc.use) {
-        ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, (INV ? T.itwf : T.twf) + (size_t)pr * N, t, gl, logN);
+        const double2 *twf = (INV ? T.itwf : T.twf) + (size_t)pr * N;
+        if (COLS) {
+            double2 *st = reinterpret_cast<double2 *>(smtw);
+            for (int k = tid; k < G::S; k += 256) st[k] = twf[k];
+            __syncthreads();
+            twf = st;
+        }
+        ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, twf, t, gl, logN);
         return;
     }
     const PrimeC pc = T.pc[pr];
     const u64 q = pc.q, q2 = 2 * q, q4 = 4 * q;
     const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
     const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
+    if (COLS) {
+        for (int k = tid; k < G::S; k += 256) {
+            smtw[k] = tw[k];
+            smtw[256 + k] = tws[k];
+        }
+        __syncthreads();
+        tw = smtw;
+        tws = smtw + 256;
+    }
     const size_t C = COLS ? (N >> LOGS) : (size_t)G::S;   // row length of the R x C view
     u64 *sl = sm + line * G::LS;
     auto addr = [&](int e) -> size_t { return COLS ? (size_t)e * C + gl : (size_t)gl * G::S + e; };
@@ -497,9 +516,10 @@ template <int LOGS, bool INV, bool COLS>
 __global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN)
 {
     __shared__ u64 sm[Geo<LOGS>::LINES * Geo<LOGS>::LS];
+    __shared__ __attribute__((aligned(16))) u64 smtw[COLS ? 512 : 2];
     const int limb = blockIdx.z, poly = blockIdx.y;
     u64 *base = data + (size_t)poly * poly_stride + ((size_t)limb << logN);
-    ntt16_tile<LOGS, INV, COLS>(base, sm, T, map.prime(limb), blockIdx.x, logN);
+    ntt16_tile<LOGS, INV, COLS>(base, sm, smtw, T, map.prime(limb), blockIdx.x, logN);
 }
 
 // Descriptor-list form: a persistent grid walks the (item, tile) units of a
@@ -512,8 +532,12 @@ __global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, Limb
 template <bool INV, bool FIRST>
 __global__ __launch_bounds__(256) void k_ntt16_list(const NttItem *items, const int *prefix, int n_items, int total)
 {
-    __shared__ u64 sm[Geo<8>::LINES * Geo<8>::LS > NTT_TILE ? Geo<8>::LINES * Geo<8>::LS : NTT_TILE];
     constexpr bool COLS = INV ? !FIRST : FIRST;
+    // the largest tile of the three geometries and of the one-pass row tile
+    constexpr int W6 = Geo<6>::LINES * Geo<6>::LS, W7 = Geo<7>::LINES * Geo<7>::LS, W8 = Geo<8>::LINES * Geo<8>::LS;
+    constexpr int W67 = W6 > W7 ? W6 : W7, W678 = W67 > W8 ? W67 : W8;
+    __shared__ u64 sm[W678 > NTT_TILE ? W678 : NTT_TILE];
+    __shared__ __attribute__((aligned(16))) u64 smtw[COLS ? 512 : 2];
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         // the item holding unit u: prefix[it] <= u < prefix[it + 1]
         int lo = 0, hi = n_items - 1;
@@ -531,9 +555,9 @@ __global__ __launch_bounds__(256) void k_ntt16_list(const NttItem *items, const 
         }
         const int logs = COLS ? it.logN - it.logC : it.logC;
         switch (logs) {
-        case 6: ntt16_tile<6, INV, COLS>(it.data, sm, *it.tabs, it.prime, tile, it.logN); break;
-        case 7: ntt16_tile<7, INV, COLS>(it.data, sm, *it.tabs, it.prime, tile, it.logN); break;
-        default: ntt16_tile<8, INV, COLS>(it.data, sm, *it.tabs, it.prime, tile, it.logN); break;
+        case 6: ntt16_tile<6, INV, COLS>(it.data, sm, smtw, *it.tabs, it.prime, tile, it.logN); break;
+        case 7: ntt16_tile<7, INV, COLS>(it.data, sm, smtw, *it.tabs, it.prime, tile, it.logN); break;
+        default: ntt16_tile<8, INV, COLS>(it.data, sm, smtw, *it.tabs, it.prime, tile, it.logN); break;
         }
         __syncthreads();  // the next unit reuses the LDS tile
     }
