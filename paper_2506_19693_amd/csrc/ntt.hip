@@ -227,15 +227,72 @@ struct Geo {
 
 __device__ __forceinline__ int lidx(int e) { return e + (e >> 4); }
 
+// Twiddle index of local stage s for element e of line line_id.  STG = 0: the
+// table itself (forward (1 << (off+s)) + (line << s) + (e >> (LOGS-s)),
+// inverse (1 << (logN-1-off-s)) + (line << (LOGS-s-1)) + (e >> (s+1))).
+// STG = 1: the copy a row pass stages for its block of LINES rows starting at
+// row lb: the forward stages 0..3 (2^s twiddles per row, stage s at
+// LINES (2^s - 1)) or the inverse stages 4..LOGS-1 (2^(LOGS-s-1) per row,
+// stage s at LINES (2^(LOGS-4) - 2^(LOGS-s))).
+template <bool INV, int LOGS, int STG>
+__device__ __forceinline__ int tw_index(int s, int off, int line_id, int lb, int e, int logN)
+{
+    constexpr int LINES = Geo<LOGS>::LINES;
+    if (STG == 0) {
+        if (!INV) return (1 << (off + s)) + (line_id << s) + (e >> (LOGS - s));
+        return (1 << (logN - 1 - off - s)) + (line_id << (LOGS - s - 1)) + (e >> (s + 1));
+    }
+    if (!INV) return LINES * ((1 << s) - 1) + ((line_id - lb) << s) + (e >> (LOGS - s));
+    return LINES * ((1 << (LOGS - 4)) - (1 << (LOGS - s))) + ((line_id - lb) << (LOGS - s - 1)) + (e >> (s + 1));
+}
+
+// Row passes stage twiddles only for 256-element rows: there a block's copy
+// (15 per row, both directions) takes 3.75 KB beside the 35 KB tile; for
+// shorter rows (more rows per block) it would cost a block per CU.
+// TwWords: the words of LDS a pass needs for its staged twiddles (two words
+// per twiddle).
+template <int LOGS>
+struct RowStage {
+    static constexpr bool on = LOGS == 8;
+    static constexpr int ENTRIES = on ? 15 * Geo<LOGS>::LINES : 1;
+};
+template <int LOGS, bool COLS>
+struct TwWords {
+    static constexpr int value = COLS ? 2 * (1 << LOGS) : 2 * RowStage<LOGS>::ENTRIES;
+};
+
+// Copy into LDS the twiddles a row pass reads through tw_index<., ., 1> for
+// the block of rows starting at lb: dst[k] = src[global index of entry k].
+template <bool INV, int LOGS, class T>
+__device__ __forceinline__ void stage_row_twiddles(T *dst, const T *src, int lb, int logN, int tid)
+{
+    constexpr int LINES = Geo<LOGS>::LINES;
+    if (!INV) {
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int cnt = LINES << s, o = LINES * ((1 << s) - 1);
+            const size_t g0 = ((size_t)1 << (logN - LOGS + s)) + ((size_t)lb << s);
+            for (int w = tid; w < cnt; w += 256) dst[o + w] = src[g0 + w];
+        }
+    } else {
+#pragma unroll
+        for (int s = 4; s < LOGS; s++) {
+            const int cnt = LINES << (LOGS - s - 1), o = LINES * ((1 << (LOGS - 4)) - (1 << (LOGS - s)));
+            const size_t g0 = ((size_t)1 << (logN - 1 - s)) + ((size_t)lb << (LOGS - s - 1));
+            for (int w = tid; w < cnt; w += 256) dst[o + w] = src[g0 + w];
+        }
+    }
+}
+
 // NST butterfly stages on the 16 registers; register distance starts at RD0
 // and halves (forward) or doubles (inverse).  Element i has line index
 // ebase + estride*i.  Forward local stage s = s0+k uses twiddle
 // (1 << (off+s)) + (line_id << s) + (e >> (LOGS-s)); inverse local stage
 // (distance 2^s in the line) uses (1 << (logN-1-off-s)) + (line_id << (LOGS-s-1)) + (e >> (s+1)).
-template <bool INV, int NST, int RD0, int LOGS>
+template <bool INV, int NST, int RD0, int LOGS, int STG = 0>
 __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride, int s0, int off, int line_id, int logN,
                                             const u64 *tw, const u64 *tws, u64 q, u64 q4, bool fold, u64 ninv,
-                                            u64 ninv_sh, u64 lw, u64 lw_sh)
+                                            u64 ninv_sh, u64 lw, u64 lw_sh, int lb = 0)
 {
 #pragma unroll
     for (int k = 0; k < NST; k++) {
@@ -246,7 +303,7 @@ __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride
             const int i0 = (j / d) * 2 * d + (j % d), i1 = i0 + d;
             const int e = ebase + estride * i0;
             if (!INV) {
-                const int ti = (1 << (off + s)) + (line_id << s) + (e >> (LOGS - s));
+                const int ti = tw_index<false, LOGS, STG>(s, off, line_id, lb, e, logN);
                 bfly_ct8(x[i0], x[i1], tw[ti], tws[ti], q, q4);
             } else if (fold && k == NST - 1) {
                 u64 sum = csub(x[i0] + x[i1], q4);
@@ -254,7 +311,7 @@ __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride
                 x[i0] = shoup_lazy4(sum, ninv, ninv_sh, q);
                 x[i1] = shoup_lazy4(dd, lw, lw_sh, q);
             } else {
-                const int ti = (1 << (logN - 1 - off - s)) + (line_id << (LOGS - s - 1)) + (e >> (s + 1));
+                const int ti = tw_index<true, LOGS, STG>(s, off, line_id, lb, e, logN);
                 bfly_gs4(x[i0], x[i1], tw[ti], tws[ti], q, q4);
             }
         }
@@ -286,9 +343,9 @@ using wa::fp_mul;
 using wa::fp_red;
 using wa::fp_to_u64;
 
-template <int LOGS, int NST, int RD0, bool INV>
+template <int LOGS, int NST, int RD0, bool INV, int STG = 0>
 __device__ __forceinline__ void fp_round16(double (&x)[16], int ebase, int estride, int s0, int off, int line_id, int logN,
-                                           const double2 *twf, double p, bool fold, const FpC &fc)
+                                           const double2 *twf, double p, bool fold, const FpC &fc, int lb = 0)
 {
 #pragma unroll
     for (int k = 0; k < NST; k++) {
@@ -299,7 +356,7 @@ __device__ __forceinline__ void fp_round16(double (&x)[16], int ebase, int estri
             const int i0 = (j / d) * 2 * d + (j % d), i1 = i0 + d;
             const int e = ebase + estride * i0;
             if (!INV) {
-                const int ti = (1 << (off + s)) + (line_id << s) + (e >> (LOGS - s));
+                const int ti = tw_index<false, LOGS, STG>(s, off, line_id, lb, e, logN);
                 const double2 w = twf[ti];
                 const double t = fp_mul(x[i1], w.x, w.y, p);
                 const double u = x[i0];
@@ -310,7 +367,7 @@ __device__ __forceinline__ void fp_round16(double (&x)[16], int ebase, int estri
                 x[i0] = fp_mul(u + v, fc.ninv, fc.ninv_p, p);
                 x[i1] = fp_mul(u - v, fc.lw, fc.lw_p, p);
             } else {
-                const int ti = (1 << (logN - 1 - off - s)) + (line_id << (LOGS - s - 1)) + (e >> (s + 1));
+                const int ti = tw_index<true, LOGS, STG>(s, off, line_id, lb, e, logN);
                 const double2 w = twf[ti];
                 const double u = x[i0], v = x[i1];
                 x[i0] = u + v;
@@ -329,12 +386,15 @@ __device__ __forceinline__ void fp_reduce16(double (&x)[16], double p, double pi
 
 // One pass of the register NTT in FP64 (same geometry and twiddle indexing as
 // the integer pass in k_ntt16).
+// twf: the twiddles of the unstaged rounds; twr (row passes): the block's
+// staged copy for the round whose twiddles repeat within a row (lines from lb)
 template <int LOGS, bool INV, bool COLS>
-__device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, int t, int gl,
-                                         int logN)
+__device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, const double2 *twr,
+                                         int lb, int t, int gl, int logN)
 {
     typedef Geo<LOGS> G;
     constexpr int NST2 = LOGS - 4;
+    constexpr int RS = (!COLS && RowStage<LOGS>::on) ? 1 : 0;
     const size_t N = (size_t)1 << logN;
     const size_t C = COLS ? (N >> LOGS) : (size_t)G::S;
     auto addr = [&](int e) -> size_t { return COLS ? (size_t)e * C + gl : (size_t)gl * G::S + e; };
@@ -354,7 +414,7 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
             for (int i = 0; i < 16; i++) x[i] = __longlong_as_double((long long)base[addr(t + G::TPL * i)]);
         }
         fp_reduce16<LOGS>(x, p, pinv);
-        fp_round16<LOGS, 4, 8, false>(x, t, G::TPL, 0, off_f, lid, logN, twf, p, false, fc);
+        fp_round16<LOGS, 4, 8, false, RS>(x, t, G::TPL, 0, off_f, lid, logN, RS ? twr : twf, p, false, fc, lb);
 #pragma unroll
         for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = x[i];
         __syncthreads();
@@ -395,7 +455,7 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = sl[lidx(t + G::TPL * i)];
         fp_reduce16<LOGS>(x, p, pinv);
-        fp_round16<LOGS, NST2, (16 >> NST2), true>(x, t, G::TPL, 4, off_i, lid, logN, twf, p, COLS, fc);
+        fp_round16<LOGS, NST2, (16 >> NST2), true, RS>(x, t, G::TPL, 4, off_i, lid, logN, RS ? twr : twf, p, COLS, fc, lb);
         if (COLS) {
 #pragma unroll
             for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = fp_to_u64(x[i], p, pinv);
@@ -407,10 +467,13 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 }
 
 // One tile (4096 elements: LINES lines of S) of one pass over the limb at
-// base (prime pr of the tables T).  sm: LINES * LS words of LDS; smtw: 512
-// words of LDS for the column passes.  A column pass uses only the twiddles
-// 1 .. 2^LOGS - 1 (the same for every column of the limb), so the block stages
-// them in LDS once instead of every thread loading them from memory.
+// base (prime pr of the tables T).  sm: LINES * LS words of LDS; smtw:
+// TwWords<LOGS, COLS> words of LDS for staged twiddles.  A column pass uses
+// only the twiddles 1 .. 2^LOGS - 1 (the same for every column of the limb),
+// so the block stages them in LDS once instead of every thread loading them
+// from memory.  A row pass stages the round whose twiddles depend on the row
+// (forward stages 0..3, inverse stages 4..LOGS-1): the block's rows use a
+// contiguous range of each stage's table, which is read once per block.
 template <int LOGS, bool INV, bool COLS>
 __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const NttTables &T, int pr, int tile, int logN)
 {
@@ -428,29 +491,42 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
     }
     const int gl = tile * G::LINES + line;                // column (COLS) or row index
     const FpC fc = T.fc[pr];
+    const int lb = tile * G::LINES;                        // first line of the block
     if (fc.use) {
         const double2 *twf = (INV ? T.itwf : T.twf) + (size_t)pr * N;
+        double2 *st = reinterpret_cast<double2 *>(smtw);
         if (COLS) {
-            double2 *st = reinterpret_cast<double2 *>(smtw);
             for (int k = tid; k < G::S; k += 256) st[k] = twf[k];
-            __syncthreads();
             twf = st;
+            __syncthreads();
+        } else if (RowStage<LOGS>::on) {
+            stage_row_twiddles<INV, LOGS>(st, twf, lb, logN, tid);
+            __syncthreads();
         }
-        ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, twf, t, gl, logN);
+        ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN);
         return;
     }
     const PrimeC pc = T.pc[pr];
     const u64 q = pc.q, q2 = 2 * q, q4 = 4 * q;
     const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
     const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
+    // staged copies: for a column pass every twiddle it uses, for a row pass
+    // the round whose twiddles repeat within a row (twr / twsr)
+    constexpr int TH = TwWords<LOGS, COLS>::value / 2;
+    constexpr int RS = (!COLS && RowStage<LOGS>::on) ? 1 : 0;
+    const u64 *twr = RS ? smtw : tw, *twsr = RS ? smtw + TH : tws;
     if (COLS) {
         for (int k = tid; k < G::S; k += 256) {
             smtw[k] = tw[k];
-            smtw[256 + k] = tws[k];
+            smtw[TH + k] = tws[k];
         }
-        __syncthreads();
         tw = smtw;
-        tws = smtw + 256;
+        tws = smtw + TH;
+        __syncthreads();
+    } else if (RS) {
+        stage_row_twiddles<INV, LOGS>(smtw, tw, lb, logN, tid);
+        stage_row_twiddles<INV, LOGS>(smtw + TH, tws, lb, logN, tid);
+        __syncthreads();
     }
     const size_t C = COLS ? (N >> LOGS) : (size_t)G::S;   // row length of the R x C view
     u64 *sl = sm + line * G::LS;
@@ -463,7 +539,8 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
     if (!INV) {
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = base[addr(t + G::TPL * i)];
-        ntt_round16<false, 4, 8, LOGS>(x, t, G::TPL, 0, off_f, lid, logN, tw, tws, q, q4, false, 0, 0, 0, 0);
+        ntt_round16<false, 4, 8, LOGS, RS>(x, t, G::TPL, 0, off_f, lid, logN, RS ? twr : tw, RS ? twsr : tws, q, q4, false,
+                                           0, 0, 0, 0, lb);
 #pragma unroll
         for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = x[i];
         __syncthreads();
@@ -500,8 +577,8 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = sl[lidx(t + G::TPL * i)];
-        ntt_round16<true, NST2, (16 >> NST2), LOGS>(x, t, G::TPL, 4, off_i, lid, logN, tw, tws, q, q4, COLS, pc.ninv,
-                                                    pc.ninv_sh, T.last[pr], T.last_sh[pr]);
+        ntt_round16<true, NST2, (16 >> NST2), LOGS, RS>(x, t, G::TPL, 4, off_i, lid, logN, RS ? twr : tw, RS ? twsr : tws, q,
+                                                        q4, COLS, pc.ninv, pc.ninv_sh, T.last[pr], T.last_sh[pr], lb);
         if (COLS) {
 #pragma unroll
             for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = csub(csub(x[i], q2), q);
@@ -516,7 +593,7 @@ template <int LOGS, bool INV, bool COLS>
 __global__ __launch_bounds__(256) void k_ntt16(u64 *data, long poly_stride, LimbMap map, NttTables T, int logN)
 {
     __shared__ u64 sm[Geo<LOGS>::LINES * Geo<LOGS>::LS];
-    __shared__ __attribute__((aligned(16))) u64 smtw[COLS ? 512 : 2];
+    __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, COLS>::value];
     const int limb = blockIdx.z, poly = blockIdx.y;
     u64 *base = data + (size_t)poly * poly_stride + ((size_t)limb << logN);
     ntt16_tile<LOGS, INV, COLS>(base, sm, smtw, T, map.prime(limb), blockIdx.x, logN);
@@ -537,7 +614,9 @@ __global__ __launch_bounds__(256) void k_ntt16_list(const NttItem *items, const 
     constexpr int W6 = Geo<6>::LINES * Geo<6>::LS, W7 = Geo<7>::LINES * Geo<7>::LS, W8 = Geo<8>::LINES * Geo<8>::LS;
     constexpr int W67 = W6 > W7 ? W6 : W7, W678 = W67 > W8 ? W67 : W8;
     __shared__ u64 sm[W678 > NTT_TILE ? W678 : NTT_TILE];
-    __shared__ __attribute__((aligned(16))) u64 smtw[COLS ? 512 : 2];
+    constexpr int T6 = TwWords<6, COLS>::value, T7 = TwWords<7, COLS>::value, T8 = TwWords<8, COLS>::value;
+    constexpr int T67 = T6 > T7 ? T6 : T7, T678 = T67 > T8 ? T67 : T8;
+    __shared__ __attribute__((aligned(16))) u64 smtw[T678];
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         // the item holding unit u: prefix[it] <= u < prefix[it + 1]
         int lo = 0, hi = n_items - 1;
