@@ -246,19 +246,32 @@ __device__ __forceinline__ int tw_index(int s, int off, int line_id, int lb, int
     return LINES * ((1 << (LOGS - 4)) - (1 << (LOGS - s))) + ((line_id - lb) << (LOGS - s - 1)) + (e >> (s + 1));
 }
 
-// Row passes stage twiddles only for 256-element rows: there a block's copy
-// (15 per row, both directions) takes 3.75 KB beside the 35 KB tile; for
-// shorter rows (more rows per block) it would cost a block per CU.
+// Row passes stage the round whose twiddles repeat within a row only for
+// 256-element rows: there a block's copy (15 per row, both directions) takes
+// 3.75 KB beside the 35 KB tile; for shorter rows (more rows per block) it
+// would cost a block per CU.
+// The other round of an FP64 row pass (forward stages 4..LOGS-1, inverse
+// stages 0..3) needs a distinct twiddle for almost every butterfly; those are
+// formed in registers instead (GenStage): with tw[j] = psi^brv(j), an index
+// m = hi + lo whose parts have disjoint bits gives tw[m] = tw[hi] tw[lo], so a
+// block stages, per row, the four entries tw[hi] of its stages (A) and, for
+// all rows, the entries tw[lo] for lo < 2^(LOGS-1) (R).
 // TwWords: the words of LDS a pass needs for its staged twiddles (two words
 // per twiddle).
 template <int LOGS>
 struct RowStage {
     static constexpr bool on = LOGS == 8;
-    static constexpr int ENTRIES = on ? 15 * Geo<LOGS>::LINES : 1;
+    static constexpr int ENTRIES = on ? 15 * Geo<LOGS>::LINES : 0;
+};
+template <int LOGS>
+struct GenStage {
+    static constexpr int A = RowStage<LOGS>::ENTRIES;              // double2 offset of A (4 per row)
+    static constexpr int R = A + 4 * Geo<LOGS>::LINES;             // double2 offset of R (doubles)
+    static constexpr int END = R + (1 << (LOGS - 2));              // double2 entries in all
 };
 template <int LOGS, bool COLS>
 struct TwWords {
-    static constexpr int value = COLS ? 2 * (1 << LOGS) : 2 * RowStage<LOGS>::ENTRIES;
+    static constexpr int value = COLS ? 2 * (1 << LOGS) : 2 * GenStage<LOGS>::END;
 };
 
 // Copy into LDS the twiddles a row pass reads through tw_index<., ., 1> for
@@ -282,6 +295,23 @@ __device__ __forceinline__ void stage_row_twiddles(T *dst, const T *src, int lb,
             for (int w = tid; w < cnt; w += 256) dst[o + w] = src[g0 + w];
         }
     }
+}
+
+// The A and R entries of GenStage for the block of rows starting at lb, from
+// the direction's FP64 table: A[4 r + k] = tw[hi] of local stage k + 4
+// (forward) or k (inverse) of row lb + r; R[k] = tw[k].x for k < 2^(LOGS-1).
+template <bool INV, int LOGS>
+__device__ __forceinline__ void stage_gen_twiddles(double2 *A, const double2 *src, int lb, int logN, int tid)
+{
+    constexpr int LINES = Geo<LOGS>::LINES, NS = INV ? 4 : LOGS - 4, HALF = 1 << (LOGS - 1);
+    double *R = reinterpret_cast<double *>(A + 4 * LINES);
+    for (int w = tid; w < LINES * NS; w += 256) {
+        const int r = w / NS, k = w % NS;
+        const size_t gi = INV ? ((size_t)1 << (logN - 1 - k)) + ((size_t)(lb + r) << (LOGS - 1 - k))
+                              : ((size_t)1 << (logN - LOGS + 4 + k)) + ((size_t)(lb + r) << (4 + k));
+        A[r * 4 + k] = src[gi];
+    }
+    for (int k = tid; k < HALF; k += 256) R[k] = src[k].x;
 }
 
 // NST butterfly stages on the 16 registers; register distance starts at RD0
@@ -377,6 +407,41 @@ __device__ __forceinline__ void fp_round16(double (&x)[16], int ebase, int estri
     }
 }
 
+// The GenStage round of an FP64 row pass on the contiguous pattern
+// (e = 16 t + i): forward local stages 4..3+NST, inverse 0..NST-1.  The
+// twiddle of element e at local stage s has index hi + lo with
+// lo = e >> (LOGS - s) (forward) or e >> (s + 1) (inverse); hi is the row's
+// entry A[k].  Each distinct twiddle of the thread is formed once per stage.
+template <int LOGS, int NST, int RD0, bool INV>
+__device__ __forceinline__ void fp_round16_gen(double (&x)[16], int t, const double2 *A, const double *R, double p,
+                                               double pinv)
+{
+#pragma unroll
+    for (int k = 0; k < NST; k++) {
+        const int d = INV ? (RD0 << k) : (RD0 >> k);
+        const int s = (INV ? 0 : 4) + k;
+        const int sh = INV ? s + 1 : LOGS - s;                    // element -> twiddle shift, 1..4
+        const double2 a = A[k];
+        double w[8], wp[8];
+#pragma unroll
+        for (int sl = 0; sl < (16 >> sh); sl++) wa::fp_twiddle(R[(t << (4 - sh)) + sl], a.x, a.y, p, pinv, w[sl], wp[sl]);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int i0 = (j / d) * 2 * d + (j % d), i1 = i0 + d;
+            const int sl = i0 >> sh;
+            const double u = x[i0], v = x[i1];
+            if (!INV) {
+                const double tt = fp_mul(v, w[sl], wp[sl], p);
+                x[i0] = u + tt;
+                x[i1] = u - tt;
+            } else {
+                x[i0] = u + v;
+                x[i1] = fp_mul(u - v, w[sl], wp[sl], p);
+            }
+        }
+    }
+}
+
 template <int LOGS>
 __device__ __forceinline__ void fp_reduce16(double (&x)[16], double p, double pinv)
 {
@@ -386,10 +451,10 @@ __device__ __forceinline__ void fp_reduce16(double (&x)[16], double p, double pi
 
 // One pass of the register NTT in FP64 (same geometry and twiddle indexing as
 // the integer pass in k_ntt16).
-// twf: the twiddles of the unstaged rounds; twr (row passes): the block's
-// staged copy for the round whose twiddles repeat within a row (lines from lb)
+// twf: the twiddles of the column pass (staged) or the table; stg (row
+// passes): the block's staged RowStage and GenStage entries (rows from lb)
 template <int LOGS, bool INV, bool COLS>
-__device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, const double2 *twr,
+__device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, const double2 *stg,
                                          int lb, int t, int gl, int logN)
 {
     typedef Geo<LOGS> G;
@@ -403,6 +468,9 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
     const int lid = COLS ? 0 : gl;
     const double p = fc.p, pinv = fc.pinv;
     double *sl = reinterpret_cast<double *>(sm_line);
+    const double2 *twr = stg;                                       // RowStage entries
+    const double2 *gA = stg + GenStage<LOGS>::A + 4 * (gl - lb);    // this row's A
+    const double *gR = reinterpret_cast<const double *>(stg + GenStage<LOGS>::R);
     double x[16];
 
     if (!INV) {
@@ -421,7 +489,8 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
         fp_reduce16<LOGS>(x, p, pinv);
-        fp_round16<LOGS, NST2, (1 << (NST2 - 1)), false>(x, 16 * t, 1, 4, off_f, lid, logN, twf, p, false, fc);
+        if (COLS) fp_round16<LOGS, NST2, (1 << (NST2 - 1)), false>(x, 16 * t, 1, 4, off_f, lid, logN, twf, p, false, fc);
+        else fp_round16_gen<LOGS, NST2, (1 << (NST2 - 1)), false>(x, t, gA, gR, p, pinv);
         if (COLS) {
 #pragma unroll
             for (int i = 0; i < 16; i++) base[addr(16 * t + i)] = (u64)__double_as_longlong(x[i]);
@@ -448,7 +517,8 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
             __syncthreads();
         }
         fp_reduce16<LOGS>(x, p, pinv);
-        fp_round16<LOGS, 4, 1, true>(x, 16 * t, 1, 0, off_i, lid, logN, twf, p, false, fc);
+        if (COLS) fp_round16<LOGS, 4, 1, true>(x, 16 * t, 1, 0, off_i, lid, logN, twf, p, false, fc);
+        else fp_round16_gen<LOGS, 4, 1, true>(x, t, gA, gR, p, pinv);
 #pragma unroll
         for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = x[i];
         __syncthreads();
@@ -499,8 +569,9 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
             for (int k = tid; k < G::S; k += 256) st[k] = twf[k];
             twf = st;
             __syncthreads();
-        } else if (RowStage<LOGS>::on) {
-            stage_row_twiddles<INV, LOGS>(st, twf, lb, logN, tid);
+        } else {
+            if (RowStage<LOGS>::on) stage_row_twiddles<INV, LOGS>(st, twf, lb, logN, tid);
+            stage_gen_twiddles<INV, LOGS>(st + GenStage<LOGS>::A, twf, lb, logN, tid);
             __syncthreads();
         }
         ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN);
@@ -611,12 +682,13 @@ __global__ __launch_bounds__(256) void k_ntt16_list(const NttItem *items, const 
 {
     constexpr bool COLS = INV ? !FIRST : FIRST;
     // the largest tile of the three geometries and of the one-pass row tile
+    // (tile and staged twiddles of one geometry, one array: the staged part
+    // starts at the end of that geometry's tile)
     constexpr int W6 = Geo<6>::LINES * Geo<6>::LS, W7 = Geo<7>::LINES * Geo<7>::LS, W8 = Geo<8>::LINES * Geo<8>::LS;
-    constexpr int W67 = W6 > W7 ? W6 : W7, W678 = W67 > W8 ? W67 : W8;
-    __shared__ u64 sm[W678 > NTT_TILE ? W678 : NTT_TILE];
-    constexpr int T6 = TwWords<6, COLS>::value, T7 = TwWords<7, COLS>::value, T8 = TwWords<8, COLS>::value;
-    constexpr int T67 = T6 > T7 ? T6 : T7, T678 = T67 > T8 ? T67 : T8;
-    __shared__ __attribute__((aligned(16))) u64 smtw[T678];
+    constexpr int A6 = W6 + TwWords<6, COLS>::value, A7 = W7 + TwWords<7, COLS>::value, A8 = W8 + TwWords<8, COLS>::value;
+    constexpr int A67 = A6 > A7 ? A6 : A7, A678 = A67 > A8 ? A67 : A8;
+    static_assert(W6 % 2 == 0 && W7 % 2 == 0 && W8 % 2 == 0, "staged twiddles must stay 16-byte aligned");
+    __shared__ __attribute__((aligned(16))) u64 sm[A678 > NTT_TILE ? A678 : NTT_TILE];
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         // the item holding unit u: prefix[it] <= u < prefix[it + 1]
         int lo = 0, hi = n_items - 1;
@@ -634,9 +706,9 @@ __global__ __launch_bounds__(256) void k_ntt16_list(const NttItem *items, const 
         }
         const int logs = COLS ? it.logN - it.logC : it.logC;
         switch (logs) {
-        case 6: ntt16_tile<6, INV, COLS>(it.data, sm, smtw, *it.tabs, it.prime, tile, it.logN); break;
-        case 7: ntt16_tile<7, INV, COLS>(it.data, sm, smtw, *it.tabs, it.prime, tile, it.logN); break;
-        default: ntt16_tile<8, INV, COLS>(it.data, sm, smtw, *it.tabs, it.prime, tile, it.logN); break;
+        case 6: ntt16_tile<6, INV, COLS>(it.data, sm, sm + W6, *it.tabs, it.prime, tile, it.logN); break;
+        case 7: ntt16_tile<7, INV, COLS>(it.data, sm, sm + W7, *it.tabs, it.prime, tile, it.logN); break;
+        default: ntt16_tile<8, INV, COLS>(it.data, sm, sm + W8, *it.tabs, it.prime, tile, it.logN); break;
         }
         __syncthreads();  // the next unit reuses the LDS tile
     }

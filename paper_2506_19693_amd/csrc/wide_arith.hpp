@@ -64,6 +64,17 @@ WA_HD double fp_mul(double a, double w, double wp, double p)
 // x - rint(x / p) p: exact, |result| <= (p - 1) / 2 for |x| < 2^53
 WA_HD double fp_red(double x, double p, double pinv) { return fma(-rint(x * pinv), p, x); }
 
+// A twiddle formed from two table entries: w = r a mod p with |w| <= (p-1)/2
+// (r in [0, p); a canonical with ap = fl(a / p)) and wp = fl(w fl(1/p)).  The
+// quotient estimate of a later fp_mul(x, w, wp, p) then carries three
+// roundings of a value at most |x| / 2, an error below |x| 2^-53 * 3/4, so
+// the bound (1/2 + |x| 2^-52) p of fp_mul still holds.
+WA_HD void fp_twiddle(double r, double a, double ap, double p, double pinv, double &w, double &wp)
+{
+    w = fp_red(fp_mul(r, a, ap, p), p, pinv);
+    wp = w * pinv;
+}
+
 // canonical residue (< 2^52) -> double
 WA_HD double fp_from_u64(u64 v)
 {

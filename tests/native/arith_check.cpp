@@ -174,9 +174,26 @@ static void check_integer_transform(int bits, int lg, int kind)
     for (size_t i = 0; i < N; i++) CHECK(wa::csub(wa::csub(x[i], q2), q) == a[i], "inverse value, %d bits", bits);
 }
 
+// The FP64 twiddle of table index m formed as the row passes form it:
+// tw[m] = tw[m - lo] tw[lo] for an index part lo whose bits are disjoint from
+// the rest (fp_twiddle from the canonical entries).
+static void gen_twiddle(const std::vector<u64> &tab, size_t m, size_t lo, u64 q, double p, double pinv, double &w,
+                        double &wp)
+{
+    const size_t hi = m - lo;
+    CHECK((hi & lo) == 0, "twiddle index split");
+    const double a = (double)tab[hi], ap = a / p;
+    wa::fp_twiddle((double)tab[lo], a, ap, p, pinv, w, wp);
+    CHECK(std::fabs(w) <= (p - 1) / 2 && (double)(long long)w == w, "formed twiddle range");
+    const long long wi = (long long)w;
+    CHECK((u64)((wi % (long long)q + (long long)q) % (long long)q) == tab[m], "formed twiddle value");
+}
+
 // FP64 transform with the kernels' reduction points: with the NTT split r
 // (column pass first), rounds start at stages {0, 4, r, r + 4} forward and at
-// log-distances {0, 4, logC, logC + 4} inverse.
+// log-distances {0, 4, logC, logC + 4} inverse.  The twiddles of forward
+// stages r+4.. and of inverse log-distances 0..3 (the row-pass rounds whose
+// twiddles differ per butterfly) are formed from two table entries.
 static void check_fp_transform(int bits, int lg, int r, int kind)
 {
     const size_t N = (size_t)1 << lg;
@@ -199,7 +216,8 @@ static void check_fp_transform(int bits, int lg, int r, int kind)
         const size_t m = (size_t)1 << s, d = N >> (s + 1);
         for (size_t g = 0; g < m; g++) {
             const u64 w = T.tw[m + g];
-            const double wd = (double)w, wp = (double)w / p;
+            double wd = (double)w, wp = (double)w / p;
+            if (s >= r + 4) gen_twiddle(T.tw, m + g, g & (((size_t)1 << (s - r)) - 1), q, p, pinv, wd, wp);
             for (size_t j = g * 2 * d; j < g * 2 * d + d; j++) {
                 const double t = wa::fp_mul(x[j + d], wd, wp, p), u = x[j];
                 x[j] = u + t;
@@ -217,7 +235,9 @@ static void check_fp_transform(int bits, int lg, int r, int kind)
         const size_t d = (size_t)1 << s, m = N >> (s + 1);
         for (size_t g = 0; g < m; g++) {
             const u64 w = T.itw[m + g], lw = mulm(w, T.ninv, q);
-            const double wd = (double)w, wp = wd / p, lwd = (double)lw, lwp = lwd / p;
+            double wd = (double)w, wp = wd / p;
+            const double lwd = (double)lw, lwp = lwd / p;
+            if (s < 4) gen_twiddle(T.itw, m + g, g & (((size_t)1 << (logC - 1 - s)) - 1), q, p, pinv, wd, wp);
             for (size_t j = g * 2 * d; j < g * 2 * d + d; j++) {
                 const double u = x[j], v = x[j + d];
                 if (s < lg - 1) {
@@ -284,6 +304,31 @@ int main()
         check_fp_transform(50, 15, 7, kind);
         check_fp_transform(49, 14, 6, kind);
         check_fp_transform(40, 13, 6, kind);
+        check_fp_transform(50, 14, 8, kind);
+    }
+    // products with formed twiddles keep the fp_mul bound
+    for (int bits : {30, 45, 50}) {
+        const u64 q = ntt_prime(bits, 1 << 16);
+        const double p = (double)q, pinv = 1.0 / p;
+        for (int it = 0; it < 400000; it++) {
+            const u64 r0 = it % 5 == 0 ? q - 1 : next64() % q, a0 = it % 7 == 0 ? q - 1 : next64() % q;
+            double w, wp;
+            wa::fp_twiddle((double)r0, (double)a0, (double)a0 / p, p, pinv, w, wp);
+            const long long wi = (long long)w;
+            CHECK(std::fabs(w) <= (p - 1) / 2 && (double)wi == w, "formed twiddle range, %d bits", bits);
+            CHECK((u64)((wi % (long long)q + (long long)q) % (long long)q) == mulm(r0, a0, q), "formed twiddle, %d bits",
+                  bits);
+            const long long amax = 8 * (long long)q - 1;
+            long long ai = (long long)(next64() % (u64)(2 * amax + 1)) - amax;
+            if (it % 4 == 0) ai = it % 8 ? amax : -amax;
+            const double x = (double)ai, t = wa::fp_mul(x, w, wp, p);
+            CHECK(std::fabs(t) <= (0.5 + std::fabs(x) * std::ldexp(1.0, -52)) * p, "formed product bound, %d bits", bits);
+            const long long ti = (long long)t;
+            const u64 wc = (u64)((wi % (long long)q + (long long)q) % (long long)q);
+            const u64 want = mulm((u64)(ai % (long long)q + (long long)q) % q, wc, q);
+            CHECK((double)ti == t && (u64)((ti % (long long)q + (long long)q) % (long long)q) == want,
+                  "formed product residue, %d bits", bits);
+        }
     }
     // carry-free accumulation of up to 16 products of 60-bit values
     const u64 top = ((u64)1 << 60) - 1;
