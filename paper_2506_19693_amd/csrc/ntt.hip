@@ -348,6 +348,66 @@ __device__ __forceinline__ void ntt_round16(u64 (&x)[16], int ebase, int estride
     }
 }
 
+// The integer row-pass round on the contiguous pattern (e = 16 t + i) whose
+// twiddles differ per butterfly: forward local stages 4..LOGS-1, inverse
+// 0..3.  Stage s needs 16 >> sh consecutive table entries per thread
+// (sh = LOGS - s forward, s + 1 inverse); they are loaded into registers
+// before the block's first barrier, pairs as one 16-byte load (the pairs
+// start at even indices of a 16-byte aligned table).
+template <bool INV, int LOGS>
+struct PreTw {
+    static constexpr int NST = INV ? 4 : LOGS - 4;
+    static constexpr int S0 = INV ? 0 : 4;
+};
+
+template <bool INV, int LOGS>
+__device__ __forceinline__ void prefetch_tw(u64 (&w)[15], u64 (&ws)[15], const u64 *tw, const u64 *tws, int t, int gl,
+                                            int logN)
+{
+    int o = 0;
+#pragma unroll
+    for (int k = 0; k < PreTw<INV, LOGS>::NST; k++) {
+        const int s = PreTw<INV, LOGS>::S0 + k, sh = INV ? s + 1 : LOGS - s, ns = 16 >> sh;
+        const size_t i0 = (INV ? ((size_t)1 << (logN - 1 - s)) + ((size_t)gl << (LOGS - s - 1))
+                               : ((size_t)1 << (logN - LOGS + s)) + ((size_t)gl << s)) +
+                          ((size_t)t << (4 - sh));
+        if (ns == 1) {
+            w[o] = tw[i0];
+            ws[o] = tws[i0];
+        } else {
+#pragma unroll
+            for (int j = 0; j < ns; j += 2) {
+                const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(tw + i0 + j);
+                const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(tws + i0 + j);
+                w[o + j] = a.x;
+                w[o + j + 1] = a.y;
+                ws[o + j] = b.x;
+                ws[o + j + 1] = b.y;
+            }
+        }
+        o += ns;
+    }
+}
+
+template <bool INV, int LOGS>
+__device__ __forceinline__ void ntt_round16_pre(u64 (&x)[16], const u64 (&w)[15], const u64 (&ws)[15], u64 q, u64 q4)
+{
+    constexpr int NST = PreTw<INV, LOGS>::NST;
+    int o = 0;
+#pragma unroll
+    for (int k = 0; k < NST; k++) {
+        const int d = INV ? (1 << k) : ((1 << (NST - 1)) >> k);
+        const int s = PreTw<INV, LOGS>::S0 + k, sh = INV ? s + 1 : LOGS - s;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int i0 = (j / d) * 2 * d + (j % d), i1 = i0 + d, sl = o + (i0 >> sh);
+            if (!INV) bfly_ct8(x[i0], x[i1], w[sl], ws[sl], q, q4);
+            else bfly_gs4(x[i0], x[i1], w[sl], ws[sl], q, q4);
+        }
+        o += 16 >> sh;
+    }
+}
+
 // ---------------------------------------------------------------- FP64 butterflies (primes below 2^50)
 //
 // For p < 2^50 the pass runs on the FP64 pipes: residues are integers held
@@ -583,6 +643,8 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
     const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
     // staged copies: for a column pass every twiddle it uses, for a row pass
     // the round whose twiddles repeat within a row (twr / twsr)
+    u64 ipw[15], ipws[15];
+    if (INV && !COLS) prefetch_tw<true, LOGS>(ipw, ipws, tw, tws, t, gl, logN);
     constexpr int TH = TwWords<LOGS, COLS>::value / 2;
     constexpr int RS = (!COLS && RowStage<LOGS>::on) ? 1 : 0;
     const u64 *twr = RS ? smtw : tw, *twsr = RS ? smtw + TH : tws;
@@ -607,9 +669,11 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
     const int lid = COLS ? 0 : gl;
     u64 x[16];
 
+    u64 pw[15], pws[15];                                 // row passes: prefetched twiddles
     if (!INV) {
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = base[addr(t + G::TPL * i)];
+        if (!COLS) prefetch_tw<false, LOGS>(pw, pws, tw, tws, t, gl, logN);
         ntt_round16<false, 4, 8, LOGS, RS>(x, t, G::TPL, 0, off_f, lid, logN, RS ? twr : tw, RS ? twsr : tws, q, q4, false,
                                            0, 0, 0, 0, lb);
 #pragma unroll
@@ -617,8 +681,11 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
-        ntt_round16<false, NST2, (1 << (NST2 - 1)), LOGS>(x, 16 * t, 1, 4, off_f, lid, logN, tw, tws, q, q4, false, 0, 0, 0,
-                                                          0);
+        if (COLS)
+            ntt_round16<false, NST2, (1 << (NST2 - 1)), LOGS>(x, 16 * t, 1, 4, off_f, lid, logN, tw, tws, q, q4, false, 0, 0,
+                                                              0, 0);
+        else
+            ntt_round16_pre<false, LOGS>(x, pw, pws, q, q4);
         if (COLS) {
 #pragma unroll
             for (int i = 0; i < 16; i++) base[addr(16 * t + i)] = x[i];
@@ -642,7 +709,8 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
             for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
             __syncthreads();
         }
-        ntt_round16<true, 4, 1, LOGS>(x, 16 * t, 1, 0, off_i, lid, logN, tw, tws, q, q4, false, 0, 0, 0, 0);
+        if (COLS) ntt_round16<true, 4, 1, LOGS>(x, 16 * t, 1, 0, off_i, lid, logN, tw, tws, q, q4, false, 0, 0, 0, 0);
+        else ntt_round16_pre<true, LOGS>(x, ipw, ipws, q, q4);
 #pragma unroll
         for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = x[i];
         __syncthreads();
