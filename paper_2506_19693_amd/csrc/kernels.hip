@@ -494,15 +494,15 @@ __global__ __launch_bounds__(EW_THREADS) void k_ip_p(const u64 *__restrict__ ext
 //   out[h][i] = (sum_j ext_j[i] key_j[h][i] - conv[h][i]) * P^-1 mod q_i (+ add_h[i]).
 // add (through sigma_{add_g} when add_g != 0) goes to poly 0, and to poly 1
 // when add_both != 0.
-template <int BETA>
+template <int BETA, int ADD>
 __global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *__restrict__ ext, long ext_stride,
                                                            const u64 *__restrict__ key, const u64 *__restrict__ conv,
                                                            long conv_stride, const u64 *__restrict__ add, long add_stride,
-                                                           u64 add_g, int add_both, u64 *__restrict__ out,
-                                                           long out_stride, int logN, int L1, int E,
-                                                           int nT, int count, int cpc, u64 g, const u64 *Pinv,
-                                                           const u64 *Pinv_sh, const PrimeC *pc)
+                                                           u64 add_g, u64 *__restrict__ out, long out_stride, int logN,
+                                                           int L1, int E, int nT, int count, int cpc, u64 g,
+                                                           const u64 *Pinv, const u64 *Pinv_sh, const PrimeC *pc)
 {
+    // ADD: 0 none, 1 add to the first output polynomial, 2 to both
     const size_t N = (size_t)1 << logN;
     const size_t k = 2 * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
     const int i = blockIdx.y;
@@ -521,33 +521,36 @@ __global__ __launch_bounds__(EW_THREADS) void k_moddown_ip(const u64 *__restrict
     const size_t per = (size_t)L1 * N, li = (size_t)i * N;
 #pragma unroll 2
     for (int ct = ct0; ct < ct1; ct++) {
+        // every load of the ciphertext first, then the arithmetic
         const u64 *x = ext + ct * ext_stride + li;
+        u64x2 d[BETA];
+#pragma unroll
+        for (int j = 0; j < BETA; j++) d[j] = ld2_perm(x + (size_t)j * E * N, src);
+        const u64 *cv = conv + ct * conv_stride + li + k;
+        const u64x2 c0 = ld2(cv), c1 = ld2(cv + per);
+        u64x2 a0 = {0, 0}, a1 = {0, 0};
+        if (ADD >= 1) a0 = ld2_perm(add + ct * add_stride + li, asrc);
+        if (ADD == 2) a1 = ld2_perm(add + ct * add_stride + li + per, asrc);
         u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
 #pragma unroll
         for (int j = 0; j < BETA; j++) {
-                u64x2 d = ld2_perm(x + (size_t)j * E * N, src);
-                acc_wide(s0, mul_wide(d.x, kb[j].x));
-                acc_wide(t0, mul_wide(d.y, kb[j].y));
-                acc_wide(s1, mul_wide(d.x, ka[j].x));
-                acc_wide(t1, mul_wide(d.y, ka[j].y));
+                acc_wide(s0, mul_wide(d[j].x, kb[j].x));
+                acc_wide(t0, mul_wide(d[j].y, kb[j].y));
+                acc_wide(s1, mul_wide(d[j].x, ka[j].x));
+                acc_wide(t1, mul_wide(d[j].y, ka[j].y));
             }
-        const u64 *cv = conv + ct * conv_stride + li + k;
-        u64x2 c0 = ld2(cv), c1 = ld2(cv + per);
         // beta <= 8 products below q^2: every sum is below q 2^64, a plain REDC suffices
         u64 v0 = shoup(sub_mod(redc(s0, p.q, p.qneg), c0.x, p.q), pinv, pinv_sh, p.q);
         u64 w0 = shoup(sub_mod(redc(t0, p.q, p.qneg), c0.y, p.q), pinv, pinv_sh, p.q);
         u64 v1 = shoup(sub_mod(redc(s1, p.q, p.qneg), c1.x, p.q), pinv, pinv_sh, p.q);
         u64 w1 = shoup(sub_mod(redc(t1, p.q, p.qneg), c1.y, p.q), pinv, pinv_sh, p.q);
-        if (add) {
-            const u64 *ad = add + ct * add_stride + li;
-            u64x2 a0 = ld2_perm(ad, asrc);
+        if (ADD >= 1) {
             v0 = add_mod(v0, a0.x, p.q);
             w0 = add_mod(w0, a0.y, p.q);
-            if (add_both) {
-                u64x2 a1 = ld2_perm(ad + per, asrc);
-                v1 = add_mod(v1, a1.x, p.q);
-                w1 = add_mod(w1, a1.y, p.q);
-            }
+        }
+        if (ADD == 2) {
+            v1 = add_mod(v1, a1.x, p.q);
+            w1 = add_mod(w1, a1.y, p.q);
         }
         u64 *o = out + ct * out_stride + li + k;
         st2_nt(o, v0, w0);
@@ -584,14 +587,20 @@ void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, c
     const int cpc = c->ip_cpc;
     dim3 grid((unsigned)((c->N / 2 + EW_THREADS - 1) / EW_THREADS), L1, (count + cpc - 1) / cpc);
     kt_begin(c, KC_MODDOWN_IP, st);
+    const int addm = add ? (add_both ? 2 : 1) : 0;
+#define MDI_LAUNCH(B, A)                                                                                        \
+    hipLaunchKernelGGL((k_moddown_ip<B, A>), grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, conv, conv_stride, add, \
+                       add_stride, add_g, out, out_stride, c->logN, L1, E, c->nT, count, cpc, g, c->d_Pinv, c->d_Pinv_sh, \
+                       c->d_pc)
 #define MDI_CASE(B)                                                                                           \
     case B:                                                                                                    \
-        hipLaunchKernelGGL(k_moddown_ip<B>, grid, dim3(EW_THREADS), 0, st, ext, ext_stride, key, conv, conv_stride, add, \
-                           add_stride, add_g, add_both, out, out_stride, c->logN, L1, E, c->nT, count, cpc, g, c->d_Pinv, \
-                           c->d_Pinv_sh, c->d_pc);                                                             \
+        if (addm == 0) MDI_LAUNCH(B, 0);                                                                       \
+        else if (addm == 1) MDI_LAUNCH(B, 1);                                                                  \
+        else MDI_LAUNCH(B, 2);                                                                                 \
         break;
     switch (beta_l) { MDI_CASE(1) MDI_CASE(2) MDI_CASE(3) MDI_CASE(4) MDI_CASE(5) MDI_CASE(6) MDI_CASE(7) default: MDI_CASE(8) }
 #undef MDI_CASE
+#undef MDI_LAUNCH
     double words = (double)count * L1 * (beta_l + 2 + 2 + (add ? (add_both ? 2 : 1) : 0)) + 2.0 * beta_l * L1;
     kt_end(c, KC_MODDOWN_IP, words * c->N * sizeof(u64), st);
 }
