@@ -948,12 +948,13 @@ static int moddown_fused_run(rbk_ctx *c, const u64 *ext, long ext_stride, const 
         ip_p_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, st);
         ntt_launch(c, tp, (long)nP * N, 2 * count, nP, LimbMap{0, 0, c->nQ}, true, st);
         bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, st);
-        ntt_launch(c, conv, (long)L1 * N, 2 * count, L1, qmap(c), false, st);
+        moddown_tail_launch(c, ext, ext_stride, key->data, conv, add, add_stride, add_g, add_both, out, out_stride, level,
+                            count, perm_g, st);
     } else {
         ew_launch(c, EW_ZERO, conv, nullptr, conv, 2 * count, L1, qmap(c), st);
+        moddown_ip_launch(c, ext, ext_stride, key->data, conv, (long)2 * L1 * N, add, add_stride, add_g, add_both, out,
+                          out_stride, level, count, perm_g, st);
     }
-    moddown_ip_launch(c, ext, ext_stride, key->data, conv, (long)2 * L1 * N, add, add_stride, add_g, add_both, out,
-                      out_stride, level, count, perm_g, st);
     HIPCK_LAUNCH();
     return RBK_OK;
 }
@@ -1186,7 +1187,7 @@ extern "C" int rbk_rotate_hoisted(rbk_ctx *c, const uint64_t *ct, const int64_t 
 static const char *kc_names[KC_COUNT] = {
     "ntt_cols_fwd",      "ntt_rows_fwd",      "ntt_rows_inv",     "ntt_cols_inv",      "k_bconv_modup",
     "k_bconv_moddown",   "k_ip",              "k_moddown_finish", "k_tensor",          "k_rescale_lift+finish",
-    "elementwise",       "k_ip_p",            "k_moddown_ip",
+    "elementwise",       "k_ip_p",            "k_moddown_ip",     "ntt_rows_fwd+moddown_ip",
 };
 
 static hipEvent_t take_event(const rbk_ctx_impl *c)

@@ -10,16 +10,6 @@
 
 #define EW_THREADS 256
 
-__device__ __forceinline__ u32 brv_bits(u32 x, int bits) { return __brev(x) >> (32 - bits); }
-
-// Source index of an NTT-domain automorphism X -> X^g: the value stored at
-// brv(k) is a(psi^(2k+1)); after sigma_g it is a(psi^((2k+1) g)).
-__device__ __forceinline__ u32 auto_src(u32 o, u64 g, int logN)
-{
-    u32 k = brv_bits(o, logN);
-    u64 e = ((2 * (u64)k + 1) * g) & ((2ull << logN) - 1);
-    return brv_bits((u32)((e - 1) >> 1), logN);
-}
 
 // ---------------------------------------------------------------- elementwise
 

@@ -513,7 +513,7 @@ __device__ __forceinline__ void fp_reduce16(double (&x)[16], double p, double pi
 // the integer pass in k_ntt16).
 // twf: the twiddles of the column pass (staged) or the table; stg (row
 // passes): the block's staged RowStage and GenStage entries (rows from lb)
-template <int LOGS, bool INV, bool COLS>
+template <int LOGS, bool INV, bool COLS, bool KEEP = false>
 __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, const double2 *stg,
                                          int lb, int t, int gl, int logN)
 {
@@ -560,8 +560,10 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 #pragma unroll
             for (int i = 0; i < 16; i++) su[lidx(16 * t + i)] = fp_to_u64(x[i], p, pinv);
             __syncthreads();
+            if (!KEEP) {
 #pragma unroll
-            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = su[lidx(t + G::TPL * i)];
+                for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = su[lidx(t + G::TPL * i)];
+            }
         }
     } else {
         if (COLS) {
@@ -604,9 +606,13 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 // from memory.  A row pass stages the round whose twiddles depend on the row
 // (forward stages 0..3, inverse stages 4..LOGS-1): the block's rows use a
 // contiguous range of each stage's table, which is read once per block.
-template <int LOGS, bool INV, bool COLS>
+// KEEP (forward row pass only): the canonical outputs stay in the LDS tile
+// (element e of the block's row line at sm[line LS + lidx(e)], visible to the
+// whole block) instead of being stored.
+template <int LOGS, bool INV, bool COLS, bool KEEP = false>
 __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const NttTables &T, int pr, int tile, int logN)
 {
+    static_assert(!KEEP || (!INV && !COLS), "only the forward row pass keeps its outputs");
     typedef Geo<LOGS> G;
     constexpr int NST2 = LOGS - 4;
     const size_t N = (size_t)1 << logN;
@@ -634,7 +640,7 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
             stage_gen_twiddles<INV, LOGS>(st + GenStage<LOGS>::A, twf, lb, logN, tid);
             __syncthreads();
         }
-        ntt16_fp<LOGS, INV, COLS>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN);
+        ntt16_fp<LOGS, INV, COLS, KEEP>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN);
         return;
     }
     const PrimeC pc = T.pc[pr];
@@ -694,8 +700,10 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
 #pragma unroll
             for (int i = 0; i < 16; i++) sl[lidx(16 * t + i)] = csub(csub(csub(x[i], q4), q2), q);
             __syncthreads();
+            if (!KEEP) {
 #pragma unroll
-            for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = sl[lidx(t + G::TPL * i)];
+                for (int i = 0; i < 16; i++) base[addr(t + G::TPL * i)] = sl[lidx(t + G::TPL * i)];
+            }
         }
     } else {
         if (COLS) {
@@ -800,6 +808,152 @@ static void launch16_logs(int logs, u64 *data, long poly_stride, int npoly, int 
     case 7: launch16<7, INV, COLS>(data, poly_stride, npoly, nlimbs, map, T, logN, st); break;
     default: launch16<8, INV, COLS>(data, poly_stride, npoly, nlimbs, map, T, logN, st); break;
     }
+}
+
+// ---------------------------------------------------------------- ModDown: last NTT pass fused with the epilogue
+//
+// The ModDown of a key switch converts the special-prime part to the Q basis
+// (conv, coefficient domain), transforms it and combines it with the Q part
+// of the key inner product: out_p = (sum_j d_j key_{j,p} - NTT(conv_p)) P^-1
+// (+ the addend).  Here the forward row pass of conv_p (after its column
+// pass) keeps its canonical outputs in registers and applies that epilogue
+// directly, so the transformed conv is never written to and read back from
+// memory.  One block per (row tile, limb, ciphertext, polynomial).  Blocks
+// are numbered so that each XCD (blocks b, b+8, ...) walks a contiguous range
+// in which all ciphertexts and both polynomials of one (limb, tile) follow
+// each other: the tile's key words and ModUp digits are then re-read from
+// that XCD's L2.
+template <int LOGS, int BETA, int ADD>
+__global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ ext, long ext_stride,
+                                                    const u64 *__restrict__ key, u64 *conv, long conv_stride,
+                                                    const u64 *__restrict__ add, long add_stride, u64 add_g,
+                                                    u64 *__restrict__ out, long out_stride, NttTables T, int logN, int L1,
+                                                    int E, int nT, int count, u64 g, const u64 *Pinv, const u64 *Pinv_sh)
+{
+    typedef Geo<LOGS> G;
+    __shared__ u64 sm[G::LINES * G::LS];
+    __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, false>::value];
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned u = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int poly = (int)(u % 2);
+    const int ct = (int)((u / 2) % (unsigned)count);
+    const unsigned rest = u / (2u * (unsigned)count);
+    const unsigned tiles = 1u << (logN - 12);
+    const int tile = (int)(rest % tiles), limb = (int)(rest / tiles);
+    const size_t N = (size_t)1 << logN, per = (size_t)L1 * N, li = (size_t)limb * N;
+
+    ntt16_tile<LOGS, false, false, true>(conv + ct * conv_stride + poly * per + li, sm, smtw, T, limb, tile, logN);
+
+    // the transformed row tile is in LDS; each thread finishes the elements
+    // t + TPL i of its row (the strided pattern: lanes on adjacent positions)
+    const int t = threadIdx.x % G::TPL, line = threadIdx.x / G::TPL;
+    const u64 *cl = sm + line * G::LS;
+    const size_t row0 = ((size_t)tile * G::LINES + line) * G::S + t;   // position of element i: row0 + TPL i
+    const PrimeC p = T.pc[limb];
+    const u64 pinv = Pinv[limb], pinv_sh = Pinv_sh[limb];
+    const u64 *x = ext + ct * ext_stride + li;
+    const u64 *kp = key + ((size_t)poly * nT + limb) * N;              // digit j at + j 2 nT N
+    const bool do_add = (ADD >= 1 && poly == 0) || (ADD == 2 && poly == 1);
+    const u64 *ad = add + ct * add_stride + poly * per + li;
+    u64 *o = out + ct * out_stride + poly * per + li;
+#pragma unroll 8
+    for (int i = 0; i < 16; i++) {
+        const size_t pos = row0 + (size_t)G::TPL * i;
+        const size_t src = g ? auto_src((u32)pos, g, logN) : pos;
+        u64 d[BETA], kw[BETA];
+#pragma unroll
+        for (int j = 0; j < BETA; j++) {
+            d[j] = x[(size_t)j * E * N + src];
+            kw[j] = kp[(size_t)j * 2 * nT * N + pos];
+        }
+        u64 a = 0;
+        if (ADD && do_add) a = ad[add_g ? auto_src((u32)pos, add_g, logN) : pos];
+        u128w s = {0, 0};
+#pragma unroll
+        for (int j = 0; j < BETA; j++) acc_wide(s, mul_wide(d[j], kw[j]));
+        // beta <= 8 products below q^2: the sum is below q 2^64, a plain REDC suffices
+        u64 v = shoup(sub_mod(redc(s, p.q, p.qneg), cl[lidx(t + G::TPL * i)], p.q), pinv, pinv_sh, p.q);
+        if (ADD && do_add) v = add_mod(v, a, p.q);
+        o[pos] = v;
+    }
+}
+
+static bool ntt_rows_md_ok(const rbk_ctx_impl *c)
+{
+    const int logN = c->logN, logC = c->ntt_logC, r = logN - logC;
+    return logN >= 13 && logN <= 16 && r >= 6 && r <= 8 && logC >= 6 && logC <= 8;
+}
+
+static void ntt_cols_fwd_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map,
+                                hipStream_t st)
+{
+    if (npoly <= 0 || nlimbs <= 0) return;
+    const int logN = c->logN, r = logN - c->ntt_logC;
+    kt_begin(c, KC_NTT_COLS_FWD, st);
+    launch16_logs<false, true>(r, data, poly_stride, npoly, nlimbs, map, c->tabs, logN, st);
+    kt_end(c, KC_NTT_COLS_FWD, 2.0 * npoly * nlimbs * c->N * sizeof(u64), st);
+}
+
+static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
+                               long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
+                               long out_stride, int level, int count, u64 g, hipStream_t st)
+{
+    const int L1 = level + 1, E = L1 + c->nP, logN = c->logN, logC = c->ntt_logC;
+    const int beta_l = (L1 + c->alpha - 1) / c->alpha;
+    const int addm = add ? (add_both ? 2 : 1) : 0;
+    const dim3 grid((unsigned)(((size_t)1 << logN) / 4096 * 2 * (size_t)count * L1));
+    kt_begin(c, KC_NTT_ROWS_MD, st);
+#define RMD_LAUNCH(LG, B, A)                                                                                     \
+    hipLaunchKernelGGL((k_ntt_rows_md<LG, B, A>), grid, dim3(256), 0, st, ext, ext_stride, key, conv, conv_stride, add, \
+                       add_stride, add_g, out, out_stride, c->tabs, logN, L1, E, c->nT, count, g, c->d_Pinv,          \
+                       c->d_Pinv_sh)
+#define RMD_ADD(LG, B)                                                                                          \
+    do {                                                                                                        \
+        if (addm == 0) RMD_LAUNCH(LG, B, 0);                                                                    \
+        else if (addm == 1) RMD_LAUNCH(LG, B, 1);                                                               \
+        else RMD_LAUNCH(LG, B, 2);                                                                              \
+    } while (0)
+#define RMD_BETA(LG)                                                                                            \
+    switch (beta_l) {                                                                                           \
+    case 1: RMD_ADD(LG, 1); break;                                                                              \
+    case 2: RMD_ADD(LG, 2); break;                                                                              \
+    case 3: RMD_ADD(LG, 3); break;                                                                              \
+    case 4: RMD_ADD(LG, 4); break;                                                                              \
+    case 5: RMD_ADD(LG, 5); break;                                                                              \
+    case 6: RMD_ADD(LG, 6); break;                                                                              \
+    case 7: RMD_ADD(LG, 7); break;                                                                              \
+    default: RMD_ADD(LG, 8); break;                                                                             \
+    }
+    switch (logC) {
+    case 6: RMD_BETA(6); break;
+    case 7: RMD_BETA(7); break;
+    default: RMD_BETA(8); break;
+    }
+#undef RMD_BETA
+#undef RMD_ADD
+#undef RMD_LAUNCH
+    // algorithmic bytes: conv (after its column pass) and the ModUp digits
+    // read, the outputs written, the addends read, the key words read once
+    const double words = (double)count * L1 * (beta_l + 2 + 2 + addm) + 2.0 * beta_l * L1;
+    kt_end(c, KC_NTT_ROWS_MD, words * c->N * sizeof(u64), st);
+}
+
+void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
+                         const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
+                         int count, u64 g, hipStream_t st)
+{
+    const int L1 = level + 1;
+    const size_t N = c->N;
+    const LimbMap qm{0, c->nQ, c->nQ};
+    if (ntt_rows_md_ok(c)) {
+        ntt_cols_fwd_launch(c, conv, (long)(L1 * N), 2 * count, L1, qm, st);
+        ntt_rows_md_launch(c, ext, ext_stride, key, conv, (long)(2 * L1 * N), add, add_stride, add_g, add_both, out,
+                           out_stride, level, count, g, st);
+        return;
+    }
+    ntt_launch(c, conv, (long)(L1 * N), 2 * count, L1, qm, false, st);
+    moddown_ip_launch(c, ext, ext_stride, key, conv, (long)(2 * L1 * N), add, add_stride, add_g, add_both, out, out_stride,
+                      level, count, g, st);
 }
 
 void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, int nlimbs, LimbMap map, bool inverse,

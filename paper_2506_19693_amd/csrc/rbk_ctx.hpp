@@ -38,6 +38,7 @@ enum KClass {
     KC_ELEMENTWISE,
     KC_IP_P,
     KC_MODDOWN_IP,
+    KC_NTT_ROWS_MD,
     KC_COUNT
 };
 
@@ -184,6 +185,12 @@ void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u
 void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
                        long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
                        long out_stride, int level, int count, u64 g, hipStream_t st);
+// ModDown tail: NTT of the converted special-prime part conv ([count][2][l+1]
+// limbs) and the epilogue of moddown_ip_launch; for the register NTT
+// geometries the row pass and the epilogue are one kernel.  conv is clobbered.
+void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
+                         const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
+                         int count, u64 g, hipStream_t st);
 void rescale_lift_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, int level, int npoly, hipStream_t st);
 void rescale_finish_launch(const rbk_ctx_impl *c, const u64 *in, const u64 *lifted, u64 *out, int level, int npoly,
                            hipStream_t st);

@@ -213,9 +213,8 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
                 ip_p_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);
                 ntt_launch(c, tp, (long)(c->nP * N), 2 * count, c->nP, pm, true, c->stream);
                 bconv_moddown_launch(c, tp, (long)(c->nP * N), conv, (long)(L1 * N), level, 2 * count, c->stream);
-                ntt_launch(c, conv, (long)(L1 * N), 2 * count, (int)L1, qm, false, c->stream);
-                moddown_ip_launch(c, ext, (long)(beta * E * N), key_d->data, conv, (long)(2 * L1 * N), c0,
-                                  (long)(2 * L1 * N), g, 0, out, (long)(2 * L1 * N), level, count, g, c->stream);
+                moddown_tail_launch(c, ext, (long)(beta * E * N), key_d->data, conv, c0, (long)(2 * L1 * N), g, 0, out,
+                                    (long)(2 * L1 * N), level, count, g, c->stream);
             }, scrub);
             c->ip_cpc = cpc = cpcs[k];
         }
