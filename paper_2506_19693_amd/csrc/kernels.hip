@@ -405,40 +405,6 @@ void moddown_finish_launch(const rbk_ctx_impl *c, const u64 *u, long u_stride, c
 // ciphertexts handled by one thread of the fused inner-product kernels: the
 // key words are loaded once per thread, the grid's z dimension covers the rest
 
-// Two adjacent NTT-domain coefficients (o, o+1), o even, are the values at
-// psi^(2k+1) and psi^(2k+1+N) (bit reversal); an automorphism maps them to the
-// two halves of one aligned pair, possibly swapped: auto_src(o+1) = auto_src(o) ^ 1.
-// So every kernel below moves 16-byte pairs.
-struct __attribute__((aligned(16))) u64x2 {
-    u64 x, y;
-};
-
-__device__ __forceinline__ u64x2 ld2(const u64 *p) { return *reinterpret_cast<const u64x2 *>(p); }
-__device__ __forceinline__ void st2(u64 *p, u64 a, u64 b)
-{
-    u64x2 v;
-    v.x = a;
-    v.y = b;
-    *reinterpret_cast<u64x2 *>(p) = v;
-}
-// the same, streamed: the data is not read again soon, so it bypasses the caches' retention
-__device__ __forceinline__ void st2_nt(u64 *p, u64 a, u64 b)
-{
-    __builtin_nontemporal_store(a, p);
-    __builtin_nontemporal_store(b, p + 1);
-}
-// the pair at source index src (even-aligned load, swapped when src is odd)
-__device__ __forceinline__ u64x2 ld2_perm(const u64 *base, size_t src)
-{
-    u64x2 v = ld2(base + (src & ~(size_t)1));
-    if (src & 1) {
-        u64 t = v.x;
-        v.x = v.y;
-        v.y = t;
-    }
-    return v;
-}
-
 // Inner product restricted to the special-prime positions, written to
 // tp[count][2][nP][N] (the input of the ModDown inverse NTT).
 template <int BETA>

@@ -844,11 +844,9 @@ __global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ 
 
     ntt16_tile<LOGS, false, false, true>(conv + ct * conv_stride + poly * per + li, sm, smtw, T, limb, tile, logN);
 
-    // the transformed row tile is in LDS; each thread finishes the elements
-    // t + TPL i of its row (the strided pattern: lanes on adjacent positions)
-    const int t = threadIdx.x % G::TPL, line = threadIdx.x / G::TPL;
-    const u64 *cl = sm + line * G::LS;
-    const size_t row0 = ((size_t)tile * G::LINES + line) * G::S + t;   // position of element i: row0 + TPL i
+    // the transformed tile (4096 consecutive positions of the limb) is in
+    // LDS; each thread finishes 8 adjacent pairs, lanes on adjacent pairs
+    const size_t tbase = (size_t)tile * 4096;
     const PrimeC p = T.pc[limb];
     const u64 pinv = Pinv[limb], pinv_sh = Pinv_sh[limb];
     const u64 *x = ext + ct * ext_stride + li;
@@ -856,25 +854,36 @@ __global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ 
     const bool do_add = (ADD >= 1 && poly == 0) || (ADD == 2 && poly == 1);
     const u64 *ad = add + ct * add_stride + poly * per + li;
     u64 *o = out + ct * out_stride + poly * per + li;
-#pragma unroll 8
-    for (int i = 0; i < 16; i++) {
-        const size_t pos = row0 + (size_t)G::TPL * i;
+#pragma unroll 4
+    for (int m = 0; m < 8; m++) {
+        const int e = 2 * (int)threadIdx.x + 512 * m;                  // even position in the tile
+        const size_t pos = tbase + e;
         const size_t src = g ? auto_src((u32)pos, g, logN) : pos;
-        u64 d[BETA], kw[BETA];
+        u64x2 d[BETA], kw[BETA];
 #pragma unroll
         for (int j = 0; j < BETA; j++) {
-            d[j] = x[(size_t)j * E * N + src];
-            kw[j] = kp[(size_t)j * 2 * nT * N + pos];
+            d[j] = ld2_perm(x + (size_t)j * E * N, src);
+            kw[j] = ld2(kp + (size_t)j * 2 * nT * N + pos);
         }
-        u64 a = 0;
-        if (ADD && do_add) a = ad[add_g ? auto_src((u32)pos, add_g, logN) : pos];
-        u128w s = {0, 0};
+        u64x2 a = {0, 0};
+        if (ADD && do_add) a = ld2_perm(ad, add_g ? auto_src((u32)pos, add_g, logN) : pos);
+        const u64 *cl = sm + (e >> LOGS) * G::LS;
+        const int cc = e & (G::S - 1);
+        const u64 c0 = cl[lidx(cc)], c1 = cl[lidx(cc + 1)];
+        u128w s0 = {0, 0}, s1 = {0, 0};
 #pragma unroll
-        for (int j = 0; j < BETA; j++) acc_wide(s, mul_wide(d[j], kw[j]));
-        // beta <= 8 products below q^2: the sum is below q 2^64, a plain REDC suffices
-        u64 v = shoup(sub_mod(redc(s, p.q, p.qneg), cl[lidx(t + G::TPL * i)], p.q), pinv, pinv_sh, p.q);
-        if (ADD && do_add) v = add_mod(v, a, p.q);
-        o[pos] = v;
+        for (int j = 0; j < BETA; j++) {
+            acc_wide(s0, mul_wide(d[j].x, kw[j].x));
+            acc_wide(s1, mul_wide(d[j].y, kw[j].y));
+        }
+        // beta <= 8 products below q^2: every sum is below q 2^64, a plain REDC suffices
+        u64 v0 = shoup(sub_mod(redc(s0, p.q, p.qneg), c0, p.q), pinv, pinv_sh, p.q);
+        u64 v1 = shoup(sub_mod(redc(s1, p.q, p.qneg), c1, p.q), pinv, pinv_sh, p.q);
+        if (ADD && do_add) {
+            v0 = add_mod(v0, a.x, p.q);
+            v1 = add_mod(v1, a.y, p.q);
+        }
+        st2_nt(o + pos, v0, v1);
     }
 }
 
