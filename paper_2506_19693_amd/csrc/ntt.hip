@@ -854,7 +854,7 @@ __global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ 
     const bool do_add = (ADD >= 1 && poly == 0) || (ADD == 2 && poly == 1);
     const u64 *ad = add + ct * add_stride + poly * per + li;
     u64 *o = out + ct * out_stride + poly * per + li;
-#pragma unroll 4
+#pragma unroll
     for (int m = 0; m < 8; m++) {
         const int e = 2 * (int)threadIdx.x + 512 * m;                  // even position in the tile
         const size_t pos = tbase + e;
