@@ -945,8 +945,7 @@ static int moddown_fused_run(rbk_ctx *c, const u64 *ext, long ext_stride, const 
     const int L1 = level + 1, nP = c->nP;
     if (!st) st = c->stream;
     if (nP > 0) {
-        ip_p_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, st);
-        ntt_launch(c, tp, (long)nP * N, 2 * count, nP, LimbMap{0, 0, c->nQ}, true, st);
+        moddown_head_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, st);
         bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, st);
         moddown_tail_launch(c, ext, ext_stride, key->data, conv, add, add_stride, add_g, add_both, out, out_stride, level,
                             count, perm_g, st);
@@ -1188,6 +1187,7 @@ static const char *kc_names[KC_COUNT] = {
     "ntt_cols_fwd",      "ntt_rows_fwd",      "ntt_rows_inv",     "ntt_cols_inv",      "k_bconv_modup",
     "k_bconv_moddown",   "k_ip",              "k_moddown_finish", "k_tensor",          "k_rescale_lift+finish",
     "elementwise",       "k_ip_p",            "k_moddown_ip",     "ntt_rows_fwd+moddown_ip",
+    "k_ip_p+ntt_rows_inv",
 };
 
 static hipEvent_t take_event(const rbk_ctx_impl *c)

@@ -513,7 +513,7 @@ __device__ __forceinline__ void fp_reduce16(double (&x)[16], double p, double pi
 // the integer pass in k_ntt16).
 // twf: the twiddles of the column pass (staged) or the table; stg (row
 // passes): the block's staged RowStage and GenStage entries (rows from lb)
-template <int LOGS, bool INV, bool COLS, bool KEEP = false>
+template <int LOGS, bool INV, bool COLS, bool KEEP = false, bool LDSIN = false>
 __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, const double2 *stg,
                                          int lb, int t, int gl, int logN)
 {
@@ -571,8 +571,10 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
             for (int i = 0; i < 16; i++) x[i] = __longlong_as_double((long long)base[addr(16 * t + i)]);
         } else {
             u64 *su = sm_line;
+            if (!LDSIN) {
 #pragma unroll
-            for (int i = 0; i < 16; i++) su[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+                for (int i = 0; i < 16; i++) su[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+            }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 16; i++) x[i] = fp_from_u64(su[lidx(16 * t + i)]);
@@ -609,10 +611,13 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 // KEEP (forward row pass only): the canonical outputs stay in the LDS tile
 // (element e of the block's row line at sm[line LS + lidx(e)], visible to the
 // whole block) instead of being stored.
-template <int LOGS, bool INV, bool COLS, bool KEEP = false>
+// LDSIN (inverse row pass only): the caller has written the canonical inputs
+// to the LDS tile in that layout; they are not loaded from base.
+template <int LOGS, bool INV, bool COLS, bool KEEP = false, bool LDSIN = false>
 __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const NttTables &T, int pr, int tile, int logN)
 {
     static_assert(!KEEP || (!INV && !COLS), "only the forward row pass keeps its outputs");
+    static_assert(!LDSIN || (INV && !COLS), "only the inverse row pass takes its inputs from LDS");
     typedef Geo<LOGS> G;
     constexpr int NST2 = LOGS - 4;
     const size_t N = (size_t)1 << logN;
@@ -640,7 +645,7 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
             stage_gen_twiddles<INV, LOGS>(st + GenStage<LOGS>::A, twf, lb, logN, tid);
             __syncthreads();
         }
-        ntt16_fp<LOGS, INV, COLS, KEEP>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN);
+        ntt16_fp<LOGS, INV, COLS, KEEP, LDSIN>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN);
         return;
     }
     const PrimeC pc = T.pc[pr];
@@ -710,8 +715,10 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
 #pragma unroll
             for (int i = 0; i < 16; i++) x[i] = base[addr(16 * t + i)];
         } else {
+            if (!LDSIN) {
 #pragma unroll
-            for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+                for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+            }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 16; i++) x[i] = sl[lidx(16 * t + i)];
@@ -945,6 +952,110 @@ static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_s
     // read, the outputs written, the addends read, the key words read once
     const double words = (double)count * L1 * (beta_l + 2 + 2 + addm) + 2.0 * beta_l * L1;
     kt_end(c, KC_NTT_ROWS_MD, words * c->N * sizeof(u64), st);
+}
+
+// ---------------------------------------------------------------- ModDown: inner product fused with the first iNTT pass
+//
+// The special-prime part of the key inner product, tp_p = sum_j d_j key_{j,p}
+// on the special primes, is only read by the inverse NTT that starts the
+// ModDown.  Its first (row) pass computes the tile in LDS instead of loading
+// it (adjacent pairs, as in k_ntt_rows_md), so tp is written once, by the row
+// pass.  Blocks per (row tile, special prime, ciphertext, polynomial),
+// numbered per XCD as in k_ntt_rows_md.
+template <int LOGS, int BETA>
+__global__ __launch_bounds__(256, 4) void k_ntt_rows_ip(const u64 *__restrict__ ext, long ext_stride,
+                                                       const u64 *__restrict__ key, u64 *tp, NttTables T, int logN,
+                                                       int L1, int E, int nT, int nQ, int nP, int count, u64 g)
+{
+    typedef Geo<LOGS> G;
+    __shared__ u64 sm[G::LINES * G::LS];
+    __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, false>::value];
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned u = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int poly = (int)(u % 2);
+    const int ct = (int)((u / 2) % (unsigned)count);
+    const unsigned rest = u / (2u * (unsigned)count);
+    const unsigned tiles = 1u << (logN - 12);
+    const int tile = (int)(rest % tiles), k = (int)(rest / tiles);
+    const size_t N = (size_t)1 << logN, tbase = (size_t)tile * 4096;
+    const int pr = nQ + k;
+    const PrimeC p = T.pc[pr];
+    const u64 *x = ext + ct * ext_stride + (size_t)(L1 + k) * N;     // digit j at + j E N
+    const u64 *kp = key + ((size_t)poly * nT + pr) * N;              // digit j at + j 2 nT N
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        const int e = 2 * (int)threadIdx.x + 512 * m;                // even position in the tile
+        const size_t pos = tbase + e;
+        const size_t src = g ? auto_src((u32)pos, g, logN) : pos;
+        u64x2 d[BETA], kw[BETA];
+#pragma unroll
+        for (int j = 0; j < BETA; j++) {
+            d[j] = ld2_perm(x + (size_t)j * E * N, src);
+            kw[j] = ld2(kp + (size_t)j * 2 * nT * N + pos);
+        }
+        u128w s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < BETA; j++) {
+            acc_wide(s0, mul_wide(d[j].x, kw[j].x));
+            acc_wide(s1, mul_wide(d[j].y, kw[j].y));
+        }
+        // beta <= 8 products below p^2: every sum is below p 2^64, a plain REDC suffices
+        u64 *row = sm + (e >> LOGS) * G::LS;
+        const int cc = e & (G::S - 1);
+        row[lidx(cc)] = redc(s0, p.q, p.qneg);
+        row[lidx(cc + 1)] = redc(s1, p.q, p.qneg);
+    }
+    ntt16_tile<LOGS, true, false, false, true>(tp + (((size_t)ct * 2 + poly) * nP + k) * N, sm, smtw, T, pr, tile, logN);
+}
+
+static void ntt_rows_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *tp,
+                               int level, int count, u64 g, hipStream_t st)
+{
+    const int L1 = level + 1, E = L1 + c->nP, logN = c->logN, logC = c->ntt_logC;
+    const int beta_l = (L1 + c->alpha - 1) / c->alpha;
+    const dim3 grid((unsigned)(((size_t)1 << logN) / 4096 * 2 * (size_t)count * c->nP));
+    kt_begin(c, KC_NTT_ROWS_IP, st);
+#define RIP_LAUNCH(LG, B)                                                                                       \
+    hipLaunchKernelGGL((k_ntt_rows_ip<LG, B>), grid, dim3(256), 0, st, ext, ext_stride, key, tp, c->tabs, logN, L1, E, \
+                       c->nT, c->nQ, c->nP, count, g)
+#define RIP_BETA(LG)                                                                                            \
+    switch (beta_l) {                                                                                           \
+    case 1: RIP_LAUNCH(LG, 1); break;                                                                           \
+    case 2: RIP_LAUNCH(LG, 2); break;                                                                           \
+    case 3: RIP_LAUNCH(LG, 3); break;                                                                           \
+    case 4: RIP_LAUNCH(LG, 4); break;                                                                           \
+    case 5: RIP_LAUNCH(LG, 5); break;                                                                           \
+    case 6: RIP_LAUNCH(LG, 6); break;                                                                           \
+    case 7: RIP_LAUNCH(LG, 7); break;                                                                           \
+    default: RIP_LAUNCH(LG, 8); break;                                                                          \
+    }
+    switch (logC) {
+    case 6: RIP_BETA(6); break;
+    case 7: RIP_BETA(7); break;
+    default: RIP_BETA(8); break;
+    }
+#undef RIP_BETA
+#undef RIP_LAUNCH
+    // algorithmic bytes: the digits' special-prime limbs and the key words
+    // read once, tp written once
+    const double words = (double)count * c->nP * (beta_l + 2) + 2.0 * beta_l * c->nP;
+    kt_end(c, KC_NTT_ROWS_IP, words * c->N * sizeof(u64), st);
+}
+
+void moddown_head_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int level,
+                         int count, u64 g, hipStream_t st)
+{
+    const int nP = c->nP;
+    const LimbMap pm{0, 0, c->nQ};
+    if (ntt_rows_md_ok(c)) {
+        ntt_rows_ip_launch(c, ext, ext_stride, key, tp, level, count, g, st);
+        kt_begin(c, KC_NTT_COLS_INV, st);
+        launch16_logs<true, true>(c->logN - c->ntt_logC, tp, (long)nP * c->N, 2 * count, nP, pm, c->tabs, c->logN, st);
+        kt_end(c, KC_NTT_COLS_INV, 2.0 * 2 * count * nP * c->N * sizeof(u64), st);
+        return;
+    }
+    ip_p_launch(c, ext, ext_stride, key, tp, level, count, g, st);
+    ntt_launch(c, tp, (long)nP * c->N, 2 * count, nP, pm, true, st);
 }
 
 void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,

@@ -39,6 +39,7 @@ enum KClass {
     KC_IP_P,
     KC_MODDOWN_IP,
     KC_NTT_ROWS_MD,
+    KC_NTT_ROWS_IP,
     KC_COUNT
 };
 
@@ -185,6 +186,11 @@ void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u
 void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
                        long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
                        long out_stride, int level, int count, u64 g, hipStream_t st);
+// ModDown head: tp ([count][2][k] limbs) = the special-prime part of the key
+// inner product, brought to the coefficient domain; for the register NTT
+// geometries the inner product is computed inside the first iNTT pass.
+void moddown_head_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int level,
+                         int count, u64 g, hipStream_t st);
 // ModDown tail: NTT of the converted special-prime part conv ([count][2][l+1]
 // limbs) and the epilogue of moddown_ip_launch; for the register NTT
 // geometries the row pass and the epilogue are one kernel.  conv is clobbered.

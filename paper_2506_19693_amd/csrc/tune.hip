@@ -208,10 +208,8 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
             // the whole ModDown of a hoisted rotation, with c0 (through the
             // automorphism) added in the epilogue: the other kernels between the
             // two inner products decide what is still cached when they run
-            const LimbMap pm{0, 0, c->nQ};
             const int k = pick_fastest(c, 3, [&](int i) { c->ip_cpc = cpcs[i]; }, [&] {
-                ip_p_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);
-                ntt_launch(c, tp, (long)(c->nP * N), 2 * count, c->nP, pm, true, c->stream);
+                moddown_head_launch(c, ext, (long)(beta * E * N), key_d->data, tp, level, count, g, c->stream);
                 bconv_moddown_launch(c, tp, (long)(c->nP * N), conv, (long)(L1 * N), level, 2 * count, c->stream);
                 moddown_tail_launch(c, ext, (long)(beta * E * N), key_d->data, conv, c0, (long)(2 * L1 * N), g, 0, out,
                                     (long)(2 * L1 * N), level, count, g, c->stream);
