@@ -246,18 +246,18 @@ char *desc_upload(rbk_ctx_impl *c, const DescBlob &b, int *rc)
     return (char *)c->desc_dev;
 }
 
-// the two side streams (default priority) and three events of the
-// two-lane ModDown, created on first use on the context's device
+// the side streams (default priority) and events of the multi-lane ModDown,
+// created on first use on the context's device
 static int side_streams(rbk_ctx_impl *c)
 {
-    if (c->side[0]) return RBK_OK;
-    for (int k = 0; k < 2; k++)
-        if (hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking) != hipSuccess) {
+    if (c->side[RBK_LANES - 1] && c->side_ev[RBK_LANES]) return RBK_OK;
+    for (int k = 0; k < RBK_LANES; k++)
+        if (!c->side[k] && hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking) != hipSuccess) {
             c->side[k] = nullptr;
             return rbk_set_error(RBK_EDEVICE, "side stream creation failed");
         }
-    for (int k = 0; k < 3; k++)
-        if (hipEventCreateWithFlags(&c->side_ev[k], hipEventDisableTiming) != hipSuccess) {
+    for (int k = 0; k <= RBK_LANES; k++)
+        if (!c->side_ev[k] && hipEventCreateWithFlags(&c->side_ev[k], hipEventDisableTiming) != hipSuccess) {
             c->side_ev[k] = nullptr;
             return rbk_set_error(RBK_EDEVICE, "event creation failed");
         }
@@ -493,12 +493,12 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
     for (void *p : c->retired) (void)hipFree(p);
     if (c->ws) (void)hipFree(c->ws);
     if (c->desc_dev) (void)hipFree(c->desc_dev);
-    for (int k = 0; k < 2; k++)
+    for (int k = 0; k < RBK_LANES; k++)
         if (c->side[k]) {
             (void)hipStreamSynchronize(c->side[k]);
             (void)hipStreamDestroy(c->side[k]);
         }
-    for (int k = 0; k < 3; k++)
+    for (int k = 0; k <= RBK_LANES; k++)
         if (c->side_ev[k]) (void)hipEventDestroy(c->side_ev[k]);
     for (int k = 0; k < 2; k++) {
         if (c->desc_host[k]) (void)hipHostFree(c->desc_host[k]);
@@ -1136,23 +1136,28 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
         keys[r] = gs[r] == 1 ? nullptr : find_key(c, gs[r]);
         if (gs[r] != 1 && !keys[r]) return fail(RBK_ENOKEY, "no Galois key for rotation " + std::to_string(ks[r]));
     }
-    // two ModDown lanes for small batches: the rotations' independent
-    // ModDowns alternate over two side streams with buffers of their own, so
-    // kernels too small to fill the GPU overlap (per-ciphertext calls gain
-    // ~20%, a 64-ciphertext batch ~1%).  One lane for large batches, while the
-    // stream is being captured, and while per-kernel timers run (overlapping
-    // kernels would not have durations of their own)
+    // ModDown lanes: the rotations' independent ModDowns go round-robin over
+    // RBK_LANES side streams, each with tp and conv buffers of its own, so the
+    // VALU-bound kernels of one rotation (inner product + first iNTT pass,
+    // base conversion) overlap the memory-bound ones of another.  One lane
+    // while the stream is being captured and while per-kernel timers run
+    // (overlapping kernels would not have durations of their own)
+    const int nl = (!c->capturing && !c->timing && n > 1 && side_streams(c) == RBK_OK) ? std::min(RBK_LANES, n) : 1;
     const size_t tp_words = (size_t)count * 2 * c->nP * N, conv_words = (size_t)count * 2 * L1 * N;
-    WS(ws, ks_words(c, level, count) + tp_words + conv_words);
+    WS(ws, ks_words(c, level, count) + (size_t)(nl - 1) * (tp_words + conv_words));
     KsBufs b = ks_layout(c, ws, level, count);
-    u64 *tp2 = ws + ks_words(c, level, count), *conv2 = tp2 + tp_words;
+    u64 *lane_tp[RBK_LANES], *lane_conv[RBK_LANES];
+    lane_tp[0] = b.tp;
+    lane_conv[0] = b.conv;
+    for (int k = 1; k < nl; k++) {
+        lane_tp[k] = ws + ks_words(c, level, count) + (size_t)(k - 1) * (tp_words + conv_words);
+        lane_conv[k] = lane_tp[k] + tp_words;
+    }
     int rc = modup_run(c, ct + per, (long)(2 * per), b.ext, (long)(beta * E * N), level, count, b.coef);
     if (rc) return rc;
-    const bool small = (size_t)2 * count * L1 < 1024;  // limbs of one ModDown transform
-    const bool two = small && !c->capturing && !c->timing && n > 1 && side_streams(c) == RBK_OK;
-    if (two) {
-        HIPCK(hipEventRecord(c->side_ev[2], c->stream));
-        for (int k = 0; k < 2; k++) HIPCK(hipStreamWaitEvent(c->side[k], c->side_ev[2], 0));
+    if (nl > 1) {
+        HIPCK(hipEventRecord(c->side_ev[RBK_LANES], c->stream));
+        for (int k = 0; k < nl; k++) HIPCK(hipStreamWaitEvent(c->side[k], c->side_ev[RBK_LANES], 0));
     }
     int lane = 0;
     for (int r = 0; r < n; r++) {
@@ -1162,14 +1167,14 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
                                    hipMemcpyDeviceToDevice, c->stream));
             continue;
         }
-        hipStream_t st = two ? c->side[lane] : c->stream;
+        hipStream_t st = nl > 1 ? c->side[lane] : c->stream;
         rc = moddown_fused_run(c, b.ext, (long)(beta * E * N), keys[r], gs[r], ct, (long)(2 * per), gs[r], 0, o,
-                               (long)(n * 2 * per), level, count, lane ? tp2 : b.tp, lane ? conv2 : b.conv, st);
+                               (long)(n * 2 * per), level, count, lane_tp[lane], lane_conv[lane], st);
         if (rc) return rc;
-        if (two) lane ^= 1;
+        lane = (lane + 1) % nl;
     }
-    if (two)
-        for (int k = 0; k < 2; k++) {
+    if (nl > 1)
+        for (int k = 0; k < nl; k++) {
             HIPCK(hipEventRecord(c->side_ev[k], c->side[k]));
             HIPCK(hipStreamWaitEvent(c->stream, c->side_ev[k], 0));
         }

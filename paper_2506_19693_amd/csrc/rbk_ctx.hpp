@@ -24,6 +24,11 @@ struct ModUpTables {
 // Per-kernel timers (HIP events around every launch of a kernel on the
 // context stream), enabled by rbk_timer_enable.  'bytes' accumulates the
 // algorithmic HBM bytes of each launch: what the kernel must read and write.
+// ModDown lanes of a batch of hoisted rotations (side streams, default
+// priority): two overlap one rotation's VALU-bound kernels with another's
+// memory-bound ones; a third measured no better
+#define RBK_LANES 2
+
 enum KClass {
     KC_NTT_COLS_FWD = 0,
     KC_NTT_ROWS_FWD,
@@ -118,9 +123,10 @@ struct rbk_ctx_impl {
     size_t desc_host_bytes[2] = {0, 0};
     hipEvent_t desc_evt[2] = {nullptr, nullptr};
     int desc_turn = 0;
-    // side streams of the two-lane ModDown of hoisted rotations (lazily created)
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t side_ev[3] = {nullptr, nullptr, nullptr};
+    // side streams of the multi-lane ModDown of hoisted rotations (lazily
+    // created); side_ev[RBK_LANES] forks the lanes off the context stream
+    hipStream_t side[RBK_LANES] = {};
+    hipEvent_t side_ev[RBK_LANES + 1] = {};
     mutable KTimer timers[KC_COUNT];
     mutable std::vector<hipEvent_t> event_pool;
 };
