@@ -823,9 +823,9 @@ static void launch16_logs(int logs, u64 *data, long poly_stride, int npoly, int 
 // (conv, coefficient domain), transforms it and combines it with the Q part
 // of the key inner product: out_p = (sum_j d_j key_{j,p} - NTT(conv_p)) P^-1
 // (+ the addend).  Here the forward row pass of conv_p (after its column
-// pass) keeps its canonical outputs in registers and applies that epilogue
-// directly, so the transformed conv is never written to and read back from
-// memory.  One block per (row tile, limb, ciphertext, polynomial).  Blocks
+// pass) leaves its canonical outputs in its LDS tile and the same block
+// applies that epilogue, so the transformed conv is never written to and read
+// back from memory.  One block per (row tile, limb, ciphertext, polynomial).  Blocks
 // are numbered so that each XCD (blocks b, b+8, ...) walks a contiguous range
 // in which all ciphertexts and both polynomials of one (limb, tile) follow
 // each other: the tile's key words and ModUp digits are then re-read from
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ 
     const u64 *x = ext + ct * ext_stride + li;
     const u64 *kp = key + ((size_t)poly * nT + limb) * N;              // digit j at + j 2 nT N
     const bool do_add = (ADD >= 1 && poly == 0) || (ADD == 2 && poly == 1);
-    const u64 *ad = add + ct * add_stride + poly * per + li;
+    const u64 *ad = ADD ? add + ct * add_stride + poly * per + li : nullptr;
     u64 *o = out + ct * out_stride + poly * per + li;
 #pragma unroll
     for (int m = 0; m < 8; m++) {
