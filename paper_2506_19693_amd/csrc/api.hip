@@ -1063,9 +1063,11 @@ extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, 
     HIPCK(hipMemcpy2DAsync(last, N * sizeof(u64), ct + (size_t)level * N, L1 * N * sizeof(u64), N * sizeof(u64), 2 * count,
                            hipMemcpyDeviceToDevice, c->stream));
     ntt_launch(c, last, (long)N, 2 * count, 1, LimbMap{level, c->nQ, c->nQ}, true, c->stream);
-    rescale_lift_launch(c, last, lifted, level, 2 * count, c->stream);
-    ntt_launch(c, lifted, (long)level * N, 2 * count, level, qmap(c), false, c->stream);
-    rescale_finish_launch(c, ct, lifted, out, level, 2 * count, c->stream);
+    if (!rescale_fused_launch(c, last, lifted, ct, out, level, 2 * count, c->stream)) {
+        rescale_lift_launch(c, last, lifted, level, 2 * count, c->stream);
+        ntt_launch(c, lifted, (long)level * N, 2 * count, level, qmap(c), false, c->stream);
+        rescale_finish_launch(c, ct, lifted, out, level, 2 * count, c->stream);
+    }
     HIPCK_LAUNCH();
     return RBK_OK;
 }

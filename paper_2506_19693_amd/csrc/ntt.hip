@@ -513,9 +513,9 @@ __device__ __forceinline__ void fp_reduce16(double (&x)[16], double p, double pi
 // the integer pass in k_ntt16).
 // twf: the twiddles of the column pass (staged) or the table; stg (row
 // passes): the block's staged RowStage and GenStage entries (rows from lb)
-template <int LOGS, bool INV, bool COLS, bool KEEP = false, bool LDSIN = false>
+template <int LOGS, bool INV, bool COLS, bool KEEP, bool LDSIN, class LD>
 __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc, const double2 *twf, const double2 *stg,
-                                         int lb, int t, int gl, int logN)
+                                         int lb, int t, int gl, int logN, const LD &ld)
 {
     typedef Geo<LOGS> G;
     constexpr int NST2 = LOGS - 4;
@@ -536,7 +536,7 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
     if (!INV) {
         if (COLS) {
 #pragma unroll
-            for (int i = 0; i < 16; i++) x[i] = fp_from_u64(base[addr(t + G::TPL * i)]);
+            for (int i = 0; i < 16; i++) x[i] = fp_from_u64(ld(base, addr(t + G::TPL * i)));
         } else {
 #pragma unroll
             for (int i = 0; i < 16; i++) x[i] = __longlong_as_double((long long)base[addr(t + G::TPL * i)]);
@@ -613,8 +613,15 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 // whole block) instead of being stored.
 // LDSIN (inverse row pass only): the caller has written the canonical inputs
 // to the LDS tile in that layout; they are not loaded from base.
-template <int LOGS, bool INV, bool COLS, bool KEEP = false, bool LDSIN = false>
-__device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const NttTables &T, int pr, int tile, int logN)
+// LD (forward column pass): ld(base, pos) supplies the canonical input at
+// position pos of the limb (default: base[pos]); the outputs go to base.
+struct PlainLd {
+    __device__ u64 operator()(const u64 *base, size_t pos) const { return base[pos]; }
+};
+
+template <int LOGS, bool INV, bool COLS, bool KEEP = false, bool LDSIN = false, class LD = PlainLd>
+__device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const NttTables &T, int pr, int tile, int logN,
+                                           const LD &ld = LD())
 {
     static_assert(!KEEP || (!INV && !COLS), "only the forward row pass keeps its outputs");
     static_assert(!LDSIN || (INV && !COLS), "only the inverse row pass takes its inputs from LDS");
@@ -645,7 +652,7 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
             stage_gen_twiddles<INV, LOGS>(st + GenStage<LOGS>::A, twf, lb, logN, tid);
             __syncthreads();
         }
-        ntt16_fp<LOGS, INV, COLS, KEEP, LDSIN>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN);
+        ntt16_fp<LOGS, INV, COLS, KEEP, LDSIN>(base, sm + line * G::LS, fc, twf, st, lb, t, gl, logN, ld);
         return;
     }
     const PrimeC pc = T.pc[pr];
@@ -683,7 +690,7 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
     u64 pw[15], pws[15];                                 // row passes: prefetched twiddles
     if (!INV) {
 #pragma unroll
-        for (int i = 0; i < 16; i++) x[i] = base[addr(t + G::TPL * i)];
+        for (int i = 0; i < 16; i++) x[i] = ld(base, addr(t + G::TPL * i));
         if (!COLS) prefetch_tw<false, LOGS>(pw, pws, tw, tws, t, gl, logN);
         ntt_round16<false, 4, 8, LOGS, RS>(x, t, G::TPL, 0, off_f, lid, logN, RS ? twr : tw, RS ? twsr : tws, q, q4, false,
                                            0, 0, 0, 0, lb);
@@ -1056,6 +1063,93 @@ void moddown_head_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride,
     }
     ip_p_launch(c, ext, ext_stride, key, tp, level, count, g, st);
     ntt_launch(c, tp, (long)nP * c->N, 2 * count, nP, pm, true, st);
+}
+
+// ---------------------------------------------------------------- rescale: NTT of the lifted last limb, fused at both ends
+//
+// Rescale lifts each polynomial's last limb (coefficient domain, centred)
+// to the other limbs, transforms the lifts and finishes with
+// out = (in - NTT(lift)) q_l^-1.  The column pass computes the lift of its
+// inputs from the last limb itself (LiftLd), and the row pass leaves its
+// outputs in LDS for the same block to finish, so the lifted limbs are
+// written and read once, between the two passes.
+struct LiftLd {
+    const u64 *last;  // the polynomial's last limb, coefficient domain
+    u64 q, one_sh, qmod, half;  // target prime, floor(2^64/q), q_l mod q, (q_l - 1) / 2
+    __device__ u64 operator()(const u64 *, size_t pos) const
+    {
+        const u64 x = last[pos];
+        const u64 xm = shoup(x, 1, one_sh, q);
+        return x <= half ? xm : sub_mod(xm, qmod, q);
+    }
+};
+
+template <int LOGS>
+__global__ __launch_bounds__(256) void k_ntt_cols_lift(const u64 *last, u64 *lifted, NttTables T, const u64 *qmod,
+                                                       int logN, int level)
+{
+    __shared__ u64 sm[Geo<LOGS>::LINES * Geo<LOGS>::LS];
+    __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, true>::value];
+    const int limb = blockIdx.z, poly = blockIdx.y;
+    const size_t N = (size_t)1 << logN;
+    const PrimeC p = T.pc[limb];
+    const LiftLd ld{last + (size_t)poly * N, p.q, p.one_sh, qmod[limb], (T.pc[level].q - 1) / 2};
+    ntt16_tile<LOGS, false, true, false, false, LiftLd>(lifted + ((size_t)poly * level + limb) * N, sm, smtw, T, limb,
+                                                        blockIdx.x, logN, ld);
+}
+
+template <int LOGS>
+__global__ __launch_bounds__(256) void k_ntt_rows_rs(const u64 *lifted, const u64 *__restrict__ in, u64 *__restrict__ out,
+                                                     NttTables T, const u64 *inv, const u64 *inv_sh, int logN, int level)
+{
+    typedef Geo<LOGS> G;
+    __shared__ u64 sm[G::LINES * G::LS];
+    __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, false>::value];
+    const int limb = blockIdx.z, poly = blockIdx.y, tile = blockIdx.x;
+    const size_t N = (size_t)1 << logN, li = (size_t)limb * N;
+    ntt16_tile<LOGS, false, false, true>(const_cast<u64 *>(lifted) + (size_t)poly * level * N + li, sm, smtw, T, limb, tile,
+                                         logN);
+    const u64 q = T.pc[limb].q, w = inv[limb], wsh = inv_sh[limb];
+    const u64 *x = in + (size_t)poly * (level + 1) * N + li;
+    u64 *o = out + (size_t)poly * level * N + li;
+    const size_t tbase = (size_t)tile * 4096;
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        const int e = 2 * (int)threadIdx.x + 512 * m;              // even position in the tile
+        const size_t pos = tbase + e;
+        const u64x2 v = ld2(x + pos);
+        const u64 *cl = sm + (e >> LOGS) * G::LS;
+        const int cc = e & (G::S - 1);
+        st2(o + pos, shoup(sub_mod(v.x, cl[lidx(cc)], q), w, wsh, q), shoup(sub_mod(v.y, cl[lidx(cc + 1)], q), w, wsh, q));
+    }
+}
+
+bool rescale_fused_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, const u64 *in, u64 *out, int level,
+                          int npoly, hipStream_t st)
+{
+    if (!ntt_rows_md_ok(c) || level < 1 || npoly < 1) return false;
+    if (((uintptr_t)in | (uintptr_t)out) & 15) return false;  // the finish moves 16-byte pairs
+    const int logN = c->logN, logC = c->ntt_logC, r = logN - logC;
+    const size_t N = c->N;
+    const u64 *qmod = c->d_rs_qmod + (size_t)level * c->nQ;
+    const u64 *inv = c->d_rs_inv + (size_t)level * c->nQ, *inv_sh = c->d_rs_inv_sh + (size_t)level * c->nQ;
+    const dim3 grid((unsigned)(N / 4096), npoly, level);
+    const double bytes = 2.0 * npoly * level * N * sizeof(u64);
+    kt_begin(c, KC_NTT_COLS_FWD, st);
+    switch (r) {
+    case 6: hipLaunchKernelGGL(k_ntt_cols_lift<6>, grid, dim3(256), 0, st, last, lifted, c->tabs, qmod, logN, level); break;
+    case 7: hipLaunchKernelGGL(k_ntt_cols_lift<7>, grid, dim3(256), 0, st, last, lifted, c->tabs, qmod, logN, level); break;
+    default: hipLaunchKernelGGL(k_ntt_cols_lift<8>, grid, dim3(256), 0, st, last, lifted, c->tabs, qmod, logN, level); break;
+    }
+    kt_end(c, KC_NTT_COLS_FWD, bytes / 2 + (double)npoly * N * sizeof(u64), st);
+    kt_begin(c, KC_RESCALE, st);
+    switch (logC) {
+    case 6: hipLaunchKernelGGL(k_ntt_rows_rs<6>, grid, dim3(256), 0, st, lifted, in, out, c->tabs, inv, inv_sh, logN, level); break;
+    case 7: hipLaunchKernelGGL(k_ntt_rows_rs<7>, grid, dim3(256), 0, st, lifted, in, out, c->tabs, inv, inv_sh, logN, level); break;
+    default: hipLaunchKernelGGL(k_ntt_rows_rs<8>, grid, dim3(256), 0, st, lifted, in, out, c->tabs, inv, inv_sh, logN, level); break;
+    }
+    kt_end(c, KC_RESCALE, 3.0 * npoly * level * N * sizeof(u64), st);
+    return true;
 }
 
 void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,

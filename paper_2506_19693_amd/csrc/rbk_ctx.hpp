@@ -192,6 +192,13 @@ void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u
 void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
                        long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
                        long out_stride, int level, int count, u64 g, hipStream_t st);
+// Rescale tail for the register NTT geometries: lifted ([npoly][level] limbs)
+// = NTT of the centred lift of last ([npoly] limbs, coefficient domain), then
+// out ([npoly][level]) = (in ([npoly][level+1]) - lifted) q_level^-1, the
+// lift computed inside the column pass and the finish inside the row pass.
+// Returns false (nothing launched) for other geometries.
+bool rescale_fused_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, const u64 *in, u64 *out, int level,
+                          int npoly, hipStream_t st);
 // ModDown head: tp ([count][2][k] limbs) = the special-prime part of the key
 // inner product, brought to the coefficient domain; for the register NTT
 // geometries the inner product is computed inside the first iNTT pass.
