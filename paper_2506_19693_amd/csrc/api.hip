@@ -897,9 +897,7 @@ static int modup_run(rbk_ctx *c, const u64 *d, long d_stride, u64 *ext, long ext
     const int L1 = level + 1, E = L1 + c->nP;
     const ModUpTables &T = modup_tables(c, level);
     if (!T.d_M) return fail(RBK_ENOMEM, "ModUp tables");
-    HIPCK(hipMemcpy2DAsync(coef, L1 * N * sizeof(u64), d, d_stride * sizeof(u64), L1 * N * sizeof(u64), count,
-                           hipMemcpyDeviceToDevice, c->stream));
-    ntt_launch(c, coef, (long)L1 * N, count, L1, qmap(c), true, c->stream);
+    HIPCK(ntt_inverse_from_launch(c, d, d_stride, coef, (long)L1 * N, count, L1, qmap(c), c->stream));
     // the base conversion also places each digit's own limbs (from d, NTT domain)
     bconv_modup_launch(c, coef, (long)L1 * N, d, d_stride, ext, ext_stride, level, count, c->stream);
     for (int j = 0; j < T.beta; j++) {
@@ -1060,9 +1058,8 @@ extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, 
     const size_t N = c->N, L1 = level + 1;
     WS(ws, 2 * count * N + 2 * count * level * N);
     u64 *last = ws, *lifted = ws + 2 * count * N;
-    HIPCK(hipMemcpy2DAsync(last, N * sizeof(u64), ct + (size_t)level * N, L1 * N * sizeof(u64), N * sizeof(u64), 2 * count,
-                           hipMemcpyDeviceToDevice, c->stream));
-    ntt_launch(c, last, (long)N, 2 * count, 1, LimbMap{level, c->nQ, c->nQ}, true, c->stream);
+    HIPCK(ntt_inverse_from_launch(c, ct + (size_t)level * N, (long)(L1 * N), last, (long)N, 2 * count, 1,
+                                  LimbMap{level, c->nQ, c->nQ}, c->stream));
     if (!rescale_fused_launch(c, last, lifted, ct, out, level, 2 * count, c->stream)) {
         rescale_lift_launch(c, last, lifted, level, 2 * count, c->stream);
         ntt_launch(c, lifted, (long)level * N, 2 * count, level, qmap(c), false, c->stream);

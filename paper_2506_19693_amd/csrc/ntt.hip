@@ -573,7 +573,7 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
             u64 *su = sm_line;
             if (!LDSIN) {
 #pragma unroll
-                for (int i = 0; i < 16; i++) su[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+                for (int i = 0; i < 16; i++) su[lidx(t + G::TPL * i)] = ld(base, addr(t + G::TPL * i));
             }
             __syncthreads();
 #pragma unroll
@@ -613,8 +613,9 @@ __device__ __forceinline__ void ntt16_fp(u64 *base, u64 *sm_line, const FpC &fc,
 // whole block) instead of being stored.
 // LDSIN (inverse row pass only): the caller has written the canonical inputs
 // to the LDS tile in that layout; they are not loaded from base.
-// LD (forward column pass): ld(base, pos) supplies the canonical input at
-// position pos of the limb (default: base[pos]); the outputs go to base.
+// LD (the first pass: forward column, inverse row): ld(base, pos) supplies
+// the canonical input at position pos of the limb (default: base[pos]); the
+// outputs go to base.
 struct PlainLd {
     __device__ u64 operator()(const u64 *base, size_t pos) const { return base[pos]; }
 };
@@ -724,7 +725,7 @@ __device__ __forceinline__ void ntt16_tile(u64 *base, u64 *sm, u64 *smtw, const 
         } else {
             if (!LDSIN) {
 #pragma unroll
-                for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = base[addr(t + G::TPL * i)];
+                for (int i = 0; i < 16; i++) sl[lidx(t + G::TPL * i)] = ld(base, addr(t + G::TPL * i));
             }
             __syncthreads();
 #pragma unroll
@@ -1150,6 +1151,65 @@ bool rescale_fused_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, c
     }
     kt_end(c, KC_RESCALE, 3.0 * npoly * level * N * sizeof(u64), st);
     return true;
+}
+
+// ---------------------------------------------------------------- inverse NTT out of place
+//
+// The first (row) pass reads the limbs from src and writes dst; the column
+// pass then runs in place on dst.  Saves the copy an in-place transform of a
+// buffer that must survive would need.
+struct OffsetLd {
+    const u64 *src;  // the limb's first element in the source buffer
+    __device__ u64 operator()(const u64 *, size_t pos) const { return src[pos]; }
+};
+
+template <int LOGS>
+__global__ __launch_bounds__(256) void k_ntt16_inv_from(const u64 *src, long src_stride, u64 *dst, long dst_stride,
+                                                        LimbMap map, NttTables T, int logN)
+{
+    __shared__ u64 sm[Geo<LOGS>::LINES * Geo<LOGS>::LS];
+    __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, false>::value];
+    const int limb = blockIdx.z, poly = blockIdx.y;
+    const size_t off = ((size_t)limb << logN);
+    const OffsetLd ld{src + poly * src_stride + off};
+    ntt16_tile<LOGS, true, false, false, false, OffsetLd>(dst + poly * dst_stride + off, sm, smtw, T, map.prime(limb),
+                                                          blockIdx.x, logN, ld);
+}
+
+hipError_t ntt_inverse_from_launch(const rbk_ctx_impl *c, const u64 *src, long src_stride, u64 *dst, long dst_stride,
+                                   int npoly, int nlimbs, LimbMap map, hipStream_t st)
+{
+    if (npoly <= 0 || nlimbs <= 0) return hipSuccess;
+    const int logN = c->logN, logC = c->ntt_logC, r = logN - logC;
+    if (!ntt_rows_md_ok(c)) {
+        const hipError_t e =
+            hipMemcpy2DAsync(dst, dst_stride * sizeof(u64), src, src_stride * sizeof(u64), (size_t)nlimbs * c->N * sizeof(u64),
+                             npoly, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+        ntt_launch(c, dst, dst_stride, npoly, nlimbs, map, true, st);
+        return hipSuccess;
+    }
+    // chunks of whole polynomials, both passes per chunk (as ntt_launch)
+    int ppc = npoly;
+    if (c->ntt_chunk > 0 && (long)npoly * nlimbs > c->ntt_chunk) ppc = std::max(1, c->ntt_chunk / nlimbs);
+    const double bytes = 2.0 * nlimbs * c->N * sizeof(u64);
+    for (int p0 = 0; p0 < npoly; p0 += ppc) {
+        const int np = std::min(ppc, npoly - p0);
+        const u64 *s = src + (size_t)p0 * src_stride;
+        u64 *d = dst + (size_t)p0 * dst_stride;
+        const dim3 grid((unsigned)(((size_t)1 << logN) / 4096), np, nlimbs);
+        kt_begin(c, KC_NTT_ROWS_INV, st);
+        switch (logC) {
+        case 6: hipLaunchKernelGGL(k_ntt16_inv_from<6>, grid, dim3(256), 0, st, s, src_stride, d, dst_stride, map, c->tabs, logN); break;
+        case 7: hipLaunchKernelGGL(k_ntt16_inv_from<7>, grid, dim3(256), 0, st, s, src_stride, d, dst_stride, map, c->tabs, logN); break;
+        default: hipLaunchKernelGGL(k_ntt16_inv_from<8>, grid, dim3(256), 0, st, s, src_stride, d, dst_stride, map, c->tabs, logN); break;
+        }
+        kt_end(c, KC_NTT_ROWS_INV, bytes * np, st);
+        kt_begin(c, KC_NTT_COLS_INV, st);
+        launch16_logs<true, true>(r, d, dst_stride, np, nlimbs, map, c->tabs, logN, st);
+        kt_end(c, KC_NTT_COLS_INV, bytes * np, st);
+    }
+    return hipSuccess;
 }
 
 void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,

@@ -192,6 +192,11 @@ void ip_p_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u
 void moddown_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, const u64 *conv,
                        long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
                        long out_stride, int level, int count, u64 g, hipStream_t st);
+// Inverse NTT of npoly x nlimbs limbs read from src (limb i of polynomial p
+// at src + p src_stride + i N) into dst (same layout with dst_stride); src is
+// left unchanged.
+hipError_t ntt_inverse_from_launch(const rbk_ctx_impl *c, const u64 *src, long src_stride, u64 *dst, long dst_stride,
+                                   int npoly, int nlimbs, LimbMap map, hipStream_t st);
 // Rescale tail for the register NTT geometries: lifted ([npoly][level] limbs)
 // = NTT of the centred lift of last ([npoly] limbs, coefficient domain), then
 // out ([npoly][level]) = (in ([npoly][level+1]) - lifted) q_level^-1, the
