@@ -460,30 +460,57 @@ struct CombArgs {
     int cidx;
 };
 
+__device__ __forceinline__ u64 comb_term(const CombArgs &A, int t, u64 v, const u64 *scal, int nQ, int limb, u64 q)
+{
+    if (A.vs[t] >= 0) {
+        const u64 *w = scal + ((size_t)A.vs[t] * nQ + limb) * 2;
+        v = shoup(v, w[0], w[1], q);
+    }
+    return v;
+}
+
+// PAIR: two adjacent coefficients per thread (every view and out 16-byte
+// aligned, even strides), else one
+template <bool PAIR>
 __global__ __launch_bounds__(256) void k_boot_comb(CombArgs A, u64 *out, const u64 *scal, int nQ, int logN, int L1,
                                                     const PrimeC *pc)
 {
-    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n = (PAIR ? 2 : 1) * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (n >= ((size_t)1 << logN)) return;
     const int limb = blockIdx.y;
     const unsigned ct = blockIdx.z >> 1, poly = blockIdx.z & 1;
     const u64 q = pc[limb].q;
     const size_t per = (size_t)L1 << logN;
     const size_t o = (size_t)ct * 2 * per + poly * per + ((size_t)limb << logN) + n;
+    const u64 cadd = (poly == 0 && A.cidx >= 0) ? scal[((size_t)A.cidx * nQ + limb) * 2] : 0;
+    if (PAIR) {
+        u64 r0 = 0, r1 = 0;
+        if (A.x) {
+            const u64x2 x = ld2(A.x + o);
+            r0 = add_mod(x.x, x.x, q);
+            r1 = add_mod(x.y, x.y, q);
+        }
+#pragma unroll
+        for (int t = 0; t < COMB_MAX; t++) {
+            if (t >= A.n) break;
+            const u64x2 v = ld2(A.v[t] + (size_t)ct * A.vcs[t] + poly * A.vps[t] + ((size_t)limb << logN) + n);
+            const u64 v0 = comb_term(A, t, v.x, scal, nQ, limb, q), v1 = comb_term(A, t, v.y, scal, nQ, limb, q);
+            r0 = A.vneg[t] ? sub_mod(r0, v0, q) : add_mod(r0, v0, q);
+            r1 = A.vneg[t] ? sub_mod(r1, v1, q) : add_mod(r1, v1, q);
+        }
+        st2(out + o, add_mod(r0, cadd, q), add_mod(r1, cadd, q));
+        return;
+    }
     u64 r = 0;
     if (A.x) r = add_mod(A.x[o], A.x[o], q);
 #pragma unroll
     for (int t = 0; t < COMB_MAX; t++) {
         if (t >= A.n) break;
-        u64 v = A.v[t][(size_t)ct * A.vcs[t] + poly * A.vps[t] + ((size_t)limb << logN) + n];
-        if (A.vs[t] >= 0) {
-            const u64 *w = scal + ((size_t)A.vs[t] * nQ + limb) * 2;
-            v = shoup(v, w[0], w[1], q);
-        }
+        const u64 v = comb_term(A, t, A.v[t][(size_t)ct * A.vcs[t] + poly * A.vps[t] + ((size_t)limb << logN) + n], scal,
+                                nQ, limb, q);
         r = A.vneg[t] ? sub_mod(r, v, q) : add_mod(r, v, q);
     }
-    if (poly == 0 && A.cidx >= 0) r = add_mod(r, scal[((size_t)A.cidx * nQ + limb) * 2], q);
-    out[o] = r;
+    out[o] = add_mod(r, cadd, q);
 }
 
 static int upload_scalars(rbk_ctx *c, BootPlan &P)
@@ -558,10 +585,18 @@ struct Runner {
     // one elementwise pass at level lv over n_ct ciphertexts (see k_boot_comb)
     void comb(CombArgs &A, u64 *out, int lv, int n_ct)
     {
-        const unsigned thr = (unsigned)std::min<size_t>(256, c->N);
-        dim3 grid((unsigned)(c->N / thr), lv + 1, 2 * n_ct);
+        bool pair = ((uintptr_t)out & 15) == 0 && (!A.x || ((uintptr_t)A.x & 15) == 0) && c->N >= 2;
+        for (int t = 0; t < A.n; t++) pair = pair && ((uintptr_t)A.v[t] & 15) == 0 && (A.vcs[t] | A.vps[t]) % 2 == 0;
+        const size_t work = pair ? c->N / 2 : c->N;
+        const unsigned thr = (unsigned)std::min<size_t>(256, work);
+        dim3 grid((unsigned)(work / thr), lv + 1, 2 * n_ct);
         kt_begin(c, KC_ELEMENTWISE, c->stream);
-        hipLaunchKernelGGL(k_boot_comb, grid, dim3(thr), 0, c->stream, A, out, P.d_scal, c->nQ, c->logN, lv + 1, c->d_pc);
+        if (pair)
+            hipLaunchKernelGGL(k_boot_comb<true>, grid, dim3(thr), 0, c->stream, A, out, P.d_scal, c->nQ, c->logN, lv + 1,
+                               c->d_pc);
+        else
+            hipLaunchKernelGGL(k_boot_comb<false>, grid, dim3(thr), 0, c->stream, A, out, P.d_scal, c->nQ, c->logN, lv + 1,
+                               c->d_pc);
         kt_end(c, KC_ELEMENTWISE, (double)n_ct * 2 * (lv + 1) * c->N * sizeof(u64) * (A.n + (A.x ? 2 : 1)), c->stream);
     }
     // a register seen as a view: ciphertexts 2 (level+1) N apart

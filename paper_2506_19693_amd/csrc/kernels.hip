@@ -147,22 +147,33 @@ void tensor_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, 
 }
 
 // NTT-domain automorphism of npoly x nlimbs limbs (a pure permutation).
+// PAIR: two adjacent outputs per thread, read as one aligned source pair
+// (pairs map to pairs under any automorphism; in and out 16-byte aligned)
+template <bool PAIR>
 __global__ void k_automorph(const u64 *in, u64 *out, size_t total, int logN, u64 g)
 {
-    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    size_t i = (PAIR ? 2 : 1) * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
     if (i >= total) return;
     size_t base = i & ~(((size_t)1 << logN) - 1);
     u32 o = (u32)(i & (((size_t)1 << logN) - 1));
-    out[i] = in[base + auto_src(o, g, logN)];
+    if (PAIR) {
+        const u64x2 v = ld2_perm(in + base, auto_src(o, g, logN));
+        st2(out + i, v.x, v.y);
+    } else {
+        out[i] = in[base + auto_src(o, g, logN)];
+    }
 }
 
 void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int nlimbs, u64 g, hipStream_t st)
 {
     size_t total = (size_t)npoly * nlimbs * c->N;
     if (total == 0) return;
-    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
+    const bool pair = (((uintptr_t)in | (uintptr_t)out) & 15) == 0 && c->N >= 2;
+    const size_t threads = pair ? total / 2 : total;
+    dim3 grid((unsigned)((threads + EW_THREADS - 1) / EW_THREADS));
     kt_begin(c, KC_ELEMENTWISE, st);
-    hipLaunchKernelGGL(k_automorph, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, g);
+    if (pair) hipLaunchKernelGGL(k_automorph<true>, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, g);
+    else hipLaunchKernelGGL(k_automorph<false>, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, g);
     kt_end(c, KC_ELEMENTWISE, 2.0 * total * sizeof(u64), st);
 }
 

@@ -64,14 +64,17 @@ __global__ void k_mlp_tensor(View a, View b, u64 *out, int logN, int L1, const P
     o[2 * per] = mul_mod(a1, b1, p);
 }
 
-// a +- b; grid (N/threads, L1, 2 count)
+// a +- b over adjacent coefficient pairs (views and out 16-byte aligned);
+// grid (N/(2 threads), L1, 2 count)
 __global__ void k_mlp_addsub(View a, View b, u64 *out, int logN, int L1, int sub, const PrimeC *pc)
 {
-    const unsigned n = blockIdx.x * blockDim.x + threadIdx.x, limb = blockIdx.y;
+    const unsigned n = 2 * (blockIdx.x * blockDim.x + threadIdx.x), limb = blockIdx.y;
     const unsigned ct = blockIdx.z >> 1, poly = blockIdx.z & 1;
     const u64 q = pc[limb].q;
-    const u64 x = ld(a, ct, poly, limb, logN, n), y = ld(b, ct, poly, limb, logN, n);
-    out[(((size_t)blockIdx.z * L1 + limb) << logN) + n] = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
+    const u64x2 x = ld2(&a.d[(size_t)ct * a.cs + (size_t)poly * a.ps + ((size_t)limb << logN) + n]);
+    const u64x2 y = ld2(&b.d[(size_t)ct * b.cs + (size_t)poly * b.ps + ((size_t)limb << logN) + n]);
+    st2(out + (((size_t)blockIdx.z * L1 + limb) << logN) + n, sub ? sub_mod(x.x, y.x, q) : add_mod(x.x, y.x, q),
+        sub ? sub_mod(x.y, y.y, q) : add_mod(x.y, y.y, q));
 }
 
 // a (.) pt for a plaintext pt[L1'][N] (limbs 0..L1-1 used)
@@ -509,8 +512,13 @@ struct GpuOps {
         if (a.s != b.s) mthrow(RBK_ESCALE, "MLP step: addition of ciphertexts at different scales");
         const int lv = std::min(a.lv, b.lv), cnt = bcast(a, b);
         Vec o = alloc(lv, cnt);
-        hipLaunchKernelGGL(k_mlp_addsub, grid(lv, 2 * cnt), dim3(thr), 0, c->stream, view(a, cnt), view(b, cnt),
-                           (u64 *)o.d, logN, lv + 1, sub, c->d_pc);
+        const View va = view(a, cnt), vb = view(b, cnt);
+        // buffers come from whole allocations at multiples of N words
+        if (((uintptr_t)va.d | (uintptr_t)vb.d | (uintptr_t)o.d) & 15 || (va.cs | va.ps | vb.cs | vb.ps) & 1)
+            mthrow(RBK_EINVAL, "MLP step: unaligned operands");
+        const unsigned t2 = (unsigned)std::min<size_t>(thr, N / 2);
+        const dim3 g2((unsigned)(N / (2 * t2)), (unsigned)(lv + 1), (unsigned)(2 * cnt));
+        hipLaunchKernelGGL(k_mlp_addsub, g2, dim3(t2), 0, c->stream, va, vb, (u64 *)o.d, logN, lv + 1, sub, c->d_pc);
         launched();
         o.s = a.s;
         return o;
