@@ -498,6 +498,18 @@ int rbk_capture_end(rbk_ctx *ctx, rbk_graph **out);
 int rbk_graph_launch(rbk_graph *graph);
 int rbk_graph_destroy(rbk_graph *graph);
 
+/* ---- ModDown lanes ------------------------------------------------------ */
+/* A batch of hoisted rotations (rbk_rotate_hoisted_batch) runs the
+ * independent ModDowns of its rotations round-robin on n side streams (lanes,
+ * default priority) that join the context stream before the call returns;
+ * each lane has tp/conv scratch of its own in the workspace.  Two lanes (the
+ * default) overlap one rotation's arithmetic-bound kernels with another's
+ * memory-bound ones; n = 1 runs everything on the context stream (kernels do
+ * not overlap, so profiler durations are each kernel's own).  Lanes are not
+ * used while timers run or while the stream is captured.  n outside 1..2:
+ * RBK_EINVAL, setting unchanged. */
+int rbk_set_lanes(rbk_ctx *ctx, int n);
+
 /* ---- per-kernel timers -------------------------------------------------- */
 /* With timers on, every kernel launch on the context stream is bracketed by
  * HIP events.  Class `cls` = 0, 1, ... names one kernel (rbk_timer_name);

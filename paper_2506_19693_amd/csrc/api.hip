@@ -1141,7 +1141,9 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
     // base conversion) overlap the memory-bound ones of another.  One lane
     // while the stream is being captured and while per-kernel timers run
     // (overlapping kernels would not have durations of their own)
-    const int nl = (!c->capturing && !c->timing && n > 1 && side_streams(c) == RBK_OK) ? std::min(RBK_LANES, n) : 1;
+    const int nl = (c->lanes > 1 && !c->capturing && !c->timing && n > 1 && side_streams(c) == RBK_OK)
+                       ? std::min(c->lanes, n)
+                       : 1;
     const size_t tp_words = (size_t)count * 2 * c->nP * N, conv_words = (size_t)count * 2 * L1 * N;
     WS(ws, ks_words(c, level, count) + (size_t)(nl - 1) * (tp_words + conv_words));
     KsBufs b = ks_layout(c, ws, level, count);
@@ -1238,6 +1240,14 @@ static int kt_collect(rbk_ctx *c)
         for (hipEvent_t e : t.pending) c->event_pool.push_back(e);
         t.pending.clear();
     }
+    return RBK_OK;
+}
+
+extern "C" int rbk_set_lanes(rbk_ctx *c, int n)
+{
+    if (!c) return fail(RBK_EINVAL, "null context");
+    if (n < 1 || n > RBK_LANES) return fail(RBK_EINVAL, "lanes out of range (1.." + std::to_string(RBK_LANES) + ")");
+    c->lanes = n;
     return RBK_OK;
 }
 

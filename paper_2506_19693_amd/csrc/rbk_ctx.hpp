@@ -66,6 +66,7 @@ struct rbk_ctx_impl {
     // before the next, so the intermediate can stay in the memory-side cache
     // (0: one pair of launches over the whole batch)
     int ntt_chunk = 512;
+    int lanes = RBK_LANES;  // ModDown lanes of a batch of hoisted rotations (rbk_set_lanes)
     std::vector<u64> mod, psi;
     std::vector<PrimeC> h_pc;
 

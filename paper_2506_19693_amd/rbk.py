@@ -192,6 +192,7 @@ SIGNATURES = {
     "rbk_capture_end": (ci, [vp, ctypes.POINTER(vp)]),
     "rbk_graph_launch": (ci, [vp]),
     "rbk_graph_destroy": (ci, [vp]),
+    "rbk_set_lanes": (ci, [vp, ci]),
     "rbk_timer_enable": (ci, [vp, ci]),
     "rbk_timer_read": (ci, [vp, ci, dblp, u64p, dblp]),
     "rbk_timer_name": (ctypes.c_char_p, [ci]),
@@ -632,6 +633,11 @@ class Context:
         finally:
             self.set_stream(torch.cuda.current_stream())
         return Graph(self, h, side)
+
+    # ---------------------------------------------------------------- lanes
+    def set_lanes(self, n):
+        """ModDown lanes (side streams) of a batch of hoisted rotations: 1 or 2."""
+        _check(self.lib.rbk_set_lanes(self.h, int(n)))
 
     # ---------------------------------------------------------------- timers
     def timer_enable(self, on=True):
