@@ -204,7 +204,10 @@ int rbk_rotate_hoisted(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, in
 int rbk_mult_relin_batch(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level, int count);
 /* d_ct: [count][2][l+1][N] -> d_out: [count][2][l][N] */
 int rbk_rescale_batch(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level, int count);
-/* d_ct: [count][2][l+1][N] -> d_outs: [count][n][2][l+1][N] */
+/* d_ct: [count][2][l+1][N] -> d_outs: [count][n][2][l+1][N].  The
+ * rotations' ModDowns run on the side streams set by rbk_set_lanes; the
+ * call's work is complete, as for every call, once the context stream
+ * reaches the point where it was issued. */
 int rbk_rotate_hoisted_batch(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, int n, uint64_t *d_outs, int level,
                              int count);
 
