@@ -80,3 +80,33 @@ def test_lanes_give_the_same_residues():
     for bad in (0, 3):
         with pytest.raises(RbkError):
             d.set_lanes(bad)
+
+
+def _unaligned_copy(d, t):
+    """A copy of t whose first word sits 8 bytes past a 16-byte boundary."""
+    import torch
+
+    buf = d.empty(t.numel() + 1)
+    assert buf.data_ptr() % 16 == 0
+    v = buf[1:].view(t.shape)
+    v.copy_(t)
+    assert v.data_ptr() % 16 == 8
+    return v
+
+
+def test_unaligned_buffers_take_the_single_element_kernels():
+    """Rescale and the automorphism move 16-byte pairs when their buffers are
+    16-byte aligned and fall back to single elements otherwise: both give
+    the same residues."""
+    d, g = _ctx(14)
+    L = d.L
+    A = d.to_ntt(S.uniform_residues(g, d.moduli[: L + 1], d.N, lead=(3, 2)), L)
+    want = d.rescale_batch(A, L)
+    Au = _unaligned_copy(d, A)
+    out_u = _unaligned_copy(d, d.empty_ct(L - 1, 3))
+    got = d.rescale_batch(Au, L, out=out_u)
+    assert np.array_equal(got.cpu().numpy(), want.cpu().numpy())
+    gal = d.galois_elt(5)
+    want_a = d.automorph(A[0], gal, L)
+    got_a = d.automorph(_unaligned_copy(d, A[0]), gal, L)
+    assert np.array_equal(got_a.cpu().numpy(), want_a.cpu().numpy())
