@@ -182,7 +182,8 @@ int rbk_keyswitch(rbk_ctx *ctx, uint64_t g, const uint64_t *d_d, uint64_t *d_out
 /* Homomorphic product with relinearisation (eq. mult): (d0, d1) + KS(d2).
  * The scale of the result is the product of the scales. */
 int rbk_mult_relin(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level);
-/* Rescale by q_l: out_i = (c_i - centred(c_l)) q_l^-1 mod q_i; d_out[2][l][N] */
+/* Rescale by q_l: out_i = (c_i - centred(c_l)) q_l^-1 mod q_i; d_out[2][l][N].
+ * Input and output must not overlap (their strides differ): RBK_EINVAL. */
 int rbk_rescale(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level);
 /* NTT-domain automorphism X -> X^g of npoly polynomials of level+1 limbs */
 int rbk_automorph(rbk_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, int level, int npoly, uint64_t g);
@@ -202,7 +203,7 @@ int rbk_rotate_hoisted(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, in
 
 /* d_a, d_b, d_out: [count][2][l+1][N] */
 int rbk_mult_relin_batch(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level, int count);
-/* d_ct: [count][2][l+1][N] -> d_out: [count][2][l][N] */
+/* d_ct: [count][2][l+1][N] -> d_out: [count][2][l][N]; no overlap (RBK_EINVAL) */
 int rbk_rescale_batch(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level, int count);
 /* d_ct: [count][2][l+1][N] -> d_outs: [count][n][2][l+1][N].  The
  * rotations' ModDowns run on the side streams set by rbk_set_lanes; the
@@ -238,7 +239,7 @@ int rbk_ntt_list(rbk_ctx *ctx, const rbk_ntt_item *items, int n, int inverse);
  * 0..levels[i] of its slot; d_out: [count][2][Lm][N], ciphertext i written
  * to limbs 0..levels[i]-1 (the rest of its slot is left as it was).  The
  * same residues as rbk_mult_relin_batch followed by rbk_rescale_batch at
- * each ciphertext's level. */
+ * each ciphertext's level.  d_out must not overlap d_a or d_b (RBK_EINVAL). */
 int rbk_mult_relin_rescale_list(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out,
                                 const int *levels, int count);
 

@@ -33,6 +33,13 @@ int rbk_set_error(int code, const char *msg) { return fail(code, msg); }
 
 #define HIPCK_LAUNCH() HIPCK(hipGetLastError())
 
+bool ranges_overlap(const u64 *a, size_t a_words, const u64 *b, size_t b_words)
+{
+    const uintptr_t a0 = (uintptr_t)a, a1 = a0 + a_words * sizeof(u64);
+    const uintptr_t b0 = (uintptr_t)b, b1 = b0 + b_words * sizeof(u64);
+    return a0 < b1 && b0 < a1;
+}
+
 // ---------------------------------------------------------------- host number theory
 
 static u64 h_mul(u64 a, u64 b, u64 q) { return (u64)((u128)a * b % q); }
@@ -1056,6 +1063,10 @@ extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, 
     if (!c || !ct || !out || count < 1) return fail(RBK_EINVAL, "bad argument");
     if (check_level(c, level, 1)) return RBK_ELEVEL;
     const size_t N = c->N, L1 = level + 1;
+    // input and output have different strides: blocks of one launch would
+    // overwrite limbs that others still read
+    if (ranges_overlap(ct, (size_t)count * 2 * L1 * N, out, (size_t)count * 2 * level * N))
+        return fail(RBK_EINVAL, "rescale: input and output overlap");
     WS(ws, 2 * count * N + 2 * count * level * N);
     u64 *last = ws, *lifted = ws + 2 * count * N;
     HIPCK(ntt_inverse_from_launch(c, ct + (size_t)level * N, (long)(L1 * N), last, (long)N, 2 * count, 1,
@@ -1161,25 +1172,28 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
         for (int k = 0; k < nl; k++) HIPCK(hipStreamWaitEvent(c->side[k], c->side_ev[RBK_LANES], 0));
     }
     int lane = 0;
-    for (int r = 0; r < n; r++) {
+    for (int r = 0; r < n && rc == RBK_OK; r++) {
         u64 *o = outs + (size_t)r * 2 * per;
         if (gs[r] == 1) {
-            HIPCK(hipMemcpy2DAsync(o, n * 2 * per * sizeof(u64), ct, 2 * per * sizeof(u64), 2 * per * sizeof(u64), count,
-                                   hipMemcpyDeviceToDevice, c->stream));
+            hipError_t e = hipMemcpy2DAsync(o, n * 2 * per * sizeof(u64), ct, 2 * per * sizeof(u64),
+                                            2 * per * sizeof(u64), count, hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) rc = fail(RBK_EDEVICE, std::string("hipMemcpy2DAsync: ") + hipGetErrorString(e));
             continue;
         }
         hipStream_t st = nl > 1 ? c->side[lane] : c->stream;
         rc = moddown_fused_run(c, b.ext, (long)(beta * E * N), keys[r], gs[r], ct, (long)(2 * per), gs[r], 0, o,
                                (long)(n * 2 * per), level, count, lane_tp[lane], lane_conv[lane], st);
-        if (rc) return rc;
         lane = (lane + 1) % nl;
     }
+    // join every lane, also after a failure: the context stream must not run
+    // later work on the shared workspace before a lane is done with it
     if (nl > 1)
         for (int k = 0; k < nl; k++) {
-            HIPCK(hipEventRecord(c->side_ev[k], c->side[k]));
-            HIPCK(hipStreamWaitEvent(c->stream, c->side_ev[k], 0));
+            hipError_t e = hipEventRecord(c->side_ev[k], c->side[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->side_ev[k], 0);
+            if (e != hipSuccess && rc == RBK_OK) rc = fail(RBK_EDEVICE, std::string("lane join: ") + hipGetErrorString(e));
         }
-    return RBK_OK;
+    return rc;
 }
 
 extern "C" int rbk_rotate_hoisted(rbk_ctx *c, const uint64_t *ct, const int64_t *ks, int n, uint64_t *outs, int level)

@@ -108,6 +108,9 @@ extern "C" int rbk_mult_relin_rescale_list(rbk_ctx *c, const uint64_t *d_a, cons
         Lm = std::max(Lm, levels[i]);
     }
     const size_t N = c->N, nP = c->nP, L1m = Lm + 1, Em = L1m + nP;
+    if (ranges_overlap(d_a, (size_t)count * 2 * L1m * N, d_out, (size_t)count * 2 * Lm * N) ||
+        ranges_overlap(d_b, (size_t)count * 2 * L1m * N, d_out, (size_t)count * 2 * Lm * N))
+        return rbk_set_error(RBK_EINVAL, "inputs and output overlap");
     const size_t betam = (L1m + c->alpha - 1) / c->alpha;
     // ModUp tables of every level in the batch (built on first use)
     std::vector<ListCt> cts((size_t)count);

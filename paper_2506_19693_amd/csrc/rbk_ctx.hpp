@@ -259,6 +259,8 @@ int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d, long 
 // out = Rot_g of count contiguous ciphertexts [count][2][l+1][N]
 int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g);
 int rbk_set_error(int code, const char *msg);
+// true when [a, a + a_words) and [b, b + b_words) share a word
+bool ranges_overlap(const u64 *a, size_t a_words, const u64 *b, size_t b_words);
 
 // ---- batches of uneven level (kernels.hip, list.hip) ----
 // Per-ciphertext entry of a batch whose ciphertexts differ in level: the

@@ -320,3 +320,9 @@ def test_errors_are_reported():
         d.rescale(up(p, p.rand_ct(0), 0), 0)   # nothing to drop at level 0
     with pytest.raises(RbkError):
         d.mult_relin(A, A, 9)
+    # stride-changing calls refuse overlapping input and output
+    As = A[None].clone()
+    with pytest.raises(RbkError):
+        d.rescale_batch(As, 2, out=As)
+    with pytest.raises(RbkError):
+        d.mult_relin_rescale_list(As, As.clone(), [2], out=As)
