@@ -205,6 +205,18 @@ int rbk_rotate_hoisted(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, in
 int rbk_mult_relin_batch(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level, int count);
 /* d_ct: [count][2][l+1][N] -> d_out: [count][2][l][N]; no overlap (RBK_EINVAL) */
 int rbk_rescale_batch(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level, int count);
+/* For callers that cannot allocate device memory (work recorded under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation and residues as rbk_rescale_batch, with its scratch
+ * (2 x count x (1 + level) x N words) taken from a fixed device array of
+ * RBK_NOALLOC_SCRATCH_BYTES that each GPU holds from the first context
+ * created on it until the process ends.  The call allocates nothing (no
+ * hipMalloc / hipFree, no library allocation).  Errors: RBK_EINVAL when the
+ * scratch would exceed the array (or d_ct and d_out overlap), RBK_ESTATE while
+ * per-kernel timers are on.  All calls on one GPU share the array: calls whose
+ * work overlaps in time on that GPU (other streams, other threads) race. */
+#define RBK_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int rbk_rescale_batch_noalloc(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_out, int level, int count);
 /* d_ct: [count][2][l+1][N] -> d_outs: [count][n][2][l+1][N].  The
  * rotations' ModDowns run on the side streams set by rbk_set_lanes; the
  * call's work is complete, as for every call, once the context stream

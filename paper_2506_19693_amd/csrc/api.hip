@@ -469,6 +469,10 @@ extern "C" int rbk_ctx_create(const rbk_params *p, rbk_ctx **out)
         return fail(RBK_EINVAL, "no NTT-friendly prime for a requested bit size (need log_n+2 <= bits <= 60)");
     }
     (void)hipGetDevice(&c->device);
+    if (int rc0 = noalloc_setup(c->device)) {
+        delete c;
+        return rc0;
+    }
     c->logN = (int)p->log_n;
     c->N = (size_t)1 << c->logN;
     c->nQ = (int)p->n_q;
@@ -1058,7 +1062,12 @@ extern "C" int rbk_mult_relin(rbk_ctx *c, const uint64_t *a, const uint64_t *b, 
     return rbk_mult_relin_batch(c, a, b, out, level, 1);
 }
 
-extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, int level, int count)
+size_t rescale_ws_words(const rbk_ctx *c, int level, int count)
+{
+    return 2 * (size_t)count * c->N * (1 + (size_t)level);
+}
+
+int rescale_check(rbk_ctx *c, const u64 *ct, u64 *out, int level, int count)
 {
     if (!c || !ct || !out || count < 1) return fail(RBK_EINVAL, "bad argument");
     if (check_level(c, level, 1)) return RBK_ELEVEL;
@@ -1067,7 +1076,12 @@ extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, 
     // overwrite limbs that others still read
     if (ranges_overlap(ct, (size_t)count * 2 * L1 * N, out, (size_t)count * 2 * level * N))
         return fail(RBK_EINVAL, "rescale: input and output overlap");
-    WS(ws, 2 * count * N + 2 * count * level * N);
+    return RBK_OK;
+}
+
+int rescale_run(rbk_ctx *c, const u64 *ct, u64 *out, int level, int count, u64 *ws)
+{
+    const size_t N = c->N, L1 = level + 1;
     u64 *last = ws, *lifted = ws + 2 * count * N;
     HIPCK(ntt_inverse_from_launch(c, ct + (size_t)level * N, (long)(L1 * N), last, (long)N, 2 * count, 1,
                                   LimbMap{level, c->nQ, c->nQ}, c->stream));
@@ -1078,6 +1092,14 @@ extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, 
     }
     HIPCK_LAUNCH();
     return RBK_OK;
+}
+
+extern "C" int rbk_rescale_batch(rbk_ctx *c, const uint64_t *ct, uint64_t *out, int level, int count)
+{
+    int rc = rescale_check(c, ct, out, level, count);
+    if (rc) return rc;
+    WS(ws, rescale_ws_words(c, level, count));
+    return rescale_run(c, ct, out, level, count, ws);
 }
 
 extern "C" int rbk_rescale(rbk_ctx *c, const uint64_t *ct, uint64_t *out, int level)

@@ -261,6 +261,14 @@ int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u6
 int rbk_set_error(int code, const char *msg);
 // true when [a, a + a_words) and [b, b + b_words) share a word
 bool ranges_overlap(const u64 *a, size_t a_words, const u64 *b, size_t b_words);
+// rescale pieces: workspace words, argument checks, and the launches on a
+// given workspace of rescale_ws_words() words
+size_t rescale_ws_words(const rbk_ctx *c, int level, int count);
+int rescale_check(rbk_ctx *c, const u64 *ct, u64 *out, int level, int count);
+int rescale_run(rbk_ctx *c, const u64 *ct, u64 *out, int level, int count, u64 *ws);
+// allocation-free entry points: looks up the device's scratch array (once per
+// device, with that device current)
+int noalloc_setup(int device);
 
 // ---- batches of uneven level (kernels.hip, list.hip) ----
 // Per-ciphertext entry of a batch whose ciphertexts differ in level: the

@@ -157,6 +157,7 @@ SIGNATURES = {
     "rbk_rotate_hoisted": (ci, [vp, vp, i64p, ci, vp, ci]),
     "rbk_mult_relin_batch": (ci, [vp, vp, vp, vp, ci, ci]),
     "rbk_rescale_batch": (ci, [vp, vp, vp, ci, ci]),
+    "rbk_rescale_batch_noalloc": (ci, [vp, vp, vp, ci, ci]),
     "rbk_ntt_list": (ci, [vp, ctypes.POINTER(RbkNttItem), ci, ci]),
     "rbk_mult_relin_rescale_list": (ci, [vp, vp, vp, vp, ctypes.POINTER(ci), ci]),
     "rbk_rotate_hoisted_batch": (ci, [vp, vp, i64p, ci, vp, ci, ci]),
@@ -670,6 +671,13 @@ class Context:
         count = ct.shape[0]
         out = self.empty_ct(level - 1, count) if out is None else out
         _check(self.lib.rbk_rescale_batch(self.h, _ptr(ct), _ptr(out), level, count))
+        return out
+
+    def rescale_batch_noalloc(self, ct, level, out):
+        """rescale_batch with the library's fixed scratch array (no device
+        allocation; out must be given)."""
+        count = ct.shape[0]
+        _check(self.lib.rbk_rescale_batch_noalloc(self.h, _ptr(ct), _ptr(out), level, count))
         return out
 
     def mult_relin_rescale_list(self, a, b, levels, out=None):
