@@ -25,7 +25,9 @@
  *    data (rbk_decode, rbk_key_export, rbk_moduli...), which synchronise.
  *    Device inputs must stay valid until the stream reaches the call.
  *  - A context is not thread-safe.  Scales are tracked by the caller: these
- *    functions only transform residues.
+ *    functions only transform residues, except the *_scaled additions (which
+ *    check them), the bootstrap (which returns its output scale) and the MLP
+ *    (which keeps each state ciphertext's scale).
  *
  * Errors: 0 on success, else a negative RBK_E* code; rbk_last_error()
  * returns a message for the calling thread.  No C++ exception crosses the ABI.
@@ -105,8 +107,9 @@ int rbk_reserve(rbk_ctx *ctx, int level, int count);
 int rbk_ntt(rbk_ctx *ctx, uint64_t *d_data, int count, const int *prime_idx, int n_limbs, int inverse);
 
 /* ---- keys (Section 3: sk/pk; rotation keys, one per index) -------------- */
-/* Every random input is drawn by the caller and passed in, so that the same
- * draws can be replayed elsewhere.  All host arrays, coefficient domain. */
+/* These calls take every random input from the caller, so that the same
+ * draws can be replayed elsewhere (rbk_keygen below draws them itself).
+ * All host arrays, coefficient domain. */
 
 /* s[N]: secret key coefficients (ternary). */
 int rbk_set_secret(rbk_ctx *ctx, const int64_t *s);
@@ -126,6 +129,48 @@ uint64_t rbk_galois_elt(const rbk_ctx *ctx, int64_t k);
 /* Copy a key to the host, coefficient domain, [beta][2][n_q+n_p][N]
  * (g = 0 selects the relinearisation key). */
 int rbk_key_export(rbk_ctx *ctx, uint64_t g, uint64_t *out);
+
+/* ---- keys and encryption from one seed (seeded sampling) ---------------- */
+/* The randomness of Section 3's key generation and encryption (secret,
+ * uniform public polynomials, added noise) drawn inside the library from a
+ * 64-bit seed, so a client needs no random source of its own.  Keystream:
+ * the ChaCha20 block function of RFC 8439 with key (seed low 32 bits, seed
+ * high 32 bits, 0 x 6), block counter, nonce (purpose, id, sub):
+ *   secret, uniform ternary   (1, 0, 0); exactly h non-zeros: (1, 1, 0)
+ *   public key a limb t / e   (2, 0, t) / (3, 0, 0)
+ *   switching key, element g (0 = relinearisation), digit j:
+ *                 a limb t    (4, g, j * 2^16 + t);  e  (5, g, j)
+ *   encryption number i       v (6, i_lo, i_hi), e0 (7, ...), e1 (8, ...)
+ * Coefficient j of a polynomial reads the block at counter j (then j + N,
+ * j + 2N, ... if that block gives no value): uniform mod q = the first of
+ * its eight little-endian 64-bit words, masked to bitlen(q) bits, that is
+ * below q; ternary = the first of its 256 2-bit fields (low bits of word 0
+ * first) that is not 3, with 0, 1, 2 -> 0, +1, -1; Gaussian (sigma = 3.2,
+ * |x| <= 19) = the least m with (w >> 1) < T[m], w the first 64-bit word,
+ * T[m] = floor(2^63 P(|x| <= m)) (T[19] = 2^63), negative when m > 0 and
+ * bit 0 of w is set.  Secret with h non-zeros: 32-bit stream words in
+ * counter order, two per draw, position = first & (N-1), sign = bit 0 of the
+ * second (set: -1), taken positions skipped, until h are set. */
+
+/* Secret (uniform ternary when secret_hw = 0, else exactly secret_hw
+ * non-zeros), public key, relinearisation key and one Galois key for each
+ * rotation step in rot_steps[n_rot] (host) plus the conjugation when conj is
+ * non-zero; repeated elements and steps that are multiples of N/2 are
+ * skipped.  Replaces keys of the same elements.  Synchronises. */
+int rbk_keygen(rbk_ctx *ctx, uint64_t seed, int secret_hw, const int64_t *rot_steps, int n_rot, int conj);
+/* rbk_encrypt with (v, e0, e1) drawn from (seed, index).  Asynchronous. */
+int rbk_encrypt_seeded(rbk_ctx *ctx, const uint64_t *d_pt, int level, uint64_t seed, uint64_t index, uint64_t *d_ct);
+/* host out[20]: the cumulative table T of the Gaussian sampler. */
+int rbk_gauss_table(uint64_t *out);
+
+/* ---- ciphertext export / import ---------------------------------------- */
+/* Copy npoly polynomials at `level` (a ciphertext: npoly = 2) between device
+ * memory (NTT domain) and host memory (coefficient domain,
+ * [npoly][level+1][N] canonical residues).  Export synchronises; import
+ * checks every residue (RBK_EINVAL if one is not below its prime; d_ct is
+ * then unspecified) and transforms d_ct in place. */
+int rbk_ct_export(rbk_ctx *ctx, const uint64_t *d_ct, int level, int npoly, uint64_t *out);
+int rbk_ct_import(rbk_ctx *ctx, const uint64_t *in, int level, int npoly, uint64_t *d_ct);
 
 /* ---- encoding and encryption ------------------------------------------- */
 
@@ -160,6 +205,19 @@ int rbk_add_plain(rbk_ctx *ctx, const uint64_t *d_ct, const uint64_t *d_pt, uint
 int rbk_mul_scalar(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *scal, uint64_t *d_out, int level, int npoly);
 /* ct + the constant polynomial with residues scal[i] (host, < q_i) */
 int rbk_add_scalar(rbk_ctx *ctx, const uint64_t *d_ct, const uint64_t *scal, uint64_t *d_out, int level);
+/* Scale-checked forms for callers that pass each operand's scale: the
+ * slot-wise sum or difference (eqs. add / sub) is only the sum of the
+ * messages when both operands carry the same scale, so these return
+ * RBK_ESCALE unless |scale_a / scale_b - 1| < 2^-30 (RBK_EINVAL for a scale
+ * that is not positive) and otherwise compute rbk_add / rbk_sub (one
+ * ciphertext, npoly = 2) or rbk_add_plain, with *scale_out = scale_a
+ * (scale_out may be NULL). */
+int rbk_add_scaled(rbk_ctx *ctx, const uint64_t *d_a, double scale_a, const uint64_t *d_b, double scale_b,
+                   uint64_t *d_out, int level, double *scale_out);
+int rbk_sub_scaled(rbk_ctx *ctx, const uint64_t *d_a, double scale_a, const uint64_t *d_b, double scale_b,
+                   uint64_t *d_out, int level, double *scale_out);
+int rbk_add_plain_scaled(rbk_ctx *ctx, const uint64_t *d_ct, double scale_ct, const uint64_t *d_pt, double scale_pt,
+                         uint64_t *d_out, int level, double *scale_out);
 /* (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); d_out[3][l+1][N] */
 int rbk_tensor(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out, int level);
 
@@ -356,7 +414,8 @@ typedef struct {
 
 /* Validate the description against the context's N and create the step's
  * runner (device memory is taken on the first step and kept).  *out owned by
- * the caller; destroy it before its context. */
+ * the caller; destroy it before its context (rbk_ctx_destroy returns
+ * RBK_ESTATE while MLPs of the context are alive). */
 int rbk_mlp_create(rbk_ctx *ctx, const rbk_mlp_desc *desc, rbk_mlp **out);
 int rbk_mlp_destroy(rbk_mlp *mlp);
 /* info[0] = input tiles, info[1] = state ciphertexts, info[2] = levels one
@@ -371,6 +430,20 @@ int rbk_mlp_rotations(const rbk_mlp *mlp, int64_t *ks, int max);
  * NULL, copies the ciphertext out.  V slots are not read at t = 1. */
 int rbk_mlp_set_state(rbk_mlp *mlp, int idx, const uint64_t *d_ct, int level, double scale);
 int rbk_mlp_get_state(rbk_mlp *mlp, int idx, uint64_t *d_ct, int *level, double *scale);
+/* Float64 weights in and out of the encrypted state (Algorithm 1's W, W*
+ * and the velocities V, V*).  Per block h (0-based index h-1): W[h-1] is
+ * k_{h-1} x k_h and Wstar[h-1] is k_h x o, row-major; V / Vstar the same
+ * shapes (either NULL: zero velocities / not read).  set packs each matrix
+ * into its slot matrix (Section 4.1: RE-blocks hold W in the row-wise
+ * format, tile t taking rows t r .. t r + r - 1, and W* column-wise;
+ * CE-blocks the other way round), encodes it at `level` and scale
+ * 2^log2_scale and encrypts it with randomness drawn from (seed, index =
+ * state slot) (needs the public key), replacing the state.  get decrypts
+ * (needs the secret key), decodes each state ciphertext at its own scale and
+ * unpacks it; NULL arrays are skipped.  Both synchronise. */
+int rbk_mlp_set_weights(rbk_mlp *mlp, const double *const *W, const double *const *Wstar, const double *const *V,
+                        const double *const *Vstar, int level, uint64_t seed);
+int rbk_mlp_get_weights(rbk_mlp *mlp, double *const *W, double *const *Wstar, double *const *V, double *const *Vstar);
 /* Use d_pt[level+1][N] (NTT domain, encoded at scale q_level) as the SumCols
  * mask plaintext at `level` instead of the library's own encoding. */
 int rbk_mlp_set_mask(rbk_mlp *mlp, int level, const uint64_t *d_pt);

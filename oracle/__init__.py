@@ -25,6 +25,7 @@ _LIB = None
 u64p = ctypes.POINTER(ctypes.c_uint64)
 i64p = ctypes.POINTER(ctypes.c_int64)
 intp = ctypes.POINTER(ctypes.c_int)
+u32p = ctypes.POINTER(ctypes.c_uint32)
 
 
 def lib():
@@ -80,6 +81,16 @@ def lib():
             "orc_rotate_hoisted": (None, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(u64p), u64p, u64p, u64p]),
             "orc_modraise": (None, [ctypes.c_void_p, ctypes.c_int, u64p, u64p]),
             "orc_monomial": (None, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, u64p, u64p]),
+            "orc_chacha_quarter": (None, [u32p]),
+            "orc_chacha_block": (None, [u32p, ctypes.c_uint32, u32p, u32p]),
+            "orc_sample_uniform": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint64, ctypes.c_int, u64p]),
+            "orc_sample_ternary": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_int, i64p]),
+            "orc_sample_gauss": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_int, i64p]),
+            "orc_gauss_table": (None, [u64p]),
+            "orc_sample_ternary_hw": (None, [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, i64p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -156,6 +167,55 @@ def negacyclic_schoolbook(logN, q, a, b):
     b, pb = _u(b)
     out = np.zeros_like(a)
     lib().orc_negacyclic_schoolbook(logN, int(q), pa, pb, out.ctypes.data_as(u64p))
+    return out
+
+
+# ---------------------------------------------------------------- seeded sampling (ChaCha20, RFC 8439)
+
+P_SECRET, P_PK_A, P_PK_E, P_KEY_A, P_KEY_E, P_ENC_V, P_ENC_E0, P_ENC_E1 = range(1, 9)
+
+
+def chacha_quarter(x4):
+    a = (ctypes.c_uint32 * 4)(*[int(v) for v in x4])
+    lib().orc_chacha_quarter(a)
+    return [int(v) for v in a]
+
+
+def chacha_block(key8, counter, nonce3):
+    k = (ctypes.c_uint32 * 8)(*[int(v) for v in key8])
+    n = (ctypes.c_uint32 * 3)(*[int(v) for v in nonce3])
+    out = (ctypes.c_uint32 * 16)()
+    lib().orc_chacha_block(k, int(counter), n, out)
+    return [int(v) for v in out]
+
+
+def sample_uniform(seed, purpose, ident, sub, q, logN):
+    out = np.zeros(1 << logN, dtype=np.uint64)
+    lib().orc_sample_uniform(int(seed), purpose, int(ident), int(sub), int(q), logN, out.ctypes.data_as(u64p))
+    return out
+
+
+def sample_ternary(seed, purpose, ident, sub, logN):
+    out = np.zeros(1 << logN, dtype=np.int64)
+    lib().orc_sample_ternary(int(seed), purpose, int(ident), int(sub), logN, out.ctypes.data_as(i64p))
+    return out
+
+
+def sample_gauss(seed, purpose, ident, sub, logN):
+    out = np.zeros(1 << logN, dtype=np.int64)
+    lib().orc_sample_gauss(int(seed), purpose, int(ident), int(sub), logN, out.ctypes.data_as(i64p))
+    return out
+
+
+def gauss_table():
+    out = np.zeros(20, dtype=np.uint64)
+    lib().orc_gauss_table(out.ctypes.data_as(u64p))
+    return [int(x) for x in out]
+
+
+def sample_ternary_hw(seed, logN, h):
+    out = np.zeros(1 << logN, dtype=np.int64)
+    lib().orc_sample_ternary_hw(int(seed), logN, int(h), out.ctypes.data_as(i64p))
     return out
 
 
@@ -429,6 +489,33 @@ class Oracle:
         out = np.zeros_like(a)
         lib().orc_monomial(self._h, level, a.size // ((level + 1) * self.N), int(e), pa, out.ctypes.data_as(u64p))
         return out
+
+    # ------------------------------------------------------------ keys and encryption from one seed
+    def seeded_secret(self, seed, hw=0):
+        """hw = 0: uniform ternary; hw > 0: exactly hw non-zero coefficients."""
+        if hw:
+            return sample_ternary_hw(seed, self.logN, hw)
+        return sample_ternary(seed, P_SECRET, 0, 0, self.logN)
+
+    def seeded_key_randomness(self, seed, g):
+        """(a, e) of the switching key with Galois element g (0 = relinearisation):
+        a limb t of digit j from nonce (KEY_A, g, j * 2^16 + t), e of digit j from
+        (KEY_E, g, j)."""
+        nT = self.nQ + self.nP
+        a = np.stack([np.stack([sample_uniform(seed, P_KEY_A, g, (j << 16) | t, self.moduli[t], self.logN)
+                                for t in range(nT)]) for j in range(self.beta)])
+        e = np.stack([sample_gauss(seed, P_KEY_E, g, j, self.logN) for j in range(self.beta)])
+        return a, e
+
+    def seeded_public_randomness(self, seed):
+        a = np.stack([sample_uniform(seed, P_PK_A, 0, t, self.moduli[t], self.logN) for t in range(self.nQ)])
+        return a, sample_gauss(seed, P_PK_E, 0, 0, self.logN)
+
+    def seeded_encryption_randomness(self, seed, index):
+        """(v, e0, e1) of encryption number `index` (64-bit: low word = id, high word = sub)."""
+        lo, hi = int(index) & 0xFFFFFFFF, int(index) >> 32
+        return (sample_ternary(seed, P_ENC_V, lo, hi, self.logN), sample_gauss(seed, P_ENC_E0, lo, hi, self.logN),
+                sample_gauss(seed, P_ENC_E1, lo, hi, self.logN))
 
     def drop(self, level_from, level_to, ct):
         """Keep limbs 0..level_to of every polynomial (the value is unchanged)."""

@@ -37,6 +37,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 typedef uint64_t u64;
 typedef int64_t i64;
@@ -854,4 +855,177 @@ void orc_monomial(const orc_ctx *c, int level, int npoly, u64 e, const u64 *in, 
                 else o[d - N] = negm(a[k], q);
             }
         }
+}
+
+/* ------------------------------------------------------------------ */
+/* seeded sampling                                                    */
+/* ------------------------------------------------------------------ */
+
+/* Every random quantity of key generation and encryption (Section 3: the
+ * secret, the uniform public polynomials, the added noise) can be drawn
+ * from one 64-bit seed.  The paper does not say how; the reading used here:
+ *
+ *  - keystream: the ChaCha20 block function of RFC 8439 (20 rounds), key =
+ *    (seed low 32 bits, seed high 32 bits, 0, 0, 0, 0, 0, 0), 32-bit block
+ *    counter, nonce = (purpose, id, sub) naming the quantity;
+ *  - per coefficient j of an N-coefficient polynomial: the block with
+ *    counter j (then j + N, j + 2N, ... if that block yields no value);
+ *  - uniform mod q: the block's eight little-endian 64-bit words, each masked
+ *    to bitlen(q) bits; the first below q;
+ *  - uniform ternary: the block's 256 2-bit fields (word 0 bits 1:0 first);
+ *    the first that is not 3, with 0, 1, 2 meaning 0, +1, -1;
+ *  - discrete Gaussian, sigma = 3.2, support |x| <= 19: word w = the block's
+ *    first 64-bit word; u = w >> 1 is compared with the cumulative table
+ *    T[m] = floor(2^63 P(|x| <= m)) (T[19] = 2^63), magnitude = the least m
+ *    with u < T[m], negative when m > 0 and bit 0 of w is set;
+ *  - secret with exactly h non-zero coefficients: 32-bit words of the
+ *    stream (counters 0, 1, ... in order) taken two at a time, position =
+ *    first & (N - 1), sign = bit 0 of the second (set = -1); a position
+ *    already taken is skipped, until h are set. */
+
+#define ORC_P_SECRET 1u
+#define ORC_P_PK_A 2u
+#define ORC_P_PK_E 3u
+#define ORC_P_KEY_A 4u
+#define ORC_P_KEY_E 5u
+#define ORC_P_ENC_V 6u
+#define ORC_P_ENC_E0 7u
+#define ORC_P_ENC_E1 8u
+
+static uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
+
+static void quarter(uint32_t *x, int a, int b, int c, int d)
+{
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 16);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 12);
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 8);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 7);
+}
+
+void orc_chacha_quarter(uint32_t *x4)
+{
+    quarter(x4, 0, 1, 2, 3);
+}
+
+/* RFC 8439 Section 2.3: the state is the four constants, the eight key
+ * words, the counter and the three nonce words; ten double rounds (column
+ * rounds then diagonal rounds); the output adds the input state. */
+void orc_chacha_block(const uint32_t *key8, uint32_t counter, const uint32_t *nonce3, uint32_t *out16)
+{
+    uint32_t in[16], x[16];
+    in[0] = 0x61707865u; in[1] = 0x3320646eu; in[2] = 0x79622d32u; in[3] = 0x6b206574u;
+    for (int i = 0; i < 8; i++) in[4 + i] = key8[i];
+    in[12] = counter;
+    for (int i = 0; i < 3; i++) in[13 + i] = nonce3[i];
+    for (int i = 0; i < 16; i++) x[i] = in[i];
+    for (int r = 0; r < 10; r++) {
+        quarter(x, 0, 4, 8, 12); quarter(x, 1, 5, 9, 13); quarter(x, 2, 6, 10, 14); quarter(x, 3, 7, 11, 15);
+        quarter(x, 0, 5, 10, 15); quarter(x, 1, 6, 11, 12); quarter(x, 2, 7, 8, 13); quarter(x, 3, 4, 9, 14);
+    }
+    for (int i = 0; i < 16; i++) out16[i] = x[i] + in[i];
+}
+
+static void seed_block(u64 seed, uint32_t purpose, uint32_t id, uint32_t sub, uint32_t counter, uint32_t *out16)
+{
+    uint32_t key[8] = {(uint32_t)seed, (uint32_t)(seed >> 32), 0, 0, 0, 0, 0, 0};
+    uint32_t nonce[3] = {purpose, id, sub};
+    orc_chacha_block(key, counter, nonce, out16);
+}
+
+static int bitlen(u64 q)
+{
+    int b = 0;
+    while (b < 64 && (q >> b)) b++;
+    return b;
+}
+
+void orc_sample_uniform(u64 seed, uint32_t purpose, uint32_t id, uint32_t sub, u64 q, int logN, u64 *out)
+{
+    size_t N = (size_t)1 << logN;
+    int b = bitlen(q);
+    u64 mask = b >= 64 ? ~(u64)0 : (((u64)1 << b) - 1);
+    uint32_t blk[16];
+    for (size_t j = 0; j < N; j++) {
+        for (uint32_t ctr = (uint32_t)j;; ctr += (uint32_t)N) {
+            seed_block(seed, purpose, id, sub, ctr, blk);
+            int found = 0;
+            for (int t = 0; t < 8 && !found; t++) {
+                u64 w = ((u64)blk[2 * t] | ((u64)blk[2 * t + 1] << 32)) & mask;
+                if (w < q) { out[j] = w; found = 1; }
+            }
+            if (found) break;
+        }
+    }
+}
+
+void orc_sample_ternary(u64 seed, uint32_t purpose, uint32_t id, uint32_t sub, int logN, i64 *out)
+{
+    size_t N = (size_t)1 << logN;
+    uint32_t blk[16];
+    for (size_t j = 0; j < N; j++) {
+        for (uint32_t ctr = (uint32_t)j;; ctr += (uint32_t)N) {
+            seed_block(seed, purpose, id, sub, ctr, blk);
+            int found = 0;
+            for (int f = 0; f < 256 && !found; f++) {
+                uint32_t v = (blk[f / 16] >> (2 * (f % 16))) & 3u;
+                if (v != 3) { out[j] = v == 0 ? 0 : (v == 1 ? 1 : -1); found = 1; }
+            }
+            if (found) break;
+        }
+    }
+}
+
+/* The cumulative table of the magnitude of the discrete Gaussian:
+ * rho(x) = exp(-x^2 / (2 sigma^2)), P(|x| = 0) = rho(0) / Z,
+ * P(|x| = m) = 2 rho(m) / Z, Z = rho(0) + 2 sum_{m=1}^{19} rho(m). */
+void orc_gauss_table(u64 *T20)
+{
+    const double sigma = 3.2;
+    double rho[20], Z = 0.0, acc = 0.0;
+    for (int m = 0; m < 20; m++) rho[m] = exp(-(double)(m * m) / (2.0 * sigma * sigma));
+    for (int m = 0; m < 20; m++) Z += m == 0 ? rho[m] : 2.0 * rho[m];
+    for (int m = 0; m < 19; m++) {
+        acc += m == 0 ? rho[m] : 2.0 * rho[m];
+        T20[m] = (u64)floor(ldexp(acc / Z, 63));
+    }
+    T20[19] = (u64)1 << 63;
+}
+
+void orc_sample_gauss(u64 seed, uint32_t purpose, uint32_t id, uint32_t sub, int logN, i64 *out)
+{
+    size_t N = (size_t)1 << logN;
+    u64 T[20];
+    uint32_t blk[16];
+    orc_gauss_table(T);
+    for (size_t j = 0; j < N; j++) {
+        seed_block(seed, purpose, id, sub, (uint32_t)j, blk);
+        u64 w = (u64)blk[0] | ((u64)blk[1] << 32);
+        u64 u = w >> 1;
+        int m = 0;
+        while (!(u < T[m])) m++;
+        out[j] = (m > 0 && (w & 1)) ? -(i64)m : (i64)m;
+    }
+}
+
+void orc_sample_ternary_hw(u64 seed, int logN, int h, i64 *out)
+{
+    size_t N = (size_t)1 << logN;
+    uint32_t blk[16], ctr = 0;
+    int pos = 16, set = 0;
+    uint32_t pair[2];
+    memset(out, 0, N * sizeof(i64));
+    if (h > (int)N) h = (int)N;
+    while (set < h) {
+        for (int k = 0; k < 2; k++) {
+            if (pos == 16) {
+                seed_block(seed, ORC_P_SECRET, 1, 0, ctr++, blk);
+                pos = 0;
+            }
+            pair[k] = blk[pos++];
+        }
+        size_t p = pair[0] & (uint32_t)(N - 1);
+        if (out[p] != 0) continue;
+        out[p] = (pair[1] & 1) ? -1 : 1;
+        set++;
+    }
 }

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <cmath>
 #include <vector>
 
 #include "../../include/rbk.h"
@@ -495,6 +496,7 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
 {
     if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c) return RBK_OK;
+    if (c->live_mlps > 0) return fail(RBK_ESTATE, "destroy the MLPs built on this context first");
     (void)hipStreamSynchronize(c->stream);
     boot_free(c);
     for (int k = 0; k < KC_COUNT; k++)
@@ -603,14 +605,22 @@ extern "C" int rbk_ntt(rbk_ctx *c, uint64_t *d, int count, const int *idx, int n
 
 static LimbMap allmap(const rbk_ctx *c) { return LimbMap{0, c->nQ, c->nQ}; }  // identity over every prime
 
-extern "C" int rbk_set_secret(rbk_ctx *c, const int64_t *s)
+// Randomness drawn inside the library (seeded sampling): the key stream's
+// seed and the id that names the key or encryption.
+struct Seeded {
+    u64 seed;
+    u32 id;
+    u32 sub;
+};
+
+// the secret from host coefficients s, or (s null) uniform ternary from sd
+static int set_secret(rbk_ctx *c, const int64_t *s, const Seeded *sd)
 {
-    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
-    if (!c || !s) return fail(RBK_EINVAL, "null argument");
     const size_t N = c->N;
     if (!c->d_s && dev_alloc(c, &c->d_s, c->nT * N)) return RBK_ENOMEM;
     WS(ws, N);
-    HIPCK(hipMemcpyAsync(ws, s, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    if (s) HIPCK(hipMemcpyAsync(ws, s, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    else sample_small_launch(c, (i64 *)ws, sd->seed, RBK_SAMPLE_SECRET, 0, 0, 0, c->stream);
     signed_to_limbs_launch(c, (const i64 *)ws, c->d_s, 1, c->nT, allmap(c), c->stream);
     ntt_launch(c, c->d_s, (long)c->nT * N, 1, c->nT, allmap(c), false, c->stream);
     HIPCK_LAUNCH();
@@ -618,19 +628,29 @@ extern "C" int rbk_set_secret(rbk_ctx *c, const int64_t *s)
     return RBK_OK;
 }
 
-extern "C" int rbk_keygen_public(rbk_ctx *c, const uint64_t *a, const int64_t *e)
+extern "C" int rbk_set_secret(rbk_ctx *c, const int64_t *s)
 {
     if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
-    if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
-    if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
+    if (!c || !s) return fail(RBK_EINVAL, "null argument");
+    return set_secret(c, s, nullptr);
+}
+
+// pk = (-a s + e, a) from host (a, e), or (a null) sampled from sd
+static int keygen_public(rbk_ctx *c, const uint64_t *a, const int64_t *e, const Seeded *sd)
+{
     const size_t N = c->N, nQ = c->nQ;
     if (!c->d_pk && dev_alloc(c, &c->d_pk, 2 * nQ * N)) return RBK_ENOMEM;
     WS(ws, 2 * nQ * N + N);
     u64 *ea = ws, *ee = ws + nQ * N;  // e limbs
     i64 *eraw = (i64 *)(ws + 2 * nQ * N);
     u64 *pk1 = c->d_pk + nQ * N;
-    HIPCK(hipMemcpyAsync(pk1, a, nQ * N * sizeof(u64), hipMemcpyHostToDevice, c->stream));
-    HIPCK(hipMemcpyAsync(eraw, e, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    if (a) {
+        HIPCK(hipMemcpyAsync(pk1, a, nQ * N * sizeof(u64), hipMemcpyHostToDevice, c->stream));
+        HIPCK(hipMemcpyAsync(eraw, e, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    } else {
+        sample_uniform_launch(c, pk1, (int)nQ, sd->seed, RBK_SAMPLE_PK_A, 0, 0, c->stream);
+        sample_small_launch(c, eraw, sd->seed, RBK_SAMPLE_PK_E, 0, 0, 1, c->stream);
+    }
     ntt_launch(c, pk1, (long)nQ * N, 1, (int)nQ, qmap(c), false, c->stream);
     signed_to_limbs_launch(c, eraw, ee, 1, (int)nQ, qmap(c), c->stream);
     ntt_launch(c, ee, (long)nQ * N, 1, (int)nQ, qmap(c), false, c->stream);
@@ -641,8 +661,19 @@ extern "C" int rbk_keygen_public(rbk_ctx *c, const uint64_t *a, const int64_t *e
     return RBK_OK;
 }
 
-// generic switching key: s_from NTT domain [nT][N] (device)
-static int keygen_switch(rbk_ctx *c, DevKey &k, const u64 *s_from, const uint64_t *a, const int64_t *e)
+extern "C" int rbk_keygen_public(rbk_ctx *c, const uint64_t *a, const int64_t *e)
+{
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
+    if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
+    return keygen_public(c, a, e, nullptr);
+}
+
+// generic switching key: s_from NTT domain [nT][N] (device); (a, e) from the
+// host, or (a null) sampled: limb t of digit j from nonce (KEY_A, id, j 2^16 + t),
+// the error of digit j from (KEY_E, id, j)
+static int keygen_switch(rbk_ctx *c, DevKey &k, const u64 *s_from, const uint64_t *a, const int64_t *e,
+                         const Seeded *sd = nullptr)
 {
     const size_t N = c->N, nT = c->nT, beta = c->beta;
     if (!k.data && dev_alloc(c, &k.data, beta * 2 * nT * N)) return RBK_ENOMEM;
@@ -651,8 +682,15 @@ static int keygen_switch(rbk_ctx *c, DevKey &k, const u64 *s_from, const uint64_
     i64 *eraw = (i64 *)(ws + 2 * beta * nT * N);
     u64 *sf = ws + 2 * beta * nT * N + beta * N;
     HIPCK(hipMemcpyAsync(sf, s_from, nT * N * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
-    HIPCK(hipMemcpyAsync(da, a, beta * nT * N * sizeof(u64), hipMemcpyHostToDevice, c->stream));
-    HIPCK(hipMemcpyAsync(eraw, e, beta * N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    if (a) {
+        HIPCK(hipMemcpyAsync(da, a, beta * nT * N * sizeof(u64), hipMemcpyHostToDevice, c->stream));
+        HIPCK(hipMemcpyAsync(eraw, e, beta * N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    } else {
+        for (size_t j = 0; j < beta; j++) {
+            sample_uniform_launch(c, da + j * nT * N, (int)nT, sd->seed, RBK_SAMPLE_KEY_A, sd->id, (u32)j, c->stream);
+            sample_small_launch(c, eraw + j * N, sd->seed, RBK_SAMPLE_KEY_E, sd->id, (u32)j, 1, c->stream);
+        }
+    }
     ntt_launch(c, da, (long)nT * N, (int)beta, (int)nT, allmap(c), false, c->stream);
     signed_to_limbs_launch(c, eraw, de, (int)beta, (int)nT, allmap(c), c->stream);
     ntt_launch(c, de, (long)nT * N, (int)beta, (int)nT, allmap(c), false, c->stream);
@@ -662,19 +700,24 @@ static int keygen_switch(rbk_ctx *c, DevKey &k, const u64 *s_from, const uint64_
     return RBK_OK;
 }
 
+static int keygen_relin(rbk_ctx *c, const uint64_t *a, const int64_t *e, const Seeded *sd)
+{
+    u64 *s2 = nullptr;
+    if (dev_alloc(c, &s2, c->nT * c->N)) return RBK_ENOMEM;
+    ew_launch(c, EW_MUL, c->d_s, c->d_s, s2, 1, c->nT, allmap(c), c->stream);
+    int rc = keygen_switch(c, c->relin, s2, a, e, sd);
+    (void)hipStreamSynchronize(c->stream);
+    dev_release(c, s2);
+    c->relin.g = 0;
+    return rc;
+}
+
 extern "C" int rbk_keygen_relin(rbk_ctx *c, const uint64_t *a, const int64_t *e)
 {
     if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
     if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
     if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
-    u64 *s2 = nullptr;
-    if (dev_alloc(c, &s2, c->nT * c->N)) return RBK_ENOMEM;
-    ew_launch(c, EW_MUL, c->d_s, c->d_s, s2, 1, c->nT, allmap(c), c->stream);
-    int rc = keygen_switch(c, c->relin, s2, a, e);
-    (void)hipStreamSynchronize(c->stream);
-    dev_release(c, s2);
-    c->relin.g = 0;
-    return rc;
+    return keygen_relin(c, a, e, nullptr);
 }
 
 extern "C" uint64_t rbk_galois_elt(const rbk_ctx *c, int64_t k)
@@ -685,21 +728,55 @@ extern "C" uint64_t rbk_galois_elt(const rbk_ctx *c, int64_t k)
     return h_pow(5, (u64)r, 2 * c->N);
 }
 
-extern "C" int rbk_keygen_galois(rbk_ctx *c, uint64_t g, const uint64_t *a, const int64_t *e)
+static int keygen_galois(rbk_ctx *c, uint64_t g, const uint64_t *a, const int64_t *e, const Seeded *sd)
 {
-    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
-    if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
-    if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
     if (g % 2 == 0 || g >= 2 * c->N || g == 1) return fail(RBK_EINVAL, "Galois element must be odd, in (1, 2N)");
     u64 *sg = nullptr;
     if (dev_alloc(c, &sg, c->nT * c->N)) return RBK_ENOMEM;
     automorph_launch(c, c->d_s, sg, 1, c->nT, g, c->stream);
     DevKey &k = c->gal[g];
     k.g = g;
-    int rc = keygen_switch(c, k, sg, a, e);
+    int rc = keygen_switch(c, k, sg, a, e, sd);
     (void)hipStreamSynchronize(c->stream);
     dev_release(c, sg);
     return rc;
+}
+
+extern "C" int rbk_keygen_galois(rbk_ctx *c, uint64_t g, const uint64_t *a, const int64_t *e)
+{
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if (!c || !a || !e) return fail(RBK_EINVAL, "null argument");
+    if (!c->d_s) return fail(RBK_ENOKEY, "secret key not set");
+    return keygen_galois(c, g, a, e, nullptr);
+}
+
+extern "C" int rbk_keygen(rbk_ctx *c, uint64_t seed, int secret_hw, const int64_t *rot_steps, int n_rot, int conj)
+{
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if (!c || (n_rot > 0 && !rot_steps) || n_rot < 0) return fail(RBK_EINVAL, "bad argument");
+    if (secret_hw < 0 || (size_t)secret_hw > c->N) return fail(RBK_EINVAL, "secret_hw must be in [0, N]");
+    int rc;
+    if (secret_hw > 0) {
+        std::vector<i64> s(c->N);
+        sample_ternary_hw_host(seed, c->logN, secret_hw, s.data());
+        rc = set_secret(c, s.data(), nullptr);
+    } else {
+        const Seeded sd{seed, 0, 0};
+        rc = set_secret(c, nullptr, &sd);
+    }
+    if (rc) return rc;
+    const Seeded sd{seed, 0, 0};
+    if ((rc = keygen_public(c, nullptr, nullptr, &sd))) return rc;
+    if ((rc = keygen_relin(c, nullptr, nullptr, &sd))) return rc;
+    std::vector<u64> gs;
+    for (int i = 0; i < n_rot; i++) gs.push_back(rbk_galois_elt(c, rot_steps[i]));
+    if (conj) gs.push_back(2 * c->N - 1);
+    for (u64 g : gs) {
+        if (g == 1 || c->gal.count(g)) continue;  // rotation by a multiple of N/2, or a repeated element
+        const Seeded sg{seed, (u32)g, 0};
+        if ((rc = keygen_galois(c, g, nullptr, nullptr, &sg))) return rc;
+    }
+    return RBK_OK;
 }
 
 static const DevKey *find_key(const rbk_ctx *c, u64 g)
@@ -775,26 +852,87 @@ extern "C" int rbk_decode(rbk_ctx *c, const uint64_t *d_pt, int level, double sc
     return RBK_OK;
 }
 
-extern "C" int rbk_encrypt(rbk_ctx *c, const uint64_t *d_pt, int level, const int64_t *v, const int64_t *e0,
-                           const int64_t *e1, uint64_t *d_ct)
+// (v, e0, e1) from the host, or (v null) sampled: nonces (ENC_V / ENC_E0 /
+// ENC_E1, index low word, index high word)
+static int encrypt(rbk_ctx *c, const uint64_t *d_pt, int level, const int64_t *v, const int64_t *e0, const int64_t *e1,
+                   const Seeded *sd, uint64_t *d_ct)
 {
-    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
-    if (!c || !d_pt || !v || !e0 || !e1 || !d_ct) return fail(RBK_EINVAL, "null argument");
     if (check_level(c, level)) return RBK_ELEVEL;
     if (!c->d_pk) return fail(RBK_ENOKEY, "public key not generated");
     const size_t N = c->N, L1 = level + 1;
     WS(ws, 3 * N + 3 * L1 * N);
     i64 *raw = (i64 *)ws;
     u64 *lv = ws + 3 * N;
-    HIPCK(hipMemcpyAsync(raw, v, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
-    HIPCK(hipMemcpyAsync(raw + N, e0, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
-    HIPCK(hipMemcpyAsync(raw + 2 * N, e1, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    if (v) {
+        HIPCK(hipMemcpyAsync(raw, v, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+        HIPCK(hipMemcpyAsync(raw + N, e0, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+        HIPCK(hipMemcpyAsync(raw + 2 * N, e1, N * sizeof(i64), hipMemcpyHostToDevice, c->stream));
+    } else {
+        sample_small_launch(c, raw, sd->seed, RBK_SAMPLE_ENC_V, sd->id, sd->sub, 0, c->stream);
+        sample_small_launch(c, raw + N, sd->seed, RBK_SAMPLE_ENC_E0, sd->id, sd->sub, 1, c->stream);
+        sample_small_launch(c, raw + 2 * N, sd->seed, RBK_SAMPLE_ENC_E1, sd->id, sd->sub, 1, c->stream);
+    }
     signed_to_limbs_launch(c, raw, lv, 3, (int)L1, qmap(c), c->stream);
     ntt_launch(c, lv, (long)L1 * N, 3, (int)L1, qmap(c), false, c->stream);
     encrypt_launch(c, d_pt, lv, lv + L1 * N, lv + 2 * L1 * N, d_ct, level, c->stream);
     HIPCK_LAUNCH();
     // the host arrays may be released by the caller on return
+    if (v) HIPCK(hipStreamSynchronize(c->stream));
+    return RBK_OK;
+}
+
+extern "C" int rbk_encrypt(rbk_ctx *c, const uint64_t *d_pt, int level, const int64_t *v, const int64_t *e0,
+                           const int64_t *e1, uint64_t *d_ct)
+{
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if (!c || !d_pt || !v || !e0 || !e1 || !d_ct) return fail(RBK_EINVAL, "null argument");
+    return encrypt(c, d_pt, level, v, e0, e1, nullptr, d_ct);
+}
+
+extern "C" int rbk_encrypt_seeded(rbk_ctx *c, const uint64_t *d_pt, int level, uint64_t seed, uint64_t index,
+                                  uint64_t *d_ct)
+{
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if (!c || !d_pt || !d_ct) return fail(RBK_EINVAL, "null argument");
+    const Seeded sd{seed, (u32)index, (u32)(index >> 32)};
+    return encrypt(c, d_pt, level, nullptr, nullptr, nullptr, &sd, d_ct);
+}
+
+// ---------------------------------------------------------------- ciphertext export / import
+
+extern "C" int rbk_ct_export(rbk_ctx *c, const uint64_t *d_ct, int level, int npoly, uint64_t *out)
+{
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if (!c || !d_ct || !out || npoly < 1) return fail(RBK_EINVAL, "bad argument");
+    if (check_level(c, level)) return RBK_ELEVEL;
+    const size_t words = (size_t)npoly * (level + 1) * c->N;
+    WS(ws, words);
+    HIPCK(hipMemcpyAsync(ws, d_ct, words * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
+    ntt_launch(c, ws, (long)(level + 1) * c->N, npoly, level + 1, qmap(c), true, c->stream);
+    HIPCK_LAUNCH();
+    HIPCK(hipMemcpyAsync(out, ws, words * sizeof(u64), hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
+    return RBK_OK;
+}
+
+extern "C" int rbk_ct_import(rbk_ctx *c, const uint64_t *in, int level, int npoly, uint64_t *d_ct)
+{
+    if (c && c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if (!c || !d_ct || !in || npoly < 1) return fail(RBK_EINVAL, "bad argument");
+    if (check_level(c, level)) return RBK_ELEVEL;
+    const size_t words = (size_t)npoly * (level + 1) * c->N;
+    WS(ws, 1);
+    int *flag = (int *)ws;
+    HIPCK(hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+    HIPCK(hipMemcpyAsync(d_ct, in, words * sizeof(u64), hipMemcpyHostToDevice, c->stream));
+    check_residues_launch(c, d_ct, npoly, level + 1, flag, c->stream);
+    HIPCK_LAUNCH();
+    int herr = 0;
+    HIPCK(hipMemcpyAsync(&herr, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    if (herr) return fail(RBK_EINVAL, "a residue is not below its prime");
+    ntt_launch(c, d_ct, (long)(level + 1) * c->N, npoly, level + 1, qmap(c), false, c->stream);
+    HIPCK_LAUNCH();
     return RBK_OK;
 }
 
@@ -845,6 +983,39 @@ extern "C" int rbk_add_plain(rbk_ctx *c, const uint64_t *ct, const uint64_t *pt,
     if (out != ct) HIPCK(hipMemcpyAsync(out + per, ct + per, per * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
     HIPCK_LAUNCH();
     return RBK_OK;
+}
+
+// Scale-checked additions: the operands must carry the same scale to a
+// relative 2^-30, the result keeps scale_a.
+static int scales_match(double sa, double sb, double *so)
+{
+    if (!(sa > 0) || !(sb > 0)) return fail(RBK_EINVAL, "scales must be positive");
+    if (std::fabs(sa / sb - 1.0) >= 0x1p-30)
+        return fail(RBK_ESCALE, "operands at different scales (2^" + std::to_string(std::log2(sa)) + " vs 2^" +
+                                    std::to_string(std::log2(sb)) + ")");
+    if (so) *so = sa;
+    return RBK_OK;
+}
+
+extern "C" int rbk_add_scaled(rbk_ctx *c, const uint64_t *a, double sa, const uint64_t *b, double sb, uint64_t *o,
+                              int level, double *so)
+{
+    if (int rc = scales_match(sa, sb, so)) return rc;
+    return ew(c, EW_ADD, a, b, o, level, 2);
+}
+
+extern "C" int rbk_sub_scaled(rbk_ctx *c, const uint64_t *a, double sa, const uint64_t *b, double sb, uint64_t *o,
+                              int level, double *so)
+{
+    if (int rc = scales_match(sa, sb, so)) return rc;
+    return ew(c, EW_SUB, a, b, o, level, 2);
+}
+
+extern "C" int rbk_add_plain_scaled(rbk_ctx *c, const uint64_t *ct, double sct, const uint64_t *pt, double spt,
+                                    uint64_t *out, int level, double *so)
+{
+    if (int rc = scales_match(sct, spt, so)) return rc;
+    return rbk_add_plain(c, ct, pt, out, level);
 }
 
 static int make_scal(const rbk_ctx *c, const uint64_t *scal, int level, ScalArg &s)

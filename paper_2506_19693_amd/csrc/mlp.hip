@@ -417,7 +417,10 @@ struct rbk_mlp {
 
     ~rbk_mlp()
     {
-        if (c) (void)hipStreamSynchronize(c->stream);
+        if (c) {
+            (void)hipStreamSynchronize(c->stream);
+            c->live_mlps--;
+        }
         state.clear();
         for (u64 *h : home) (void)hipFree(h);
         for (auto &kv : masks) (void)hipFree(kv.second);
@@ -694,6 +697,7 @@ extern "C" int rbk_mlp_create(rbk_ctx *c, const rbk_mlp_desc *d, rbk_mlp **out)
     rbk_mlp *m = new (std::nothrow) rbk_mlp;
     if (!m) return rbk_set_error(RBK_ENOMEM, "host allocation failed");
     m->c = c;
+    c->live_mlps++;
     m->sh = sh;
     m->state.resize(sh.layout.size());
     m->home.assign(sh.layout.size(), nullptr);
@@ -874,4 +878,127 @@ extern "C" int rbk_mlp_scalars(const rbk_mlp *m, int64_t *out, int max)
     const int n = (int)m->scalars.size();
     for (int i = 0; i < n && i < max; i++) out[i] = m->scalars[i];
     return n;
+}
+
+// ---------------------------------------------------------------- float64 weights in and out
+
+namespace {
+
+// Slot matrix (r x c, slot (i, j) at i c + j) of state slot `key` for the
+// float64 matrix A (rows x cols, row-major), or the reverse.  RE-blocks (odd
+// h) keep W in the row-wise format (W[i][j] at (i, j); tile t holds rows
+// t r .. t r + r - 1) and W* column-wise (W*[j][i] at (i, j)); CE-blocks (even
+// h) the other way round.  Velocities share the layout of their weights.
+struct Placement {
+    int rows, cols, row0;  // A's shape and the first row of A this slot holds
+    bool transposed;       // A[a][b] sits at slot (b, a) instead of (a - row0, b)
+};
+
+Placement placement(const Shape &sh, const Key &k)
+{
+    const auto dk = sh.dims(k.h);
+    const bool odd = k.h % 2 == 1;
+    const bool is_w = k.kind == K_W || k.kind == K_V;
+    Placement p;
+    p.rows = is_w ? dk.first : dk.second;
+    p.cols = is_w ? dk.second : sh.o;
+    p.row0 = is_w ? k.tile * sh.r : 0;
+    p.transposed = odd ? !is_w : is_w;
+    return p;
+}
+
+// slot index of A[a][b] in the slot matrix, or -1 when this slot does not hold it
+long slot_of(const Shape &sh, const Placement &p, int a, int b)
+{
+    if (p.transposed) return (long)b * sh.c + a;
+    const int i = a - p.row0;
+    if (i < 0 || i >= sh.r) return -1;
+    return (long)i * sh.c + b;
+}
+
+const double *matrix_of(const Key &k, const double *const *W, const double *const *Ws, const double *const *V,
+                        const double *const *Vs)
+{
+    const double *const *src = k.kind == K_W ? W : k.kind == K_WSTAR ? Ws : k.kind == K_V ? V : Vs;
+    return src ? src[k.h - 1] : nullptr;
+}
+
+}  // namespace
+
+extern "C" int rbk_mlp_set_weights(rbk_mlp *m, const double *const *W, const double *const *Wstar,
+                                   const double *const *V, const double *const *Vstar, int level, uint64_t seed)
+{
+    if (!m || !W || !Wstar) return rbk_set_error(RBK_EINVAL, "null argument");
+    rbk_ctx *c = m->c;
+    if (level < 0 || level >= c->nQ) return rbk_set_error(RBK_ELEVEL, "level out of range");
+    if (c->capturing) return rbk_set_error(RBK_ESTATE, "not allowed during graph capture");
+    const Shape &sh = m->sh;
+    for (int h = 1; h <= sh.H; h++)
+        if (!W[h - 1] || !Wstar[h - 1] || (V && !V[h - 1]) || (Vstar && !Vstar[h - 1]))
+            return rbk_set_error(RBK_EINVAL, "null weight matrix");
+    const size_t N = c->N, n = N / 2;
+    const double scale = std::exp2(sh.log2_scale);
+    std::vector<double> slots(n);
+    u64 *buf = nullptr;
+    if (hipMalloc((void **)&buf, (size_t)3 * (level + 1) * N * sizeof(u64)) != hipSuccess)
+        return rbk_set_error(RBK_ENOMEM, "device allocation failed");
+    u64 *pt = buf, *ct = buf + (size_t)(level + 1) * N;
+    int rc = RBK_OK;
+    for (size_t idx = 0; idx < sh.layout.size() && rc == RBK_OK; idx++) {
+        const Key &k = sh.layout[idx];
+        const Placement p = placement(sh, k);
+        const double *A = matrix_of(k, W, Wstar, V, Vstar);
+        std::fill(slots.begin(), slots.end(), 0.0);
+        if (A)
+            for (int a = 0; a < p.rows; a++)
+                for (int b = 0; b < p.cols; b++) {
+                    const long s = slot_of(sh, p, a, b);
+                    if (s >= 0) slots[s] = A[(size_t)a * p.cols + b];
+                }
+        rc = rbk_encode(c, slots.data(), nullptr, n, level, scale, pt);
+        if (!rc) rc = rbk_encrypt_seeded(c, pt, level, seed, idx, ct);
+        if (!rc) rc = rbk_mlp_set_state(m, (int)idx, ct, level, scale);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == RBK_OK)
+        rc = rbk_set_error(RBK_EDEVICE, "stream synchronisation failed");
+    (void)hipFree(buf);
+    return rc;
+}
+
+extern "C" int rbk_mlp_get_weights(rbk_mlp *m, double *const *W, double *const *Wstar, double *const *V,
+                                   double *const *Vstar)
+{
+    if (!m) return rbk_set_error(RBK_EINVAL, "null argument");
+    rbk_ctx *c = m->c;
+    if (c->capturing) return rbk_set_error(RBK_ESTATE, "not allowed during graph capture");
+    const Shape &sh = m->sh;
+    const size_t N = c->N, n = N / 2;
+    std::vector<double> re(n);
+    u64 *pt = nullptr;
+    if (hipMalloc((void **)&pt, (size_t)3 * c->nQ * N * sizeof(u64)) != hipSuccess)
+        return rbk_set_error(RBK_ENOMEM, "device allocation failed");
+    u64 *ct = pt + (size_t)c->nQ * N;
+    int rc = RBK_OK;
+    for (size_t idx = 0; idx < sh.layout.size() && rc == RBK_OK; idx++) {
+        const Key &k = sh.layout[idx];
+        double *const *dst = k.kind == K_W ? W : k.kind == K_WSTAR ? Wstar : k.kind == K_V ? V : Vstar;
+        if (!dst) continue;
+        double *A = dst[k.h - 1];
+        if (!A) continue;
+        int lv = 0;
+        double s = 0;
+        rc = rbk_mlp_get_state(m, (int)idx, ct, &lv, &s);  // contiguous copy (state may sit at a wider stride)
+        if (!rc) rc = rbk_decrypt(c, ct, lv, pt);
+        if (!rc) rc = rbk_decode(c, pt, lv, s, re.data(), nullptr, n);
+        if (rc) break;
+        const Placement p = placement(sh, k);
+        for (int a = 0; a < p.rows; a++)
+            for (int b = 0; b < p.cols; b++) {
+                const long s = slot_of(sh, p, a, b);
+                if (s >= 0) A[(size_t)a * p.cols + b] = re[s];
+            }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(pt);
+    return rc;
 }

@@ -107,6 +107,7 @@ struct rbk_ctx_impl {
     std::vector<void *> owned;  // device allocations freed at destroy
 
     struct BootPlan *boot = nullptr;   // bootstrapping plan (boot.hip)
+    int live_mlps = 0;                 // rbk_mlp objects built on this context (mlp.hip)
 
     bool timing = false;
     // the stream is being captured into a graph: nothing may grow, free or wait
@@ -269,6 +270,29 @@ int rescale_run(rbk_ctx *c, const u64 *ct, u64 *out, int level, int count, u64 *
 // allocation-free entry points: looks up the device's scratch array (once per
 // device, with that device current)
 int noalloc_setup(int device);
+
+// ---- seeded sampling (sample.hip) ----
+// nonce purposes of the keystream (the quantity a block belongs to)
+enum : u32 {
+    RBK_SAMPLE_SECRET = 1,
+    RBK_SAMPLE_PK_A = 2,
+    RBK_SAMPLE_PK_E = 3,
+    RBK_SAMPLE_KEY_A = 4,
+    RBK_SAMPLE_KEY_E = 5,
+    RBK_SAMPLE_ENC_V = 6,
+    RBK_SAMPLE_ENC_E0 = 7,
+    RBK_SAMPLE_ENC_E1 = 8,
+};
+// out [nlimbs][N]: limb t uniform modulo prime t of the context's table
+void sample_uniform_launch(const rbk_ctx_impl *c, u64 *out, int nlimbs, u64 seed, u32 purpose, u32 id, u32 sub_hi,
+                           hipStream_t st);
+// out [N]: uniform ternary (gaussian = 0) or the sigma = 3.2 discrete Gaussian (gaussian = 1)
+void sample_small_launch(const rbk_ctx_impl *c, i64 *out, u64 seed, u32 purpose, u32 id, u32 sub, int gaussian,
+                         hipStream_t st);
+// host: exactly h non-zero coefficients in {-1, +1}
+void sample_ternary_hw_host(u64 seed, int logN, int h, i64 *out);
+// *flag |= 1 when some residue of npoly x nlimbs limbs (prime i = limb i) is not below its prime
+void check_residues_launch(const rbk_ctx_impl *c, const u64 *data, int npoly, int nlimbs, int *flag, hipStream_t st);
 
 // ---- batches of uneven level (kernels.hip, list.hip) ----
 // Per-ciphertext entry of a batch whose ciphertexts differ in level: the

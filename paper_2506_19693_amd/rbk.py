@@ -132,6 +132,14 @@ SIGNATURES = {
     "rbk_keygen_galois": (ci, [vp, cu64, u64p, i64p]),
     "rbk_galois_elt": (cu64, [vp, ctypes.c_int64]),
     "rbk_key_export": (ci, [vp, cu64, u64p]),
+    "rbk_keygen": (ci, [vp, cu64, ci, i64p, ci, ci]),
+    "rbk_encrypt_seeded": (ci, [vp, vp, ci, cu64, cu64, vp]),
+    "rbk_gauss_table": (ci, [u64p]),
+    "rbk_ct_export": (ci, [vp, vp, ci, ci, u64p]),
+    "rbk_add_scaled": (ci, [vp, vp, ctypes.c_double, vp, ctypes.c_double, vp, ci, dblp]),
+    "rbk_sub_scaled": (ci, [vp, vp, ctypes.c_double, vp, ctypes.c_double, vp, ci, dblp]),
+    "rbk_add_plain_scaled": (ci, [vp, vp, ctypes.c_double, vp, ctypes.c_double, vp, ci, dblp]),
+    "rbk_ct_import": (ci, [vp, u64p, ci, ci, vp]),
     "rbk_encode": (ci, [vp, dblp, dblp, ctypes.c_size_t, ci, ctypes.c_double, vp]),
     "rbk_decode": (ci, [vp, vp, ci, ctypes.c_double, dblp, dblp, ctypes.c_size_t]),
     "rbk_encrypt": (ci, [vp, vp, ci, i64p, i64p, i64p, vp]),
@@ -178,6 +186,10 @@ SIGNATURES = {
     "rbk_mlp_set_mask": (ci, [vp, ci, vp]),
     "rbk_mlp_train_step": (ci, [vp, vp, vp, vp, ci, ci, ctypes.c_double, ci, ctypes.c_uint32]),
     "rbk_mlp_scalars": (ci, [vp, i64p, ci]),
+    "rbk_mlp_set_weights": (ci, [vp, ctypes.POINTER(dblp), ctypes.POINTER(dblp), ctypes.POINTER(dblp),
+                                 ctypes.POINTER(dblp), ci, cu64]),
+    "rbk_mlp_get_weights": (ci, [vp, ctypes.POINTER(dblp), ctypes.POINTER(dblp), ctypes.POINTER(dblp),
+                                 ctypes.POINTER(dblp)]),
     "rbk_server_create": (ci, [ctypes.c_uint64, ci, ci, ctypes.POINTER(vp)]),
     "rbk_server_add_tenant": (ci, [vp, vp, ctypes.POINTER(ci)]),
     "rbk_server_start": (ci, [vp]),
@@ -281,6 +293,13 @@ def _close_all():
         c.close()
 
 
+def gauss_table():
+    """The cumulative table of the library's Gaussian sampler."""
+    out = np.zeros(20, dtype=np.uint64)
+    _check(load().rbk_gauss_table(out.ctypes.data_as(u64p)))
+    return [int(x) for x in out]
+
+
 class Context:
     """One librbk context: ring degree 2^log_n, Q chain of sizes q_bits,
     special primes p_bits, alpha primes per key-switching digit."""
@@ -308,9 +327,13 @@ class Context:
         _check(self.lib.rbk_psi(self.h, p.ctypes.data_as(u64p)))
         self.psi = [int(x) for x in p]
         self.beta = self.num_digits(self.L)
+        self._deps = weakref.WeakSet()
         _LIVE_CONTEXTS.add(self)
 
     def close(self):
+        # objects built on this context (MLPs) must go first: their destructors use it
+        for dep in list(getattr(self, "_deps", ())):
+            dep.close()
         if getattr(self, "h", None):
             self.lib.rbk_ctx_destroy(self.h)
             self.h = None
@@ -393,6 +416,32 @@ class Context:
         _check(self.lib.rbk_key_export(self.h, int(g), out.ctypes.data_as(u64p)))
         return out
 
+    def keygen(self, seed, secret_hw=0, rot_steps=(), conj=False):
+        """Secret, public, relinearisation and Galois keys drawn in the library from `seed`."""
+        ks = np.ascontiguousarray(list(rot_steps) or [0], dtype=np.int64)
+        _check(self.lib.rbk_keygen(self.h, int(seed), int(secret_hw), ks.ctypes.data_as(i64p), len(rot_steps),
+                                   1 if conj else 0))
+
+    def encrypt_seeded(self, pt, level, seed, index):
+        ct = self.empty_ct(level)
+        _check(self.lib.rbk_encrypt_seeded(self.h, _ptr(pt), level, int(seed), int(index), _ptr(ct)))
+        return ct
+
+    def ct_export(self, t, level):
+        """Device NTT-domain polynomials [npoly][level+1][N] -> host coefficient domain."""
+        npoly = self._npoly(t, level)
+        out = np.zeros(tuple(t.shape), dtype=np.uint64)
+        _check(self.lib.rbk_ct_export(self.h, _ptr(t), level, npoly, out.ctypes.data_as(u64p)))
+        return out
+
+    def ct_import(self, arr, level):
+        """Host coefficient-domain residues [npoly][level+1][N] -> device NTT domain."""
+        a, pa = _h_u64(arr)
+        npoly = a.size // ((level + 1) * self.N)
+        t = self.empty(*a.shape)
+        _check(self.lib.rbk_ct_import(self.h, pa, level, npoly, _ptr(t)))
+        return t
+
     # ---------------------------------------------------------------- encoding
     def encode(self, z, level, scale):
         z = np.asarray(z)
@@ -436,6 +485,22 @@ class Context:
         out = self.empty(*a.shape)
         _check(self.lib.rbk_sub(self.h, _ptr(a), _ptr(b), _ptr(out), level, self._npoly(a, level)))
         return out
+
+    def _scaled(self, fn, a, sa, b, sb, level):
+        out = self.empty(*a.shape)
+        so = ctypes.c_double()
+        _check(fn(self.h, _ptr(a), float(sa), _ptr(b), float(sb), _ptr(out), level, ctypes.byref(so)))
+        return out, so.value
+
+    def add_scaled(self, a, sa, b, sb, level):
+        """(a + b, scale); RbkError (RBK_ESCALE) unless the scales agree to 2^-30."""
+        return self._scaled(self.lib.rbk_add_scaled, a, sa, b, sb, level)
+
+    def sub_scaled(self, a, sa, b, sb, level):
+        return self._scaled(self.lib.rbk_sub_scaled, a, sa, b, sb, level)
+
+    def add_plain_scaled(self, ct, sct, pt, spt, level):
+        return self._scaled(self.lib.rbk_add_plain_scaled, ct, sct, pt, spt, level)
 
     def neg(self, a, level):
         out = self.empty(*a.shape)
@@ -759,6 +824,7 @@ class Mlp:
         info = (ci * 3)()
         _check(self.lib.rbk_mlp_info(self.h, info))
         self.tiles, self.n_state, self.depth = list(info)
+        ctx._deps.add(self)
         _LIVE_MLPS.add(self)
 
     def close(self):
@@ -794,6 +860,29 @@ class Mlp:
 
     def set_mask(self, level, pt):
         _check(self.lib.rbk_mlp_set_mask(self.h, level, _ptr(pt)))
+
+    @staticmethod
+    def _mats(ms):
+        if ms is None:
+            return None, None
+        arrs = [np.ascontiguousarray(m, dtype=np.float64) for m in ms]
+        return arrs, (dblp * len(arrs))(*[a.ctypes.data_as(dblp) for a in arrs])
+
+    def set_weights(self, Ws, Wstars, Vs=None, Vstars=None, level=None, seed=1):
+        """Float64 weights (and velocities) -> packed, encrypted state at `level` (default: top)."""
+        level = self.ctx.L if level is None else level
+        keep = [self._mats(m) for m in (Ws, Wstars, Vs, Vstars)]
+        _check(self.lib.rbk_mlp_set_weights(self.h, keep[0][1], keep[1][1], keep[2][1], keep[3][1], level, int(seed)))
+
+    def get_weights(self, dims, n_out, velocities=True):
+        """Decrypted (Ws, Wstars, Vs, Vstars) for layer dims [(k_{h-1}, k_h)]."""
+        Ws = [np.zeros(dk) for dk in dims]
+        Wst = [np.zeros((dk[1], n_out)) for dk in dims]
+        Vs = [np.zeros(dk) for dk in dims] if velocities else None
+        Vst = [np.zeros((dk[1], n_out)) for dk in dims] if velocities else None
+        ptrs = [self._mats(m)[1] for m in (Ws, Wst, Vs, Vst)]
+        _check(self.lib.rbk_mlp_get_weights(self.h, *ptrs))
+        return Ws, Wst, Vs, Vst
 
     def train_step(self, x, y_exp, y_rep, level, scale, t, bootstrap=True, per_sample=False):
         """x: [b][tiles][2][level+1][N], y_exp / y_rep: [b][2][level+1][N] device tensors."""
