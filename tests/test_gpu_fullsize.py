@@ -173,3 +173,55 @@ def test_keyswitch_splits_match_oracle(logN, logC):
                 assert np.array_equal(d.to_coef(h[i], L - 1), wh), (lanes, i)
     finally:
         d.close()
+
+
+# ---------------------------------------------------------------- bootstrapping, N = 2^16
+
+@pytest.mark.timeout(900)
+def test_bootstrap_n16_matches_oracle():
+    """The bootstrap at the headline geometry (log2 rho = 2, the setting the
+    benchmark runs), with the oracle planner's integer constants imported:
+    every output limb of the single and the batched call against the digests
+    of the oracle's own bootstrap of the same ciphertext."""
+    from paper_2506_19693_amd import Context
+
+    p = C.BOOT
+    gold = golden("bootstrap_n16.json")
+    d = Context(p["logN"], p["qbits"], p["pbits"], p["alpha"])
+    try:
+        assert d.moduli == gold["moduli"]
+        o = O.Oracle(p["logN"], p["qbits"], p["pbits"], p["alpha"])
+        N = d.N
+        plan = B.Plan(N, o.Q, B.BootParams(log2_rho=p["log2_rho"]))
+        rots = plan.rotations()
+        assert rots == gold["rotations"]
+        dr = C.boot_draws(d.moduli, d.nQ, d.beta, N, rots)
+        d.set_secret(dr["s"])
+        d.keygen_public(*dr["pk"])
+        d.keygen_relin(*dr["rlk"])
+        for k, r in zip(list(rots) + ["conj"], dr["gal"]):
+            d.keygen_galois(d.galois_conj() if k == "conj" else d.galois_elt(k), *r)
+        d.boot_setup(log2_rho=p["log2_rho"])
+        assert d.boot_rotations() == rots and d.boot_levels[3] == gold["level_out"]
+        d.boot_import([pt for _, pt in plan.plains], [sc for _, sc in plan.scalars])
+        # the input: the oracle's encryption of the seeded slots at level 0
+        pk = o.keygen_public(dr["s"], *dr["pk"])
+        ct = o.encrypt(0, pk, O.encode(dr["z"], N, C.BOOT_SCALE, o.Q[:1]), *dr["enc"])
+        assert C.limb_digests(ct) == gold["input"]
+        lo = gold["level_out"]
+        print("N=2^16 bootstrap with the oracle's constants, output level %d" % lo, flush=True)
+        out, so = d.bootstrap(d.to_ntt(ct, 0), C.BOOT_SCALE)
+        assert so == pytest.approx(gold["scale_out"], rel=1e-12)
+        assert mismatches(d.to_coef(out, lo), gold["output"]) == []
+        # the batched call: the same ciphertext twice, next to one at another scale
+        cts = d.empty(3, 2, 1, N)
+        x = d.to_ntt(ct, 0)
+        cts[0].copy_(x)
+        cts[1].copy_(d.encrypt(d.encode(dr["z"], 0, 2.0 ** 37), 0, *S.encryption_randomness(S.rng(5, 16), N)))
+        cts[2].copy_(x)
+        outs, sos = d.bootstrap_batch(cts, [C.BOOT_SCALE, 2.0 ** 37, C.BOOT_SCALE])
+        for i in (0, 2):
+            assert sos[i] == so
+            assert mismatches(d.to_coef(outs[i], lo), gold["output"]) == [], i
+    finally:
+        d.close()
