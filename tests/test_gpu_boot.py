@@ -80,18 +80,33 @@ def test_plan_layout_and_own_constants():
     assert sl == [lv for lv, _ in plan.scalars]
     assert d.boot_rotations() == plan.rotations()
     plains, scalars = d.boot_export()
-    worst = 0
+    worst, hist = 0, {}
     for (lv, want), got in zip(plan.plains, plains):
         a = O.crt_centered(want, p.orc.Q[: lv + 1])
         b = O.crt_centered(got, p.orc.Q[: lv + 1])
-        worst = max(worst, max(abs(int(x) - int(y)) for x, y in zip(a, b)))
-    assert worst <= 2, worst      # two float64 encoders: rounding differences only
+        for x, y in zip(a, b):
+            dlt = abs(int(x) - int(y))
+            hist[dlt] = hist.get(dlt, 0) + 1
+            worst = max(worst, dlt)
+    print("diagonal coefficients: |difference| histogram", sorted(hist.items()))
+    # Two float64 encoders round values that differ by far less than one unit
+    # here, so the rounded integers differ by at most one (measured: 257 of
+    # 188416 coefficients differ, each by one)
+    assert worst <= 1, worst
+    rel, absd = 0.0, 0
     for (lv, want), got in zip(plan.scalars, scalars):
         a = int(O.crt_centered(np.asarray(want).reshape(-1, 1), p.orc.Q[: lv + 1])[0])
         b = int(O.crt_centered(np.asarray(got).reshape(-1, 1), p.orc.Q[: lv + 1])[0])
-        # both planners derive these from float64 scales and Chebyshev sums
-        # evaluated in a different order: equal to within float rounding
-        assert abs(a - b) <= max(1, abs(a) >> 30), (a, b)
+        absd = max(absd, abs(a - b))
+        if a:
+            rel = max(rel, abs(a - b) / abs(a))
+        # both planners derive these from float64 scales and 60-term Chebyshev
+        # sums evaluated in a different order; a sum's absolute rounding error
+        # (about 60 ulp of its largest term) is a larger relative error for the
+        # small high-degree coefficients (measured worst: 2^-36.8; bound with a
+        # margin of 2^2.8)
+        assert abs(a - b) <= max(1, abs(a) >> 34), (a, b)
+    print("scalars: worst |difference| %d, worst relative 2^%.1f" % (absd, np.log2(rel) if rel else -999))
 
 
 def test_bootstrap_bit_exact_with_oracle_constants():

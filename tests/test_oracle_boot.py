@@ -94,3 +94,78 @@ def test_oracle_bootstrap_precision():
     out, so = B.Evaluator(orc, plan, rlk, keys).bootstrap(ct, scale)
     back = O.decode(orc.decrypt(plan.level_out, s, out), N, so, orc.Q[: plan.level_out + 1])
     assert math.log2(np.max(np.abs(back - z))) < -12
+
+
+# ---------------------------------------------------------------- ModRaise and monomials, directly
+
+def _crt_centred(res, mods):
+    """the integer in (-Q/2, Q/2] with the given residues (Python big integers)"""
+    Q = 1
+    for m in mods:
+        Q *= m
+    x = 0
+    for r, m in zip(res, mods):
+        Qi = Q // m
+        x += int(r) * Qi * pow(Qi % m, -1, m)
+    x %= Q
+    return x - Q if x > Q // 2 else x
+
+
+def test_modraise_is_the_centred_lift():
+    """ModRaise reads a level-0 residue as the integer of least absolute
+    value and re-expresses it modulo every prime of the chain: the CRT of
+    the outputs is that integer (every input, including 0, +-(q0-1)/2 and
+    q0 - 1)."""
+    orc = O.Oracle(5, [50, 40, 40, 40, 40], [50], 5)
+    q0, N, L = orc.Q[0], orc.N, orc.L
+    g = S.rng(41, 5)
+    x = S.uniform_residues(g, orc.Q[:1], N, lead=(2,))
+    x[0, 0, :4] = [0, (q0 - 1) // 2, (q0 + 1) // 2, q0 - 1]
+    out = orc.modraise(L, x)
+    assert out.shape == (2, L + 1, N)
+    for p in range(2):
+        for k in range(N):
+            v = int(x[p, 0, k])
+            want = v if v <= (q0 - 1) // 2 else v - q0
+            assert _crt_centred(out[p, :, k], orc.Q) == want
+
+
+def _negacyclic(a, b, q):
+    """schoolbook product in Z_q[X] / (X^N + 1), Python integers"""
+    N = len(a)
+    out = [0] * N
+    for i in range(N):
+        for j in range(N):
+            t = int(a[i]) * int(b[j])
+            if i + j < N:
+                out[i + j] += t
+            else:
+                out[i + j - N] -= t
+    return [v % q for v in out]
+
+
+def test_monomial_is_the_product_with_x_to_the_e():
+    orc = O.Oracle(4, [50, 40, 40], [50], 3)
+    N, L = orc.N, orc.L
+    g = S.rng(42, 4)
+    a = S.uniform_residues(g, orc.Q, N, lead=(2,))
+    for e in (0, 1, 5, N - 1, N, N + 3, 3 * N // 2, 2 * N - 1):
+        out = orc.monomial(L, e, a)
+        xe = [0] * N
+        xe[e % N] = 1 if e < N else -1          # X^e with X^N = -1
+        for p in range(2):
+            for t in range(L + 1):
+                assert [int(v) for v in out[p, t]] == _negacyclic(a[p, t], xe, orc.Q[t]), (e, p, t)
+
+
+def test_monomial_of_quarter_turn_multiplies_slots_by_i():
+    """X^(N/2) evaluates to zeta^(5^j N/2) = i at every slot root (5^j = 1 mod 4),
+    which is how the bootstrap splits real and imaginary parts."""
+    N = 1 << 6
+    orc = O.Oracle(6, [50, 40], [50], 2)
+    g = S.rng(43, 6)
+    z = g.uniform(-1, 1, N // 2) + 1j * g.uniform(-1, 1, N // 2)
+    scale = 2.0 ** 30
+    pt = O.encode(z, N, scale, orc.Q)
+    back = O.decode(orc.monomial(orc.L, N // 2, pt[None])[0], N, scale, orc.Q)
+    assert np.max(np.abs(back - 1j * z)) < 2.0 ** -20
