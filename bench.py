@@ -56,12 +56,11 @@ def parse():
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP train_step part")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving part")
     ap.add_argument("--serve-jobs", type=int, default=200)
-    ap.add_argument("--serve-lambda", type=float, default=SERVE_LAMBDA, help="Poisson arrival rate, jobs/s")
-    ap.add_argument("--serve-calibrate", action="store_true",
-                    help="submit every job at once and report the capacity (0.8 x it is the frozen arrival rate)")
+    ap.add_argument("--serve-lambda", type=float, default=0.0,
+                    help="Poisson arrival rate, jobs/s (default: 0.8 x the capacity measured in the same run)")
     ap.add_argument("--serve-budget-gib", type=float, default=150.0)
-    ap.add_argument("--serve-max-batch", type=int, default=16)
-    ap.add_argument("--serve-max-boot", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-max-boot", type=int, default=16)
     ap.add_argument("--serve-mlp-b", type=int, default=8, help="samples per training step of serving jobs")
     ap.add_argument("--lanes", type=int, default=2,
                     help="ModDown lanes of hoisted-rotation batches (1: no overlapping kernels, as for profiling)")
@@ -97,12 +96,15 @@ def setup(ctx, count, rots):
         ctx.keygen_galois(ctx.galois_elt(k), a, e)
     A = ctx.empty_ct(L, count)
     B = ctx.empty_ct(L, count)
+    z0 = []
     for i in range(count):
         for T in (A, B):
             z = S.uniform_slots(g, N // 2)
+            if i == count - 1:
+                z0.append(z)
             T[i].copy_(ctx.encrypt(ctx.encode(z, L, SCALE), L, *S.encryption_randomness(g, N)))
     ctx.sync()
-    return s, A, B
+    return s, A, B, z0
 
 
 def batched_step(ctx, A, B, out_m, out_r, out_h, ks):
@@ -161,6 +163,15 @@ def bench_bootstrap(args, torch):
     ctx.sync()
     t_b = (time.perf_counter() - t0) / args.steps
     err = max(float(np.max(np.abs(ctx.decode(ctx.decrypt(out[i], lo), lo, so[i]).real - zs[i]))) for i in range(count))
+    # one more batched call with per-kernel timers and the key-switch count
+    ctx.timer_enable(True)
+    ctx.bootstrap_batch(cts, scales, out=out)
+    ctx.sync()
+    timers = ctx.timer_read()
+    n_ks, ks_bytes = ctx.ks_stats()
+    ctx.timer_enable(False)
+    dom = max(timers, key=lambda k: timers[k][0])
+    roof = ks_roofline(timers, dom, n_ks, ks_bytes, t_b, "bootstrap_c2")
     # the same batch captured once into a HIP graph and replayed
     out_g = ctx.empty_ct(lo, count)
     graph = ctx.capture(lambda: ctx.bootstrap_batch(cts, scales, out=out_g))
@@ -198,6 +209,10 @@ def bench_bootstrap(args, torch):
         "plain_latency_ms_p99": percentile(lat, 99),
         "output_level": lo,
         "max_slot_error_log2": float(np.log2(err)),
+        "key_switches_per_bootstrap": n_ks / count,
+        "roofline": roof,
+        "kernels": {k: {"ms": round(v[0], 3), "launches": v[1], "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)}
+                    for k, v in timers.items()},
     }
     ctx.close()
     return res
@@ -317,8 +332,16 @@ def bench_train_step(args, torch):
     run(per_sample=True)
     ctx.sync()
     t_p = time.perf_counter() - t0
+    ctx.timer_enable(True)               # one more step with per-kernel timers and the key-switch count
+    run()
+    ctx.sync()
+    timers = ctx.timer_read()
+    n_ks, ks_bytes = ctx.ks_stats()
+    ctx.timer_enable(False)
+    dom = max(timers, key=lambda k: timers[k][0])
+    roof = ks_roofline(timers, dom, n_ks, ks_bytes, t_b, "train_step_c3")
     t0 = time.perf_counter()
-    run(bootstrap=False)                  # the same step without its bootstrap: the bootstrap's share
+    run(bootstrap=False)                  # the same step without its bootstrap (last: it leaves the state unrefreshed)
     ctx.sync()
     t_nb = time.perf_counter() - t0
     lr, lc = int(np.log2(r)), int(np.log2(c))
@@ -338,6 +361,10 @@ def bench_train_step(args, torch):
         "bootstraps_per_step": mlp.n_state,
         "weight_level": lo,
         "depth": mlp.depth,
+        "key_switches_per_step": n_ks,
+        "roofline": roof,
+        "kernels": {k: {"ms": round(v[0], 3), "launches": v[1], "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)}
+                    for k, v in timers.items()},
     }
     mlp.close()
     ctx.close()
@@ -348,10 +375,9 @@ SERVE_Q_BITS = [60] + [50] * 30
 SERVE_P_BITS = [60] * 11
 SERVE_ALPHA = 11
 SERVE_LOG_NS = [14, 14, 14, 15, 15, 15, 16, 16]
-# Poisson arrival rate of the serving workload, jobs/s: 0.8 x the batched
-# capacity measured by `--serve-calibrate` (all 200 jobs submitted at once),
-# then frozen here.
-SERVE_LAMBDA = 4.1
+# The Poisson arrival rate is this fraction of the capacity measured in the
+# same run (all jobs submitted at once)
+SERVE_LOAD = 0.8
 
 
 def _dev_residues(ctx, gen, lead, level):
@@ -562,20 +588,32 @@ def bench_serve(args, torch):
     free, total = torch.cuda.mem_get_info()
     log("serving: tenants set up, %.1f of %.1f GiB free" % (free / 2.0 ** 30, total / 2.0 ** 30))
     budget = int(args.serve_budget_gib * (1 << 30))
-    lam = 0.0 if args.serve_calibrate else args.serve_lambda
-    jobs = _serve_jobs(args.serve_jobs, tenants, lam)
     # warm every tenant's workspaces and pools with one of each job kind
     _serve_run(tenants, [(0.0, i, "mult", dict(count=8, level=30)) for i in range(len(tenants))]
                + [(0.0, i, "boot", dict(count=2, scales=[2.0 ** 40] * 2)) for i in range(len(tenants))],
                budget, args.serve_max_batch, args.serve_max_boot, torch)
     log("serving: warm-up done, %.1f GiB free" % (torch.cuda.mem_get_info()[0] / 2.0 ** 30))
+    # capacity: the job list submitted at once (the queue builds up, so batches merge)
+    burst = [(0.0, i, k, p) for (_, i, k, p) in _serve_jobs(args.serve_jobs, tenants, 0.0)]
+    mk_b, lat_b, st_b = _serve_run(tenants, burst, budget, args.serve_max_batch, args.serve_max_boot, torch)
+    capacity = len(burst) / mk_b
+    log("serving: burst of %d jobs done in %.1f s (%.2f jobs/s), %d batches, %d jobs merged" % (
+        len(burst), mk_b, capacity, st_b["batches"], st_b["jobs_merged"]))
+    lam = args.serve_lambda if args.serve_lambda > 0 else SERVE_LOAD * capacity
+    jobs = _serve_jobs(args.serve_jobs, tenants, lam)
     mk, lat, stats = _serve_run(tenants, jobs, budget, args.serve_max_batch, args.serve_max_boot, torch)
-    log("serving: run done in %.1f s, %.1f GiB free" % (mk, torch.cuda.mem_get_info()[0] / 2.0 ** 30))
+    log("serving: Poisson run at %.2f jobs/s done in %.1f s, %d jobs merged, %.1f GiB free" % (
+        lam, mk, stats["jobs_merged"], torch.cuda.mem_get_info()[0] / 2.0 ** 30))
+    if stats["jobs_merged"] == 0:
+        log("serving: WARNING: no job merged into another's batch at this arrival rate")
     out = {
-        "workload": "serving: %d jobs, Poisson arrivals at %.2f jobs/s, 8 tenants (N=2^14 x3, 2^15 x3, 2^16 x2), "
-                    "31 primes (60 + 30x50) + 11 special, HW-192 secrets; jobs: 55%% mult+rescale batches (8-64 "
-                    "ciphertexts, levels 8-30), 30%% bootstraps (1-16), 15%% 1-3 train_steps (784-w-w-10, w in "
-                    "64/128; 784-256-10; %d samples) on the N=2^16 tenants" % (len(jobs), lam, args.serve_mlp_b),
+        "workload": "serving: %d jobs, Poisson arrivals at %.2f jobs/s (%.2f x the capacity measured in this run), "
+                    "8 tenants (N=2^14 x3, 2^15 x3, 2^16 x2), 31 primes (60 + 30x50) + 11 special, HW-192 secrets; "
+                    "jobs: 55%% mult+rescale batches (8-64 ciphertexts, levels 8-30), 30%% bootstraps (1-16), 15%% "
+                    "1-3 train_steps (784-w-w-10, w in 64/128; 784-256-10; %d samples) on the N=2^16 tenants; batch "
+                    "caps %d ciphertexts (mult), %d (bootstrap)" % (
+                        len(jobs), lam, lam / capacity, args.serve_mlp_b, args.serve_max_batch, args.serve_max_boot),
+        "arrival_rate_jobs_per_s": lam,
         "jobs_per_s": len(jobs) / mk,
         "makespan_s": mk,
         "latency_ms_p50": percentile(lat, 50),
@@ -584,26 +622,18 @@ def bench_serve(args, torch):
         "jobs_merged": stats["jobs_merged"],
         "ledger_peak_gib": stats["ledger_peak"] / 2.0 ** 30,
         "budget_gib": stats["budget"] / 2.0 ** 30,
-    }
-    if args.serve_calibrate:
-        out["calibration_capacity_jobs_per_s"] = len(jobs) / mk
-        out["lambda_for_0.8"] = 0.8 * len(jobs) / mk
-    else:
-        # the same jobs submitted at once: the queue builds up, so batches merge
-        # (mult jobs of any level through the uneven-level list path)
-        burst = [(0.0, i, k, p) for (_, i, k, p) in jobs]
-        mk_b, lat_b, st_b = _serve_run(tenants, burst, budget, args.serve_max_batch, args.serve_max_boot, torch)
-        log("serving: burst of %d jobs done in %.1f s, %d batches" % (len(burst), mk_b, st_b["batches"]))
-        out["burst"] = {
-            "jobs_per_s": len(burst) / mk_b,
+        "burst": {
+            "jobs_per_s": capacity,
             "makespan_s": mk_b,
             "latency_ms_p50": percentile(lat_b, 50),
             "latency_ms_p99": percentile(lat_b, 99),
             "batches": st_b["batches"],
             "jobs_merged": st_b["jobs_merged"],
-        }
-    if not args.serve_calibrate and not args.no_plain:
+        },
+    }
+    if not args.no_plain:
         mk_s, lat_s = _serial_run(tenants, jobs, torch)
+        log("serving: serial plain at the same arrivals done in %.1f s" % mk_s)
         out["serial_plain"] = {
             "jobs_per_s": len(jobs) / mk_s,
             "makespan_s": mk_s,
@@ -641,13 +671,23 @@ def _oracle_worker(idx, barrier, out):
     out.put(time.perf_counter() - t0)
 
 
+# worker processes of the CPU oracle legs: every host core, at most the 16
+# cores that one GPU's share of a GPU host is
+CPU_WORKERS_CAP = 16
+
+
+def cpu_workers():
+    return max(1, min(CPU_WORKERS_CAP, os.cpu_count() or 1))
+
+
 def cpu_baseline():
     """The oracle (plain C, one thread per process) on independent ciphertexts
     of the key-switch workload, one process per host core (at most 16): each
     does mult_relin + rescale + one hoisted rotation (2 key switches)."""
     import multiprocessing as mp
 
-    workers = max(1, min(16, os.cpu_count() or 1))
+    workers = cpu_workers()
+    nproc, model = _host_cpu()
     ctxm = mp.get_context("fork")
     barrier = ctxm.Barrier(workers)
     q = ctxm.Queue()
@@ -662,10 +702,307 @@ def cpu_baseline():
         "value": 2.0 * workers / wall,
         "unit": "key-switches/s",
         "cores": workers,
+        "host_nproc": nproc,
+        "host_cpu": model,
+        "cores_cap": "one process per core up to %d (a GPU's share of the host)" % CPU_WORKERS_CAP,
         "kind": "oracle",
         "sample": "%d independent ciphertexts at N=2^16, 24 limbs, one oracle process per core: mult_relin + rescale "
                   "+ 1 hoisted rotation each (2 key switches), %.1f s wall (single-process time %.1f s)" % (
                       workers, wall, min(dts)),
+    }
+
+
+# ---------------------------------------------------------------- oracle cost of the bootstrap and train_step legs
+
+def _host_cpu():
+    """(nproc, CPU model) of this host"""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+class _OpCounter:
+    """Stands in for the oracle inside the oracle's own bootstrap and MLP
+    code: records every ciphertext operation with its level and returns
+    placeholder arrays of the right limb count (one coefficient each)."""
+
+    def __init__(self, orc):
+        self.N = orc.N
+        self.nQ, self.nP = orc.nQ, orc.nP
+        self.moduli = orc.moduli
+        self.Q = orc.Q
+        self.ops = []
+        self.orc = orc
+
+    def _ct(self, level, npoly=2):
+        import numpy as np
+
+        return np.zeros((npoly, level + 1, 1), dtype=np.uint64)
+
+    def _rec(self, op, level, n=1):
+        self.ops.append((op, level, n))
+
+    def galois_rot(self, k):
+        return self.orc.galois_rot(k)
+
+    def galois_conj(self):
+        return 2 * self.N - 1
+
+    def drop(self, lf, lt, ct):
+        return ct[..., : lt + 1, :]
+
+    def mult_relin(self, level, rlk, a, b):
+        self._rec("mult_relin", level)
+        return self._ct(level)
+
+    def rotate(self, level, key, g, ct):
+        self._rec("rotate", level)
+        return self._ct(level)
+
+    def rotate_hoisted(self, level, keys, gs, ct):
+        self._rec("hoisted", level, len(keys))
+        return [self._ct(level) for _ in keys]
+
+    def rescale(self, level, ct):
+        self._rec("rescale", level)
+        return self._ct(level - 1, ct.shape[0])
+
+    def _ew(self, name, level, a):
+        self._rec(name, level)
+        return self._ct(level, a.shape[0] if a.ndim == 3 else 1)
+
+    def add(self, level, a, b):
+        return self._ew("add", level, a)
+
+    def sub(self, level, a, b):
+        return self._ew("add", level, a)
+
+    def mul_plain(self, level, ct, pt):
+        return self._ew("mul_plain", level, ct)
+
+    def mul_scalar(self, level, a, sc):
+        return self._ew("mul_scalar", level, a)
+
+    def add_scalar(self, level, ct, sc):
+        return self._ew("add", level, ct)
+
+    def monomial(self, level, e, a):
+        return self._ew("add", level, a)
+
+    def modraise(self, level, ct0):
+        self._rec("add", level)
+        return self._ct(level)
+
+
+def _op_sample_worker(idx, qbits, pbits, alpha, barrier, out):
+    """Times, at the top level of the chain, of the oracle operations the
+    bootstrap and the training step are made of: ModUp, key inner product,
+    ModDown, tensor product, rescale and the element-wise products / sums."""
+    import numpy as np
+
+    import oracle as O
+    import synth_inputs as S
+
+    orc = O.Oracle(LOG_N, qbits, pbits, alpha)
+    N, L = orc.N, orc.L
+    g = S.rng(9, 16, idx)
+    s = S.ternary(g, N)
+    rlk = orc.keygen_relin(s, *S.key_randomness(g, orc.beta, orc.moduli, N))
+    x = S.uniform_residues(g, orc.Q, N, lead=(2,))
+    y = S.uniform_residues(g, orc.Q, N, lead=(2,))
+    pt = S.uniform_residues(g, orc.Q, N)
+    sc = np.array([3 % q for q in orc.Q], dtype=np.uint64)
+    barrier.wait()
+    t = {}
+    t0 = time.perf_counter()
+    ext = orc.modup(L, x[1])
+    t["modup"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    u = orc.key_inner_product(L, ext, rlk)
+    t["ip"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.moddown(L, u[0])
+    t["moddown"] = 2 * (time.perf_counter() - t0)          # both polynomials
+    for name, fn in (("tensor", lambda: orc.tensor(L, x, y)),
+                     ("rescale", lambda: orc.rescale(L, x)),
+                     ("mul_plain", lambda: orc.mul_plain(L, x, pt)),
+                     ("mul_scalar", lambda: orc.mul_scalar(L, x, sc)),
+                     ("add", lambda: orc.add(L, x, y))):
+        t0 = time.perf_counter()
+        fn()
+        t[name] = time.perf_counter() - t0
+    out.put(t)
+
+
+def _op_times(qbits, pbits, alpha, workers):
+    """Median over `workers` concurrent processes of the per-operation times."""
+    import multiprocessing as mp
+
+    ctxm = mp.get_context("fork")
+    barrier = ctxm.Barrier(workers)
+    q = ctxm.Queue()
+    procs = [ctxm.Process(target=_op_sample_worker, args=(i, qbits, pbits, alpha, barrier, q)) for i in range(workers)]
+    for p_ in procs:
+        p_.start()
+    res = [q.get() for _ in procs]
+    for p_ in procs:
+        p_.join()
+    med = {}
+    for k in res[0]:
+        v = sorted(r[k] for r in res)
+        med[k] = v[len(v) // 2]
+    return med
+
+
+def _oracle_seconds(ops, t, L0, k0, k):
+    """Oracle time of an operation list, from the top-level op times t of a
+    chain with top level L0 and k0 special primes: key-switching work scales
+    with the extended basis (l+1+k), element-wise work with (l+1), rescale
+    with l.  A rotation is a ModUp, an inner product and a ModDown (plus the
+    automorphism, priced as an addition); a hoisted call of n rotations is
+    one ModUp plus n inner products and ModDowns; mult_relin adds the tensor
+    product."""
+    up, md = t["modup"], t["ip"] + t["moddown"]
+    tot = 0.0
+    for op, l, n in ops:
+        ks = (l + 1 + k) / (L0 + 1 + k0)
+        ew = (l + 1) / (L0 + 1)
+        if op == "rotate":
+            tot += (up + md) * ks + t["add"] * ew
+        elif op == "hoisted":
+            tot += (up + n * md) * ks + n * t["add"] * ew
+        elif op == "mult_relin":
+            tot += (up + md) * ks + (t["tensor"] + t["add"]) * ew
+        elif op == "rescale":
+            tot += t["rescale"] * max(l, 1) / L0
+        elif op in ("mul_plain", "mul_scalar", "add"):
+            tot += t[op] * ew
+    return tot
+
+
+def cpu_baseline_boot_and_train(workers):
+    """Oracle bootstraps/s and train_steps/s on the host cores, from a
+    bounded sample: every worker process times each ciphertext operation
+    once at the top level of the bootstrap chain (N = 2^16, 26 primes, 9
+    special); the op lists of one bootstrap and of one training step come
+    from running the oracle's own bootstrap and packed-step code with an
+    operation counter in place of the arithmetic; each op is priced by its
+    level; the workers run independent bootstraps (steps) in parallel."""
+    import oracle as O
+    from oracle import boot as B
+    from oracle import mlp as M
+
+    t_wall = time.perf_counter()
+    t = _op_times(BOOT_Q_BITS, BOOT_P_BITS, BOOT_ALPHA, workers)
+    L0, k0 = len(BOOT_Q_BITS) - 1, len(BOOT_P_BITS)
+    # one bootstrap
+    orc = O.Oracle(LOG_N, BOOT_Q_BITS, BOOT_P_BITS, BOOT_ALPHA)
+    plan = B.Plan(orc.N, orc.Q, B.BootParams(log2_rho=2))
+    cnt = _OpCounter(orc)
+    from collections import defaultdict
+
+    B.Evaluator(cnt, plan, None, defaultdict(lambda: None)).bootstrap(cnt._ct(0), 2.0 ** 40)
+    boot_ops = list(cnt.ops)
+    t_boot = _oracle_seconds(boot_ops, t, L0, k0, k0)
+    n_ks = sum(n for op, _, n in boot_ops if op in ("rotate", "hoisted", "mult_relin"))
+    # one training step (64 samples, 14 bootstraps), on the training chain
+    orc_m = O.Oracle(LOG_N, MLP_Q_BITS, MLP_P_BITS, MLP_ALPHA)
+    plan_m = B.Plan(orc_m.N, orc_m.Q, B.BootParams(log2_rho=2))
+    cnt_m = _OpCounter(orc_m)
+    cfg = M.MlpConfig(k0=784, widths=[128, 128], o=10, r=256, c=128, act=(1.0, 1.0, 1.0 / 3.0), gamma=0.001,
+                      eta=0.001, mu=0.9, log2_scale=50.0)
+    ev = B.Evaluator(cnt_m, plan_m, None, defaultdict(lambda: None))
+    ev.plan = plan_m
+    ops = M.EncOps(cnt_m, cfg, None, defaultdict(lambda: None), boot=ev)
+    ops.masks = {lv: None for lv in range(orc_m.nQ)}
+    lo, T = plan_m.level_out, 2.0 ** 50
+    state = [M.Ct(cnt_m._ct(lo), lo, T) for _ in cfg.state_layout()]
+    smp = [([M.Ct(cnt_m._ct(lo), lo, T) for _ in range(cfg.tiles)], M.Ct(cnt_m._ct(lo), lo, T),
+            M.Ct(cnt_m._ct(lo), lo, T)) for _ in range(64)]
+    M.packed_step(ops, cfg, state, smp, 2)
+    t_step = _oracle_seconds(cnt_m.ops, t, L0, k0, len(MLP_P_BITS))
+    n_ks_step = sum(n for op, _, n in cnt_m.ops if op in ("rotate", "hoisted", "mult_relin"))
+    wall = time.perf_counter() - t_wall
+    sample = ("each of %d processes times ModUp, key inner product, ModDown, tensor, rescale, mul_plain, mul_scalar "
+              "and add once at N=2^16, level 25 (26 primes + 9 special); the oracle's own bootstrap / packed-step "
+              "code run with an operation counter gives the op list, each op priced by its level "
+              "(key switching x (l+1+k), element-wise x (l+1)); %.1f s wall" % (workers, wall))
+    return t, {
+        "value": workers / t_boot,
+        "unit": "bootstraps/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": sample,
+        "extrapolated_oracle_s_per_bootstrap": t_boot,
+        "key_switches_per_bootstrap": n_ks,
+        "ops_per_bootstrap": len(boot_ops),
+    }, {
+        "value": workers / t_step,
+        "unit": "train_steps/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": sample,
+        "extrapolated_oracle_s_per_step": t_step,
+        "key_switches_per_step": n_ks_step,
+    }
+
+
+def _counters(profile, dom):
+    """(HBM bytes per launch, VALUBusy %) of kernel class `dom` from the committed
+    rocprofv3 counter runs, or None each when absent or taken on another source
+    of the kernel."""
+    import hashlib
+
+    traffic = valu = None
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", profile + "_hbm_counters.json")))
+        ent = prof["kernels"].get(dom)
+        if ent and hashlib.sha256(open(os.path.join(ROOT, ent["source"]), "rb").read()).hexdigest() == ent["source_sha256"]:
+            traffic = ent["hbm_bytes_per_launch"]
+            valu = ent.get("valu_busy_pct")
+    except (OSError, KeyError, ValueError):
+        pass
+    return traffic, valu
+
+
+def ks_roofline(timers, dom, n_ks, ks_bytes, t_total_s, profile):
+    """The roofline block: the dominant kernel's achieved rate on method bytes
+    (the key switches it finishes per launch x the per-key-switch minimum:
+    the switched polynomial read, one polynomial written, the level's key
+    words once per call) next to its rate on its own I/O, and the rate of the
+    whole measured region on method bytes."""
+    ms, n, bts = timers[dom]
+    traffic, valu = _counters(profile, dom)
+    per_launch = ks_bytes / n if dom == "ntt_rows_fwd+moddown_ip" and n else None
+    achieved = ks_bytes / (ms * 1e-3) / 1e9 if per_launch else bts / (ms * 1e-3) / 1e9
+    io = bts / (ms * 1e-3) / 1e9
+    return {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a 1 GiB copy)",
+        "method_bytes_per_launch": per_launch,
+        "key_switches_per_launch": n_ks / n if per_launch else None,
+        "avg_launch_us": round(1e3 * ms / n, 2),
+        "launches": n,
+        "kernel_io": {"bytes_per_launch": bts / n, "GBps": round(io, 1), "frac": round(io / HBM_PEAK_GBS, 4)},
+        "valu_busy_pct": valu,
+        "whole_region": {
+            "key_switches": n_ks,
+            "method_bytes": ks_bytes,
+            "GBps": round(ks_bytes / t_total_s / 1e9, 1),
+            "frac": round(ks_bytes / t_total_s / 1e9 / HBM_PEAK_GBS, 4),
+        },
     }
 
 
@@ -679,7 +1016,7 @@ def bench_keyswitch(args, torch):
     t0 = time.time()
     ctx = Context(LOG_N, Q_BITS, P_BITS, ALPHA)
     ctx.set_lanes(args.lanes)
-    s, A, B = setup(ctx, count, ks)
+    s, A, B, z_last = setup(ctx, count, ks)
     L = ctx.L
     ctx.reserve(L, count)
     tuned = ctx.autotune(L - 1, count, os.path.join(os.path.expanduser("~"), ".cache", "rbk_tune.txt")
@@ -721,10 +1058,22 @@ def bench_keyswitch(args, torch):
     ctx.sync()
     torch.cuda.synchronize()
     timers = ctx.timer_read()
+    n_ks, ks_bytes = ctx.ks_stats()
     ctx.timer_enable(False)
 
-    # correctness spot check of the timed output: decrypt one rotation
+    # correctness spot check of the timed output: the last ciphertext's first,
+    # middle and last rotation decrypt to the rotated slot-wise product
     import numpy as np
+
+    prod = z_last[0] * z_last[1]
+    s_out = SCALE * SCALE / ctx.moduli[L]
+    check = 0.0
+    for j in sorted({0, len(ks) // 2, len(ks) - 1}):
+        got = ctx.decode(ctx.decrypt(out_h[count - 1, j], L - 1), L - 1, s_out).real
+        check = max(check, float(np.max(np.abs(got - np.roll(prod, -ks[j])))))
+    log("spot check: rotations of the last ciphertext decrypt within 2^%.1f of the rotated product" % np.log2(check))
+    if not check < 2.0 ** -20:
+        raise RuntimeError("the timed key-switch output does not decrypt to the expected slots (error %g)" % check)
 
     # ---------------------------------------------------------------- plain
     plain = None
@@ -760,32 +1109,8 @@ def bench_keyswitch(args, torch):
     kern = {k: {"ms_total": v[0], "launches": v[1], "avg_us": 1e3 * v[0] / v[1], "GBps": v[2] / (v[0] * 1e-3) / 1e9}
             for k, v in timers.items()}
     dom = max(timers, key=lambda k: timers[k][0])
-    ms, n, bts = timers[dom]
-    achieved = bts / (ms * 1e-3) / 1e9
-    traffic = None
-    try:
-        import hashlib
-
-        prof = json.load(open(os.path.join(ROOT, "profiles", "keyswitch_c1_hbm_counters.json")))
-        ent = prof["kernels"].get(dom)
-        if ent and hashlib.sha256(open(os.path.join(ROOT, ent["source"]), "rb").read()).hexdigest() == ent["source_sha256"]:
-            traffic = ent["hbm_bytes_per_launch"]   # counters are valid only for the unchanged kernel source
-    except (OSError, KeyError, ValueError):
-        traffic = None
-    roofline = {
-        "kernel": dom,
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a 1 GiB copy)",
-        "algorithmic_bytes_per_launch": bts / n,
-        "avg_launch_us": round(1e3 * ms / n, 2),
-        "launches": n,
-        "share_of_step": round(ms / (t_batched * 1e3 * args.steps), 3),
-    }
+    roofline = ks_roofline(timers, dom, n_ks, ks_bytes, t_batched * args.steps, "keyswitch_c1")
+    roofline["share_of_step"] = round(timers[dom][0] / (t_batched * 1e3 * args.steps), 3)
 
     # release the key-switch workload before the next parts
     del out_m, out_r, out_h, A, B
@@ -854,6 +1179,16 @@ def main():
         log("cpu baseline (oracle, bounded sample) ...")
         cpu = cpu_baseline()
         log("cpu baseline: %.3f key-switches/s" % cpu["value"])
+        if boot is not None or mlp is not None:
+            _, cb, cm = cpu_baseline_boot_and_train(cpu_workers())
+            cb["host_nproc"] = cm["host_nproc"] = cpu["host_nproc"]
+            cb["host_cpu"] = cm["host_cpu"] = cpu["host_cpu"]
+            if boot is not None:
+                boot["cpu_baseline"] = cb
+            if mlp is not None:
+                mlp["cpu_baseline"] = cm
+            log("cpu baseline: %.5f bootstraps/s, %.2e train_steps/s (extrapolated from op timings)" % (
+                cb["value"], cm["value"]))
 
     line = {
         "metric": "bootstraps/s + key-switches/s at N=2^16, batched vs plain; p99 latency",

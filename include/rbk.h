@@ -606,10 +606,17 @@ int rbk_set_lanes(rbk_ctx *ctx, int n);
  * and the algorithmic HBM bytes of those launches (the data each launch must
  * read and write, e.g. one read and one write of every limb for an NTT pass).
  * Both synchronise the stream. */
-int rbk_timer_enable(rbk_ctx *ctx, int on);   /* resets all timers */
+int rbk_timer_enable(rbk_ctx *ctx, int on);   /* resets all timers and the key-switch count */
 int rbk_timer_read(rbk_ctx *ctx, int cls, double *ms, uint64_t *launches, double *bytes);
 /* kernel name of class cls, NULL past the last class */
 const char *rbk_timer_name(int cls);
+/* Key switches issued since the last rbk_timer_enable (each switched
+ * polynomial of a relinearisation or rotation counts one) and their method
+ * bytes, the least HBM traffic the operation needs: per key switch at level
+ * l, 2 (l+1) N words (the switched polynomial read, one polynomial written),
+ * plus beta_l x 2 x (l+1+n_p) x N key words once per call (a batch shares
+ * them); 8 bytes a word. */
+int rbk_ks_stats(const rbk_ctx *ctx, uint64_t *n_keyswitch, double *method_bytes);
 
 #ifdef __cplusplus
 }

@@ -1093,6 +1093,15 @@ static int modup_run(rbk_ctx *c, const u64 *d, long d_stride, u64 *ext, long ext
     return RBK_OK;
 }
 
+void ks_account(rbk_ctx_impl *c, const int *levels, int count, int key_level)
+{
+    const double N = (double)c->N, w = 8.0;
+    for (int i = 0; i < count; i++) c->ks_bytes += 2.0 * (levels ? levels[i] + 1 : key_level + 1) * N * w;
+    const int L1 = key_level + 1, beta = (L1 + c->alpha - 1) / c->alpha;
+    c->ks_bytes += (double)beta * 2.0 * (L1 + c->nP) * N * w;
+    c->ks_units += (unsigned long)count;
+}
+
 // ModDown of u[count][2][E][N] into out (count x [2][l+1][N] at out_stride),
 // adding `add` as described in moddown_finish_launch.
 static int moddown_run(rbk_ctx *c, u64 *u, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
@@ -1100,6 +1109,7 @@ static int moddown_run(rbk_ctx *c, u64 *u, const u64 *add, long add_stride, u64 
 {
     const size_t N = c->N;
     const int L1 = level + 1, E = L1 + c->nP, nP = c->nP;
+    ks_account(c, nullptr, count, level);
     if (nP > 0) {
         HIPCK(hipMemcpy2DAsync(tp, nP * N * sizeof(u64), u + (size_t)L1 * N, E * N * sizeof(u64), nP * N * sizeof(u64),
                                2 * count, hipMemcpyDeviceToDevice, c->stream));
@@ -1124,6 +1134,7 @@ static int moddown_fused_run(rbk_ctx *c, const u64 *ext, long ext_stride, const 
     const size_t N = c->N;
     const int L1 = level + 1, nP = c->nP;
     if (!st) st = c->stream;
+    ks_account(c, nullptr, count, level);
     if (nP > 0) {
         moddown_head_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, st);
         bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, st);
@@ -1465,7 +1476,17 @@ extern "C" int rbk_timer_enable(rbk_ctx *c, int on)
     int rc = kt_collect(c);
     if (rc) return rc;
     for (int k = 0; k < KC_COUNT; k++) c->timers[k] = KTimer();
+    c->ks_units = 0;
+    c->ks_bytes = 0;
     c->timing = on != 0;
+    return RBK_OK;
+}
+
+extern "C" int rbk_ks_stats(const rbk_ctx *c, uint64_t *n_keyswitch, double *method_bytes)
+{
+    if (!c) return fail(RBK_EINVAL, "null context");
+    if (n_keyswitch) *n_keyswitch = c->ks_units;
+    if (method_bytes) *method_bytes = c->ks_bytes;
     return RBK_OK;
 }
 

@@ -170,6 +170,11 @@ extern "C" int rbk_mult_relin_rescale_list(rbk_ctx *c, const uint64_t *d_a, cons
                          (long)(Em * N), Lm, count, dcts, st);
     run_list(dev, P_ext, false, st);
     // key inner product and ModDown, plus (d0, d1)
+    {
+        std::vector<int> lv(count);
+        for (int i = 0; i < count; i++) lv[i] = cts[i].level;
+        ks_account(c, lv.data(), count, Lm);
+    }
     ip_p_list_launch(c, ext, (long)(betam * Em * N), (long)(Em * N), c->relin.data, tp, Lm, count, dcts, st);
     ntt_launch(c, tp, (long)(nP * N), 2 * count, (int)nP, LimbMap{0, 0, c->nQ}, true, st);
     bconv_down_list_launch(c, tp, conv, (long)(L1m * N), Lm, count, dcts, st);

@@ -130,6 +130,12 @@ struct rbk_ctx_impl {
     hipStream_t side[RBK_LANES] = {};
     hipEvent_t side_ev[RBK_LANES + 1] = {};
     mutable KTimer timers[KC_COUNT];
+    // key switches since the last rbk_timer_enable and their method bytes:
+    // per key switch at level l the switched polynomial is read and one
+    // polynomial written (2 (l+1) N words), plus the key words of that level
+    // (beta_l x 2 x (l+1+k) x N) once per call, shared by the call's batch
+    unsigned long ks_units = 0;
+    double ks_bytes = 0;
     mutable std::vector<hipEvent_t> event_pool;
 };
 
@@ -158,6 +164,8 @@ void kt_begin(const rbk_ctx_impl *c, int cls, hipStream_t st);
 void kt_end(const rbk_ctx_impl *c, int cls, double bytes, hipStream_t st);
 
 // ---- helpers implemented in api.hip ----
+// count `count` key switches at `level` (one call, the key read once) for rbk_ks_stats
+void ks_account(rbk_ctx_impl *c, const int *levels, int count, int key_level);
 u64 *ws_reserve(rbk_ctx_impl *c, size_t words);
 // free a replaced device buffer, or keep it until the last graph is destroyed
 void release_buffer(rbk_ctx_impl *c, void *p);

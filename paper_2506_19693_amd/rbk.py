@@ -209,6 +209,7 @@ SIGNATURES = {
     "rbk_timer_enable": (ci, [vp, ci]),
     "rbk_timer_read": (ci, [vp, ci, dblp, u64p, dblp]),
     "rbk_timer_name": (ctypes.c_char_p, [ci]),
+    "rbk_ks_stats": (ci, [vp, u64p, dblp]),
 }
 
 _LIB = None
@@ -708,6 +709,12 @@ class Context:
     # ---------------------------------------------------------------- timers
     def timer_enable(self, on=True):
         _check(self.lib.rbk_timer_enable(self.h, 1 if on else 0))
+
+    def ks_stats(self):
+        """(key switches, method bytes) since the last timer_enable."""
+        n, b = ctypes.c_uint64(), ctypes.c_double()
+        _check(self.lib.rbk_ks_stats(self.h, ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
 
     def timer_read(self):
         """{kernel name: (ms, launches, algorithmic bytes)} of every timed kernel."""
