@@ -313,6 +313,28 @@ int rbk_ntt_list(rbk_ctx *ctx, const rbk_ntt_item *items, int n, int inverse);
 int rbk_mult_relin_rescale_list(rbk_ctx *ctx, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out,
                                 const int *levels, int count);
 
+/* Ciphertexts of DIFFERENT contexts (ring degree, modulus chain, special
+ * primes, relinearisation key; all on the device of ctx) in one set of
+ * launches: item i computes d_out = Rescale(mult_relin(d_a, d_b)) in its own
+ * context at its own level (1..L of that context), exactly as
+ * rbk_mult_relin followed by rbk_rescale there (Section 3: mult, then the
+ * switch to the next prime).  d_a, d_b: [2][level+1][N_i], d_out:
+ * [2][level][N_i], NTT domain; an item's inputs and output must not overlap.
+ * Runs on ctx's stream with ctx's workspace and descriptor arena; the item
+ * contexts are only read (tables and keys) and must not be in use on another
+ * thread.  Ring degrees 2^4..2^16 (the list transform), at most 16 primes per
+ * digit, 16 special primes and 8 digits.  Not capturable (descriptors are
+ * uploaded per call). */
+typedef struct {
+    rbk_ctx *ctx;
+    const uint64_t *d_a;
+    const uint64_t *d_b;
+    uint64_t *d_out;
+    int level;
+    int pad;
+} rbk_mr_item;
+int rbk_mult_relin_rescale_multi(rbk_ctx *ctx, const rbk_mr_item *items, int n);
+
 /* ---- approximate bootstrapping (Section 3: encoding step, scaled-sine
  *      modular reduction, decoding step; Cheon et al. 2018, Bossuat et al.
  *      2021) ------------------------------------------------------------- */

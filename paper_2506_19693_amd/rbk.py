@@ -105,6 +105,17 @@ class RbkBootParams(ctypes.Structure):
     ]
 
 
+class RbkMrItem(ctypes.Structure):
+    _fields_ = [
+        ("ctx", ctypes.c_void_p),
+        ("d_a", ctypes.c_void_p),
+        ("d_b", ctypes.c_void_p),
+        ("d_out", ctypes.c_void_p),
+        ("level", ctypes.c_int),
+        ("pad", ctypes.c_int),
+    ]
+
+
 class RbkNttItem(ctypes.Structure):
     _fields_ = [
         ("ctx", ctypes.c_void_p),
@@ -168,6 +179,7 @@ SIGNATURES = {
     "rbk_rescale_batch_noalloc": (ci, [vp, vp, vp, ci, ci]),
     "rbk_ntt_list": (ci, [vp, ctypes.POINTER(RbkNttItem), ci, ci]),
     "rbk_mult_relin_rescale_list": (ci, [vp, vp, vp, vp, ctypes.POINTER(ci), ci]),
+    "rbk_mult_relin_rescale_multi": (ci, [vp, ctypes.POINTER(RbkMrItem), ci]),
     "rbk_rotate_hoisted_batch": (ci, [vp, vp, i64p, ci, vp, ci, ci]),
     "rbk_boot_setup": (ci, [vp, ctypes.POINTER(RbkBootParams)]),
     "rbk_boot_rotations": (ci, [vp, i64p, ci]),
@@ -292,6 +304,18 @@ def _close_all():
         m.close()
     for c in list(_LIVE_CONTEXTS):
         c.close()
+
+
+def mult_relin_rescale_multi(host, jobs, outs=None):
+    """jobs: [(context, a, b, level)] of ciphertexts from any contexts (device
+    tensors [2][level+1][N]); one set of launches on host's stream.  Returns
+    the outputs [2][level][N]."""
+    if outs is None:
+        outs = [ctx.empty_ct(lv - 1) for ctx, _, _, lv in jobs]
+    arr = (RbkMrItem * len(jobs))(*[RbkMrItem(ctx.h, _ptr(a), _ptr(b), _ptr(o), lv, 0)
+                                   for (ctx, a, b, lv), o in zip(jobs, outs)])
+    _check(host.lib.rbk_mult_relin_rescale_multi(host.h, arr, len(jobs)))
+    return outs
 
 
 def gauss_table():
