@@ -55,18 +55,25 @@ def parse():
     ap.add_argument("--no-boot", action="store_true", help="skip the bootstrap throughput part")
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP train_step part")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving part")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-ring-degree part")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-lambda", type=float, default=0.0,
                     help="Poisson arrival rate, jobs/s (default: 0.8 x the capacity measured in the same run)")
     ap.add_argument("--serve-budget-gib", type=float, default=150.0)
-    ap.add_argument("--serve-max-batch", type=int, default=64)
-    ap.add_argument("--serve-max-boot", type=int, default=16)
+    ap.add_argument("--serve-max-batch", type=int, default=32)
+    ap.add_argument("--serve-max-boot", type=int, default=8)
     ap.add_argument("--serve-mlp-b", type=int, default=8, help="samples per training step of serving jobs")
     ap.add_argument("--lanes", type=int, default=2,
                     help="ModDown lanes of hoisted-rotation batches (1: no overlapping kernels, as for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device to device before the timed region (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def _tune_cache():
+    """the autotuner's text cache (per user), or None when there is no cache directory"""
+    d = os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(d, "rbk_tune.txt") if os.path.isdir(d) else None
 
 
 def percentile(xs, p):
@@ -147,6 +154,9 @@ def bench_bootstrap(args, torch):
         gal = 2 * N - 1 if k == "conj" else ctx.galois_elt(k)
         ctx.keygen_galois(gal, *S.key_randomness(g, ctx.beta, ctx.moduli, N))
     count = 16
+    tuned = ctx.autotune(ctx.L, count, _tune_cache())
+    log("bootstrap: autotuned NTT split 2^%d, chunk %d, %d ciphertexts per inner-product thread" % (
+        tuned["logC"], tuned["chunk"], tuned["cpc"]))
     scales = [2.0 ** (35 + 10 * i / 15) for i in range(count)]
     zs = [S.uniform_slots(g, N // 2) for _ in range(count)]
     cts = ctx.empty(count, 2, 1, N)
@@ -209,6 +219,7 @@ def bench_bootstrap(args, torch):
         "plain_latency_ms_p99": percentile(lat, 99),
         "output_level": lo,
         "max_slot_error_log2": float(np.log2(err)),
+        "autotuned": tuned,
         "key_switches_per_bootstrap": n_ks / count,
         "roofline": roof,
         "kernels": {k: {"ms": round(v[0], 3), "launches": v[1], "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)}
@@ -254,6 +265,9 @@ def bench_train_step(args, torch):
     lo = ctx.boot_levels[3]
     T = 2.0 ** 50
     tiles = mlp.tiles
+    tuned = ctx.autotune(lo, b, _tune_cache())
+    log("train_step: autotuned NTT split 2^%d, chunk %d, %d ciphertexts per inner-product thread" % (
+        tuned["logC"], tuned["chunk"], tuned["cpc"]))
 
     def enc(v):
         return ctx.encrypt(ctx.encode(v, lo, T), lo, *S.encryption_randomness(g, N))
@@ -361,6 +375,7 @@ def bench_train_step(args, torch):
         "bootstraps_per_step": mlp.n_state,
         "weight_level": lo,
         "depth": mlp.depth,
+        "autotuned": tuned,
         "key_switches_per_step": n_ks,
         "roofline": roof,
         "kernels": {k: {"ms": round(v[0], 3), "launches": v[1], "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)}
@@ -550,11 +565,13 @@ def _serial_run(tenants, jobs, torch):
     (or one sample) per call."""
     t0 = time.perf_counter()
     lat = []
+    busy = 0.0
     step = {id(tn): {w: 10 ** 6 for w in tn.mlps} for tn in tenants}
     for (t_arr, ti, kind, p) in jobs:
         now = time.perf_counter() - t0
         if t_arr > now:
             time.sleep(t_arr - now)
+        t_start = time.perf_counter()
         tn = tenants[ti]
         ctx = tn.ctx
         if kind == "mult":
@@ -573,8 +590,9 @@ def _serial_run(tenants, jobs, torch):
                 tn.mlps[w].train_step(x, ye, yr, tn.lo, tn.T, step[id(tn)][w], per_sample=True)
                 step[id(tn)][w] += 1
         torch.cuda.synchronize()
+        busy += time.perf_counter() - t_start
         lat.append((time.perf_counter() - t0 - t_arr) * 1e3)
-    return time.perf_counter() - t0, lat
+    return time.perf_counter() - t0, lat, busy
 
 
 def bench_serve(args, torch):
@@ -632,9 +650,11 @@ def bench_serve(args, torch):
         },
     }
     if not args.no_plain:
-        mk_s, lat_s = _serial_run(tenants, jobs, torch)
-        log("serving: serial plain at the same arrivals done in %.1f s" % mk_s)
+        mk_s, lat_s, busy_s = _serial_run(tenants, jobs, torch)
+        log("serving: serial plain at the same arrivals done in %.1f s (%.1f s busy: %.2f jobs/s capacity)" % (
+            mk_s, busy_s, len(jobs) / busy_s))
         out["serial_plain"] = {
+            "capacity_jobs_per_s": len(jobs) / busy_s,
             "jobs_per_s": len(jobs) / mk_s,
             "makespan_s": mk_s,
             "latency_ms_p50": percentile(lat_s, 50),
@@ -710,6 +730,150 @@ def cpu_baseline():
                   "+ 1 hoisted rotation each (2 key switches), %.1f s wall (single-process time %.1f s)" % (
                       workers, wall, min(dts)),
     }
+
+
+def bench_graph_small(args, torch):
+    """Launch-bound work where a captured graph pays: the small-ring pipeline
+    (N = 2^12, 50 + 3 x 40-bit chain, one 50-bit special prime, one prime per
+    digit): mult_relin -> rescale -> rotations +1 and +7 (hoisted) -> add, on
+    one ciphertext pair, eager (one launch sequence per call) vs one graph
+    replay."""
+    import numpy as np
+
+    from paper_2506_19693_amd import Context
+
+    ctx = Context(12, [50, 40, 40, 40], [50], 1)
+    ctx.set_lanes(1)
+    ctx.keygen(5, 0, [1, 7])
+    N, L = ctx.N, ctx.L
+    g = np.random.default_rng(5)
+    x = ctx.empty_ct(L, 1)
+    y = ctx.empty_ct(L, 1)
+    zx, zy = g.uniform(-1, 1, N // 2), g.uniform(-1, 1, N // 2)
+    x[0].copy_(ctx.encrypt_seeded(ctx.encode(zx, L, 2.0 ** 40), L, 5, 0))
+    y[0].copy_(ctx.encrypt_seeded(ctx.encode(zy, L, 2.0 ** 40), L, 5, 1))
+    m = ctx.empty_ct(L, 1)
+    r = ctx.empty_ct(L - 1, 1)
+    h = ctx.empty(1, 2, 2, L, N)
+    out = ctx.empty_ct(L - 1)
+
+    def pipeline():
+        ctx.mult_relin_batch(x, y, L, out=m)
+        ctx.rescale_batch(m, L, out=r)
+        ctx.rotate_hoisted_batch(r, [1, 7], L - 1, out=h)
+        _check_rc(ctx, ctx.lib.rbk_add(ctx.h, _dptr(h[0, 0]), _dptr(h[0, 1]), _dptr(out), L - 1, 2))
+
+    pipeline()
+    ctx.sync()
+    want = out.clone()
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pipeline()
+    ctx.sync()
+    t_e = (time.perf_counter() - t0) / reps
+    graph = ctx.capture(pipeline)
+    graph.launch()
+    ctx.sync()
+    same = bool(torch.equal(out, want))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.launch()
+    ctx.sync()
+    t_g = (time.perf_counter() - t0) / reps
+    graph.close()
+    s_out = 2.0 ** 80 / ctx.moduli[L]
+    got = ctx.decode(ctx.decrypt(out, L - 1), L - 1, s_out).real
+    p = zx * zy
+    err = float(np.max(np.abs(got - (np.roll(p, -1) + np.roll(p, -7)))))
+    ctx.close()
+    return {
+        "workload": "N=2^12, 50 + 3x40-bit chain + one 50-bit special prime, one prime per digit: mult_relin, "
+                    "rescale, hoisted rotations +1 and +7, add, on one ciphertext pair",
+        "eager_us": t_e * 1e6,
+        "graph_us": t_g * 1e6,
+        "graph_speedup": t_e / t_g,
+        "graph_equals_eager": same,
+        "max_slot_error_log2": float(np.log2(err)),
+    }
+
+
+def _dptr(t):
+    import ctypes
+
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_rc(ctx, rc):
+    if rc < 0:
+        raise RuntimeError("librbk error %d: %s" % (rc, ctx.lib.rbk_last_error().decode()))
+
+
+MIXED_RINGS = [14, 15, 16]
+MIXED_COUNT = 16
+
+
+def bench_mixed(args, torch):
+    """Mixed ring degrees: 16 ciphertexts at each of N = 2^14, 2^15, 2^16 (the
+    serving chain, 31 primes + 11 special, at levels 8..30), each multiplied,
+    relinearised and rescaled: one multi-context call vs one batched call per
+    context vs one call per ciphertext."""
+    import synth_inputs as S
+    from paper_2506_19693_amd import Context, rbk
+
+    ctxs = [Context(ln, SERVE_Q_BITS, SERVE_P_BITS, SERVE_ALPHA) for ln in MIXED_RINGS]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    g = S.rng(12, 1)
+    jobs, per_ctx = [], []
+    for ctx in ctxs:
+        N = ctx.N
+        ctx.set_secret(S.ternary(g, N))
+        ctx.keygen_relin(*S.key_randomness(g, ctx.beta, ctx.moduli, N))
+        levels = [int(x) for x in g.integers(8, 31, size=MIXED_COUNT)]
+        lm = max(levels)
+        A = _dev_residues(ctx, gen, (MIXED_COUNT, 2), lm)
+        B = _dev_residues(ctx, gen, (MIXED_COUNT, 2), lm)
+        mine = []
+        for i, lv in enumerate(levels):
+            a = A[i][:, : lv + 1].contiguous()
+            b = B[i][:, : lv + 1].contiguous()
+            jobs.append((ctx, a, b, lv))
+            mine.append((a, b, lv))
+        per_ctx.append((ctx, A, B, levels))
+    host = ctxs[0]
+    outs = [c.empty_ct(lv - 1) for c, _, _, lv in jobs]
+
+    def multi():
+        rbk.mult_relin_rescale_multi(host, jobs, outs)
+
+    def per_context():
+        for ctx, A, B, levels in per_ctx:
+            ctx.mult_relin_rescale_list(A, B, levels)
+
+    def plain():
+        for ctx, a, b, lv in jobs:
+            ctx.rescale(ctx.mult_relin(a, b, lv), lv)
+
+    res = {"workload": "mixed ring degrees: %d ciphertexts at each of N=2^14, 2^15, 2^16, levels 8-30 of a 31-prime "
+                       "chain (60 + 30x50) + 11 special primes, mult_relin + rescale each" % MIXED_COUNT,
+           "key_switches_per_call": len(jobs)}
+    for name, fn in (("multi_context_call", multi), ("per_context_list_calls", per_context), ("plain", plain)):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[name] = {"ms": dt * 1e3, "key_switches_per_s": len(jobs) / dt}
+    res["multi_vs_plain"] = res["plain"]["ms"] / res["multi_context_call"]["ms"]
+    res["multi_vs_per_context"] = res["per_context_list_calls"]["ms"] / res["multi_context_call"]["ms"]
+    del jobs, outs, per_ctx
+    for c in ctxs:
+        c.close()
+    return res
 
 
 # ---------------------------------------------------------------- oracle cost of the bootstrap and train_step legs
@@ -1019,8 +1183,7 @@ def bench_keyswitch(args, torch):
     s, A, B, z_last = setup(ctx, count, ks)
     L = ctx.L
     ctx.reserve(L, count)
-    tuned = ctx.autotune(L - 1, count, os.path.join(os.path.expanduser("~"), ".cache", "rbk_tune.txt")
-                         if os.path.isdir(os.path.join(os.path.expanduser("~"), ".cache")) else None)
+    tuned = ctx.autotune(L - 1, count, _tune_cache())
     log("autotuned: NTT split 2^%d columns, NTT chunk %d limbs, %d ciphertexts per inner-product thread" % (
         tuned["logC"], tuned["chunk"], tuned["cpc"]))
     out_m = ctx.empty_ct(L, count)
@@ -1163,6 +1326,21 @@ def main():
             mlp["train_steps_per_s_batched"], mlp["ms_per_step_batched"], mlp["train_steps_per_s_graph"],
             mlp["train_steps_per_s_plain"], mlp["bootstrap_share_of_step"]))
 
+    small = None
+    if not args.no_mixed:
+        small = bench_graph_small(args, torch)
+        log("small ring pipeline: eager %.1f us, graph %.1f us (%.2fx), graph == eager: %s, error 2^%.1f" % (
+            small["eager_us"], small["graph_us"], small["graph_speedup"], small["graph_equals_eager"],
+            small["max_slot_error_log2"]))
+
+    mixed = None
+    if not args.no_mixed:
+        torch.cuda.empty_cache()
+        log("mixed rings: 3 x %d ciphertexts at N=2^14, 2^15, 2^16 ..." % MIXED_COUNT)
+        mixed = bench_mixed(args, torch)
+        log("mixed rings: one call %.2f ms, per-context calls %.2f ms, plain %.2f ms" % (
+            mixed["multi_context_call"]["ms"], mixed["per_context_list_calls"]["ms"], mixed["plain"]["ms"]))
+
     serve = None
     if not args.no_serve:
         torch.cuda.empty_cache()
@@ -1218,6 +1396,8 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in ksw["kernels"].items()} if ksw else None,
         "bootstrap": boot,
         "train_step": mlp,
+        "mixed_rings": mixed,
+        "graph_small_ring": small,
         "serving": serve,
         "cpu_baseline": cpu,
     }

@@ -129,6 +129,66 @@ __global__ __launch_bounds__(NTT_THREADS) void k_ntt_rows(u64 *data, long poly_s
     ntt_rows_tile<INV>(base, s, T, map.prime(limb), logN, logC, rows_per_tile, blockIdx.x);
 }
 
+// Whole transform of one limb of a ring of at most NTT_TILE coefficients in
+// one workgroup: the limb and every twiddle (with its Shoup quotient) are
+// staged in LDS first (96 KB at N = 2^12), so no stage waits on a global
+// twiddle load.  Same stages and ranges as the row pass with logC = logN.
+template <bool INV>
+__global__ __launch_bounds__(NTT_THREADS) void k_ntt_small(u64 *data, long poly_stride, LimbMap map, NttTables T,
+                                                           int logN)
+{
+    __shared__ u64 s[NTT_TILE], sw[NTT_TILE], sws[NTT_TILE];
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    const int pr = map.prime(limb);
+    const int N = 1 << logN;
+    const PrimeC pc = T.pc[pr];
+    const u64 q = pc.q, q2 = 2 * q;
+    const u64 *tw = (INV ? T.itw : T.tw) + (size_t)pr * N;
+    const u64 *tws = (INV ? T.itw_sh : T.tw_sh) + (size_t)pr * N;
+    u64 *g = data + (size_t)poly * poly_stride + ((size_t)limb << logN);
+    for (int i = threadIdx.x; i < N; i += NTT_THREADS) {
+        s[i] = g[i];
+        sw[i] = tw[i];
+        sws[i] = tws[i];
+    }
+    __syncthreads();
+    const int half = N >> 1;
+    if (!INV) {
+        for (int st = 0; st < logN; st++) {
+            const int lt = logN - 1 - st;  // log2 of the butterfly distance
+            for (int b = threadIdx.x; b < half; b += NTT_THREADS) {
+                const int grp = b >> lt, off = b & ((1 << lt) - 1);
+                const int x0 = (grp << (lt + 1)) + off;
+                const int ti = (1 << st) + grp;
+                bfly_ct(s[x0], s[x0 + (1 << lt)], sw[ti], sws[ti], q, q2);
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < N; i += NTT_THREADS) g[i] = csub(csub(s[i], q2), q);
+    } else {
+        for (int lt = 0; lt < logN; lt++) {
+            const int h = 1 << (logN - 1 - lt);
+            const bool last = lt == logN - 1;
+            for (int b = threadIdx.x; b < half; b += NTT_THREADS) {
+                const int grp = b >> lt, off = b & ((1 << lt) - 1);
+                const int x0 = (grp << (lt + 1)) + off;
+                u64 &x = s[x0];
+                u64 &y = s[x0 + (1 << lt)];
+                if (!last) {
+                    bfly_gs(x, y, sw[h + grp], sws[h + grp], q, q2);
+                } else {
+                    const u64 sum = csub(x + y, q2);
+                    const u64 d = x + q2 - y;
+                    x = shoup_lazy(sum, pc.ninv, pc.ninv_sh, q);
+                    y = shoup_lazy(d, T.last[pr], T.last_sh[pr], q);
+                }
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < N; i += NTT_THREADS) g[i] = csub(s[i], q);
+    }
+}
+
 // Column pass over R = 2^(logN-logC) rows and 'cols' adjacent columns.
 // Forward: stages 0 .. r-1, output in [0, 4q).  Inverse: distances C .. N/2,
 // N^-1 folded into the last stage, output in [0, q).
@@ -1243,9 +1303,9 @@ void ntt_launch(const rbk_ctx_impl *c, u64 *data, long poly_stride, int npoly, i
         int cls = inverse ? KC_NTT_ROWS_INV : KC_NTT_ROWS_FWD;
         kt_begin(c, cls, st);
         if (inverse)
-            hipLaunchKernelGGL(k_ntt_rows<true>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, 1);
+            hipLaunchKernelGGL(k_ntt_small<true>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN);
         else
-            hipLaunchKernelGGL(k_ntt_rows<false>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN, logC, 1);
+            hipLaunchKernelGGL(k_ntt_small<false>, grid, dim3(NTT_THREADS), 0, st, data, poly_stride, map, T, logN);
         kt_end(c, cls, bytes, st);
         return;
     }
