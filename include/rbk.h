@@ -571,7 +571,8 @@ int rbk_server_destroy(rbk_server *srv);
 
 /* Launch parameters that change speed but never a residue (cfg: int[3]):
  *   cfg[0] = logC, the NTT split (a limb is a 2^(logN-logC) x 2^logC matrix;
- *            for 13 <= logN <= 16 both sides must be 2^6 .. 2^8);
+ *            for 13 <= logN <= 16 both sides must be 2^6 .. 2^8, for
+ *            logN = 17 logC is 8 or 9);
  *   cfg[1] = ciphertexts per thread of the fused key inner products (1..64);
  *   cfg[2] = NTT chunk: limbs covered by one pair of pass launches before
  *            the next chunk (>= 0; 0 = the whole batch at once).

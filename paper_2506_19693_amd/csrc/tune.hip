@@ -3,7 +3,8 @@
 // Three launch parameters leave every residue unchanged but move the speed:
 //  * the NTT split: a limb of N = 2^logN residues is transformed as an
 //    R x C matrix, C = 2^logC (column pass, then row pass); the register
-//    kernels support R, C in 2^6 .. 2^8;
+//    kernels support R, C in 2^6 .. 2^8 (N = 2^13 .. 2^16); N = 2^17 takes the
+//    general two-pass kernels with C = 2^8 or 2^9;
 //  * the NTT chunk: how many limbs one pair of pass launches covers before
 //    the next chunk starts (the intermediate of a chunk the size of the
 //    memory-side cache is read back from it rather than from HBM);
@@ -126,6 +127,7 @@ int pick_fastest(rbk_ctx *c, int n, Set set, Run run, u64 *scrub, int rounds = 3
 bool split_ok(int logN, int logC)
 {
     const int r = logN - logC;
+    if (logN == 17) return logC == 8 || logC == 9;  // general two-pass kernels (tiles of 4096 words)
     return logN >= 13 && logN <= 16 && r >= 6 && r <= 8 && logC >= 6 && logC <= 8;
 }
 
@@ -179,7 +181,7 @@ extern "C" int rbk_autotune(rbk_ctx *c, int level, int count, const char *cache_
         };
         // NTT split
         std::vector<int> splits;
-        for (int cand = 6; cand <= 8; cand++)
+        for (int cand = 6; cand <= 9; cand++)
             if (split_ok(c->logN, cand)) splits.push_back(cand);
         if (!splits.empty()) {
             const int k = pick_fastest(c, (int)splits.size(), [&](int i) { c->ntt_logC = splits[i]; }, ntt_pair, scrub);

@@ -125,7 +125,8 @@ def test_keyswitch_n16_plain_and_list_match_oracle():
 # ---------------------------------------------------------------- N = 2^14, 2^15: every register split
 
 MID = dict(qbits=[60] + [50] * 5, pbits=[60] * 3, alpha=2)
-SPLITS = [(14, 6), (14, 7), (14, 8), (15, 7), (15, 8)]
+# N = 2^17 (the paper's larger ring) takes the general two-pass transforms
+SPLITS = [(14, 6), (14, 7), (14, 8), (15, 7), (15, 8), (17, 8), (17, 9)]
 
 
 @pytest.mark.timeout(600)

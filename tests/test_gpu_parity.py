@@ -77,7 +77,7 @@ def down(p, t, level):
 
 # ---------------------------------------------------------------- NTT
 
-@pytest.mark.parametrize("logN", [4, 10, 12, 13, 14, 15, 16])
+@pytest.mark.parametrize("logN", [4, 10, 12, 13, 14, 15, 16, 17])
 def test_ntt_matches_oracle(logN):
     from paper_2506_19693_amd import Context, to_device, to_host
 
