@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP train_step part")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving part")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-ring-degree part")
+    ap.add_argument("--no-paper-mlps", action="store_true", help="skip the paper's eMLP architectures")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-lambda", type=float, default=0.0,
                     help="Poisson arrival rate, jobs/s (default: 0.8 x the capacity measured in the same run)")
@@ -809,6 +810,102 @@ def _check_rc(ctx, rc):
         raise RuntimeError("librbk error %d: %s" % (rc, ctx.lib.rbk_last_error().decode()))
 
 
+# The paper's own architectures (Section 5.1, Table 3) on synthetic
+# MNIST-shaped data (784 features in [0, 1), 10 one-hot classes; Table 8's
+# MNIST settings: b = 48, gamma = 0.001, eta = 0.001 / 0.005):
+#   eMLP-1: RE-Block(32), N = 2^16, depth 8;   eMLP-2: RE-Block(64) -> CE-Block(32), N = 2^17, depth 11.
+# Chains: depth + the 14 levels this bootstrap consumes, 49-bit primes for
+# eMLP-1 (Delta = 2^49); eMLP-2 uses 50-bit primes (Delta = 2^50: the
+# bootstrap's q_0 / Delta >= 4 with a 60-bit q_0 excludes the paper's 2^59).
+PAPER_MLPS = {
+    "eMLP-1": dict(logN=16, widths=[32], r=1024, c=32, qbits=[60] + [49] * 22, pbits=[60] * 8, alpha=8,
+                   log2_scale=49.0, eta=0.001),
+    "eMLP-2": dict(logN=17, widths=[64, 32], r=1024, c=64, qbits=[60] + [50] * 25, pbits=[60] * 9, alpha=9,
+                   log2_scale=50.0, eta=0.005),
+}
+
+
+def bench_paper_mlp(name, args, torch):
+    """Seconds per encrypted training iteration of one of the paper's
+    architectures: keys and encryptions drawn in the library from a seed,
+    float64 weights set through the library, 48 samples per step, every
+    weight and velocity bootstrapped each step."""
+    import numpy as np
+
+    import synth_inputs as S
+    from paper_2506_19693_amd import Context, Mlp
+
+    p = PAPER_MLPS[name]
+    k0, o, b = 784, 10, 48
+    ctx = Context(p["logN"], p["qbits"], p["pbits"], p["alpha"])
+    ctx.boot_setup(K=23, degree=59, double_angle=2, cts_levels=3, stc_levels=3, log2_rho=2)
+    mlp = Mlp(ctx, k0, p["widths"], o, p["r"], p["c"], act=(1.0, 1.0, 0.0), gamma=0.001, eta=p["eta"], mu=0.9,
+              log2_scale=p["log2_scale"])
+    lo = ctx.boot_levels[3]
+    if lo < mlp.depth:
+        raise RuntimeError("%s: bootstrap output level %d below the step's depth %d" % (name, lo, mlp.depth))
+    t0 = time.perf_counter()
+    ctx.keygen(21, 192, sorted(set(mlp.rotations()) | set(ctx.boot_rotations())), conj=True)
+    g = S.rng(22, p["logN"])
+    dims = [(k0, p["widths"][0])] + [(p["widths"][h - 1], p["widths"][h]) for h in range(1, len(p["widths"]))]
+    mlp.set_weights(S.mlp_weights(g, dims), S.mlp_weights(g, [(k, o) for _, k in dims]), level=lo, seed=23)
+    X, Y = S.mlp_batch(g, b, k0, o)
+    r, c, N = p["r"], p["c"], ctx.N
+    T = 2.0 ** p["log2_scale"]
+    tiles = mlp.tiles
+    x = ctx.empty(b, tiles, 2, lo + 1, N)
+    ye = ctx.empty(b, 2, lo + 1, N)
+    yr = ctx.empty(b, 2, lo + 1, N)
+    idx = 1000
+    for i in range(b):
+        for t in range(tiles):
+            M = np.zeros((r, c))
+            seg = X[i, t * r: (t + 1) * r]
+            M[: len(seg), :] = seg[:, None]
+            x[i, t].copy_(ctx.encrypt_seeded(ctx.encode(M.ravel(), lo, T), lo, 23, idx))
+            idx += 1
+        M = np.zeros((r, c))
+        M[:o, :] = Y[i][:, None]
+        ye[i].copy_(ctx.encrypt_seeded(ctx.encode(M.ravel(), lo, T), lo, 23, idx))
+        M = np.zeros((r, c))
+        M[:, :o] = Y[i]
+        yr[i].copy_(ctx.encrypt_seeded(ctx.encode(M.ravel(), lo, T), lo, 23, idx + 1))
+        idx += 2
+    ctx.sync()
+    t_setup = time.perf_counter() - t0
+    step = 1
+    for _ in range(max(1, args.warmup)):
+        mlp.train_step(x, ye, yr, lo, T, step)
+        step += 1
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mlp.train_step(x, ye, yr, lo, T, step)
+        step += 1
+    ctx.sync()
+    t_it = (time.perf_counter() - t0) / args.steps
+    Ws, Wst, Vs, Vst = mlp.get_weights(dims, o)
+    finite = all(np.all(np.isfinite(w)) and np.max(np.abs(w)) < 4.0 for w in Ws + Wst + Vs + Vst)
+    res = {
+        "workload": "%s (paper Table 3): %s, N=2^%d, %d primes (%s) + %d special, HW-192 secret, 784 -> %s -> 10 "
+                    "classes, r=%d c=%d, %d samples per step, paper activation z + z^2, gamma 0.001, eta %g, mu 0.9; "
+                    "every W and V bootstrapped each step" % (
+                        name, " -> ".join(("RE" if h % 2 == 0 else "CE") + "(%d)" % w for h, w in enumerate(p["widths"])),
+                        p["logN"], len(p["qbits"]), "60 + %dx%d" % (len(p["qbits"]) - 1, p["qbits"][1]),
+                        len(p["pbits"]), "-".join(str(w) for w in p["widths"]), r, c, b, p["eta"]),
+        "s_per_iteration": t_it,
+        "depth": mlp.depth,
+        "weight_level": lo,
+        "setup_s": t_setup,
+        "weights_decrypt_finite_and_bounded": bool(finite),
+        "paper_cpu_s_per_iteration": {"eMLP-1": 190.32, "eMLP-2": 629.65}[name],
+        "paper_hardware": "2x Intel Xeon Gold 5318S, OpenFHE (context only: other hardware, other software)",
+    }
+    mlp.close()
+    ctx.close()
+    return res
+
+
 MIXED_RINGS = [14, 15, 16]
 MIXED_COUNT = 16
 
@@ -1326,6 +1423,16 @@ def main():
             mlp["train_steps_per_s_batched"], mlp["ms_per_step_batched"], mlp["train_steps_per_s_graph"],
             mlp["train_steps_per_s_plain"], mlp["bootstrap_share_of_step"]))
 
+    paper = None
+    if not args.no_paper_mlps:
+        paper = {}
+        for name in PAPER_MLPS:
+            torch.cuda.empty_cache()
+            log("%s: ..." % name)
+            paper[name] = bench_paper_mlp(name, args, torch)
+            log("%s: %.2f s per iteration (paper, on CPUs: %.2f s)" % (
+                name, paper[name]["s_per_iteration"], paper[name]["paper_cpu_s_per_iteration"]))
+
     small = None
     if not args.no_mixed:
         small = bench_graph_small(args, torch)
@@ -1396,6 +1503,7 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in ksw["kernels"].items()} if ksw else None,
         "bootstrap": boot,
         "train_step": mlp,
+        "paper_mlps": paper,
         "mixed_rings": mixed,
         "graph_small_ring": small,
         "serving": serve,

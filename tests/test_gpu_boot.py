@@ -170,3 +170,22 @@ def test_bootstrap_full_size_batch():
     err = _max_err(d, out, lo, so, zs)
     print("full-size bootstrap: output level %d, max slot error 2^%.2f" % (lo, err))
     assert err < -12
+
+
+def test_bootstrap_n17_precision():
+    """N = 2^17 (the paper's eMLP-2/3 ring), full 2^16 slots, HW-192 secret,
+    chain 60 + 25 x 50 bits, 9 special primes: four ciphertexts at uneven
+    scales in one batch decrypt within 2^-12 of the input slots."""
+    p = BootPair(17, [60] + [50] * 25, [60] * 9, 9, log2_rho=2, oracle=False)
+    d = p.gpu
+    lo = d.boot_levels[3]
+    assert lo >= 10
+    scales = [2.0 ** 35, 2.0 ** 38.5, 2.0 ** 42, 2.0 ** 45]
+    zs = [S.uniform_slots(p.g, p.N // 2) for _ in scales]
+    cts = d.empty(len(scales), 2, 1, p.N)
+    for i, (z, sc) in enumerate(zip(zs, scales)):
+        cts[i].copy_(p.level0_ct(z, sc))
+    out, so = d.bootstrap_batch(cts, scales)
+    err = _max_err(d, out, lo, so, zs)
+    print("N=2^17 bootstrap: output level %d, max slot error 2^%.2f" % (lo, err))
+    assert err < -12
