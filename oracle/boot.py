@@ -484,3 +484,33 @@ class Evaluator:
             ct = self.lt(ct, lt)
         # the slots hold z * d' / D_ref at the arithmetic scale s_out
         return ct, p.s_out * d_prime / 2.0 ** p.dref_log2
+
+
+# ---------------------------------------------------------------- the overflow polynomial I of ModRaise
+
+def modraise_overflow(orc, s, ct0):
+    """I(X) with c0 + c1 s = m + q_0 I over the integers, for a level-0
+    ciphertext ct0 ([2][1][N], residues mod q_0) read as centred integers and
+    the secret s (small integers).  The bootstrap's EvalMod is valid only
+    while every |I_j| <= K.
+
+    t = c0 + c1 s is known modulo 2^64 (wrapping uint64 arithmetic of the
+    negacyclic product) and modulo q_0 (m, the decryption); |t| < 2^63 and
+    q_0 is odd, so I = (t - m) q_0^-1 mod 2^64, read as a signed word."""
+    N = orc.N
+    q0 = int(orc.Q[0])
+    c = np.asarray(ct0, dtype=np.uint64).reshape(2, N)
+    half = np.uint64((q0 - 1) // 2)
+    # centred lifts, as uint64 words (two's complement for negative values)
+    lift = [np.where(c[p] <= half, c[p], c[p] - np.uint64(q0)) for p in range(2)]
+    t = lift[0].copy()
+    with np.errstate(over="ignore"):
+        for j in np.nonzero(s)[0]:
+            sh = np.roll(lift[1], int(j))          # X^j c1: coefficient k comes from k - j
+            sh[: int(j)] = np.uint64(0) - sh[: int(j)]   # wrapped past X^N: negated
+            t = t + sh if s[j] > 0 else t - sh
+        m = orc.decrypt(0, s, ct0).reshape(N)
+        mc = np.where(m <= half, m, m - np.uint64(q0))
+        inv = pow(q0, -1, 1 << 64)
+        I = (t - mc) * np.uint64(inv)
+    return I.view(np.int64)

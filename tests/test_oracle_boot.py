@@ -54,8 +54,12 @@ def test_decoding_map_direct_definition_small():
     assert np.max(np.abs(ENC.embed(t, N) - direct)) < 1e-12
 
 
-def test_chebyshev_split_identity_and_error():
-    K, deg, r = 23, 59, 2
+@pytest.mark.parametrize("K,r,fit_log2,sin_log2", [(23, 2, -24, -20), (25, 3, -44, -40)])
+def test_chebyshev_split_identity_and_error(K, r, fit_log2, sin_log2):
+    """Degree 59 at K = 23 with two double angles (the default), and the
+    SURVEY's fallback K = 25 with three (one more level, failure rate per
+    N = 2^16 bootstrap 1.3e-5 instead of 3e-4)."""
+    deg = 59
     c = B.cheb_coeffs(B.evalmod_function(K, r), deg)
     u = np.linspace(-1, 1, 4001)
     T = np.polynomial.chebyshev
@@ -65,22 +69,24 @@ def test_chebyshev_split_identity_and_error():
         rhs = T.chebval(u, q) * T.chebval(u, np.eye(m + 1)[m]) + T.chebval(u, rr)
         assert np.max(np.abs(lhs - rhs)) < 1e-12
     err = np.max(np.abs(T.chebval(u, c) - B.evalmod_function(K, r)(u)))
-    assert err < 2.0 ** -24        # degree 59 on [-(K+1), K+1]
+    assert err < 2.0 ** fit_log2   # degree 59 on [-(K+1), K+1]
     # after r double angles the result approximates sin(2 pi x) near integers
     x = np.concatenate([I + np.linspace(-1e-3, 1e-3, 101) for I in range(-K, K + 1)])
     y = T.chebval(x / (K + 1), c)
     for _ in range(r):
         y = 2 * y * y - 1
-    assert np.max(np.abs(y - np.sin(2 * np.pi * x))) < 2.0 ** -20
+    assert np.max(np.abs(y - np.sin(2 * np.pi * x))) < 2.0 ** sin_log2
 
 
-def test_oracle_bootstrap_precision():
+@pytest.mark.parametrize("K,r", [(23, 2), (25, 3)])
+def test_oracle_bootstrap_precision(K, r):
     logN = 11
     orc = O.Oracle(logN, [60] + [50] * 17, [60] * 6, 6)
     N = orc.N
     g = S.rng(41, logN)
-    plan = B.Plan(N, orc.Q, B.BootParams(log2_rho=4))
-    assert plan.level_out == 3      # 17 - 3 (CoeffToSlot) - 8 (EvalMod) - 3 (SlotToCoeff)
+    plan = B.Plan(N, orc.Q, B.BootParams(K=K, double_angle=r, log2_rho=4))
+    # 17 - 3 (CoeffToSlot) - 6 + r (EvalMod: degree 59, r double angles) - 3 (SlotToCoeff)
+    assert plan.level_out == 17 - 3 - (6 + r) - 3
     s = S.ternary_hw(g, N, 192)
     pk = orc.keygen_public(s, S.uniform_residues(g, orc.Q, N), S.gaussian(g, N))
     rlk = orc.keygen_relin(s, *S.key_randomness(g, orc.beta, orc.moduli, N))
@@ -169,3 +175,67 @@ def test_monomial_of_quarter_turn_multiplies_slots_by_i():
     pt = O.encode(z, N, scale, orc.Q)
     back = O.decode(orc.monomial(orc.L, N // 2, pt[None])[0], N, scale, orc.Q)
     assert np.max(np.abs(back - 1j * z)) < 2.0 ** -20
+
+
+# ---------------------------------------------------------------- ModRaise overflow and the bootstrap's failure rate
+
+def test_modraise_overflow_matches_big_integers():
+    """I from the wrapping-word computation equals (c0 + c1 s - m) / q_0 over
+    the integers (Python big integers, schoolbook negacyclic product)."""
+    orc = O.Oracle(6, [60, 50], [60], 2)
+    N, q0 = orc.N, orc.Q[0]
+    g = S.rng(44, 6)
+    s = S.ternary_hw(g, N, 20)
+    ct = S.uniform_residues(g, orc.Q[:1], N, lead=(2,))
+    got = B.modraise_overflow(orc, s, ct)
+    cen = lambda v: int(v) if int(v) <= (q0 - 1) // 2 else int(v) - q0
+    c0 = [cen(v) for v in ct[0, 0]]
+    c1 = [cen(v) for v in ct[1, 0]]
+    t = list(c0)
+    for i in range(N):
+        for j in range(N):
+            if s[j]:
+                k = i + j
+                if k < N:
+                    t[k] += c1[i] * int(s[j])
+                else:
+                    t[k - N] -= c1[i] * int(s[j])
+    for k in range(N):
+        m = t[k] % q0
+        m = m if m <= (q0 - 1) // 2 else m - q0
+        assert (t[k] - m) % q0 == 0
+        assert got[k] == (t[k] - m) // q0
+
+
+def test_bootstrap_failure_rate_over_seeds():
+    """Empirical law of I at the bootstrap workload's shape (N = 2^16,
+    HW-192 secret, fresh level-0 encryptions): its spread matches
+    sqrt((h + 1) / 12), the tail counts match the normal law where the
+    sample reaches, and the failure rate P(some |I_j| > K) per bootstrap
+    follows: about 3e-4 at K = 23 (EvalMod r = 2) and below 2e-5 at K = 25
+    (r = 3)."""
+    from math import erfc, sqrt
+
+    logN, h, n_ct = 16, 192, 24
+    orc = O.Oracle(logN, [60, 50], [60], 2)
+    N = orc.N
+    g = S.rng(45, logN)
+    samples = []
+    for i in range(n_ct):
+        s = S.ternary_hw(g, N, h)
+        pk = orc.keygen_public(s, S.uniform_residues(g, orc.Q, N), S.gaussian(g, N))
+        m = S.uniform_residues(g, orc.Q, N) % np.uint64(1 << 40)      # any small message
+        ct = orc.encrypt(0, pk, m[:1], *S.encryption_randomness(g, N))
+        samples.append(B.modraise_overflow(orc, s, ct))
+    I = np.concatenate(samples).astype(np.float64)
+    sigma = sqrt((h + 1) / 12.0)
+    assert abs(I.std() / sigma - 1) < 0.02 and abs(I.mean()) < 0.02
+    tail = lambda t: erfc((t + 0.5) / (sigma * sqrt(2.0)))     # P(|I| > t), I integer
+    for t in (8, 12, 15):
+        want = tail(t) * I.size
+        got = float(np.sum(np.abs(I) > t))
+        assert abs(got - want) < 5 * sqrt(want) + 1, (t, got, want)
+    per_bootstrap = {K: 1 - (1 - tail(K)) ** N for K in (23, 25)}
+    print("failure rate per N=2^16 bootstrap: K=23 %.1e, K=25 %.1e (max |I| seen %d over %d coefficients)" % (
+        per_bootstrap[23], per_bootstrap[25], int(np.abs(I).max()), I.size))
+    assert 1e-4 < per_bootstrap[23] < 1e-3 and per_bootstrap[25] < 2e-5
