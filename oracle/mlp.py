@@ -262,25 +262,64 @@ def sum_cols(ops, u, cfg):
     return u
 
 
-def activation(ops, cfg, z):
-    """(f(z), f'(z)); f'(z) is None with the literal derivative."""
+def activation(ops, cfg, z, need_deriv=True):
+    """(f(z), f'(z)); f'(z) is None with the literal derivative or when
+    need_deriv is False (a forward pass only)."""
     a1, a2, a3 = cfg.act
     z2 = ops.mul(z, z)
     if cfg.degree == 2:
         t2 = ops.affine(z2, a2, 0.0)
         a = ops.add(t2, ops.lincomb([(z, a1)], like=t2)) if a1 != 0.0 else t2
-        d = None if cfg.literal_deriv else ops.affine(z, 2.0 * a2, a1)
+        d = None if (cfg.literal_deriv or not need_deriv) else ops.affine(z, 2.0 * a2, a1)
         return a, d
     z3 = ops.mul(z2, z)
     t3 = ops.affine(z3, a3, 0.0)
     terms = [(x, cf) for x, cf in ((z2, a2), (z, a1)) if cf != 0.0]
     a = ops.add(t3, ops.lincomb(terms, like=t3)) if terms else t3
     d = None
-    if not cfg.literal_deriv:
+    if not cfg.literal_deriv and need_deriv:
         d2 = ops.affine(z2, 3.0 * a3, 0.0)
         d = ops.add(d2, ops.lincomb([(z, 2.0 * a2)], like=d2)) if a2 != 0.0 else d2
         d = ops.affine(d, 1.0, a1)
     return a, d
+
+
+def reference_infer(cfg, Ws, Wstars, x):
+    """Float64 forward pass of one sample: the output of every block's local
+    classifier, yhat_h = f(a_(h-1) W_h) W*_h with a_0 = x."""
+    outs, a = [], np.asarray(x, dtype=np.float64)
+    for h in range(cfg.H):
+        a = act(cfg, a @ Ws[h])
+        outs.append(a @ Wstars[h])
+    return outs
+
+
+def packed_infer(ops, cfg, state, x_tiles, last):
+    """Encrypted inference with early exit (Section 4.2.3: after training the
+    local classifiers can serve as exits): the forward pass of blocks
+    1..last on one sample, returning the local classifiers' outputs
+    [yhat_1 .. yhat_last].  A RE-block's output is in the expanded format
+    (class i in row i), a CE-block's in the repeated format (class j in
+    column j), as in the training step."""
+    layout = cfg.state_layout()
+    pos = {key: i for i, key in enumerate(layout)}
+    out, a_in = [], list(x_tiles)
+    for h in range(1, last + 1):
+        nt = cfg.n_tiles(h)
+        W = [state[pos[("W", h, i)]] for i in range(nt)]
+        Ws = state[pos[("Wstar", h, 0)]]
+        if h % 2 == 1:
+            p = None
+            for i in range(nt):
+                t = ops.mul(a_in[i], W[i])
+                p = t if p is None else ops.add(p, t)
+            a, _ = activation(ops, cfg, sum_rows(ops, p, cfg), need_deriv=False)
+            out.append(sum_cols(ops, ops.mul(a, Ws), cfg))
+        else:
+            a, _ = activation(ops, cfg, sum_cols(ops, ops.mul(a_in[0], W[0]), cfg), need_deriv=False)
+            out.append(sum_rows(ops, ops.mul(a, Ws), cfg))
+        a_in = [a]
+    return out
 
 
 def packed_step(ops, cfg, state, samples, t, bootstrap=True):

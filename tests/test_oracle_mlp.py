@@ -199,3 +199,30 @@ def test_encrypted_step_decrypts_to_packed_step():
     assert math.log2(worst) < -18, math.log2(worst)
     assert min(c.lv for c in got) == wl - M.depth(cfg)
     assert all(c.s == T for c in got)
+
+
+@pytest.mark.parametrize("act", [(1.0, 1.0, 0.0), (0.5, 0.7, 0.2)])
+def test_packed_inference_equals_matrix_forward(act):
+    """Early-exit inference: the packed forward pass of blocks 1..3 (two input
+    tiles) gives every local classifier's output, in the expanded format
+    after a RE-block and the repeated format after a CE-block, equal to the
+    unpacked float64 forward pass; the float64 pass itself equals torch's."""
+    cfg = _cfg(widths=[8, 8, 6], act=act)
+    Ws, Wst = _model(cfg, 5)
+    g = S.rng(5, 9)
+    X, _ = S.mlp_batch(g, 2, cfg.k0, cfg.o)
+    state = M.pack_state(cfg, Ws, Wst)
+    for x in X:
+        want = M.reference_infer(cfg, Ws, Wst, x)
+        a = torch.tensor(x)
+        for h in range(cfg.H):
+            z = a @ torch.tensor(Ws[h])
+            a = act[0] * z + act[1] * z * z + act[2] * z ** 3
+            assert np.max(np.abs((a @ torch.tensor(Wst[h])).numpy() - want[h])) < 1e-12
+        xt, _, _ = M.pack_sample(cfg, x, np.zeros(cfg.o))
+        for last in (1, 3):
+            got = M.packed_infer(M.PlainOps(cfg), cfg, state, xt, last)
+            assert len(got) == last
+            for h, (gv, wv) in enumerate(zip(got, want), start=1):
+                packed = M.vec_exp(wv, cfg.r, cfg.c) if h % 2 == 1 else M.vec_rep(wv, cfg.r, cfg.c)
+                assert np.max(np.abs(gv - packed)) < 1e-12, (h, last)
