@@ -22,11 +22,11 @@ SMALL = dict(logN=11, qbits=[60] + [50] * 17, pbits=[60] * 6, alpha=6, log2_rho=
 
 
 class BootPair:
-    def __init__(self, logN, qbits, pbits, alpha, log2_rho, oracle=True, seed=17):
+    def __init__(self, logN, qbits, pbits, alpha, log2_rho, oracle=True, seed=17, K=23, r=2):
         from paper_2506_19693_amd import Context
 
         self.gpu = Context(logN, qbits, pbits, alpha)
-        self.gpu.boot_setup(log2_rho=log2_rho)
+        self.gpu.boot_setup(K=K, double_angle=r, log2_rho=log2_rho)
         d = self.gpu
         N = d.N
         self.N = N
@@ -52,7 +52,7 @@ class BootPair:
             self.pk = o.keygen_public(self.s, pa, pe)
             self.rlk = o.keygen_relin(self.s, ra, re_)
             self.keys = {gal: o.keygen_galois(self.s, gal, a, e) for gal, (a, e) in gal_rand.items()}
-            self.plan = B.Plan(N, o.Q, B.BootParams(log2_rho=log2_rho))
+            self.plan = B.Plan(N, o.Q, B.BootParams(K=K, double_angle=r, log2_rho=log2_rho))
 
     def level0_ct(self, z, scale):
         d = self.gpu
@@ -189,3 +189,40 @@ def test_bootstrap_n17_precision():
     err = _max_err(d, out, lo, so, zs)
     print("N=2^17 bootstrap: output level %d, max slot error 2^%.2f" % (lo, err))
     assert err < -12
+
+
+def test_bootstrap_k25_r3_bit_exact_and_full_size_precision():
+    """EvalMod with K = 25 and three double angles (failure rate 1.3e-5 per
+    N = 2^16 bootstrap instead of 3e-4, one level more): residue-exact with
+    the oracle's constants at N = 2^11, and at N = 2^16 (26 primes, 9
+    special) eight ciphertexts of uneven scales within 2^-12, output level 10."""
+    p = BootPair(**SMALL, K=25, r=3, seed=18)
+    d, o, plan = p.gpu, p.orc, p.plan
+    try:
+        assert d.boot_levels[3] == plan.level_out == SMALL["qbits"].__len__() - 1 - 15
+        d.boot_import([pt for _, pt in plan.plains], [s for _, s in plan.scalars])
+        z = S.uniform_slots(p.g, p.N // 2)
+        scale = 2.0 ** 39
+        ct_host = o.encrypt(0, p.pk, O.encode(z, p.N, scale, o.Q[:1]), *S.encryption_randomness(p.g, p.N))
+        out, so = d.bootstrap(d.to_ntt(ct_host, 0), scale)
+        want, so_o = B.Evaluator(o, plan, p.rlk, p.keys).bootstrap(ct_host, scale)
+        assert so == pytest.approx(so_o, rel=1e-12)
+        assert np.array_equal(d.to_coef(out, plan.level_out), want)
+    finally:
+        d.close()
+    q = BootPair(16, [60] + [50] * 25, [60] * 9, 9, log2_rho=2, oracle=False, K=25, r=3)
+    try:
+        d = q.gpu
+        lo = d.boot_levels[3]
+        assert lo == 10
+        scales = [2.0 ** (35 + 10 * i / 7) for i in range(8)]
+        zs = [S.uniform_slots(q.g, q.N // 2) for _ in scales]
+        cts = d.empty(len(scales), 2, 1, q.N)
+        for i, (z, sc) in enumerate(zip(zs, scales)):
+            cts[i].copy_(q.level0_ct(z, sc))
+        out, so = d.bootstrap_batch(cts, scales)
+        err = _max_err(d, out, lo, so, zs)
+        print("N=2^16 bootstrap, K=25, r=3: output level %d, max slot error 2^%.2f" % (lo, err))
+        assert err < -12
+    finally:
+        q.gpu.close()
