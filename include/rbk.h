@@ -485,6 +485,19 @@ int rbk_mlp_set_mask(rbk_mlp *mlp, int level, const uint64_t *d_pt);
 #define RBK_MLP_PER_SAMPLE 2u
 int rbk_mlp_train_step(rbk_mlp *mlp, const uint64_t *d_x, const uint64_t *d_y_exp, const uint64_t *d_y_rep, int b,
                        int level, double scale, int t, uint32_t step_flags);
+/* Encrypted inference with early exit (Section 4.2.3: after training, the
+ * local classifiers can serve as exits): the forward pass of blocks
+ * 1..last on b samples d_x [b][tiles][2][level+1][N] (expanded format, at
+ * `level` and `scale`), and the output Yhat_h of every local classifier
+ * h <= last.  d_out [last][b][2][level+1][N]: sample i's output of block h
+ * is the ciphertext [2][levels[h-1]+1][N] at the start of slot (h-1, i),
+ * scale scales[h-1] (levels / scales may be NULL).  A RE-block's output is
+ * in the expanded format (class j in row j), a CE-block's in the repeated
+ * format (class j in column j).  Needs the W and W* state of blocks
+ * 1..last, the relinearisation key and the keys of rbk_mlp_rotations;
+ * deeper blocks are not evaluated.  Synchronises. */
+int rbk_mlp_infer(rbk_mlp *mlp, const uint64_t *d_x, int b, int level, double scale, int last, uint64_t *d_out,
+                  int *levels, double *scales);
 /* The integer constants the last step multiplied or added, in evaluation
  * order (with RBK_MLP_PER_SAMPLE: sample by sample, block by block, then
  * the updates).  Writes at most max, returns the count. */

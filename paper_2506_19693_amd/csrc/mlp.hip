@@ -248,12 +248,12 @@ struct Step {
         for (int k = 1; k < sh.c; k <<= 1) u = ops.add(u, ops.rot(u, -(int64_t)k));
         return u;
     }
-    // (f(z), f'(z)); has_d false with the literal derivative
-    void activation(const T &z, T &a, T &d, bool &has_d)
+    // (f(z), f'(z)); has_d false with the literal derivative or without want_d (a forward pass only)
+    void activation(const T &z, T &a, T &d, bool &has_d, bool want_d = true)
     {
         const double a1 = sh.act[0], a2 = sh.act[1], a3 = sh.act[2];
         T z2 = ops.mul(z, z);
-        has_d = !sh.literal;
+        has_d = !sh.literal && want_d;
         if (sh.degree == 2) {
             T t2 = ops.affine(z2, a2, 0.0);
             a = a1 != 0.0 ? ops.add(t2, ops.lincomb({{z, a1}}, &t2, 0.0)) : t2;
@@ -281,6 +281,35 @@ struct Step {
         } else {
             slot = ops.add(slot, v);
         }
+    }
+
+    // Inference with early exit: the forward pass of blocks 1..last on one
+    // (batched) sample; the output of every block's local classifier.
+    std::vector<T> infer(const std::vector<T> &state, const std::vector<T> &x, int last)
+    {
+        std::vector<T> out;
+        std::vector<T> a_in = x;
+        for (int h = 1; h <= last; h++) {
+            const T &Ws = state[sh.pos(K_WSTAR, h, 0)];
+            T a, d;
+            bool has_d = false;
+            if (h % 2 == 1) {
+                T p;
+                bool have_p = false;
+                for (int i = 0; i < sh.n_tiles(h); i++) {
+                    bool hp = have_p;
+                    acc(p, hp, ops.mul(a_in[i], state[sh.pos(K_W, h, i)]), ops);
+                    have_p = hp;
+                }
+                activation(sum_rows(p), a, d, has_d, false);
+                out.push_back(sum_cols(ops.mul(a, Ws)));
+            } else {
+                activation(sum_cols(ops.mul(a_in[0], state[sh.pos(K_W, h, 0)])), a, d, has_d, false);
+                out.push_back(sum_rows(ops.mul(a, Ws)));
+            }
+            a_in.assign(1, a);
+        }
+        return out;
     }
 
     std::vector<T> run(const std::vector<T> &state, const std::vector<Sample<T>> &samples, int b, int t, bool boot)
@@ -864,6 +893,58 @@ extern "C" int rbk_mlp_train_step(rbk_mlp *m, const uint64_t *d_x, const uint64_
             v.s = x.s;
             m->state[i] = v;
         }
+    } catch (const MlpError &e) {
+        return mfail(e);
+    } catch (const std::bad_alloc &) {
+        return rbk_set_error(RBK_ENOMEM, "host allocation failed");
+    }
+    return RBK_OK;
+}
+
+extern "C" int rbk_mlp_infer(rbk_mlp *m, const uint64_t *d_x, int b, int level, double scale, int last,
+                             uint64_t *d_out, int *levels, double *scales)
+{
+    if (!m || !d_x || !d_out) return rbk_set_error(RBK_EINVAL, "null argument");
+    const Shape &sh = m->sh;
+    if (b < 1 || last < 1 || last > sh.H) return rbk_set_error(RBK_EINVAL, "need b >= 1 and 1 <= last <= H");
+    if (level < 0 || level >= m->c->nQ) return rbk_set_error(RBK_ELEVEL, "level out of range");
+    if (!(scale > 0.0)) return rbk_set_error(RBK_EINVAL, "scale must be positive");
+    for (size_t i = 0; i < sh.layout.size(); i++) {
+        const bool used = sh.layout[i].h <= last && (sh.layout[i].kind == K_W || sh.layout[i].kind == K_WSTAR);
+        if (used && !m->state[i].d) return rbk_set_error(RBK_ESTATE, "weight ciphertext not set");
+    }
+    try {
+        GpuOps ops(m);
+        m->scalars.clear();
+        const size_t P = ops.per(level), N = m->c->N;
+        const long ct_x = (long)(sh.tiles * 2 * P);
+        std::vector<Vec> x;
+        for (int tt = 0; tt < sh.tiles; tt++) {
+            Vec v;
+            v.d = d_x + tt * 2 * P;
+            v.lv = level;
+            v.ps = (long)P;
+            v.cs = ct_x;
+            v.count = b;
+            v.s = scale;
+            x.push_back(v);
+        }
+        Step<GpuOps> st{ops, sh};
+        std::vector<Vec> out = st.infer(m->state, x, last);
+        for (int h = 0; h < last; h++) {
+            const Vec &y = out[h];
+            const size_t Py = (size_t)(y.lv + 1) * N;
+            for (int i = 0; i < b; i++) {
+                const u64 *src = y.d + (size_t)(y.count == 1 ? 0 : i) * y.cs;
+                u64 *dst = d_out + ((size_t)h * b + i) * 2 * P;
+                hck(hipMemcpy2DAsync(dst, Py * sizeof(u64), src, y.ps * sizeof(u64), Py * sizeof(u64), 2,
+                                     hipMemcpyDeviceToDevice, m->c->stream),
+                    "copy");
+            }
+            if (levels) levels[h] = y.lv;
+            if (scales) scales[h] = y.s;
+        }
+        hck(hipStreamSynchronize(m->c->stream), "synchronise");   // the pooled results are released on return
     } catch (const MlpError &e) {
         return mfail(e);
     } catch (const std::bad_alloc &) {

@@ -198,6 +198,7 @@ SIGNATURES = {
     "rbk_mlp_set_mask": (ci, [vp, ci, vp]),
     "rbk_mlp_train_step": (ci, [vp, vp, vp, vp, ci, ci, ctypes.c_double, ci, ctypes.c_uint32]),
     "rbk_mlp_scalars": (ci, [vp, i64p, ci]),
+    "rbk_mlp_infer": (ci, [vp, vp, ci, ci, ctypes.c_double, ci, vp, ctypes.POINTER(ci), dblp]),
     "rbk_mlp_set_weights": (ci, [vp, ctypes.POINTER(dblp), ctypes.POINTER(dblp), ctypes.POINTER(dblp),
                                  ctypes.POINTER(dblp), ci, cu64]),
     "rbk_mlp_get_weights": (ci, [vp, ctypes.POINTER(dblp), ctypes.POINTER(dblp), ctypes.POINTER(dblp),
@@ -921,6 +922,20 @@ class Mlp:
         flags = (0 if bootstrap else MLP_NO_BOOTSTRAP) | (MLP_PER_SAMPLE if per_sample else 0)
         _check(self.lib.rbk_mlp_train_step(self.h, _ptr(x), _ptr(y_exp), _ptr(y_rep), b, level, float(scale), t,
                                            flags))
+
+    def infer(self, x, level, scale, last):
+        """Forward pass of blocks 1..last on x [b][tiles][2][level+1][N]; returns
+        [(outputs [b][2][lv+1][N], lv, scale)] of each local classifier h <= last."""
+        b = x.shape[0]
+        out = self.ctx.empty(last, b, 2, level + 1, self.ctx.N)
+        lv = (ci * last)()
+        sc = (ctypes.c_double * last)()
+        _check(self.lib.rbk_mlp_infer(self.h, _ptr(x), b, level, float(scale), last, _ptr(out), lv, sc))
+        res = []
+        for h in range(last):
+            n = 2 * (lv[h] + 1) * self.ctx.N       # each output sits at the start of its slot
+            res.append((out[h].reshape(b, -1)[:, :n].reshape(b, 2, lv[h] + 1, self.ctx.N).contiguous(), lv[h], sc[h]))
+        return res
 
     def scalars(self):
         n = _check(self.lib.rbk_mlp_scalars(self.h, None, 0))

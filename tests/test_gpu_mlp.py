@@ -253,3 +253,44 @@ def test_train_step_full_size_two_steps():
             worst = max(worst, math.log2(np.max(np.abs(back - ref[i])) + 1e-300))
     print("full-size train_step: max slot error after two steps 2^%.2f" % worst)
     assert worst < -10
+
+
+@pytest.mark.parametrize("name", ["paper", "deg3"])
+def test_inference_early_exit_bit_exact(name):
+    """Encrypted inference through the local classifiers (forward pass of
+    blocks 1..last, two input tiles, two samples in one call): every output
+    ciphertext bit-exact with the oracle's packed inference, the same
+    levels, scales and constants; and it decrypts to the float64 forward pass."""
+    cfg = M.MlpConfig(k0=20, widths=[8, 8], o=4, r=16, c=32, gamma=0.05, log2_scale=40.0, **VARIANTS[name])
+    L = 14
+    p = Pair(cfg, 10, [60] + [40] * L, [60] * 3, 3)
+    g = S.rng(26, 1)
+    Ws, Wst, _, _ = _model(cfg, g, False)
+    X, _ = S.mlp_batch(g, 2, cfg.k0, cfg.o)
+    T = 2.0 ** cfg.log2_scale
+    wl = L
+    st = [p.oracle_enc(v, wl, T) for v in M.pack_state(cfg, Ws, Wst)]
+    layout = cfg.state_layout()
+    p.set_state([c if layout[i][0] in ("W", "Wstar") else None for i, c in enumerate(st)])
+    xs = [[p.oracle_enc(v, L, T) for v in M.pack_sample(cfg, X[i], np.zeros(cfg.o))[0]] for i in range(2)]
+    ops = M.EncOps(p.o, cfg, p.rlk, p.keys)
+    want = [M.packed_infer(ops, cfg, st, xs[i], cfg.H) for i in range(2)]
+    for lv, pt in ops.masks.items():
+        p.mlp.set_mask(lv, p.d.to_ntt(pt, lv))
+    x = p.d.to_ntt(np.stack([np.stack([c.d for c in xt]) for xt in xs]), L)
+    for last in (1, 2):
+        got = p.mlp.infer(x, L, T, last)
+        assert len(got) == last
+        for h, (cts, lv, s) in enumerate(got):
+            for i in range(2):
+                w = want[i][h]
+                assert lv == w.lv and s == w.s
+                assert np.array_equal(p.d.to_coef(cts[i], lv), w.d), (last, h, i)
+    # precision against the float64 forward pass (class j of block h's output)
+    got = p.mlp.infer(x, L, T, cfg.H)
+    for i in range(2):
+        ref = M.reference_infer(cfg, Ws, Wst, X[i])
+        for h, (cts, lv, s) in enumerate(got, start=1):
+            back = p.d.decode(p.d.decrypt(cts[i], lv), lv, s).real.reshape(cfg.r, cfg.c)
+            vals = back[: cfg.o, 0] if h % 2 == 1 else back[0, : cfg.o]
+            assert np.max(np.abs(vals - ref[h - 1])) < 2.0 ** -20, (i, h)
