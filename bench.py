@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--serve-lambda", type=float, default=0.0,
                     help="Poisson arrival rate, jobs/s (default: 0.8 x the capacity measured in the same run)")
     ap.add_argument("--serve-budget-gib", type=float, default=150.0)
-    ap.add_argument("--serve-max-batch", type=int, default=32)
-    ap.add_argument("--serve-max-boot", type=int, default=8)
+    ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-max-boot", type=int, default=16)
     ap.add_argument("--serve-mlp-b", type=int, default=8, help="samples per training step of serving jobs")
     ap.add_argument("--lanes", type=int, default=2,
                     help="ModDown lanes of hoisted-rotation batches (1: no overlapping kernels, as for profiling)")
@@ -905,6 +905,17 @@ def bench_paper_mlp(name, args, torch):
     t_it = (time.perf_counter() - t0) / args.steps
     Ws, Wst, Vs, Vst = mlp.get_weights(dims, o)
     finite = all(np.all(np.isfinite(w)) and np.max(np.abs(w)) < 4.0 for w in Ws + Wst + Vs + Vst)
+    # encrypted inference of the same 48 samples through every local classifier (early exit at block 1 .. H)
+    H = len(p["widths"])
+    t_inf = {}
+    for last in sorted({1, H}):
+        mlp.infer(x, lo, T, last)
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mlp.infer(x, lo, T, last)
+        ctx.sync()
+        t_inf["exit_after_block_%d" % last] = (time.perf_counter() - t0) / args.steps
     res = {
         "workload": "%s (paper Table 3): %s, N=2^%d, %d primes (%s) + %d special, HW-192 secret, 784 -> %s -> 10 "
                     "classes, r=%d c=%d, %d samples per step, paper activation z + z^2, gamma 0.001, eta %g, mu 0.9; "
@@ -917,6 +928,7 @@ def bench_paper_mlp(name, args, torch):
         "weight_level": lo,
         "setup_s": t_setup,
         "weights_decrypt_finite_and_bounded": bool(finite),
+        "inference_s_per_batch": t_inf,
         "paper_cpu_s_per_iteration": {"eMLP-1": 190.32, "eMLP-2": 629.65}[name],
         "paper_hardware": "2x Intel Xeon Gold 5318S, OpenFHE (context only: other hardware, other software)",
     }
