@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--serve-lambda", type=float, default=0.0,
                     help="Poisson arrival rate, jobs/s (default: 0.8 x the capacity measured in the same run)")
     ap.add_argument("--serve-budget-gib", type=float, default=150.0)
+    ap.add_argument("--no-serve-cross", action="store_true", help="no cross-tenant batching in the serving part")
     ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--serve-max-boot", type=int, default=16)
     ap.add_argument("--serve-mlp-b", type=int, default=8, help="samples per training step of serving jobs")
@@ -537,6 +538,9 @@ def _serve_jobs(n_jobs, tenants, lam):
     return jobs
 
 
+_SERVE_CROSS = [True]   # cross-tenant batching of mult jobs (--no-serve-cross turns it off)
+
+
 def _serve_run(tenants, jobs, budget, max_batch, max_boot, torch):
     """Submit at the arrival times; returns (makespan s, per-job latency ms, stats)."""
     import threading
@@ -546,6 +550,7 @@ def _serve_run(tenants, jobs, budget, max_batch, max_boot, torch):
     srv = Server(budget, max_batch, max_boot)
     for tn in tenants:
         srv.add_tenant(tn.ctx)
+    srv.set_cross_tenant(_SERVE_CROSS[0])
     srv.start()
     step = {id(tn): {w: 1 for w in tn.mlps} for tn in tenants}
     ids = []
@@ -620,6 +625,7 @@ def bench_serve(args, torch):
     primes, 11 special; HW-192 secrets; resident relinearisation, bootstrap
     and MLP keys), Poisson arrivals of mixed jobs, served (continuous batching,
     HBM-ledger admission, per-tenant streams) vs serial plain FIFO."""
+    _SERVE_CROSS[0] = not args.no_serve_cross
     rand_cache = {}
     tenants = [_Tenant(ln, i, rand_cache, args.serve_mlp_b) for i, ln in enumerate(SERVE_LOG_NS)]
     rand_cache.clear()
@@ -640,8 +646,8 @@ def bench_serve(args, torch):
     lam = args.serve_lambda if args.serve_lambda > 0 else SERVE_LOAD * capacity
     jobs = _serve_jobs(args.serve_jobs, tenants, lam)
     mk, lat, stats = _serve_run(tenants, jobs, budget, args.serve_max_batch, args.serve_max_boot, torch)
-    log("serving: Poisson run at %.2f jobs/s done in %.1f s, %d jobs merged, %.1f GiB free" % (
-        lam, mk, stats["jobs_merged"], torch.cuda.mem_get_info()[0] / 2.0 ** 30))
+    log("serving: Poisson run at %.2f jobs/s done in %.1f s, %d jobs merged (%d across tenants), %.1f GiB free" % (
+        lam, mk, stats["jobs_merged"], stats["jobs_cross_tenant"], torch.cuda.mem_get_info()[0] / 2.0 ** 30))
     if stats["jobs_merged"] == 0:
         log("serving: WARNING: no job merged into another's batch at this arrival rate")
     out = {
@@ -658,6 +664,8 @@ def bench_serve(args, torch):
         "latency_ms_p99": percentile(lat, 99),
         "batches": stats["batches"],
         "jobs_merged": stats["jobs_merged"],
+        "jobs_cross_tenant": stats["jobs_cross_tenant"],
+        "cross_tenant_batching": _SERVE_CROSS[0],
         "ledger_peak_gib": stats["ledger_peak"] / 2.0 ** 30,
         "budget_gib": stats["budget"] / 2.0 ** 30,
         "burst": {
@@ -667,6 +675,7 @@ def bench_serve(args, torch):
             "latency_ms_p99": percentile(lat_b, 99),
             "batches": st_b["batches"],
             "jobs_merged": st_b["jobs_merged"],
+            "jobs_cross_tenant": st_b["jobs_cross_tenant"],
         },
     }
     if not args.no_plain:

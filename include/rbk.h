@@ -576,6 +576,17 @@ int rbk_server_drain(rbk_server *srv);
 /* stats[6] = {jobs completed, batches run, jobs that ran merged with others,
  * peak ledger bytes, ledger bytes now, budget} */
 int rbk_server_stats(rbk_server *srv, uint64_t *stats);
+/* Cross-tenant batching (off by default; set before rbk_server_start): a
+ * tenant's mult batch also takes admitted mult jobs of other tenants whose
+ * contexts have special primes and a ring degree up to 2^16 (any level, any
+ * ring degree, oldest first, within max_batch), and runs them in one
+ * multi-context launch set (rbk_mult_relin_rescale_multi: every ciphertext
+ * with its own tenant's keys and tables) on the leading tenant's stream.
+ * The other contexts are only read; their ModUp tables of every level are
+ * built at rbk_server_start. */
+int rbk_server_set_cross_tenant(rbk_server *srv, int on);
+/* *n = jobs that ran in a batch led by another tenant's worker */
+int rbk_server_cross_merged(rbk_server *srv, uint64_t *n);
 /* Run what was submitted, stop the workers, give the contexts their streams
  * back, free the server. */
 int rbk_server_destroy(rbk_server *srv);

@@ -78,8 +78,9 @@ struct rbk_server {
     std::vector<Tenant *> tenants;
     uint64_t next_id = 1;
     bool running = false, stopping = false;
-    uint64_t n_batches = 0, n_jobs_done = 0, n_merged = 0, n_outstanding = 0;
+    uint64_t n_batches = 0, n_jobs_done = 0, n_merged = 0, n_outstanding = 0, n_cross = 0;
     int max_batch, max_boot;
+    bool cross = false;
 
     rbk_server(uint64_t budget, int mb, int mbb) : sched(budget, mb, mbb), max_batch(mb), max_boot(mbb) {}
 };
@@ -215,6 +216,41 @@ int run_mult_list(Tenant *t, std::vector<SJob *> &b, int cap)
     return RBK_OK;
 }
 
+// A mult batch holding other tenants' jobs: every ciphertext runs in its own
+// tenant's context (keys, tables) through one multi-context call per chunk,
+// on this worker's stream and workspace; results go straight to the jobs'
+// outputs.  The other contexts are only read (their ModUp tables were built
+// before the workers started).
+int run_mult_multi(rbk_server *S, Tenant *t, std::vector<SJob *> &b, int cap)
+{
+    for (auto &ch : chunks(b, cap)) {
+        size_t words = 0;
+        for (auto &p : ch) words += (size_t)p.n * 2 * ct_words(S->tenants[p.s->j.tenant]->c, p.s->j.level);
+        u64 *A = stage_reserve(t, words);
+        if (!A) return rbk_set_error(RBK_ENOMEM, "staging allocation failed");
+        std::vector<rbk_mr_item> items;
+        size_t off = 0;
+        for (auto &p : ch) {
+            const rbk_job &j = p.s->j;
+            rbk_ctx *uc = S->tenants[j.tenant]->c;
+            const size_t N = uc->N, ct = ct_words(uc, j.level), in_ct = ct_words(uc, j.in_level);
+            const size_t out_ct = ct_words(uc, j.level - 1), w = (size_t)(j.level + 1) * N;
+            u64 *Ap = A + off, *Bp = Ap + (size_t)p.n * ct;
+            // limbs 0..level of every polynomial, from inputs laid out at in_level
+            if (hipMemcpy2DAsync(Ap, w * sizeof(u64), j.d_a + p.first * in_ct, (size_t)(j.in_level + 1) * N * sizeof(u64),
+                                 w * sizeof(u64), (size_t)2 * p.n, hipMemcpyDeviceToDevice, t->st) != hipSuccess ||
+                hipMemcpy2DAsync(Bp, w * sizeof(u64), j.d_b + p.first * in_ct, (size_t)(j.in_level + 1) * N * sizeof(u64),
+                                 w * sizeof(u64), (size_t)2 * p.n, hipMemcpyDeviceToDevice, t->st) != hipSuccess)
+                return rbk_set_error(RBK_EDEVICE, "gather copy failed");
+            for (int i = 0; i < p.n; i++)
+                items.push_back(rbk_mr_item{uc, Ap + i * ct, Bp + i * ct, j.d_out + (p.first + i) * out_ct, j.level, 0});
+            off += (size_t)p.n * 2 * ct;
+        }
+        if (int rc = rbk_mult_relin_rescale_multi(t->c, items.data(), (int)items.size())) return rc;
+    }
+    return RBK_OK;
+}
+
 int run_mult(Tenant *t, std::vector<SJob *> &b, int cap)
 {
     rbk_ctx *c = t->c;
@@ -319,9 +355,12 @@ void worker(rbk_server *S, Tenant *t)
                 sj.push_back(&s);
             }
         }
-        int rc;
+        int rc, foreign = 0;
+        for (SJob *x : sj) foreign += x->j.tenant != t->id;
         switch (sj[0]->j.kind) {
-        case RBK_JOB_MULT_RESCALE: rc = run_mult(t, sj, S->max_batch); break;
+        case RBK_JOB_MULT_RESCALE:
+            rc = foreign ? run_mult_multi(S, t, sj, S->max_batch) : run_mult(t, sj, S->max_batch);
+            break;
         case RBK_JOB_BOOTSTRAP: rc = run_boot(t, sj, S->max_boot); break;
         default: rc = run_train(t, sj); break;
         }
@@ -341,6 +380,7 @@ void worker(rbk_server *S, Tenant *t)
             S->n_batches++;
             S->n_jobs_done += batch.size();
             if (batch.size() > 1) S->n_merged += batch.size();
+            S->n_cross += foreign;
             for (auto &x : S->sched.admit()) {
                 S->jobs[x.id].admitted = true;
                 S->jobs[x.id].t_admit = now;
@@ -373,7 +413,7 @@ extern "C" int rbk_server_add_tenant(rbk_server *S, rbk_ctx *c, int *tenant)
     t->id = (int)S->tenants.size();
     t->c = c;
     t->resident = key_bytes(c) + boot_resident_bytes(c);
-    if (!S->sched.add_tenant(t->id, t->resident, mixed_levels(c))) {
+    if (!S->sched.add_tenant(t->id, t->resident, mixed_levels(c), mixed_levels(c))) {
         delete t;
         return rbk_set_error(RBK_ENOMEM, "the tenant's resident keys do not fit the HBM budget");
     }
@@ -393,8 +433,35 @@ extern "C" int rbk_server_start(rbk_server *S)
     if (!S) return rbk_set_error(RBK_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->running) return RBK_OK;
+    if (S->cross) {
+        // other workers read these tables: build every level now, so later lookups only read
+        for (Tenant *t : S->tenants) {
+            if (!mixed_levels(t->c)) continue;
+            if (hipSetDevice(t->c->device) != hipSuccess) return rbk_set_error(RBK_EDEVICE, "hipSetDevice failed");
+            for (int l = 1; l < t->c->nQ; l++)
+                if (!modup_tables(t->c, l).d_M) return rbk_set_error(RBK_ENOMEM, "ModUp tables");
+        }
+    }
     S->running = true;
     for (Tenant *t : S->tenants) t->th = std::thread(worker, S, t);
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_set_cross_tenant(rbk_server *S, int on)
+{
+    if (!S) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->running) return rbk_set_error(RBK_ESTATE, "set before rbk_server_start");
+    S->cross = on != 0;
+    S->sched.set_cross_tenant(S->cross);
+    return RBK_OK;
+}
+
+extern "C" int rbk_server_cross_merged(rbk_server *S, uint64_t *n)
+{
+    if (!S || !n) return rbk_set_error(RBK_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *n = S->n_cross;
     return RBK_OK;
 }
 

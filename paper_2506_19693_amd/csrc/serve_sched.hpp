@@ -15,6 +15,11 @@
 //   KIND_MULT jobs merge whatever their level (the server runs such batches
 //   through the uneven-level list path).  Jobs of kind KIND_SOLO (a training
 //   step) are never merged.
+// * With cross-tenant batching on, a KIND_MULT batch of a tenant registered
+//   as cross-capable also takes admitted KIND_MULT jobs of the other
+//   cross-capable tenants, oldest first, within the same cap (the server runs
+//   such batches through the multi-context path: every ciphertext with its
+//   own tenant's keys and tables).
 // * Completing a batch releases its footprints.
 #pragma once
 #include <cstddef>
@@ -46,8 +51,10 @@ public:
     {
     }
 
+    void set_cross_tenant(bool on) { cross_ = on; }
+
     // false if the resident bytes do not fit next to what is already resident
-    bool add_tenant(int tenant, uint64_t resident, bool mixed_levels = false)
+    bool add_tenant(int tenant, uint64_t resident, bool mixed_levels = false, bool cross_capable = false)
     {
         if (ready_.count(tenant)) return false;
         if (resident_ + resident > budget_) return false;
@@ -56,6 +63,7 @@ public:
         peak_ = ledger_ > peak_ ? ledger_ : peak_;
         ready_[tenant];
         mixed_[tenant] = mixed_levels;
+        cross_ok_[tenant] = cross_capable;
         return true;
     }
 
@@ -117,6 +125,29 @@ public:
             }
             k++;
         }
+        if (cross_ && b[0].kind == KIND_MULT && cross_ok_[tenant]) {
+            // other tenants' admitted mult jobs, oldest (smallest id) first
+            for (;;) {
+                int best_t = -1;
+                size_t best_k = 0;
+                uint64_t best_id = 0;
+                for (auto &kv : ready_) {
+                    if (kv.first == tenant || !cross_ok_[kv.first]) continue;
+                    const std::deque<Job> &o = kv.second;
+                    for (size_t k = 0; k < o.size(); k++)
+                        if (o[k].kind == KIND_MULT && total + o[k].count <= cap && (best_t < 0 || o[k].id < best_id)) {
+                            best_t = kv.first;
+                            best_k = k;
+                            best_id = o[k].id;
+                        }
+                }
+                if (best_t < 0) break;
+                std::deque<Job> &o = ready_[best_t];
+                total += o[best_k].count;
+                b.push_back(o[best_k]);
+                o.erase(o.begin() + (long)best_k);
+            }
+        }
         return b;
     }
 
@@ -140,7 +171,8 @@ private:
     int max_batch_, max_boot_, max_skips_, head_skips_ = 0;
     std::deque<Job> pending_;
     std::map<int, std::deque<Job>> ready_;
-    std::map<int, bool> mixed_;
+    std::map<int, bool> mixed_, cross_ok_;
+    bool cross_ = false;
 };
 
 }  // namespace rbk_sched

@@ -211,6 +211,8 @@ SIGNATURES = {
     "rbk_server_drain": (ci, [vp]),
     "rbk_server_stats": (ci, [vp, u64p]),
     "rbk_server_destroy": (ci, [vp]),
+    "rbk_server_set_cross_tenant": (ci, [vp, ci]),
+    "rbk_server_cross_merged": (ci, [vp, u64p]),
     "rbk_autotune": (ci, [vp, ci, ci, ctypes.c_char_p, ctypes.POINTER(ci)]),
     "rbk_tune_get": (ci, [vp, ctypes.POINTER(ci)]),
     "rbk_tune_set": (ci, [vp, ctypes.POINTER(ci)]),
@@ -1004,11 +1006,18 @@ class Server:
     def drain(self):
         _check(self.lib.rbk_server_drain(self.h))
 
+    def set_cross_tenant(self, on=True):
+        _check(self.lib.rbk_server_set_cross_tenant(self.h, 1 if on else 0))
+
     def stats(self):
         st = np.zeros(6, dtype=np.uint64)
         _check(self.lib.rbk_server_stats(self.h, st.ctypes.data_as(u64p)))
         keys = ["jobs_done", "batches", "jobs_merged", "ledger_peak", "ledger_now", "budget"]
-        return {k: int(v) for k, v in zip(keys, st)}
+        out = {k: int(v) for k, v in zip(keys, st)}
+        n = ctypes.c_uint64()
+        _check(self.lib.rbk_server_cross_merged(self.h, ctypes.byref(n)))
+        out["jobs_cross_tenant"] = int(n.value)
+        return out
 
     def close(self):
         if getattr(self, "h", None):

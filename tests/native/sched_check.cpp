@@ -194,6 +194,40 @@ int main()
         CHECK(s.ledger() == 200 * tenants);
         CHECK(s.peak() <= budget);
     }
+    // cross-tenant batching: mult jobs of other cross-capable tenants join, oldest first, within the cap;
+    // bootstraps, training steps and tenants that are not cross-capable never do
+    {
+        Scheduler s(1 << 20, 32, 16);
+        s.set_cross_tenant(true);
+        CHECK(s.add_tenant(0, 0, true, true));
+        CHECK(s.add_tenant(1, 0, true, true));
+        CHECK(s.add_tenant(2, 0, true, false));
+        CHECK(s.submit(job(1, 0, KIND_MULT, 5, 8, 1)));
+        CHECK(s.submit(job(2, 1, KIND_MULT, 9, 16, 1)));
+        CHECK(s.submit(job(3, 2, KIND_MULT, 5, 4, 1)));
+        CHECK(s.submit(job(4, 1, KIND_BOOT, 0, 2, 1)));
+        CHECK(s.submit(job(5, 1, KIND_MULT, 7, 8, 1)));
+        CHECK(s.submit(job(6, 1, KIND_MULT, 7, 4, 1)));
+        CHECK(s.admit().size() == 6);
+        auto b = s.next_batch(0);
+        CHECK(ids(b) == (std::vector<uint64_t>{1, 2, 5}));    // 8 + 16 + 8 = 32; job 6 does not fit
+        CHECK(s.ready(1) == 2 && s.ready(2) == 1);
+        auto b1 = s.next_batch(1);
+        CHECK(ids(b1) == (std::vector<uint64_t>{4}));          // a bootstrap head merges with nothing here
+        auto b2 = s.next_batch(1);
+        CHECK(ids(b2) == (std::vector<uint64_t>{6}));          // tenant 2 is not cross-capable
+        CHECK(ids(s.next_batch(2)) == (std::vector<uint64_t>{3}));
+    }
+    // off by default
+    {
+        Scheduler s(1 << 20, 32, 16);
+        CHECK(s.add_tenant(0, 0, true, true));
+        CHECK(s.add_tenant(1, 0, true, true));
+        CHECK(s.submit(job(1, 0, KIND_MULT, 5, 8, 1)));
+        CHECK(s.submit(job(2, 1, KIND_MULT, 5, 8, 1)));
+        CHECK(s.admit().size() == 2);
+        CHECK(ids(s.next_batch(0)) == (std::vector<uint64_t>{1}));
+    }
     std::printf("ok\n");
     return 0;
 }

@@ -114,7 +114,7 @@ class World:
         ctx.sync()
         return want
 
-    def served(self, budget, max_batch, max_boot_batch=16):
+    def served(self, budget, max_batch, max_boot_batch=16, cross=False):
         import torch
 
         from paper_2506_19693_amd import Server
@@ -125,6 +125,8 @@ class World:
         srv = Server(budget, max_batch, max_boot_batch)
         for c in self.ctxs:
             srv.add_tenant(c)
+        if cross:
+            srv.set_cross_tenant(True)
         srv.start()
         ids, outs = [], []
         for kind, t, a in self.jobs:
@@ -213,3 +215,17 @@ def test_mix_equals_alone_tight_budget():
     _compare(w, want, got, final)
     assert resident < stats["ledger_peak"] <= budget
     assert stats["jobs_done"] == len(w.jobs)
+
+
+def test_mix_equals_alone_cross_tenant_batching():
+    """Mult jobs of different tenants (N = 2^11 and 2^12, different keys and
+    chains) merged into one multi-context launch set: every result is still
+    the one the job gets alone."""
+    w = world()
+    want = _W.get("want") or w.alone()
+    got, final, res, stats = w.served(budget=200 << 30, max_batch=64, cross=True)
+    _compare(w, want, got, final)
+    assert stats["jobs_done"] == len(w.jobs)
+    print("cross-tenant: %d jobs merged, %d ran in another tenant's batch, %d batches" % (
+        stats["jobs_merged"], stats["jobs_cross_tenant"], stats["batches"]))
+    assert stats["jobs_cross_tenant"] > 0
