@@ -261,8 +261,9 @@ def bench_train_step(args, torch):
     -> 128 (CE block), each with a 10-way local classifier; degree-3
     activation z + z^2 + z^3/3; r = 256, c = 128, four input tiles; gamma =
     eta = 0.001, mu = 0.9; every W and V bootstrapped each step (14
-    ciphertexts).  Batched (every operation on the 64 samples at once) vs
-    plain (one sample at a time)."""
+    ciphertexts).  Batched (every operation on the 64 samples at once, each
+    block's backward pass on a second stream beside the next block's
+    forward pass) vs single-stream batched vs plain (one sample at a time)."""
     import numpy as np
 
     import synth_inputs as S
@@ -353,6 +354,12 @@ def bench_train_step(args, torch):
         run()
     ctx.sync()
     t_b = (time.perf_counter() - t0) / args.steps
+    # the same steps with every block's backward pass on the context stream
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run(block_parallel=False)
+    ctx.sync()
+    t_s = (time.perf_counter() - t0) / args.steps
     # one step captured into a HIP graph; each replay runs the next step
     graph = ctx.capture(lambda: mlp.train_step(x, ye, yr, lo, T, 2))
     graph.launch()
@@ -388,6 +395,8 @@ def bench_train_step(args, torch):
         "train_steps_per_s_batched": 1.0 / t_b,
         "train_steps_per_s_plain": 1.0 / t_p,
         "train_steps_per_s_graph": 1.0 / t_g,
+        "train_steps_per_s_single_stream": 1.0 / t_s,
+        "block_parallel_gain": t_s / t_b,
         "batched_vs_plain": t_p / t_b,
         "ms_per_step_batched": t_b * 1e3,
         "ms_per_step_plain": t_p * 1e3,

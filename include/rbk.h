@@ -478,11 +478,17 @@ int rbk_mlp_set_mask(rbk_mlp *mlp, int level, const uint64_t *d_pt);
  * context needs rbk_boot_setup and its keys) unless RBK_MLP_NO_BOOTSTRAP.
  * RBK_MLP_PER_SAMPLE runs the samples one at a time (the plain form; the
  * default processes the b samples of every operation in one launch set);
- * the residues are the same either way.  Needs the relinearisation key and
- * the keys of rbk_mlp_rotations.  RBK_ELEVEL if a product would go below
- * level 0. */
+ * the residues are the same either way.  In that batched form block h's
+ * classifier, loss and backward pass run on a second stream of the MLP,
+ * beside block h+1's forward pass (Section 4.2.3: no information flows
+ * between blocks in the backward pass), and the updates wait for both;
+ * RBK_MLP_SEQUENTIAL keeps everything on the context stream, as do per-kernel
+ * timers and graph capture.  The residues are the same either way.  Needs
+ * the relinearisation key and the keys of rbk_mlp_rotations.  RBK_ELEVEL if
+ * a product would go below level 0. */
 #define RBK_MLP_NO_BOOTSTRAP 1u
 #define RBK_MLP_PER_SAMPLE 2u
+#define RBK_MLP_SEQUENTIAL 4u
 int rbk_mlp_train_step(rbk_mlp *mlp, const uint64_t *d_x, const uint64_t *d_y_exp, const uint64_t *d_y_rep, int b,
                        int level, double scale, int t, uint32_t step_flags);
 /* Encrypted inference with early exit (Section 4.2.3: after training, the

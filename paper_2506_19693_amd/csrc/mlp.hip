@@ -158,20 +158,26 @@ void rck(int rc)
 
 // best-fit pool of device buffers; a buffer is reused by later work on the
 // same stream only, so stream order keeps reuse safe
+// Device buffers of step results, reused best-fit.  With block-parallel
+// steps two lanes issue work (the context stream and a side stream): each
+// lane reuses only buffers last used by itself (stream order keeps that
+// safe); a buffer both lanes used waits in `deferred` until the lanes join.
 struct Pool {
-    std::multimap<size_t, u64 *> free_;
+    std::multimap<size_t, u64 *> free_[2];
+    std::vector<std::pair<u64 *, size_t>> deferred;
     std::vector<u64 *> all_;
     ~Pool()
     {
         for (u64 *p : all_) (void)hipFree(p);
     }
-    u64 *take(size_t words, size_t &cap)
+    u64 *take(size_t words, size_t &cap, int lane)
     {
-        auto it = free_.lower_bound(words);
-        if (it != free_.end() && it->first <= 2 * words) {
+        auto &fl = free_[lane];
+        auto it = fl.lower_bound(words);
+        if (it != fl.end() && it->first <= 2 * words) {
             cap = it->first;
             u64 *p = it->second;
-            free_.erase(it);
+            fl.erase(it);
             return p;
         }
         u64 *p = nullptr;
@@ -180,14 +186,30 @@ struct Pool {
         cap = words;
         return p;
     }
-    void give(u64 *p, size_t cap) { free_.emplace(cap, p); }
+    void give(u64 *p, size_t cap, int lane) { free_[lane].emplace(cap, p); }
+    void defer(u64 *p, size_t cap) { deferred.emplace_back(p, cap); }
+    // the side lane has finished everything issued so far (the context stream waited for it)
+    void joined()
+    {
+        for (auto &d : deferred) free_[0].emplace(d.second, d.first);
+        deferred.clear();
+    }
 };
 
 struct Blk {
     Pool *pool;
     u64 *d;
     size_t cap;
-    ~Blk() { pool->give(d, cap); }
+    bool main_use = false;   // touched by the context-stream lane
+    int side_epoch = -1;     // last side-lane epoch that touched it
+    const int *epoch = nullptr;  // the current (not yet joined) side epoch
+    ~Blk()
+    {
+        const bool side_now = epoch && side_epoch == *epoch;
+        if (!side_now) pool->give(d, cap, 0);        // only the context stream may still use it
+        else if (!main_use) pool->give(d, cap, 1);   // only the side lane used it
+        else pool->defer(d, cap);
+    }
 };
 
 struct Vec {
@@ -323,6 +345,9 @@ struct Step {
             grads[h].resize(sh.n_tiles(h));
             have_g[h].assign(sh.n_tiles(h), 0);
         }
+        // one batched sample: every block's classifier and backward pass on
+        // the side lane, next to the following block's forward pass
+        const bool par = samples.size() == 1 && H > 1 && ops.parallel_ok();
         for (const Sample<T> &smp : samples) {
             std::vector<T> a_in = smp.x;
             for (int h = 1; h <= H; h++) {
@@ -340,6 +365,7 @@ struct Step {
                     }
                     z = sum_rows(p);
                     activation(z, a, d, has_d);
+                    if (par) ops.side_begin();
                     yhat = sum_cols(ops.mul(a, Ws));
                     g = ops.sub(yhat, ops.lincomb({{smp.ye, 1.0}}, &yhat, 0.0));
                     bool hs = have_s[h];
@@ -349,6 +375,7 @@ struct Step {
                 } else {
                     z = sum_cols(ops.mul(a_in[0], state[sh.pos(K_W, h, 0)]));
                     activation(z, a, d, has_d);
+                    if (par) ops.side_begin();
                     yhat = sum_rows(ops.mul(a, Ws));
                     g = ops.sub(yhat, ops.lincomb({{smp.yr, 1.0}}, &yhat, 0.0));
                     bool hs = have_s[h];
@@ -362,9 +389,11 @@ struct Step {
                     acc(grads[h][i], hg, ops.bsum(ops.mul(a_in[i], dz)), ops);
                     have_g[h][i] = hg;
                 }
+                if (par) ops.side_end();
                 a_in.assign(1, a);
             }
         }
+        if (par) ops.join();
 
         const double gm = sh.gamma, e = sh.eta, m = sh.mu;
         const double Tsc = std::pow(2.0, sh.log2_scale);
@@ -415,6 +444,10 @@ struct LevelOps {
         return lv - 1;
     }
     void bootstrap(std::vector<int> &) {}
+    bool parallel_ok() { return false; }
+    void side_begin() {}
+    void side_end() {}
+    void join() {}
 };
 
 int step_depth(const Shape &sh)
@@ -434,6 +467,14 @@ struct rbk_mlp {
     rbk_ctx *c = nullptr;
     Shape sh;
     Pool pool;
+    // block-parallel steps: the side lane's stream, its own key-switching
+    // workspace, the fork / join events and the side epoch (joins so far)
+    hipStream_t side = nullptr;
+    u64 *side_ws = nullptr;
+    size_t side_ws_words = 0;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int epoch = 0;
+    bool block_parallel = true;
     // every state ciphertext lives in a buffer of its own ("home", sized for
     // the top level): a step reads the homes and copies its results into them
     // last, so the same device addresses serve every step (and the replays of
@@ -450,6 +491,13 @@ struct rbk_mlp {
             (void)hipStreamSynchronize(c->stream);
             c->live_mlps--;
         }
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        if (side_ws) (void)hipFree(side_ws);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         state.clear();
         for (u64 *h : home) (void)hipFree(h);
         for (auto &kv : masks) (void)hipFree(kv.second);
@@ -466,9 +514,74 @@ struct GpuOps {
     int logN;
     unsigned thr;
 
+    int lane = 0;   // 0: the context stream; 1: the side lane (block-parallel steps)
+
     explicit GpuOps(rbk_mlp *mm) : m(mm), c(mm->c), N(mm->c->N), logN(mm->c->logN)
     {
         thr = (unsigned)std::min<size_t>(MT, N);
+    }
+
+    // ---- block-parallel steps: a block's classifier and backward pass run on
+    // the side lane while the next block's forward pass continues on the
+    // context stream (paper Section 4.2.3: no information flows between
+    // blocks in the backward pass)
+    bool parallel_ok()
+    {
+        if (!m->block_parallel || c->capturing || c->timing) return false;
+        if (!m->side) {
+            if (hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess) {
+                m->side = nullptr;
+                return false;
+            }
+            if (hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess)
+                return false;
+        }
+        return true;
+    }
+    // swap the context's stream and key-switching workspace with the side lane's
+    void swap_lane()
+    {
+        std::swap(c->stream, m->side);
+        std::swap(c->ws, m->side_ws);
+        std::swap(c->ws_words, m->side_ws_words);
+        lane ^= 1;
+    }
+    bool forked = false;   // the side lane has work the context stream has not waited for
+    void side_begin()
+    {
+        hck(hipEventRecord(m->ev_fork, c->stream), "fork");
+        hck(hipStreamWaitEvent(m->side, m->ev_fork, 0), "fork");
+        forked = true;
+        swap_lane();
+    }
+    void side_end() { swap_lane(); }
+    void join()
+    {
+        hck(hipEventRecord(m->ev_join, m->side), "join");
+        hck(hipStreamWaitEvent(c->stream, m->ev_join, 0), "join");
+        forked = false;
+        m->epoch++;
+        m->pool.joined();
+    }
+    // a step that fails half-way leaves the context on its own stream and
+    // workspace, joined with the side lane
+    ~GpuOps()
+    {
+        if (lane) swap_lane();
+        if (forked) {
+            if (hipEventRecord(m->ev_join, m->side) != hipSuccess ||
+                hipStreamWaitEvent(c->stream, m->ev_join, 0) != hipSuccess)
+                (void)hipStreamSynchronize(m->side);
+            m->epoch++;
+            m->pool.joined();
+        }
+    }
+    void touch(const Vec &v)
+    {
+        if (!v.blk) return;
+        if (lane) v.blk->side_epoch = m->epoch;
+        else v.blk->main_use = true;
     }
 
     double q(int lv) const { return (double)c->mod[lv]; }
@@ -478,9 +591,11 @@ struct GpuOps {
     {
         size_t cap = 0;
         const size_t words = (size_t)count * 2 * per(lv);
-        u64 *d = m->pool.take(words, cap);
+        u64 *d = m->pool.take(words, cap, lane);
         Vec v;
         v.blk = std::shared_ptr<Blk>(new Blk{&m->pool, d, cap});
+        v.blk->epoch = &m->epoch;
+        touch(v);
         v.d = d;
         v.lv = lv;
         v.ps = (long)per(lv);
@@ -505,6 +620,7 @@ struct GpuOps {
 
     Vec contiguous(const Vec &a)
     {
+        touch(a);
         if (a.ps == (long)per(a.lv) && (a.count == 1 || a.cs == 2 * a.ps)) return a;
         Vec o = alloc(a.lv, a.count);
         for (int p = 0; p < 2; p++)
@@ -524,6 +640,8 @@ struct GpuOps {
 
     Vec mul(const Vec &a, const Vec &b)
     {
+        touch(a);
+        touch(b);
         const int lv = std::min(a.lv, b.lv);
         if (lv < 1) mthrow(RBK_ELEVEL, "MLP step: no level left for a product");
         if (!c->relin.data) mthrow(RBK_ENOKEY, "relinearisation key not generated");
@@ -541,6 +659,8 @@ struct GpuOps {
     }
     Vec addsub(const Vec &a, const Vec &b, int sub)
     {
+        touch(a);
+        touch(b);
         if (a.s != b.s) mthrow(RBK_ESCALE, "MLP step: addition of ciphertexts at different scales");
         const int lv = std::min(a.lv, b.lv), cnt = bcast(a, b);
         Vec o = alloc(lv, cnt);
@@ -580,6 +700,7 @@ struct GpuOps {
     }
     Vec mask(const Vec &a)
     {
+        touch(a);
         const int lv = a.lv;
         if (lv < 1) mthrow(RBK_ELEVEL, "MLP step: no level left for the mask");
         const u64 *pt = mask_pt(lv);
@@ -591,6 +712,7 @@ struct GpuOps {
     }
     Vec affine(const Vec &a, double alpha, double beta)
     {
+        touch(a);
         const double s = a.s / alpha;
         if (beta == 0.0) {
             Vec r = a;
@@ -620,6 +742,7 @@ struct GpuOps {
         }
         if (lv < 1) mthrow(RBK_ELEVEL, "MLP step: no level left for a constant product");
         const double ql = q(lv);
+        for (auto &t : terms) touch(t.first);
         Terms K{};
         K.n = (int)terms.size();
         for (int j = 0; j < K.n; j++) {
@@ -639,6 +762,7 @@ struct GpuOps {
     }
     Vec bsum(const Vec &a)
     {
+        touch(a);
         if (a.count == 1) return a;
         Vec o = alloc(a.lv, 1);
         hipLaunchKernelGGL(k_mlp_batchsum, grid(a.lv, 2), dim3(thr), 0, c->stream, view(a, a.count), a.count,
@@ -649,6 +773,7 @@ struct GpuOps {
     }
     void bootstrap(std::vector<Vec> &cts)
     {
+        for (auto &x : cts) touch(x);
         if (!c->boot) mthrow(RBK_ESTATE, "bootstrapping is not set up (rbk_boot_setup)");
         int levels[4], np = 0, ns = 0;
         rck(rbk_boot_info(c, levels, &np, &ns));
@@ -838,6 +963,7 @@ extern "C" int rbk_mlp_train_step(rbk_mlp *m, const uint64_t *d_x, const uint64_
         if ((!is_v || t > 1) && !m->state[i].d) return rbk_set_error(RBK_ESTATE, "state ciphertext not set");
     }
     try {
+        m->block_parallel = (flags & RBK_MLP_SEQUENTIAL) == 0;
         GpuOps ops(m);
         m->scalars.clear();
         const size_t P = ops.per(level);

@@ -55,6 +55,7 @@ MLP_LITERAL_DERIV = 1
 MLP_L2_DECAY = 2
 MLP_NO_BOOTSTRAP = 1
 MLP_PER_SAMPLE = 2
+MLP_SEQUENTIAL = 4
 
 
 class RbkJob(ctypes.Structure):
@@ -918,10 +919,12 @@ class Mlp:
         _check(self.lib.rbk_mlp_get_weights(self.h, *ptrs))
         return Ws, Wst, Vs, Vst
 
-    def train_step(self, x, y_exp, y_rep, level, scale, t, bootstrap=True, per_sample=False):
-        """x: [b][tiles][2][level+1][N], y_exp / y_rep: [b][2][level+1][N] device tensors."""
+    def train_step(self, x, y_exp, y_rep, level, scale, t, bootstrap=True, per_sample=False, block_parallel=True):
+        """x: [b][tiles][2][level+1][N], y_exp / y_rep: [b][2][level+1][N] device tensors.
+        block_parallel=False keeps every block's backward pass on the context stream."""
         b = x.shape[0]
-        flags = (0 if bootstrap else MLP_NO_BOOTSTRAP) | (MLP_PER_SAMPLE if per_sample else 0)
+        flags = ((0 if bootstrap else MLP_NO_BOOTSTRAP) | (MLP_PER_SAMPLE if per_sample else 0)
+                 | (0 if block_parallel else MLP_SEQUENTIAL))
         _check(self.lib.rbk_mlp_train_step(self.h, _ptr(x), _ptr(y_exp), _ptr(y_rep), b, level, float(scale), t,
                                            flags))
 

@@ -133,15 +133,58 @@ def test_train_step_bit_exact_no_bootstrap(name):
     for lv, pt in ops.masks.items():
         p.mlp.set_mask(lv, p.d.to_ntt(pt, lv))
     x, ye, yr = p.upload_inputs(samples, L)
-    for per_sample in (True, False):
+    # per sample; batched on one stream; batched with the blocks' backward passes on the side stream
+    for per_sample, par in ((True, False), (False, False), (False, True)):
         p.set_state(st)
-        p.mlp.train_step(x, ye, yr, L, T, 2, bootstrap=False, per_sample=per_sample)
+        p.mlp.train_step(x, ye, yr, L, T, 2, bootstrap=False, per_sample=per_sample, block_parallel=par)
         got = p.state()
         for (res, lv, s), w in zip(got, want):
             assert lv == w.lv and s == w.s
             assert np.array_equal(res, w.d)
         if per_sample:
             assert p.mlp.scalars() == ops.scalars
+
+
+def test_block_parallel_equals_sequential_four_blocks():
+    """Section 4.2.3: no information flows between blocks in the backward
+    pass, so block h's classifier and backward pass may run beside block
+    h+1's forward pass.  Four blocks (RE, CE, RE, CE), three samples, steps
+    t = 1 and t = 2 from the same state, repeated so that the side stream
+    reuses its buffers: every state ciphertext, level, scale and integer
+    constant equals the single-stream step's."""
+    cfg = M.MlpConfig(k0=20, widths=[8, 8, 8, 8], o=4, r=16, c=32, gamma=0.05, log2_scale=40.0)
+    L = 18
+    p = Pair(cfg, 10, [60] + [40] * L, [60] * 3, 3, oracle=False)
+    d = p.d
+    assert cfg.H == 4 and M.depth(cfg) <= L - 1
+    g = S.rng(23, 1)
+    Ws, Wst, Vs, Vst = _model(cfg, g, True)
+    X, Y = S.mlp_batch(g, 3, cfg.k0, cfg.o)
+    T = 2.0 ** cfg.log2_scale
+    wl = M.depth(cfg) + 1
+    st = [p.gpu_enc(v, wl, T) for v in M.pack_state(cfg, Ws, Wst, Vs, Vst)]
+    packed = [M.pack_sample(cfg, X[i], Y[i]) for i in range(len(X))]
+    x = d.empty(len(X), cfg.tiles, 2, L + 1, p.N)
+    ye, yr = d.empty(len(X), 2, L + 1, p.N), d.empty(len(X), 2, L + 1, p.N)
+    for i, (xt, e, r) in enumerate(packed):
+        for t, v in enumerate(xt):
+            x[i, t].copy_(p.gpu_enc(v, L, T))
+        ye[i].copy_(p.gpu_enc(e, L, T))
+        yr[i].copy_(p.gpu_enc(r, L, T))
+
+    def step(t, par):
+        for i, c in enumerate(st):
+            p.mlp.set_state(i, c, wl, T)
+        p.mlp.train_step(x, ye, yr, L, T, t, bootstrap=False, block_parallel=par)
+        return p.state(), p.mlp.scalars()
+
+    for t in (1, 2, 2):
+        want = step(t, False)
+        got = step(t, True)
+        assert got[1] == want[1]
+        for (a, la, sa), (b, lb, sb) in zip(got[0], want[0]):
+            assert la == lb and sa == sb
+            assert np.array_equal(a, b)
 
 
 def test_train_step_t1_ignores_velocities_and_rejects_missing_state():
