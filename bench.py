@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving part")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-ring-degree part")
     ap.add_argument("--no-paper-mlps", action="store_true", help="skip the paper's eMLP architectures")
+    ap.add_argument("--train-small-b", type=int, default=8,
+                    help="samples of the small-batch block-parallel timing of the train_step leg (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-lambda", type=float, default=0.0,
                     help="Poisson arrival rate, jobs/s (default: 0.8 x the capacity measured in the same run)")
@@ -360,6 +362,24 @@ def bench_train_step(args, torch):
         run(block_parallel=False)
     ctx.sync()
     t_s = (time.perf_counter() - t0) / args.steps
+    # a small batch (8 samples), where one operation leaves the device part idle
+    nb = min(args.train_small_b, b)
+    xs, yes, yrs = x[:nb], ye[:nb], yr[:nb]
+
+    def small(par):
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mlp.train_step(xs, yes, yrs, lo, T, step[0], block_parallel=par)
+            step[0] += 1
+        ctx.sync()
+        return (time.perf_counter() - t0) / args.steps
+
+    small_res = None
+    if nb > 0:
+        small(True)
+        t_8p, t_8s = small(True), small(False)
+        small_res = {"samples": nb, "ms_per_step_block_parallel": t_8p * 1e3,
+                     "ms_per_step_single_stream": t_8s * 1e3, "block_parallel_gain": t_8s / t_8p}
     # one step captured into a HIP graph; each replay runs the next step
     graph = ctx.capture(lambda: mlp.train_step(x, ye, yr, lo, T, 2))
     graph.launch()
@@ -397,6 +417,7 @@ def bench_train_step(args, torch):
         "train_steps_per_s_graph": 1.0 / t_g,
         "train_steps_per_s_single_stream": 1.0 / t_s,
         "block_parallel_gain": t_s / t_b,
+        "small_batch": small_res,
         "batched_vs_plain": t_p / t_b,
         "ms_per_step_batched": t_b * 1e3,
         "ms_per_step_plain": t_p * 1e3,
