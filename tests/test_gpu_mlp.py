@@ -187,6 +187,64 @@ def test_block_parallel_equals_sequential_four_blocks():
             assert np.array_equal(a, b)
 
 
+def test_failed_step_leaves_context_and_mlp_usable():
+    """Steps whose inputs sit too low fail part-way -- for the middle levels
+    in block 1's classifier or backward pass, issued on the side stream --
+    with RBK_ELEVEL.  Afterwards the context is back on its own stream and
+    workspace: a full step gives the single-stream step's residues, and once
+    the MLP (and with it the side stream's workspace) is gone, the context's
+    own mult_relin still matches the oracle."""
+    from paper_2506_19693_amd import RbkError
+
+    cfg = M.MlpConfig(k0=20, widths=[8, 8], o=4, r=16, c=32, gamma=0.05, log2_scale=40.0)
+    L = 14
+    p = Pair(cfg, 10, [60] + [40] * L, [60] * 3, 3)
+    d = p.d
+    g = S.rng(27, 1)
+    Ws, Wst, Vs, Vst = _model(cfg, g, True)
+    X, Y = S.mlp_batch(g, 2, cfg.k0, cfg.o)
+    T = 2.0 ** cfg.log2_scale
+    wl = M.depth(cfg) + 1
+    st = [p.gpu_enc(v, wl, T) for v in M.pack_state(cfg, Ws, Wst, Vs, Vst)]
+    packed = [M.pack_sample(cfg, X[i], Y[i]) for i in range(len(X))]
+
+    def inputs(lv):
+        x = d.empty(2, cfg.tiles, 2, lv + 1, p.N)
+        ye, yr = d.empty(2, 2, lv + 1, p.N), d.empty(2, 2, lv + 1, p.N)
+        for i, (xt, e, r) in enumerate(packed):
+            for t, v in enumerate(xt):
+                x[i, t].copy_(p.gpu_enc(v, lv, T))
+            ye[i].copy_(p.gpu_enc(e, lv, T))
+            yr[i].copy_(p.gpu_enc(r, lv, T))
+        return x, ye, yr
+
+    def run(lv, ins, par=True):
+        for i, c in enumerate(st):
+            p.mlp.set_state(i, c, wl, T)
+        p.mlp.train_step(*ins, lv, T, 2, bootstrap=False, block_parallel=par)
+
+    failed = []
+    for lv in range(1, L):
+        try:
+            run(lv, inputs(lv))
+        except RbkError:
+            failed.append(lv)
+    print("steps that failed part-way: input levels %s" % failed)
+    assert len(failed) >= 4
+    ins = inputs(L)                      # encrypted once: both forms see the same ciphertexts
+    got = []
+    for par in (True, False):
+        run(L, ins, par)
+        got.append(p.state())
+    for (a, la, sa), (b, lb, sb) in zip(*got):
+        assert la == lb and sa == sb and np.array_equal(a, b)
+    p.mlp.close()
+    a = S.uniform_residues(p.g, p.o.Q, p.N, lead=(2,))
+    b = S.uniform_residues(p.g, p.o.Q, p.N, lead=(2,))
+    res = d.to_coef(d.mult_relin(d.to_ntt(a, L), d.to_ntt(b, L), L), L)
+    assert np.array_equal(res, p.o.mult_relin(L, p.rlk, a, b))
+
+
 def test_train_step_t1_ignores_velocities_and_rejects_missing_state():
     from paper_2506_19693_amd import RbkError
 
