@@ -7,6 +7,9 @@
   literal derivative and L2 decay; the batched form equals the per-sample form;
 * N = 2^11 with the bootstrap (oracle constants imported): the bootstrapped
   state is bit-exact with the oracle's bootstrap of its updated state;
+* block parallelism (a block's backward pass on a second stream) gives the
+  single-stream residues: four blocks, and two blocks with the bootstrap;
+  a step that fails part-way leaves the context usable;
 * N = 2^16 at the full workload shape (784 -> 128 -> 128, ten classes,
   r = 256, c = 128, four input tiles, 64 samples, degree-3 activation): two
   steps decrypt to the float64 packed step within 2^-10.
@@ -184,6 +187,45 @@ def test_block_parallel_equals_sequential_four_blocks():
         assert got[1] == want[1]
         for (a, la, sa), (b, lb, sb) in zip(got[0], want[0]):
             assert la == lb and sa == sb
+            assert np.array_equal(a, b)
+
+
+def test_block_parallel_with_bootstrap_equals_sequential():
+    """Two blocks at N = 2^11 with the bootstrap of every W and V after the
+    update (one batched call on the context stream, after it has waited for
+    the side stream): steps t = 1 and t = 2 give the same residues, levels
+    and scales with and without block parallelism."""
+    cfg = M.MlpConfig(k0=24, widths=[16, 16], o=4, r=32, c=32, gamma=0.05, log2_scale=50.0)
+    p = Pair(cfg, 11, [60] + [50] * 26, [60] * 6, 6, hw=64, boot_rho=4, oracle=False)
+    d = p.d
+    lo = d.boot_levels[3]
+    assert lo >= M.depth(cfg)
+    g = S.rng(28, 1)
+    Ws, Wst, _, _ = _model(cfg, g, False)
+    X, Y = S.mlp_batch(g, 2, cfg.k0, cfg.o)
+    T = 2.0 ** cfg.log2_scale
+    st = {i: p.gpu_enc(v, lo, T) for i, v in enumerate(M.pack_state(cfg, Ws, Wst))
+          if cfg.state_layout()[i][0] in ("W", "Wstar")}
+    packed = [M.pack_sample(cfg, X[i], Y[i]) for i in range(len(X))]
+    x = d.empty(2, cfg.tiles, 2, lo + 1, p.N)
+    ye, yr = d.empty(2, 2, lo + 1, p.N), d.empty(2, 2, lo + 1, p.N)
+    for i, (xt, e, r) in enumerate(packed):
+        for t, v in enumerate(xt):
+            x[i, t].copy_(p.gpu_enc(v, lo, T))
+        ye[i].copy_(p.gpu_enc(e, lo, T))
+        yr[i].copy_(p.gpu_enc(r, lo, T))
+    got = []
+    for par in (True, False):
+        for i, c in st.items():
+            p.mlp.set_state(i, c, lo, T)
+        states = []
+        for t in (1, 2):
+            p.mlp.train_step(x, ye, yr, lo, T, t, block_parallel=par)
+            states.append(p.state())
+        got.append(states)
+    for sa, sb in zip(*got):
+        for (a, la, xa), (b, lb, xb) in zip(sa, sb):
+            assert la == lb == lo and xa == xb
             assert np.array_equal(a, b)
 
 
