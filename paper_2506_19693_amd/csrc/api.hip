@@ -256,7 +256,7 @@ char *desc_upload(rbk_ctx_impl *c, const DescBlob &b, int *rc)
 
 // the side streams (default priority) and events of the multi-lane ModDown,
 // created on first use on the context's device
-static int side_streams(rbk_ctx_impl *c)
+int side_streams(rbk_ctx_impl *c)
 {
     if (c->side[RBK_LANES - 1] && c->side_ev[RBK_LANES]) return RBK_OK;
     for (int k = 0; k < RBK_LANES; k++)

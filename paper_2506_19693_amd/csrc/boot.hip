@@ -67,6 +67,9 @@ struct BootPlan {
     size_t pool_words = 0;
     u64 *rot_area = nullptr;  // hoisted baby rotations of a transform
     size_t rot_words = 0;
+    // key-switching workspaces of the giant-step lanes (side streams)
+    u64 *lane_ws[RBK_LANES] = {};
+    size_t lane_ws_words[RBK_LANES] = {};
     // the scalars with Shoup quotients, [n_scalars][nQ][2], uploaded when they change
     u64 *d_scal = nullptr;
     bool scal_dirty = true;
@@ -371,6 +374,7 @@ void boot_free(rbk_ctx_impl *ci)
     for (u64 *d : P->d_plain) release_buffer(ci, d);
     for (u64 *d : P->pool) release_buffer(ci, d);
     release_buffer(ci, P->rot_area);
+    for (int k = 0; k < RBK_LANES; k++) release_buffer(ci, P->lane_ws[k]);
     release_buffer(ci, P->d_scal);
     delete P;
     ci->boot = nullptr;
@@ -648,13 +652,43 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
         if (rc) return rc;
         rots = P.rot_area;
     }
-    u64 *inner = take(), *irot = take(), *total = take();
-    if (!inner || !irot || !total) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
-    bool have_total = false;
     std::vector<int> gs;
     for (auto &e : L.ents)
         if (std::find(gs.begin(), gs.end(), e.g) == gs.end()) gs.push_back(e.g);
+    const int n_rot = (int)std::count_if(gs.begin(), gs.end(), [](int g) { return g != 0; });
+    // Giant-step lanes: the giant steps are independent up to the final sum,
+    // so those with a rotation go round-robin over the context's side streams
+    // (each with key-switching workspace and registers of its own) and every
+    // lane keeps a partial sum; the context stream adds the partial sums.
+    // Modular sums do not depend on their order, so the residues are those of
+    // one lane.  One lane while the stream is captured or timers run.
+    const int nl = (c->lanes > 1 && !c->capturing && !c->timing && n_rot > 1 && side_streams(c) == RBK_OK)
+                       ? std::min(c->lanes, n_rot)
+                       : 0;
+    u64 *inner = take(), *irot = take(), *total = take();
+    if (!inner || !irot || !total) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+    u64 *l_inner[RBK_LANES] = {}, *l_irot[RBK_LANES] = {}, *l_acc[RBK_LANES] = {};
+    bool l_have[RBK_LANES] = {};
+    for (int k = 0; k < nl; k++) {
+        l_inner[k] = take();
+        l_irot[k] = take();
+        l_acc[k] = take();
+        if (!l_inner[k] || !l_irot[k] || !l_acc[k]) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+    }
+    const LimbMap qm{0, c->nQ, c->nQ};
+    if (nl) {
+        if (hipEventRecord(c->side_ev[RBK_LANES], c->stream) != hipSuccess) return rbk_set_error(RBK_EDEVICE, "fork");
+        for (int k = 0; k < nl; k++)
+            if (hipStreamWaitEvent(c->side[k], c->side_ev[RBK_LANES], 0) != hipSuccess)
+                return rbk_set_error(RBK_EDEVICE, "fork");
+    }
+    bool have_total = false;
+    int lane = 0;
     for (int g : gs) {
+        const bool on_lane = nl && g != 0;
+        const int k = lane;
+        hipStream_t st = on_lane ? c->side[k] : c->stream;
+        u64 *in_buf = on_lane ? l_inner[k] : inner, *rot_buf = on_lane ? l_irot[k] : irot;
         // the giant step's diagonal products, up to MAC_MAX_TERMS per pass
         MacTerms T{};
         bool first = true;
@@ -670,17 +704,40 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
             }
             T.pt[T.n] = P.d_plain[e.plain];
             if (++T.n == MAC_MAX_TERMS) {
-                mac_multi_launch(c, T, inner, lvl, n_ct, first ? 0 : 1, c->stream);
+                mac_multi_launch(c, T, in_buf, lvl, n_ct, first ? 0 : 1, st);
                 first = false;
                 T.n = 0;
             }
         }
-        if (T.n) mac_multi_launch(c, T, inner, lvl, n_ct, first ? 0 : 1, c->stream);
-        u64 *term = inner;
-        if (g) {
-            rc = rotate(inner, irot, lvl, n_ct, (int64_t)g * L.n1 * L.h0);
+        if (T.n) mac_multi_launch(c, T, in_buf, lvl, n_ct, first ? 0 : 1, st);
+        if (on_lane) {
+            // the rotation on the lane's stream and workspace
+            std::swap(c->stream, c->side[k]);
+            std::swap(c->ws, P.lane_ws[k]);
+            std::swap(c->ws_words, P.lane_ws_words[k]);
+            rc = rotate(in_buf, rot_buf, lvl, n_ct, (int64_t)g * L.n1 * L.h0);
+            std::swap(c->stream, c->side[k]);
+            std::swap(c->ws, P.lane_ws[k]);
+            std::swap(c->ws_words, P.lane_ws_words[k]);
             if (rc) break;
-            term = irot;
+            if (!l_have[k]) {
+                if (hipMemcpyAsync(l_acc[k], rot_buf, (size_t)n_ct * ctw * sizeof(u64), hipMemcpyDeviceToDevice, st) !=
+                    hipSuccess) {
+                    rc = RBK_EDEVICE;
+                    break;
+                }
+                l_have[k] = true;
+            } else {
+                ew_launch(c, EW_ADD, l_acc[k], rot_buf, l_acc[k], 2 * n_ct, lvl + 1, qm, st);
+            }
+            lane = (lane + 1) % nl;
+            continue;
+        }
+        u64 *term = in_buf;
+        if (g) {
+            rc = rotate(in_buf, rot_buf, lvl, n_ct, (int64_t)g * L.n1 * L.h0);
+            if (rc) break;
+            term = rot_buf;
         }
         if (!have_total) {
             if (hipMemcpyAsync(total, term, (size_t)n_ct * ctw * sizeof(u64), hipMemcpyDeviceToDevice, c->stream) !=
@@ -690,8 +747,31 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
             }
             have_total = true;
         } else {
-            ew_launch(c, EW_ADD, total, term, total, 2 * n_ct, lvl + 1, LimbMap{0, c->nQ, c->nQ}, c->stream);
+            ew_launch(c, EW_ADD, total, term, total, 2 * n_ct, lvl + 1, qm, c->stream);
         }
+    }
+    // join every lane, also after a failure: later work on the context stream
+    // reuses the registers and workspaces the lanes still read
+    for (int k = 0; k < nl; k++) {
+        hipError_t e = hipEventRecord(c->side_ev[k], c->side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->side_ev[k], 0);
+        if (e != hipSuccess && rc == RBK_OK) rc = rbk_set_error(RBK_EDEVICE, "lane join");
+    }
+    for (int k = 0; k < nl && rc == RBK_OK; k++) {
+        if (!l_have[k]) continue;
+        if (!have_total) {
+            if (hipMemcpyAsync(total, l_acc[k], (size_t)n_ct * ctw * sizeof(u64), hipMemcpyDeviceToDevice, c->stream) !=
+                hipSuccess)
+                rc = RBK_EDEVICE;
+            have_total = true;
+        } else {
+            ew_launch(c, EW_ADD, total, l_acc[k], total, 2 * n_ct, lvl + 1, qm, c->stream);
+        }
+    }
+    for (int k = 0; k < nl; k++) {
+        give(l_inner[k]);
+        give(l_irot[k]);
+        give(l_acc[k]);
     }
     if (!rc) rc = rbk_rescale_batch(c, total, x.d, lvl, n_ct);
     x.level = lvl - 1;

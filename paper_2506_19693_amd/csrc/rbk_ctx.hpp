@@ -167,6 +167,8 @@ void kt_end(const rbk_ctx_impl *c, int cls, double bytes, hipStream_t st);
 // count `count` key switches at `level` (one call, the key read once) for rbk_ks_stats
 void ks_account(rbk_ctx_impl *c, const int *levels, int count, int key_level);
 u64 *ws_reserve(rbk_ctx_impl *c, size_t words);
+// the context's side streams and their fork / join events (created once)
+int side_streams(rbk_ctx_impl *c);
 // free a replaced device buffer, or keep it until the last graph is destroyed
 void release_buffer(rbk_ctx_impl *c, void *p);
 const ModUpTables &modup_tables(rbk_ctx_impl *c, int level);
