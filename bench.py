@@ -15,7 +15,7 @@ secret; all inputs are resident in HBM before the timed region.
 * plain:   one call per ciphertext (mult_relin, rescale, hoisted rotations).
 
 value = batched key switches per second.  The hoisted rotations' ModDowns
-run on two lanes (side streams) unless --lanes 1.  Per-kernel HIP-event
+run on three lanes (side streams) unless --lanes 1.  Per-kernel HIP-event
 timers run over a second pass of the same steps (not the timed one; kernels
 do not overlap there); the kernel with the largest total time is reported
 against the MI355X HBM roofline.  The CPU oracle is timed on a bounded sample.
@@ -67,8 +67,9 @@ def parse():
     ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--serve-max-boot", type=int, default=16)
     ap.add_argument("--serve-mlp-b", type=int, default=8, help="samples per training step of serving jobs")
-    ap.add_argument("--lanes", type=int, default=2,
-                    help="ModDown lanes of hoisted-rotation batches (1: no overlapping kernels, as for profiling)")
+    ap.add_argument("--lanes", type=int, default=3,
+                    help="side-stream lanes of hoisted-rotation ModDowns and bootstrap giant steps "
+                         "(1: no overlapping kernels, as for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device to device before the timed region (calibrates HBM byte counters)")
     return ap.parse_args()

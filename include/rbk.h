@@ -514,9 +514,10 @@ int rbk_mlp_scalars(const rbk_mlp *mlp, int64_t *out, int max);
 /* Encrypted-training jobs of several tenants on one GPU.  A tenant is a
  * context with its keys (and bootstrap plan) set up; from rbk_server_add_tenant
  * until rbk_server_destroy the server owns it: it gets a stream of its own and
- * a worker thread of its own, and the caller must not call into it (the
- * device memory a job names stays the caller's).  Work of different tenants
- * overlaps on the device.
+ * a worker thread of its own, runs on one lane (rbk_set_lanes; restored at
+ * destroy), and the caller must not call into it (the device memory a job
+ * names stays the caller's).  Work of different tenants overlaps on the
+ * device.
  *
  * Admission: an HBM ledger starts with every tenant's resident bytes (its
  * evaluation keys and bootstrap diagonals); a job is admitted, in arrival
@@ -640,16 +641,20 @@ int rbk_capture_end(rbk_ctx *ctx, rbk_graph **out);
 int rbk_graph_launch(rbk_graph *graph);
 int rbk_graph_destroy(rbk_graph *graph);
 
-/* ---- ModDown lanes ------------------------------------------------------ */
+/* ---- lanes --------------------------------------------------------------- */
 /* A batch of hoisted rotations (rbk_rotate_hoisted_batch) runs the
  * independent ModDowns of its rotations round-robin on n side streams (lanes,
  * default priority) that join the context stream before the call returns;
- * each lane has tp/conv scratch of its own in the workspace.  Two lanes (the
- * default) overlap one rotation's arithmetic-bound kernels with another's
- * memory-bound ones; n = 1 runs everything on the context stream (kernels do
- * not overlap, so profiler durations are each kernel's own).  Lanes are not
- * used while timers run or while the stream is captured.  n outside 1..2:
- * RBK_EINVAL, setting unchanged. */
+ * each lane has tp/conv scratch of its own in the workspace.  The bootstrap
+ * runs the giant steps of its linear transforms on the same lanes (each with
+ * a key-switching workspace and registers of its own; partial sums added on
+ * the context stream).  Lanes overlap one rotation's arithmetic-bound kernels
+ * with another's memory-bound ones, and small kernels of single-ciphertext
+ * calls with each other; the default is 3; n = 1 runs everything on the
+ * context stream (kernels do not overlap, so profiler durations are each
+ * kernel's own).  Residues do not depend on n.  Lanes are not used while
+ * timers run or while the stream is captured.  n outside 1..3: RBK_EINVAL,
+ * setting unchanged. */
 int rbk_set_lanes(rbk_ctx *ctx, int n);
 
 /* ---- per-kernel timers -------------------------------------------------- */

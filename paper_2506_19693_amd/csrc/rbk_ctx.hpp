@@ -24,10 +24,11 @@ struct ModUpTables {
 // Per-kernel timers (HIP events around every launch of a kernel on the
 // context stream), enabled by rbk_timer_enable.  'bytes' accumulates the
 // algorithmic HBM bytes of each launch: what the kernel must read and write.
-// ModDown lanes of a batch of hoisted rotations (side streams, default
-// priority): two overlap one rotation's VALU-bound kernels with another's
-// memory-bound ones; a third measured no better
-#define RBK_LANES 2
+// Side-stream lanes (default priority) of a batch of hoisted rotations'
+// ModDowns and of the bootstrap's giant steps: they overlap one rotation's
+// VALU-bound kernels with another's memory-bound ones, and kernels too small
+// to fill the GPU (single-ciphertext calls) with each other
+#define RBK_LANES 3
 
 enum KClass {
     KC_NTT_COLS_FWD = 0,

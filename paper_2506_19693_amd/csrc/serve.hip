@@ -51,6 +51,7 @@ struct Tenant {
     rbk_ctx *c = nullptr;
     hipStream_t st = nullptr;
     hipStream_t old_stream = nullptr;
+    int old_lanes = 1;
     uint64_t resident = 0;
     std::thread th;
     u64 *stage = nullptr;
@@ -423,6 +424,11 @@ extern "C" int rbk_server_add_tenant(rbk_server *S, rbk_ctx *c, int *tenant)
     }
     t->old_stream = c->stream;
     c->stream = t->st;
+    // a served context runs on one lane: the tenants' streams overlap each
+    // other instead, and the footprints the ledger admits by assume no lane
+    // buffers
+    t->old_lanes = c->lanes;
+    c->lanes = 1;
     S->tenants.push_back(t);
     *tenant = t->id;
     return RBK_OK;
@@ -572,6 +578,7 @@ extern "C" int rbk_server_destroy(rbk_server *S)
         (void)hipStreamSynchronize(t->st);
         if (t->stage) (void)hipFree(t->stage);
         t->c->stream = t->old_stream;
+        t->c->lanes = t->old_lanes;
         (void)hipStreamDestroy(t->st);
         delete t;
     }

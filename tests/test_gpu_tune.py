@@ -65,19 +65,20 @@ def test_every_configuration_gives_the_same_residues(log_n):
 
 
 def test_lanes_give_the_same_residues():
-    """Hoisted rotations on one lane (context stream only) and on two side
-    streams give the same residues; lane counts outside 1..2 are refused."""
+    """Hoisted rotations on one lane (context stream only) and on two and
+    three side streams give the same residues; lane counts outside 1..3 are
+    refused."""
     from paper_2506_19693_amd import RbkError
 
     d, g = _ctx(14)
     L = d.L
     A = d.to_ntt(S.uniform_residues(g, d.moduli[: L + 1], d.N, lead=(6, 2)), L)
     got = []
-    for lanes in (1, 2, 1):
+    for lanes in (1, 2, 3, 1):
         d.set_lanes(lanes)
         got.append(d.to_coef(d.rotate_hoisted_batch(A, [1, 5, -3, 0], L), L))
-    assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[2])
-    for bad in (0, 3):
+    assert all(np.array_equal(got[0], x) for x in got[1:])
+    for bad in (0, 4):
         with pytest.raises(RbkError):
             d.set_lanes(bad)
 
