@@ -648,7 +648,8 @@ int rbk_graph_destroy(rbk_graph *graph);
  * each lane has tp/conv scratch of its own in the workspace.  The bootstrap
  * runs the giant steps of its linear transforms on the same lanes (each with
  * a key-switching workspace and registers of its own; partial sums added on
- * the context stream).  Lanes overlap one rotation's arithmetic-bound kernels
+ * the context stream) and, for batches of up to 4 ciphertexts, the EvalMod
+ * products of one dependency depth.  Lanes overlap one rotation's arithmetic-bound kernels
  * with another's memory-bound ones, and small kernels of single-ciphertext
  * calls with each other; the default is 3; n = 1 runs everything on the
  * context stream (kernels do not overlap, so profiler durations are each

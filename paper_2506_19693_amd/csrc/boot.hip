@@ -557,9 +557,12 @@ struct Runner {
         P.pool.push_back(d);
         return d;
     }
+    // while steps run on several lanes, registers they release are held back
+    // until the lanes join (another lane could otherwise take one still in use)
+    std::vector<u64 *> *held = nullptr;
     void give(u64 *d)
     {
-        if (d) free_.push_back(d);
+        if (d) (held ? *held : free_).push_back(d);
     }
     size_t per(int level) const { return (size_t)(level + 1) * c->N; }
 
@@ -794,7 +797,7 @@ int Runner::evalmod(Reg &x, int n_ct)
         drop(r.d, r.level, lv, dst, n_ct);
         return dst;
     };
-    for (const BootStep &st : P.prog) {
+    auto run_step = [&](const BootStep &st) -> int {
         if (st.kind == ST_PROD) {
             // T_k = 2 T_a T_b - T_c (or + constant when c = 0), exact scale via the scalar
             const int lv = st.lv;
@@ -882,6 +885,84 @@ int Runner::evalmod(Reg &x, int n_ct)
             give(A);
             give(X);
         }
+        return RBK_OK;
+    };
+    // EvalMod lanes: for small batches the products of one dependency depth
+    // (powers T_3 and T_4; T_5 .. T_8; the giant steps of one level of the
+    // evaluation tree) run on the side streams, each lane with a
+    // key-switching workspace of its own; the lanes join after every depth.
+    // Larger batches fill the GPU by themselves and keep the program order
+    // (fewer registers alive).  The residues do not depend on the lanes.
+    const int nl = (n_ct <= 8 && c->lanes > 1 && !c->capturing && !c->timing && side_streams(c) == RBK_OK)
+                       ? c->lanes
+                       : 0;
+    if (!nl) {
+        for (const BootStep &st : P.prog)
+            if ((rc = run_step(st)) != RBK_OK) return rc;
+    } else {
+        // dependency depth of every step: one more than that of its deepest input
+        const size_t ns = P.prog.size();
+        std::vector<int> depth(ns, 0);
+        std::map<int, int> dT{{1, 0}};
+        std::map<std::string, int> dR;
+        int max_d = 0;
+        for (size_t i = 0; i < ns; i++) {
+            const BootStep &st = P.prog[i];
+            int d = 0;
+            if (st.kind == ST_PROD) {
+                d = std::max(dT[st.a], dT[st.b]);
+                if (st.cc) d = std::max(d, dT[st.cc]);
+                dT[st.k] = d + 1;
+            } else if (st.kind == ST_LEAF) {
+                for (auto &t : st.terms) d = std::max(d, dT[t.first]);
+                dR[st.reg] = d + 1;
+            } else if (st.kind == ST_GIANT) {
+                d = std::max({dR[st.reg + "q"], dR[st.reg + "r"], dT[st.m]});
+                dR[st.reg] = d + 1;
+            } else {
+                d = dR["p"];
+                dR["p"] = d + 1;
+            }
+            depth[i] = d + 1;
+            max_d = std::max(max_d, d + 1);
+        }
+        std::vector<u64 *> held_regs;
+        for (int dd = 1; dd <= max_d && rc == RBK_OK; dd++) {
+            std::vector<size_t> grp;
+            for (size_t i = 0; i < ns; i++)
+                if (depth[i] == dd) grp.push_back(i);
+            if (grp.size() < 2) {
+                for (size_t i : grp)
+                    if ((rc = run_step(P.prog[i])) != RBK_OK) break;
+                continue;
+            }
+            const int nq = std::min(nl, (int)grp.size());
+            if (hipEventRecord(c->side_ev[RBK_LANES], c->stream) != hipSuccess) return rbk_set_error(RBK_EDEVICE, "fork");
+            for (int k = 0; k < nq; k++)
+                if (hipStreamWaitEvent(c->side[k], c->side_ev[RBK_LANES], 0) != hipSuccess)
+                    return rbk_set_error(RBK_EDEVICE, "fork");
+            held = &held_regs;
+            for (size_t j = 0; j < grp.size() && rc == RBK_OK; j++) {
+                const int k = (int)(j % nq);
+                std::swap(c->stream, c->side[k]);
+                std::swap(c->ws, P.lane_ws[k]);
+                std::swap(c->ws_words, P.lane_ws_words[k]);
+                rc = run_step(P.prog[grp[j]]);
+                std::swap(c->stream, c->side[k]);
+                std::swap(c->ws, P.lane_ws[k]);
+                std::swap(c->ws_words, P.lane_ws_words[k]);
+            }
+            held = nullptr;
+            // join every lane, also after a failure
+            for (int k = 0; k < nq; k++) {
+                hipError_t e = hipEventRecord(c->side_ev[k], c->side[k]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->side_ev[k], 0);
+                if (e != hipSuccess && rc == RBK_OK) rc = rbk_set_error(RBK_EDEVICE, "lane join");
+            }
+            for (u64 *d : held_regs) free_.push_back(d);
+            held_regs.clear();
+        }
+        if (rc) return rc;
     }
     // release the powers (T[1] is the caller's register)
     for (auto &t : T)
