@@ -645,7 +645,9 @@ int rbk_graph_destroy(rbk_graph *graph);
 /* A batch of hoisted rotations (rbk_rotate_hoisted_batch) runs the
  * independent ModDowns of its rotations round-robin on n side streams (lanes,
  * default priority) that join the context stream before the call returns;
- * each lane has tp/conv scratch of its own in the workspace.  The bootstrap
+ * each lane has tp/conv scratch of its own in the workspace (batches of up to
+ * 4 ciphertexts instead run the ModDowns of all rotations as one set of
+ * launches).  The bootstrap
  * runs the giant steps of its linear transforms on the same lanes (each with
  * a key-switching workspace and registers of its own; partial sums added on
  * the context stream) and, for batches of up to 4 ciphertexts, the EvalMod

@@ -1350,6 +1350,47 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
         keys[r] = gs[r] == 1 ? nullptr : find_key(c, gs[r]);
         if (gs[r] != 1 && !keys[r]) return fail(RBK_ENOKEY, "no Galois key for rotation " + std::to_string(ks[r]));
     }
+    // Small batches: the rotations' ModDowns as one set of launches over
+    // (rotation, ciphertext) slots (up to KS_MAX_ITEMS rotations per set), so
+    // that every launch fills the GPU; larger batches fill it rotation by
+    // rotation and take the lanes below
+    const int n_sw = (int)std::count_if(gs.begin(), gs.end(), [](u64 g) { return g != 1; });
+    if (count <= 4 && n_sw > 1 && c->nP > 0 && moddown_items_ok(c)) {
+        const int gsz = std::min(n_sw, KS_MAX_ITEMS);
+        const size_t tp_words = (size_t)count * 2 * c->nP * N, conv_words = (size_t)count * 2 * L1 * N;
+        WS(ws, ks_words(c, level, count) + (size_t)gsz * (tp_words + conv_words));
+        KsBufs b = ks_layout(c, ws, level, count);
+        u64 *tpb = ws + ks_words(c, level, count), *convb = tpb + (size_t)gsz * tp_words;
+        int rc = modup_run(c, ct + per, (long)(2 * per), b.ext, (long)(beta * E * N), level, count, b.coef);
+        if (rc) return rc;
+        std::vector<int> sw;
+        for (int r = 0; r < n; r++) {
+            if (gs[r] != 1) {
+                sw.push_back(r);
+                continue;
+            }
+            HIPCK(hipMemcpy2DAsync(outs + (size_t)r * 2 * per, n * 2 * per * sizeof(u64), ct, 2 * per * sizeof(u64),
+                                   2 * per * sizeof(u64), count, hipMemcpyDeviceToDevice, c->stream));
+        }
+        for (size_t i0 = 0; i0 < sw.size(); i0 += KS_MAX_ITEMS) {
+            KsItems I{};
+            I.n = (int)std::min<size_t>(KS_MAX_ITEMS, sw.size() - i0);
+            for (int i = 0; i < I.n; i++) {
+                const int r = sw[i0 + i];
+                I.key[i] = keys[r]->data;
+                I.g[i] = gs[r];
+                I.add_g[i] = gs[r];
+                I.out_off[i] = (long)r * 2 * (long)per;
+                ks_account(c, nullptr, count, level);
+            }
+            moddown_head_items_launch(c, b.ext, (long)(beta * E * N), I, tpb, level, count, c->stream);
+            bconv_moddown_launch(c, tpb, (long)c->nP * (long)N, convb, (long)(L1 * N), level, 2 * count * I.n, c->stream);
+            moddown_tail_items_launch(c, b.ext, (long)(beta * E * N), I, convb, ct, (long)(2 * per), 0, outs,
+                                      (long)(n * 2 * per), level, count, c->stream);
+        }
+        HIPCK_LAUNCH();
+        return RBK_OK;
+    }
     // ModDown lanes: the rotations' independent ModDowns go round-robin over
     // RBK_LANES side streams, each with tp and conv buffers of its own, so the
     // VALU-bound kernels of one rotation (inner product + first iNTT pass,

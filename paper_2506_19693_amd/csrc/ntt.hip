@@ -899,25 +899,28 @@ static void launch16_logs(int logs, u64 *data, long poly_stride, int npoly, int 
 // each other: the tile's key words and ModUp digits are then re-read from
 // that XCD's L2.
 template <int LOGS, int BETA, int ADD>
-__global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ ext, long ext_stride,
-                                                    const u64 *__restrict__ key, u64 *conv, long conv_stride,
-                                                    const u64 *__restrict__ add, long add_stride, u64 add_g,
-                                                    u64 *__restrict__ out, long out_stride, NttTables T, int logN, int L1,
-                                                    int E, int nT, int count, u64 g, const u64 *Pinv, const u64 *Pinv_sh)
+__global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ ext, long ext_stride, KsItems I,
+                                                    u64 *conv, long conv_stride, const u64 *__restrict__ add,
+                                                    long add_stride, u64 *__restrict__ out, long out_stride,
+                                                    NttTables T, int logN, int L1, int E, int nT, int count,
+                                                    const u64 *Pinv, const u64 *Pinv_sh)
 {
     typedef Geo<LOGS> G;
     __shared__ u64 sm[G::LINES * G::LS];
     __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, false>::value];
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned u = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const unsigned slots = (unsigned)count * (unsigned)I.n;         // (item, ciphertext) slots of conv
     const int poly = (int)(u % 2);
-    const int ct = (int)((u / 2) % (unsigned)count);
-    const unsigned rest = u / (2u * (unsigned)count);
+    const int cs = (int)((u / 2) % slots), item = cs / count, ct = cs % count;
+    const unsigned rest = u / (2u * slots);
     const unsigned tiles = 1u << (logN - 12);
     const int tile = (int)(rest % tiles), limb = (int)(rest / tiles);
     const size_t N = (size_t)1 << logN, per = (size_t)L1 * N, li = (size_t)limb * N;
+    const u64 g = I.g[item], add_g = I.add_g[item], *key = I.key[item];
+    out += I.out_off[item];
 
-    ntt16_tile<LOGS, false, false, true>(conv + ct * conv_stride + poly * per + li, sm, smtw, T, limb, tile, logN);
+    ntt16_tile<LOGS, false, false, true>(conv + cs * conv_stride + poly * per + li, sm, smtw, T, limb, tile, logN);
 
     // the transformed tile (4096 consecutive positions of the limb) is in
     // LDS; each thread finishes 8 adjacent pairs, lanes on adjacent pairs
@@ -978,19 +981,18 @@ static void ntt_cols_fwd_launch(const rbk_ctx_impl *c, u64 *data, long poly_stri
     kt_end(c, KC_NTT_COLS_FWD, 2.0 * npoly * nlimbs * c->N * sizeof(u64), st);
 }
 
-static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
-                               long conv_stride, const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out,
-                               long out_stride, int level, int count, u64 g, hipStream_t st)
+static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *conv,
+                               long conv_stride, const u64 *add, long add_stride, int add_both, u64 *out,
+                               long out_stride, int level, int count, hipStream_t st)
 {
     const int L1 = level + 1, E = L1 + c->nP, logN = c->logN, logC = c->ntt_logC;
     const int beta_l = (L1 + c->alpha - 1) / c->alpha;
     const int addm = add ? (add_both ? 2 : 1) : 0;
-    const dim3 grid((unsigned)(((size_t)1 << logN) / 4096 * 2 * (size_t)count * L1));
+    const dim3 grid((unsigned)(((size_t)1 << logN) / 4096 * 2 * (size_t)count * I.n * L1));
     kt_begin(c, KC_NTT_ROWS_MD, st);
 #define RMD_LAUNCH(LG, B, A)                                                                                     \
-    hipLaunchKernelGGL((k_ntt_rows_md<LG, B, A>), grid, dim3(256), 0, st, ext, ext_stride, key, conv, conv_stride, add, \
-                       add_stride, add_g, out, out_stride, c->tabs, logN, L1, E, c->nT, count, g, c->d_Pinv,          \
-                       c->d_Pinv_sh)
+    hipLaunchKernelGGL((k_ntt_rows_md<LG, B, A>), grid, dim3(256), 0, st, ext, ext_stride, I, conv, conv_stride, add,   \
+                       add_stride, out, out_stride, c->tabs, logN, L1, E, c->nT, count, c->d_Pinv, c->d_Pinv_sh)
 #define RMD_ADD(LG, B)                                                                                          \
     do {                                                                                                        \
         if (addm == 0) RMD_LAUNCH(LG, B, 0);                                                                    \
@@ -1017,8 +1019,8 @@ static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_s
 #undef RMD_ADD
 #undef RMD_LAUNCH
     // algorithmic bytes: conv (after its column pass) and the ModUp digits
-    // read, the outputs written, the addends read, the key words read once
-    const double words = (double)count * L1 * (beta_l + 2 + 2 + addm) + 2.0 * beta_l * L1;
+    // read, the outputs written, the addends read, each item's key words read once
+    const double words = (double)count * I.n * L1 * (beta_l + 2 + 2 + addm) + 2.0 * I.n * beta_l * L1;
     kt_end(c, KC_NTT_ROWS_MD, words * c->N * sizeof(u64), st);
 }
 
@@ -1031,20 +1033,22 @@ static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_s
 // pass.  Blocks per (row tile, special prime, ciphertext, polynomial),
 // numbered per XCD as in k_ntt_rows_md.
 template <int LOGS, int BETA>
-__global__ __launch_bounds__(256, 4) void k_ntt_rows_ip(const u64 *__restrict__ ext, long ext_stride,
-                                                       const u64 *__restrict__ key, u64 *tp, NttTables T, int logN,
-                                                       int L1, int E, int nT, int nQ, int nP, int count, u64 g)
+__global__ __launch_bounds__(256, 4) void k_ntt_rows_ip(const u64 *__restrict__ ext, long ext_stride, KsItems I,
+                                                       u64 *tp, NttTables T, int logN, int L1, int E, int nT, int nQ,
+                                                       int nP, int count)
 {
     typedef Geo<LOGS> G;
     __shared__ u64 sm[G::LINES * G::LS];
     __shared__ __attribute__((aligned(16))) u64 smtw[TwWords<LOGS, false>::value];
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned u = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const unsigned slots = (unsigned)count * (unsigned)I.n;         // (item, ciphertext) slots of tp
     const int poly = (int)(u % 2);
-    const int ct = (int)((u / 2) % (unsigned)count);
-    const unsigned rest = u / (2u * (unsigned)count);
+    const int cs = (int)((u / 2) % slots), item = cs / count, ct = cs % count;
+    const unsigned rest = u / (2u * slots);
     const unsigned tiles = 1u << (logN - 12);
     const int tile = (int)(rest % tiles), k = (int)(rest / tiles);
+    const u64 g = I.g[item], *key = I.key[item];
     const size_t N = (size_t)1 << logN, tbase = (size_t)tile * 4096;
     const int pr = nQ + k;
     const PrimeC p = T.pc[pr];
@@ -1073,19 +1077,19 @@ __global__ __launch_bounds__(256, 4) void k_ntt_rows_ip(const u64 *__restrict__ 
         row[lidx(cc)] = redc(s0, p.q, p.qneg);
         row[lidx(cc + 1)] = redc(s1, p.q, p.qneg);
     }
-    ntt16_tile<LOGS, true, false, false, true>(tp + (((size_t)ct * 2 + poly) * nP + k) * N, sm, smtw, T, pr, tile, logN);
+    ntt16_tile<LOGS, true, false, false, true>(tp + (((size_t)cs * 2 + poly) * nP + k) * N, sm, smtw, T, pr, tile, logN);
 }
 
-static void ntt_rows_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *tp,
-                               int level, int count, u64 g, hipStream_t st)
+static void ntt_rows_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *tp,
+                               int level, int count, hipStream_t st)
 {
     const int L1 = level + 1, E = L1 + c->nP, logN = c->logN, logC = c->ntt_logC;
     const int beta_l = (L1 + c->alpha - 1) / c->alpha;
-    const dim3 grid((unsigned)(((size_t)1 << logN) / 4096 * 2 * (size_t)count * c->nP));
+    const dim3 grid((unsigned)(((size_t)1 << logN) / 4096 * 2 * (size_t)count * I.n * c->nP));
     kt_begin(c, KC_NTT_ROWS_IP, st);
 #define RIP_LAUNCH(LG, B)                                                                                       \
-    hipLaunchKernelGGL((k_ntt_rows_ip<LG, B>), grid, dim3(256), 0, st, ext, ext_stride, key, tp, c->tabs, logN, L1, E, \
-                       c->nT, c->nQ, c->nP, count, g)
+    hipLaunchKernelGGL((k_ntt_rows_ip<LG, B>), grid, dim3(256), 0, st, ext, ext_stride, I, tp, c->tabs, logN, L1, E,   \
+                       c->nT, c->nQ, c->nP, count)
 #define RIP_BETA(LG)                                                                                            \
     switch (beta_l) {                                                                                           \
     case 1: RIP_LAUNCH(LG, 1); break;                                                                           \
@@ -1104,10 +1108,34 @@ static void ntt_rows_ip_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_s
     }
 #undef RIP_BETA
 #undef RIP_LAUNCH
-    // algorithmic bytes: the digits' special-prime limbs and the key words
-    // read once, tp written once
-    const double words = (double)count * c->nP * (beta_l + 2) + 2.0 * beta_l * c->nP;
+    // algorithmic bytes: the digits' special-prime limbs and each item's key
+    // words read once, tp written once
+    const double words = (double)count * I.n * c->nP * (beta_l + 2) + 2.0 * I.n * beta_l * c->nP;
     kt_end(c, KC_NTT_ROWS_IP, words * c->N * sizeof(u64), st);
+}
+
+static KsItems one_item(const u64 *key, u64 g, u64 add_g)
+{
+    KsItems I{};
+    I.key[0] = key;
+    I.g[0] = g;
+    I.add_g[0] = add_g;
+    I.out_off[0] = 0;
+    I.n = 1;
+    return I;
+}
+
+bool moddown_items_ok(const rbk_ctx_impl *c) { return ntt_rows_md_ok(c); }
+
+void moddown_head_items_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *tp,
+                               int level, int count, hipStream_t st)
+{
+    const int nP = c->nP;
+    const LimbMap pm{0, 0, c->nQ};
+    ntt_rows_ip_launch(c, ext, ext_stride, I, tp, level, count, st);
+    kt_begin(c, KC_NTT_COLS_INV, st);
+    launch16_logs<true, true>(c->logN - c->ntt_logC, tp, (long)nP * c->N, 2 * count * I.n, nP, pm, c->tabs, c->logN, st);
+    kt_end(c, KC_NTT_COLS_INV, 2.0 * 2 * count * I.n * nP * c->N * sizeof(u64), st);
 }
 
 void moddown_head_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *tp, int level,
@@ -1116,10 +1144,7 @@ void moddown_head_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride,
     const int nP = c->nP;
     const LimbMap pm{0, 0, c->nQ};
     if (ntt_rows_md_ok(c)) {
-        ntt_rows_ip_launch(c, ext, ext_stride, key, tp, level, count, g, st);
-        kt_begin(c, KC_NTT_COLS_INV, st);
-        launch16_logs<true, true>(c->logN - c->ntt_logC, tp, (long)nP * c->N, 2 * count, nP, pm, c->tabs, c->logN, st);
-        kt_end(c, KC_NTT_COLS_INV, 2.0 * 2 * count * nP * c->N * sizeof(u64), st);
+        moddown_head_items_launch(c, ext, ext_stride, one_item(key, g, 0), tp, level, count, st);
         return;
     }
     ip_p_launch(c, ext, ext_stride, key, tp, level, count, g, st);
@@ -1272,6 +1297,18 @@ hipError_t ntt_inverse_from_launch(const rbk_ctx_impl *c, const u64 *src, long s
     return hipSuccess;
 }
 
+void moddown_tail_items_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *conv,
+                               const u64 *add, long add_stride, int add_both, u64 *out, long out_stride, int level,
+                               int count, hipStream_t st)
+{
+    const int L1 = level + 1;
+    const size_t N = c->N;
+    const LimbMap qm{0, c->nQ, c->nQ};
+    ntt_cols_fwd_launch(c, conv, (long)(L1 * N), 2 * count * I.n, L1, qm, st);
+    ntt_rows_md_launch(c, ext, ext_stride, I, conv, (long)(2 * L1 * N), add, add_stride, add_both, out, out_stride, level,
+                       count, st);
+}
+
 void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
                          const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
                          int count, u64 g, hipStream_t st)
@@ -1280,9 +1317,8 @@ void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride,
     const size_t N = c->N;
     const LimbMap qm{0, c->nQ, c->nQ};
     if (ntt_rows_md_ok(c)) {
-        ntt_cols_fwd_launch(c, conv, (long)(L1 * N), 2 * count, L1, qm, st);
-        ntt_rows_md_launch(c, ext, ext_stride, key, conv, (long)(2 * L1 * N), add, add_stride, add_g, add_both, out,
-                           out_stride, level, count, g, st);
+        moddown_tail_items_launch(c, ext, ext_stride, one_item(key, g, add_g), conv, add, add_stride, add_both, out,
+                                  out_stride, level, count, st);
         return;
     }
     ntt_launch(c, conv, (long)(L1 * N), 2 * count, L1, qm, false, st);

@@ -225,6 +225,26 @@ void moddown_head_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride,
 // ModDown tail: NTT of the converted special-prime part conv ([count][2][l+1]
 // limbs) and the epilogue of moddown_ip_launch; for the register NTT
 // geometries the row pass and the epilogue are one kernel.  conv is clobbered.
+// Several key switches of one batch in one launch set (the rotations of a
+// hoisted batch): per item a switching key, the Galois element its digits
+// are read through, that of its addend, and the offset (words) of its
+// outputs.  tp / conv hold item i's ciphertexts at slots i count ..
+// i count + count - 1.  For the register NTT geometries only
+// (moddown_items_ok).
+#define KS_MAX_ITEMS 32
+struct KsItems {
+    const u64 *key[KS_MAX_ITEMS];
+    u64 g[KS_MAX_ITEMS];
+    u64 add_g[KS_MAX_ITEMS];
+    long out_off[KS_MAX_ITEMS];
+    int n;
+};
+bool moddown_items_ok(const rbk_ctx_impl *c);
+void moddown_head_items_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *tp,
+                               int level, int count, hipStream_t st);
+void moddown_tail_items_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *conv,
+                               const u64 *add, long add_stride, int add_both, u64 *out, long out_stride, int level,
+                               int count, hipStream_t st);
 void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
                          const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
                          int count, u64 g, hipStream_t st);

@@ -235,6 +235,36 @@ def test_batched_equals_plain(name):
         assert np.array_equal(down(p, hb[c], level), down(p, d.rotate_hoisted(A[c], ks, level), level))
 
 
+def test_hoisted_many_rotations_every_path():
+    """More rotations than one launch set takes (32), identities among them,
+    for batches of 1 and 3 ciphertexts (the ModDowns of all rotations as one
+    set of launches over (rotation, ciphertext) slots) and 6 (rotation by
+    rotation, on the lanes): every output equals the oracle's hoisted rotation
+    of its ciphertext, every identity its input."""
+    p = Pair("mid", seed=9)
+    o, d = p.orc, p.gpu
+    level = o.L
+    rots = list(range(1, 37)) + [-5, 64]
+    for k in rots:
+        if k not in p.gal:
+            gal = o.galois_rot(k)
+            a, e = S.key_randomness(p.g, o.beta, o.moduli, p.N)
+            p.gal[k] = (gal, o.keygen_galois(p.s, gal, a, e))
+            d.keygen_galois(gal, a, e)
+    ks = rots[:20] + [0] + rots[20:] + [0]
+    for cnt in (1, 3, 6):
+        a = p.rand_ct(level, lead=(cnt, 2))
+        hb = d.rotate_hoisted_batch(up(p, a, level), ks, level)
+        print("hoisted: %d ciphertexts x %d rotations" % (cnt, len(ks)), flush=True)
+        for c in range(cnt):
+            want = o.rotate_hoisted(level, [p.gal[k][1] for k in rots], [p.gal[k][0] for k in rots], a[c])
+            got = down(p, hb[c], level)
+            assert np.array_equal(got[[i for i, k in enumerate(ks) if k != 0]], want), cnt
+            for i, k in enumerate(ks):
+                if k == 0:
+                    assert np.array_equal(got[i], a[c])
+
+
 @pytest.mark.parametrize("name", list(PARAMS))
 def test_uneven_level_list_bit_exact(name):
     """Ciphertexts at uneven levels in one list call: each equals the
