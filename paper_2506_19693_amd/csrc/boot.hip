@@ -62,9 +62,9 @@ struct BootPlan {
     std::vector<int> scalar_level;
     std::vector<std::vector<u64>> scalars;  // residues [level+1]
     std::vector<int64_t> rots;
-    // device scratch for runs (grow-only)
-    std::vector<u64 *> pool;
-    size_t pool_words = 0;
+    // registers of earlier runs, with their capacities in words (kept for
+    // later runs; a run takes any register at least as large as it needs)
+    std::vector<std::pair<u64 *, size_t>> pool;
     u64 *rot_area = nullptr;  // hoisted baby rotations of a transform
     size_t rot_words = 0;
     // key-switching workspaces of the giant-step lanes (side streams)
@@ -372,7 +372,7 @@ void boot_free(rbk_ctx_impl *ci)
     BootPlan *P = ci->boot;
     if (!P) return;
     for (u64 *d : P->d_plain) release_buffer(ci, d);
-    for (u64 *d : P->pool) release_buffer(ci, d);
+    for (auto &r : P->pool) release_buffer(ci, r.first);
     release_buffer(ci, P->rot_area);
     for (int k = 0; k < RBK_LANES; k++) release_buffer(ci, P->lane_ws[k]);
     release_buffer(ci, P->d_scal);
@@ -542,8 +542,8 @@ struct Runner {
     rbk_ctx *c;
     BootPlan &P;
     int cnt;                 // ciphertexts per register
-    size_t reg_words;        // capacity of one register
-    std::vector<u64 *> free_;
+    size_t reg_words;        // the words one register of this run needs
+    std::vector<u64 *> free_;  // pooled registers not in use (each holds at least reg_words)
 
     u64 *take()
     {
@@ -552,9 +552,10 @@ struct Runner {
             free_.pop_back();
             return d;
         }
+        // a new register of exactly this run's size
         u64 *d = nullptr;
         if (hipMalloc((void **)&d, reg_words * sizeof(u64)) != hipSuccess) return nullptr;
-        P.pool.push_back(d);
+        P.pool.emplace_back(d, reg_words);
         return d;
     }
     // while steps run on several lanes, registers they release are held back
@@ -1132,15 +1133,21 @@ extern "C" int rbk_bootstrap_batch(rbk_ctx *c, const uint64_t *d_in, const doubl
     // EvalMod runs the real and imaginary halves of the batch together
     if (int rc0 = upload_scalars(c, P)) return rc0;
     Runner R{c, P, count, (size_t)2 * count * 2 * (P.L + 1) * N, {}};
-    // reuse the pooled registers of earlier runs when they are large enough
-    if (P.pool_words >= R.reg_words) {
-        R.reg_words = P.pool_words;
-        R.free_ = P.pool;
-    } else {
-        if (c->capturing) return boot_fail(RBK_ESTATE, "bootstrap registers too small during graph capture: run the call once before capturing");
-        for (u64 *d : P.pool) release_buffer(c, d);
-        P.pool.clear();
-        P.pool_words = R.reg_words;
+    // pooled registers large enough for this run are reused; smaller ones are
+    // released (a larger batch than before), new ones have this run's size
+    {
+        std::vector<std::pair<u64 *, size_t>> keep;
+        for (auto &r : P.pool) {
+            if (r.second >= R.reg_words) {
+                keep.push_back(r);
+                R.free_.push_back(r.first);
+            } else if (c->capturing) {
+                return boot_fail(RBK_ESTATE, "bootstrap registers too small during graph capture: run the call once before capturing");
+            } else {
+                release_buffer(c, r.first);
+            }
+        }
+        P.pool = keep;
     }
     const LimbMap qm{0, c->nQ, c->nQ};
     int rc;
@@ -1201,7 +1208,6 @@ extern "C" int rbk_bootstrap_batch(rbk_ctx *c, const uint64_t *d_in, const doubl
         return boot_fail(RBK_EDEVICE, "output copy");
     R.give(x0);
     R.give(tmp);
-    P.pool_words = R.reg_words;
     // the slots hold z * d' / D_ref at the arithmetic scale s_out
     for (int i = 0; i < count; i++) scales_out[i] = P.s_out * dprime[i] / std::ldexp(1.0, P.dref_log2);
     return RBK_OK;
