@@ -515,7 +515,8 @@ int rbk_mlp_scalars(const rbk_mlp *mlp, int64_t *out, int max);
  * context with its keys (and bootstrap plan) set up; from rbk_server_add_tenant
  * until rbk_server_destroy the server owns it: it gets a stream of its own and
  * a worker thread of its own, runs on one lane (rbk_set_lanes; restored at
- * destroy), and the caller must not call into it (the device memory a job
+ * destroy; training steps with RBK_MLP_SEQUENTIAL), and the caller must not
+ * call into it (the device memory a job
  * names stays the caller's).  Work of different tenants overlaps on the
  * device.
  *

@@ -326,7 +326,9 @@ int run_train(Tenant *, std::vector<SJob *> &b)
 {
     const rbk_job &j = b[0]->j;
     for (int s = 0; s < j.count; s++) {
-        int rc = rbk_mlp_train_step(j.mlp, j.d_x, j.d_y_exp, j.d_y_rep, j.b, j.level, j.scale, j.t0 + s, 0);
+        // one stream, like every served call (the footprint has no side-stream workspace)
+        int rc = rbk_mlp_train_step(j.mlp, j.d_x, j.d_y_exp, j.d_y_rep, j.b, j.level, j.scale, j.t0 + s,
+                                    RBK_MLP_SEQUENTIAL);
         if (rc) return rc;
     }
     return RBK_OK;
