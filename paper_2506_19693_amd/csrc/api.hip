@@ -1395,9 +1395,10 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
     // RBK_LANES side streams, each with tp and conv buffers of its own, so the
     // VALU-bound kernels of one rotation (inner product + first iNTT pass,
     // base conversion) overlap the memory-bound ones of another.  One lane
-    // while the stream is being captured and while per-kernel timers run
-    // (overlapping kernels would not have durations of their own)
-    const int nl = (c->lanes > 1 && !c->capturing && !c->timing && n > 1 && side_streams(c) == RBK_OK)
+    // while per-kernel timers run (overlapping kernels would not have
+    // durations of their own).  Under graph capture the lanes join the
+    // capture through the fork event and leave it at the join.
+    const int nl = (c->lanes > 1 && !c->timing && n > 1 && side_streams(c) == RBK_OK)
                        ? std::min(c->lanes, n)
                        : 1;
     const size_t tp_words = (size_t)count * 2 * c->nP * N, conv_words = (size_t)count * 2 * L1 * N;
