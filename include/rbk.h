@@ -94,6 +94,19 @@ int rbk_num_digits(const rbk_ctx *ctx, int level);
 /* Pre-size the device workspace for `count` ciphertexts at `level` doing
  * hoisted rotations (optional; calls grow it on demand otherwise). */
 int rbk_reserve(rbk_ctx *ctx, int level, int count);
+/* Words of workspace that batched calls on `count` ciphertexts at `level`
+ * need: mult_relin, rescale and a hoisted batch of n_rot rotations with the
+ * current lane setting. */
+int rbk_workspace_words(const rbk_ctx *ctx, int level, int count, int n_rot, size_t *words);
+/* The context's workspace (key-switching scratch of every call) becomes the
+ * caller's device buffer d_ws of `words` 64-bit words: the caller owns it,
+ * keeps it alive and leaves it alone while calls are in flight; a call that
+ * needs more returns RBK_ENOMEM instead of allocating.  Synchronises with
+ * the context stream, releases a library-owned workspace; d_ws = NULL with
+ * words = 0 returns to a library-owned one.  The lanes' scratch, bootstrap
+ * registers, MLP buffers and descriptor arenas keep their own allocations.
+ * RBK_ESTATE during graph capture. */
+int rbk_set_workspace(rbk_ctx *ctx, uint64_t *d_ws, size_t words);
 
 /* ---- transforms --------------------------------------------------------- */
 

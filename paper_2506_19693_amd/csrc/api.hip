@@ -183,6 +183,11 @@ void release_buffer(rbk_ctx_impl *c, void *p)
 u64 *ws_reserve(rbk_ctx_impl *c, size_t words)
 {
     if (words <= c->ws_words) return c->ws;
+    if (c->ws_ext && c->ws == c->ws_ext) {
+        // the caller's buffer (lanes swap their own workspaces in and grow those)
+        fail(RBK_ENOMEM, "caller-provided workspace too small: " + std::to_string(words) + " words needed");
+        return nullptr;
+    }
     if (c->capturing) {
         // the captured work already points into the current workspace
         rbk_set_error(RBK_ESTATE, "workspace too small during graph capture: run the sequence once before capturing");
@@ -274,7 +279,10 @@ int side_streams(rbk_ctx_impl *c)
 
 #define WS(ptr, words)                                                                         \
     u64 *ptr = ws_reserve(c, (words));                                                          \
-    if (!ptr) return c->capturing ? RBK_ESTATE : fail(RBK_ENOMEM, "device workspace allocation failed");
+    if (!ptr)                                                                                   \
+        return c->capturing ? RBK_ESTATE                                                        \
+                            : (c->ws_ext && c->ws == c->ws_ext ? RBK_ENOMEM                     \
+                                                               : fail(RBK_ENOMEM, "device workspace allocation failed"));
 
 // ---------------------------------------------------------------- tables
 
@@ -504,7 +512,7 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     for (void *p : c->owned) (void)hipFree(p);
     for (void *p : c->retired) (void)hipFree(p);
-    if (c->ws) (void)hipFree(c->ws);
+    if (c->ws && c->ws != c->ws_ext) (void)hipFree(c->ws);
     if (c->desc_dev) (void)hipFree(c->desc_dev);
     for (int k = 0; k < RBK_LANES; k++)
         if (c->side[k]) {
@@ -582,6 +590,36 @@ extern "C" int rbk_reserve(rbk_ctx *c, int level, int count)
     WS(ws, ks_words(c, level, count) + count * 3 * L1 * N + count * 2 * L1 * N);
     (void)ws;
     modup_tables(c, level);
+    return RBK_OK;
+}
+
+extern "C" int rbk_workspace_words(const rbk_ctx *c, int level, int count, int n_rot, size_t *words)
+{
+    if (!c || !words || count < 1 || n_rot < 0) return fail(RBK_EINVAL, "bad argument");
+    if (check_level(c, level)) return RBK_ELEVEL;
+    const size_t L1 = level + 1, N = c->N, per = L1 * N, ks = ks_words(c, level, count);
+    const size_t slot = (size_t)count * 2 * (c->nP + L1) * N;   // tp + conv of one rotation's ModDown
+    size_t need = std::max((size_t)count * 3 * per + ks, 2 * (size_t)count * per);   // mult_relin, rescale
+    if (n_rot > 1) {
+        const size_t extra = (count <= 4 && c->nP > 0) ? (size_t)std::min(n_rot, KS_MAX_ITEMS) * slot
+                                                       : (size_t)(std::min(c->lanes, n_rot) - 1) * slot;
+        need = std::max(need, ks + extra);
+    }
+    *words = need;
+    return RBK_OK;
+}
+
+extern "C" int rbk_set_workspace(rbk_ctx *c, uint64_t *d_ws, size_t words)
+{
+    if (!c) return fail(RBK_EINVAL, "null argument");
+    if (c->capturing) return fail(RBK_ESTATE, "not allowed during graph capture");
+    if ((d_ws == nullptr) != (words == 0)) return fail(RBK_EINVAL, "a buffer needs a size, no buffer none");
+    // earlier calls may still use the workspace that is replaced
+    HIPCK(hipStreamSynchronize(c->stream));
+    if (c->ws && c->ws != c->ws_ext) release_buffer(c, c->ws);
+    c->ws = d_ws;
+    c->ws_words = words;
+    c->ws_ext = d_ws;
     return RBK_OK;
 }
 

@@ -101,9 +101,10 @@ struct rbk_ctx_impl {
     DevKey relin;
     std::map<u64, DevKey> gal;
 
-    // workspace (grow-only)
+    // workspace (grow-only), or a caller's buffer (ws_ext, never grown or freed)
     u64 *ws = nullptr;
     size_t ws_words = 0;
+    u64 *ws_ext = nullptr;
 
     std::vector<void *> owned;  // device allocations freed at destroy
 

@@ -217,6 +217,8 @@ SIGNATURES = {
     "rbk_autotune": (ci, [vp, ci, ci, ctypes.c_char_p, ctypes.POINTER(ci)]),
     "rbk_tune_get": (ci, [vp, ctypes.POINTER(ci)]),
     "rbk_tune_set": (ci, [vp, ctypes.POINTER(ci)]),
+    "rbk_workspace_words": (ci, [vp, ci, ci, ci, ctypes.POINTER(ctypes.c_size_t)]),
+    "rbk_set_workspace": (ci, [vp, vp, ctypes.c_size_t]),
     "rbk_capture_begin": (ci, [vp]),
     "rbk_capture_end": (ci, [vp, ctypes.POINTER(vp)]),
     "rbk_graph_launch": (ci, [vp]),
@@ -686,6 +688,23 @@ class Context:
         so = ctypes.c_double()
         _check(self.lib.rbk_bootstrap(self.h, _ptr(ct), float(scale), _ptr(out), ctypes.byref(so)))
         return out, so.value
+
+    # ---------------------------------------------------------------- workspace
+    def workspace_words(self, level, count, n_rot=0):
+        """Words of workspace batched calls on count ciphertexts at level need
+        (mult_relin, rescale, a hoisted batch of n_rot rotations)."""
+        w = ctypes.c_size_t()
+        _check(self.lib.rbk_workspace_words(self.h, level, count, n_rot, ctypes.byref(w)))
+        return w.value
+
+    def set_workspace(self, buf):
+        """Use the device tensor buf (int64, kept alive by this object) as the
+        context's workspace; None returns to a library-owned one."""
+        if buf is None:
+            _check(self.lib.rbk_set_workspace(self.h, None, 0))
+        else:
+            _check(self.lib.rbk_set_workspace(self.h, _ptr(buf), buf.numel()))
+        self._ws_buf = buf
 
     # ---------------------------------------------------------------- autotuner
     def autotune(self, level, count, cache_path=None):

@@ -64,6 +64,47 @@ def test_every_configuration_gives_the_same_residues(log_n):
         d.tune_set(splits[0], 8, -1)                          # negative chunk
 
 
+def test_caller_workspace():
+    """The context's workspace as a caller's buffer of the size
+    rbk_workspace_words reports: the same residues as with the library's own
+    workspace; a buffer too small makes the calls fail with RBK_ENOMEM (no
+    allocation behind the caller's back); dropping it returns to the
+    library's workspace."""
+    import torch
+
+    from paper_2506_19693_amd import RbkError
+
+    def run(d, A, B, L, ks):
+        m = d.rescale_batch(d.mult_relin_batch(A, B, L), L)
+        h = d.rotate_hoisted_batch(m, ks, L - 1)
+        return d.to_coef(m, L - 1), d.to_coef(h, L - 1)
+
+    ks = [1, 5, -3]
+    for cnt in (3, 6):                        # one set of launches for all rotations; lanes
+        ref = None
+        for mode in ("library", "caller", "small"):
+            d, _ = _ctx(14)
+            g = S.rng(52, 14)
+            L = d.L
+            A = d.to_ntt(S.uniform_residues(g, d.moduli[: L + 1], d.N, lead=(cnt, 2)), L)
+            B = d.to_ntt(S.uniform_residues(g, d.moduli[: L + 1], d.N, lead=(cnt, 2)), L)
+            need = d.workspace_words(L, cnt, len(ks))
+            if mode == "library":
+                ref = run(d, A, B, L, ks)
+                continue
+            if mode == "caller":
+                d.set_workspace(torch.empty(need, dtype=torch.int64, device="cuda"))
+                got = run(d, A, B, L, ks)
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), cnt
+                continue
+            d.set_workspace(torch.empty(need // 8, dtype=torch.int64, device="cuda"))
+            with pytest.raises(RbkError, match="-2"):
+                run(d, A, B, L, ks)
+            d.set_workspace(None)
+            got = run(d, A, B, L, ks)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), cnt
+
+
 def test_lanes_give_the_same_residues():
     """Hoisted rotations on one lane (context stream only) and on two and
     three side streams give the same residues; lane counts outside 1..3 are
