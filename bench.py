@@ -42,6 +42,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def log_free(torch, where):
+    """Device memory left free after a part (torch's cache emptied first)."""
+    import gc
+
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    log("%s: %.1f of %.1f GiB free" % (where, free / 2.0 ** 30, total / 2.0 ** 30))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1473,9 +1483,11 @@ def main():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    log_free(torch, "start")
     ksw = None
     if not args.no_ks:
         ksw = bench_keyswitch(args, torch)
+        log_free(torch, "after key switches")
 
     boot = None
     if not args.no_boot:
@@ -1484,6 +1496,7 @@ def main():
         log("bootstrap: %.2f/s batched, %.2f/s graph, %.2f/s plain, p99 %.1f ms, max error 2^%.2f" % (
             boot["bootstraps_per_s_batched"], boot["bootstraps_per_s_graph"], boot["bootstraps_per_s_plain"],
             boot["plain_latency_ms_p99"], boot["max_slot_error_log2"]))
+        log_free(torch, "after bootstraps")
 
     mlp = None
     if not args.no_mlp:
@@ -1493,6 +1506,7 @@ def main():
         log("train_step: %.3f steps/s batched (%.0f ms), %.3f graph, %.3f plain, bootstrap share %.2f" % (
             mlp["train_steps_per_s_batched"], mlp["ms_per_step_batched"], mlp["train_steps_per_s_graph"],
             mlp["train_steps_per_s_plain"], mlp["bootstrap_share_of_step"]))
+        log_free(torch, "after training steps")
 
     paper = None
     if not args.no_paper_mlps:
@@ -1503,6 +1517,7 @@ def main():
             paper[name] = bench_paper_mlp(name, args, torch)
             log("%s: %.2f s per iteration (paper, on CPUs: %.2f s)" % (
                 name, paper[name]["s_per_iteration"], paper[name]["paper_cpu_s_per_iteration"]))
+            log_free(torch, "after " + name)
 
     small = None
     if not args.no_mixed:
@@ -1510,6 +1525,7 @@ def main():
         log("small ring pipeline: eager %.1f us, graph %.1f us (%.2fx), graph == eager: %s, error 2^%.1f" % (
             small["eager_us"], small["graph_us"], small["graph_speedup"], small["graph_equals_eager"],
             small["max_slot_error_log2"]))
+        log_free(torch, "after the small ring pipeline")
 
     mixed = None
     if not args.no_mixed:
@@ -1518,6 +1534,7 @@ def main():
         mixed = bench_mixed(args, torch)
         log("mixed rings: one call %.2f ms, per-context calls %.2f ms, plain %.2f ms" % (
             mixed["multi_context_call"]["ms"], mixed["per_context_list_calls"]["ms"], mixed["plain"]["ms"]))
+        log_free(torch, "after mixed rings")
 
     serve = None
     if not args.no_serve:

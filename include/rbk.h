@@ -670,8 +670,8 @@ int rbk_graph_destroy(rbk_graph *graph);
  * calls with each other; the default is 3; n = 1 runs everything on the
  * context stream (kernels do not overlap, so profiler durations are each
  * kernel's own).  Residues do not depend on n.  Lanes are not used while
- * timers run; under graph capture they join the capture.  n outside 1..3:
- * RBK_EINVAL, setting unchanged. */
+ * timers run or while the stream is captured (a captured graph is one chain
+ * of kernels).  n outside 1..3: RBK_EINVAL, setting unchanged. */
 int rbk_set_lanes(rbk_ctx *ctx, int n);
 
 /* ---- per-kernel timers -------------------------------------------------- */

@@ -161,12 +161,20 @@ static int dev_upload(rbk_ctx *c, T **p, const std::vector<T> &h)
     return RBK_OK;
 }
 
+// hipFree that keeps the first failure for rbk_ctx_destroy to report
+void dev_free(rbk_ctx_impl *c, void *p)
+{
+    if (!p) return;
+    hipError_t e = hipFree(p);
+    if (e != hipSuccess && c->free_error == hipSuccess) c->free_error = e;
+}
+
 static void dev_release(rbk_ctx *c, void *p)
 {
     if (!p) return;
     auto it = std::find(c->owned.begin(), c->owned.end(), p);
     if (it != c->owned.end()) c->owned.erase(it);
-    (void)hipFree(p);
+    dev_free(c, p);
 }
 
 void release_buffer(rbk_ctx_impl *c, void *p)
@@ -177,7 +185,7 @@ void release_buffer(rbk_ctx_impl *c, void *p)
         return;
     }
     (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(p);
+    dev_free(c, p);
 }
 
 u64 *ws_reserve(rbk_ctx_impl *c, size_t words)
@@ -510,10 +518,10 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
     for (int k = 0; k < KC_COUNT; k++)
         for (hipEvent_t e : c->timers[k].pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
-    for (void *p : c->owned) (void)hipFree(p);
-    for (void *p : c->retired) (void)hipFree(p);
-    if (c->ws && c->ws != c->ws_ext) (void)hipFree(c->ws);
-    if (c->desc_dev) (void)hipFree(c->desc_dev);
+    for (void *p : c->owned) dev_free(c, p);
+    for (void *p : c->retired) dev_free(c, p);
+    if (c->ws != c->ws_ext) dev_free(c, c->ws);
+    dev_free(c, c->desc_dev);
     for (int k = 0; k < RBK_LANES; k++)
         if (c->side[k]) {
             (void)hipStreamSynchronize(c->side[k]);
@@ -525,7 +533,9 @@ extern "C" int rbk_ctx_destroy(rbk_ctx *c)
         if (c->desc_host[k]) (void)hipHostFree(c->desc_host[k]);
         if (c->desc_evt[k]) (void)hipEventDestroy(c->desc_evt[k]);
     }
+    const hipError_t fe = c->free_error;
     delete c;
+    if (fe != hipSuccess) return fail(RBK_EDEVICE, std::string("device memory release failed: ") + hipGetErrorString(fe));
     return RBK_OK;
 }
 
@@ -1434,9 +1444,10 @@ extern "C" int rbk_rotate_hoisted_batch(rbk_ctx *c, const uint64_t *ct, const in
     // VALU-bound kernels of one rotation (inner product + first iNTT pass,
     // base conversion) overlap the memory-bound ones of another.  One lane
     // while per-kernel timers run (overlapping kernels would not have
-    // durations of their own).  Under graph capture the lanes join the
-    // capture through the fork event and leave it at the join.
-    const int nl = (c->lanes > 1 && !c->timing && n > 1 && side_streams(c) == RBK_OK)
+    // durations of their own) and while the stream is captured: buffers that
+    // kernels of a captured graph with parallel branches touched were not
+    // given back by hipFree (the runtime kept them for reuse at the same size)
+    const int nl = (c->lanes > 1 && !c->capturing && !c->timing && n > 1 && side_streams(c) == RBK_OK)
                        ? std::min(c->lanes, n)
                        : 1;
     const size_t tp_words = (size_t)count * 2 * c->nP * N, conv_words = (size_t)count * 2 * L1 * N;
@@ -1649,7 +1660,7 @@ extern "C" int rbk_graph_destroy(rbk_graph *g)
     if (g->g) (void)hipGraphDestroy(g->g);
     delete g;
     if (--c->live_graphs == 0) {
-        for (void *p : c->retired) (void)hipFree(p);
+        for (void *p : c->retired) dev_free(c, p);
         c->retired.clear();
     }
     return RBK_OK;

@@ -665,8 +665,9 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
     // (each with key-switching workspace and registers of its own) and every
     // lane keeps a partial sum; the context stream adds the partial sums.
     // Modular sums do not depend on their order, so the residues are those of
-    // one lane.  One lane while timers run.
-    const int nl = (c->lanes > 1 && !c->timing && n_rot > 1 && side_streams(c) == RBK_OK)
+    // one lane.  One lane while timers run or the stream is captured (a
+    // captured graph stays one chain of kernels).
+    const int nl = (c->lanes > 1 && !c->capturing && !c->timing && n_rot > 1 && side_streams(c) == RBK_OK)
                        ? std::min(c->lanes, n_rot)
                        : 0;
     u64 *inner = take(), *irot = take(), *total = take();
@@ -894,8 +895,8 @@ int Runner::evalmod(Reg &x, int n_ct)
     // key-switching workspace of its own; the lanes join after every depth.
     // Larger batches fill the GPU by themselves and keep the program order
     // (fewer registers alive).  The residues do not depend on the lanes.
-    // One lane while timers run.
-    const int nl = (n_ct <= 8 && c->lanes > 1 && !c->timing && side_streams(c) == RBK_OK)
+    // One lane while timers run or the stream is captured.
+    const int nl = (n_ct <= 8 && c->lanes > 1 && !c->capturing && !c->timing && side_streams(c) == RBK_OK)
                        ? c->lanes
                        : 0;
     if (!nl) {

@@ -118,6 +118,7 @@ struct rbk_ctx_impl {
     // alive, a buffer that is replaced is retired instead of freed
     int live_graphs = 0;
     std::vector<void *> retired;
+    hipError_t free_error = hipSuccess;  // first failed hipFree, reported at destroy
     // descriptor uploads of the list entry points: one device arena reused by
     // every call (stream order protects it) and two pinned host arenas used
     // in turn, each reusable once the event after its last copy has passed
@@ -173,6 +174,7 @@ u64 *ws_reserve(rbk_ctx_impl *c, size_t words);
 int side_streams(rbk_ctx_impl *c);
 // free a replaced device buffer, or keep it until the last graph is destroyed
 void release_buffer(rbk_ctx_impl *c, void *p);
+void dev_free(rbk_ctx_impl *c, void *p);
 const ModUpTables &modup_tables(rbk_ctx_impl *c, int level);
 
 // ---- kernel launchers implemented in kernels.hip ----

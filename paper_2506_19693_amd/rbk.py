@@ -750,7 +750,9 @@ class Context:
 
     # ---------------------------------------------------------------- lanes
     def set_lanes(self, n):
-        """ModDown lanes (side streams) of a batch of hoisted rotations: 1 or 2."""
+        """Side streams (lanes, 1..3) for hoisted-rotation ModDowns, bootstrap
+        giant steps and EvalMod products; 1 runs everything on the context
+        stream.  Not used while timers run or while the stream is captured."""
         _check(self.lib.rbk_set_lanes(self.h, int(n)))
 
     # ---------------------------------------------------------------- timers
