@@ -294,6 +294,16 @@ int rbk_rescale_batch_noalloc(rbk_ctx *ctx, const uint64_t *d_ct, uint64_t *d_ou
  * reaches the point where it was issued. */
 int rbk_rotate_hoisted_batch(rbk_ctx *ctx, const uint64_t *d_ct, const int64_t *ks, int n, uint64_t *d_outs, int level,
                              int count);
+/* out = add + Rot(ct, k) for count ciphertexts: Section 3's Rot followed by
+ * Add, in one pass where the ring allows (the rotation's ModDown adds `add`),
+ * the step of the rotate-and-sum that the packed MLP's row and column sums
+ * (Section 4.1) and the bootstrap's giant steps repeat.  d_ct, d_add, d_out:
+ * [count][2][l+1][N], NTT domain.  d_add may be d_ct (ct + Rot(ct, k)) or
+ * d_out (accumulation in place); d_ct must not overlap d_out, nor d_add
+ * overlap d_out other than being it (RBK_EINVAL).  RBK_ENOKEY without the
+ * Galois key of 5^k.  Residues equal rbk_rotate followed by rbk_add. */
+int rbk_rotate_add_batch(rbk_ctx *ctx, const uint64_t *d_ct, const uint64_t *d_add, uint64_t *d_out, int level,
+                         int count, int64_t k);
 
 /* ---- descriptor lists: uneven level and ring degree per launch ---------- */
 /* Work whose shapes differ goes through one set of launches: the transforms

@@ -1175,19 +1175,24 @@ static int moddown_run(rbk_ctx *c, u64 *u, const u64 *add, long add_stride, u64 
 
 // ModDown fused with the key inner product: only the special-prime part of
 // the inner product is stored; the Q part is recomputed in the final kernel.
+// add2 (moddown_add2_ok only): a second addend on both polynomials, with the
+// rotation form of add; it may be out itself
 static int moddown_fused_run(rbk_ctx *c, const u64 *ext, long ext_stride, const DevKey *key, u64 perm_g, const u64 *add,
                              long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count,
-                             u64 *tp, u64 *conv, hipStream_t st = nullptr)
+                             u64 *tp, u64 *conv, hipStream_t st = nullptr, const u64 *add2 = nullptr,
+                             long add2_stride = 0)
 {
     const size_t N = c->N;
     const int L1 = level + 1, nP = c->nP;
     if (!st) st = c->stream;
+    if (add2 && (!moddown_add2_ok(c) || !add || add_both))
+        return fail(RBK_EINVAL, "internal: second addend outside the fused ModDown");
     ks_account(c, nullptr, count, level);
     if (nP > 0) {
         moddown_head_launch(c, ext, ext_stride, key->data, tp, level, count, perm_g, st);
         bconv_moddown_launch(c, tp, (long)nP * N, conv, (long)L1 * N, level, 2 * count, st);
         moddown_tail_launch(c, ext, ext_stride, key->data, conv, add, add_stride, add_g, add_both, out, out_stride, level,
-                            count, perm_g, st);
+                            count, perm_g, st, add2, add2_stride);
     } else {
         ew_launch(c, EW_ZERO, conv, nullptr, conv, 2 * count, L1, qmap(c), st);
         moddown_ip_launch(c, ext, ext_stride, key->data, conv, (long)2 * L1 * N, add, add_stride, add_g, add_both, out,
@@ -1253,14 +1258,15 @@ extern "C" int rbk_moddown(rbk_ctx *c, const uint64_t *u, uint64_t *out, int lev
 // key switch of count polynomials d (at d_stride) with key g (0 = relin),
 // results into out (count x [2][l+1][N] at out_stride) plus `add`.
 int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d, long d_stride, const u64 *add,
-                         long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count, u64 *base)
+                  long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count, u64 *base,
+                  const u64 *add2, long add2_stride)
 {
     const size_t N = c->N, L1 = level + 1, E = L1 + c->nP, beta = (L1 + c->alpha - 1) / c->alpha;
     KsBufs b = ks_layout(c, base, level, count);
     int rc = modup_run(c, d, d_stride, b.ext, (long)(beta * E * N), level, count, b.coef);
     if (rc) return rc;
     return moddown_fused_run(c, b.ext, (long)(beta * E * N), key, perm_g, add, add_stride, add_g, add_both, out, out_stride,
-                             level, count, b.tp, b.conv);
+                             level, count, b.tp, b.conv, nullptr, add2, add2_stride);
 }
 
 extern "C" int rbk_keyswitch(rbk_ctx *c, uint64_t g, const uint64_t *d, uint64_t *out, int level)
@@ -1338,37 +1344,75 @@ extern "C" int rbk_rescale(rbk_ctx *c, const uint64_t *ct, uint64_t *out, int le
 }
 
 // Rot for count ciphertexts [count][2][l+1][N] by the Galois element g:
-// out = (sigma_g(c0), 0) + KS(sigma_g(c1)), as rbk_rotate does for one.
-int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g)
+// out = (sigma_g(c0), 0) + KS(sigma_g(c1)) (+ add2, count ciphertexts in the
+// same layout, which may be out itself).  Only sigma_g(c1) is written out
+// (the ModUp input); the ModDown reads c0 through the permutation and adds
+// add2 in the same pass where the geometry allows.  An output over the
+// input (rbk_rotate in place) takes the permuted copy of both polynomials.
+static int rotate_run(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g, const u64 *add2)
 {
-    const size_t L1 = level + 1, N = c->N, per = L1 * N;
+    const size_t L1 = level + 1, N = c->N, per = L1 * N, words = (size_t)count * 2 * per;
+    if (ranges_overlap(in, words, out, words)) {
+        if (add2 || (g == 1 && in != out)) return fail(RBK_EINVAL, "rotation: input and output overlap");
+        if (g == 1) return RBK_OK;
+        const DevKey *k = find_key(c, g);
+        if (!k) return fail(RBK_ENOKEY, "no Galois key for element " + std::to_string(g));
+        WS(ws, words + ks_words(c, level, count));
+        automorph_launch(c, in, ws, 2 * count, (int)L1, g, c->stream);
+        return keyswitch_run(c, k, 0, ws + per, (long)(2 * per), ws, (long)(2 * per), 0, 0, out, (long)(2 * per), level,
+                             count, ws + words);
+    }
     if (g == 1) {
-        HIPCK(hipMemcpyAsync(out, in, count * 2 * per * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
+        if (add2) ew_launch(c, EW_ADD, in, add2, out, 2 * count, (int)L1, qmap(c), c->stream);
+        else HIPCK(hipMemcpyAsync(out, in, words * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
+        HIPCK_LAUNCH();
         return RBK_OK;
     }
     const DevKey *k = find_key(c, g);
     if (!k) return fail(RBK_ENOKEY, "no Galois key for element " + std::to_string(g));
-    WS(ws, count * 2 * per + ks_words(c, level, count));
-    u64 *rot = ws;
-    automorph_launch(c, in, rot, 2 * count, (int)L1, g, c->stream);
-    return keyswitch_run(c, k, 0, rot + per, (long)(2 * per), rot, (long)(2 * per), 0, 0, out, (long)(2 * per), level, count,
-                         ws + count * 2 * per);
+    if (add2 && !moddown_add2_ok(c)) {
+        // the rotation into the workspace, then the sum
+        WS(ws, words + count * per + ks_words(c, level, count));
+        u64 *rot1 = ws + words;
+        automorph_polys_launch(c, in + per, (long)(2 * per), rot1, (long)per, count, (int)L1, g, c->stream);
+        int rc = keyswitch_run(c, k, 0, rot1, (long)per, in, (long)(2 * per), g, 0, ws, (long)(2 * per), level, count,
+                               ws + words + count * per);
+        if (rc) return rc;
+        ew_launch(c, EW_ADD, ws, add2, out, 2 * count, (int)L1, qmap(c), c->stream);
+        HIPCK_LAUNCH();
+        return RBK_OK;
+    }
+    WS(ws, count * per + ks_words(c, level, count));
+    automorph_polys_launch(c, in + per, (long)(2 * per), ws, (long)per, count, (int)L1, g, c->stream);
+    return keyswitch_run(c, k, 0, ws, (long)per, in, (long)(2 * per), g, 0, out, (long)(2 * per), level, count,
+                         ws + count * per, add2, (long)(2 * per));
+}
+
+int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g)
+{
+    return rotate_run(c, in, out, level, count, g, nullptr);
+}
+
+int rotate_add_batch_g(rbk_ctx *c, const u64 *in, const u64 *add2, u64 *out, int level, int count, u64 g)
+{
+    return rotate_run(c, in, out, level, count, g, add2);
 }
 
 static int rotate_g(rbk_ctx *c, const u64 *ct, u64 *out, int level, u64 g)
 {
-    const size_t L1 = level + 1, N = c->N, per = L1 * N;
-    if (g == 1) {
-        HIPCK(hipMemcpyAsync(out, ct, 2 * per * sizeof(u64), hipMemcpyDeviceToDevice, c->stream));
-        return RBK_OK;
-    }
-    const DevKey *k = find_key(c, g);
-    if (!k) return fail(RBK_ENOKEY, "no Galois key for element " + std::to_string(g));
-    WS(ws, 2 * per + ks_words(c, level, 1));
-    u64 *rot = ws;
-    automorph_launch(c, ct, rot, 2, (int)L1, g, c->stream);
-    return keyswitch_run(c, k, 0, rot + per, (long)per, rot, (long)(2 * per), 0, 0, out, (long)(2 * per), level, 1,
-                         ws + 2 * per);
+    return rotate_run(c, ct, out, level, 1, g, nullptr);
+}
+
+extern "C" int rbk_rotate_add_batch(rbk_ctx *c, const uint64_t *ct, const uint64_t *add, uint64_t *out, int level,
+                                    int count, int64_t k)
+{
+    if (!c || !ct || !add || !out || count < 1) return fail(RBK_EINVAL, "bad argument");
+    if (check_level(c, level)) return RBK_ELEVEL;
+    const size_t words = (size_t)count * 2 * (level + 1) * c->N;
+    if (ranges_overlap(ct, words, out, words)) return fail(RBK_EINVAL, "rotate_add: input and output overlap");
+    if (add != out && ranges_overlap(add, words, out, words))
+        return fail(RBK_EINVAL, "rotate_add: addend partly overlaps the output");
+    return rotate_add_batch_g(c, ct, add, out, level, count, rbk_galois_elt(c, k));
 }
 
 extern "C" int rbk_rotate(rbk_ctx *c, const uint64_t *ct, uint64_t *out, int level, int64_t k)

@@ -590,6 +590,8 @@ struct Runner {
     }
 
     int rotate(const u64 *in, u64 *out, int level, int n_ct, int64_t k);
+    // out = add + Rot_k(in) (add may be out)
+    int rotate_add(const u64 *in, const u64 *add, u64 *out, int level, int n_ct, int64_t k);
     // one elementwise pass at level lv over n_ct ciphertexts (see k_boot_comb)
     void comb(CombArgs &A, u64 *out, int lv, int n_ct)
     {
@@ -621,11 +623,14 @@ struct Runner {
     int evalmod(Reg &x, int n_ct);
 };
 
-int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g);
-
 int Runner::rotate(const u64 *in, u64 *out, int level, int n_ct, int64_t k)
 {
     return rotate_batch_g(c, in, out, level, n_ct, rbk_galois_elt(c, k));
+}
+
+int Runner::rotate_add(const u64 *in, const u64 *add, u64 *out, int level, int n_ct, int64_t k)
+{
+    return rotate_add_batch_g(c, in, add, out, level, n_ct, rbk_galois_elt(c, k));
 }
 
 int Runner::lt(Reg &x, const BootLT &L, int n_ct)
@@ -670,15 +675,14 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
     const int nl = (c->lanes > 1 && !c->capturing && !c->timing && n_rot > 1 && side_streams(c) == RBK_OK)
                        ? std::min(c->lanes, n_rot)
                        : 0;
-    u64 *inner = take(), *irot = take(), *total = take();
-    if (!inner || !irot || !total) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
-    u64 *l_inner[RBK_LANES] = {}, *l_irot[RBK_LANES] = {}, *l_acc[RBK_LANES] = {};
+    u64 *inner = take(), *total = take();
+    if (!inner || !total) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+    u64 *l_inner[RBK_LANES] = {}, *l_acc[RBK_LANES] = {};
     bool l_have[RBK_LANES] = {};
     for (int k = 0; k < nl; k++) {
         l_inner[k] = take();
-        l_irot[k] = take();
         l_acc[k] = take();
-        if (!l_inner[k] || !l_irot[k] || !l_acc[k]) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+        if (!l_inner[k] || !l_acc[k]) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
     }
     const LimbMap qm{0, c->nQ, c->nQ};
     if (nl) {
@@ -693,10 +697,14 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
         const bool on_lane = nl && g != 0;
         const int k = lane;
         hipStream_t st = on_lane ? c->side[k] : c->stream;
-        u64 *in_buf = on_lane ? l_inner[k] : inner, *rot_buf = on_lane ? l_irot[k] : irot;
+        // the giant step without a rotation accumulates its products straight
+        // into the sum; a rotated one adds its rotation to the sum in the
+        // rotation's ModDown
+        const bool direct = g == 0;
+        u64 *in_buf = on_lane ? l_inner[k] : direct ? total : inner;
         // the giant step's diagonal products, up to MAC_MAX_TERMS per pass
         MacTerms T{};
-        bool first = true;
+        bool first = !(direct && have_total);
         for (auto &e : L.ents) {
             if (e.g != g) continue;
             if (e.b == 0) {
@@ -715,45 +723,29 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
             }
         }
         if (T.n) mac_multi_launch(c, T, in_buf, lvl, n_ct, first ? 0 : 1, st);
+        if (direct) {
+            have_total = true;
+            continue;
+        }
+        const int64_t rk = (int64_t)g * L.n1 * L.h0;
         if (on_lane) {
-            // the rotation on the lane's stream and workspace
+            // the rotation on the lane's stream and workspace, into the lane's partial sum
             std::swap(c->stream, c->side[k]);
             std::swap(c->ws, P.lane_ws[k]);
             std::swap(c->ws_words, P.lane_ws_words[k]);
-            rc = rotate(in_buf, rot_buf, lvl, n_ct, (int64_t)g * L.n1 * L.h0);
+            rc = l_have[k] ? rotate_add(in_buf, l_acc[k], l_acc[k], lvl, n_ct, rk)
+                           : rotate(in_buf, l_acc[k], lvl, n_ct, rk);
             std::swap(c->stream, c->side[k]);
             std::swap(c->ws, P.lane_ws[k]);
             std::swap(c->ws_words, P.lane_ws_words[k]);
             if (rc) break;
-            if (!l_have[k]) {
-                if (hipMemcpyAsync(l_acc[k], rot_buf, (size_t)n_ct * ctw * sizeof(u64), hipMemcpyDeviceToDevice, st) !=
-                    hipSuccess) {
-                    rc = RBK_EDEVICE;
-                    break;
-                }
-                l_have[k] = true;
-            } else {
-                ew_launch(c, EW_ADD, l_acc[k], rot_buf, l_acc[k], 2 * n_ct, lvl + 1, qm, st);
-            }
+            l_have[k] = true;
             lane = (lane + 1) % nl;
             continue;
         }
-        u64 *term = in_buf;
-        if (g) {
-            rc = rotate(in_buf, rot_buf, lvl, n_ct, (int64_t)g * L.n1 * L.h0);
-            if (rc) break;
-            term = rot_buf;
-        }
-        if (!have_total) {
-            if (hipMemcpyAsync(total, term, (size_t)n_ct * ctw * sizeof(u64), hipMemcpyDeviceToDevice, c->stream) !=
-                hipSuccess) {
-                rc = RBK_EDEVICE;
-                break;
-            }
-            have_total = true;
-        } else {
-            ew_launch(c, EW_ADD, total, term, total, 2 * n_ct, lvl + 1, qm, c->stream);
-        }
+        rc = have_total ? rotate_add(in_buf, total, total, lvl, n_ct, rk) : rotate(in_buf, total, lvl, n_ct, rk);
+        if (rc) break;
+        have_total = true;
     }
     // join every lane, also after a failure: later work on the context stream
     // reuses the registers and workspaces the lanes still read
@@ -775,13 +767,11 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
     }
     for (int k = 0; k < nl; k++) {
         give(l_inner[k]);
-        give(l_irot[k]);
         give(l_acc[k]);
     }
     if (!rc) rc = rbk_rescale_batch(c, total, x.d, lvl, n_ct);
     x.level = lvl - 1;
     give(inner);
-    give(irot);
     give(total);
     return rc;
 }

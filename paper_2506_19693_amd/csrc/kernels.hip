@@ -5,6 +5,8 @@
 // Layouts: ciphertext [2][l+1][N]; batch of ciphertexts outermost;
 // ModUp output [beta_l][E][N] with E = l+1+nP positions (q_0..q_l, p_0..);
 // inner-product output [2][E][N].
+#include <algorithm>
+
 #include "rbk_ctx.hpp"
 #include "wide_arith.hpp"
 
@@ -175,6 +177,45 @@ void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly,
     if (pair) hipLaunchKernelGGL(k_automorph<true>, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, g);
     else hipLaunchKernelGGL(k_automorph<false>, grid, dim3(EW_THREADS), 0, st, in, out, total, c->logN, g);
     kt_end(c, KC_ELEMENTWISE, 2.0 * total * sizeof(u64), st);
+}
+
+// The same permutation of npoly polynomials of nlimbs limbs each, polynomial
+// p read at in + p in_stride and written at out + p out_stride (grid.y runs
+// over the polynomials)
+template <bool PAIR>
+__global__ void k_automorph_polys(const u64 *in, long in_stride, u64 *out, long out_stride, size_t per, int logN, u64 g)
+{
+    size_t i = (PAIR ? 2 : 1) * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
+    if (i >= per) return;
+    const u64 *src = in + (size_t)blockIdx.y * in_stride;
+    u64 *dst = out + (size_t)blockIdx.y * out_stride;
+    size_t base = i & ~(((size_t)1 << logN) - 1);
+    u32 o = (u32)(i & (((size_t)1 << logN) - 1));
+    if (PAIR) {
+        const u64x2 v = ld2_perm(src + base, auto_src(o, g, logN));
+        st2(dst + i, v.x, v.y);
+    } else {
+        dst[i] = src[base + auto_src(o, g, logN)];
+    }
+}
+
+void automorph_polys_launch(const rbk_ctx_impl *c, const u64 *in, long in_stride, u64 *out, long out_stride, int npoly,
+                            int nlimbs, u64 g, hipStream_t st)
+{
+    const size_t per = (size_t)nlimbs * c->N;
+    if (per == 0 || npoly <= 0) return;
+    const bool pair = (((uintptr_t)in | (uintptr_t)out) & 15) == 0 && ((in_stride | out_stride) & 1) == 0 && c->N >= 2;
+    const size_t threads = pair ? per / 2 : per;
+    kt_begin(c, KC_ELEMENTWISE, st);
+    for (int p0 = 0; p0 < npoly; p0 += 65535) {
+        const int np = std::min(npoly - p0, 65535);
+        dim3 grid((unsigned)((threads + EW_THREADS - 1) / EW_THREADS), (unsigned)np);
+        const u64 *src = in + (size_t)p0 * in_stride;
+        u64 *dst = out + (size_t)p0 * out_stride;
+        if (pair) hipLaunchKernelGGL(k_automorph_polys<true>, grid, dim3(EW_THREADS), 0, st, src, in_stride, dst, out_stride, per, c->logN, g);
+        else hipLaunchKernelGGL(k_automorph_polys<false>, grid, dim3(EW_THREADS), 0, st, src, in_stride, dst, out_stride, per, c->logN, g);
+    }
+    kt_end(c, KC_ELEMENTWISE, 2.0 * npoly * per * sizeof(u64), st);
 }
 
 // ---------------------------------------------------------------- base conversion

@@ -260,14 +260,14 @@ struct Step {
 
     T sum_rows(T s)
     {
-        for (int k = sh.r >> 1; k >= 1; k >>= 1) s = ops.add(s, ops.rot(s, (int64_t)sh.c * k));
+        for (int k = sh.r >> 1; k >= 1; k >>= 1) s = ops.rot_add(s, (int64_t)sh.c * k);
         return s;
     }
     T sum_cols(T u)
     {
-        for (int k = sh.c >> 1; k >= 1; k >>= 1) u = ops.add(u, ops.rot(u, k));
+        for (int k = sh.c >> 1; k >= 1; k >>= 1) u = ops.rot_add(u, k);
         u = ops.mask(u);
-        for (int k = 1; k < sh.c; k <<= 1) u = ops.add(u, ops.rot(u, -(int64_t)k));
+        for (int k = 1; k < sh.c; k <<= 1) u = ops.rot_add(u, -(int64_t)k);
         return u;
     }
     // (f(z), f'(z)); has_d false with the literal derivative or without want_d (a forward pass only)
@@ -432,7 +432,7 @@ struct LevelOps {
     int mul(int a, int b) { return std::min(a, b) - 1; }
     int add(int a, int b) { return std::min(a, b); }
     int sub(int a, int b) { return std::min(a, b); }
-    int rot(int a, int64_t) { return a; }
+    int rot_add(int a, int64_t) { return a; }
     int mask(int a) { return a - 1; }
     int affine(int a, double, double) { return a; }
     int bsum(int a) { return a; }
@@ -677,11 +677,12 @@ struct GpuOps {
     }
     Vec add(const Vec &a, const Vec &b) { return addsub(a, b, 0); }
     Vec sub(const Vec &a, const Vec &b) { return addsub(a, b, 1); }
-    Vec rot(const Vec &a, int64_t k)
+    // a + Rot_k(a): the rotation's ModDown adds a in the same pass
+    Vec rot_add(const Vec &a, int64_t k)
     {
         Vec x = contiguous(a);
         Vec o = alloc(a.lv, a.count);
-        rck(rotate_batch_g(c, x.d, (u64 *)o.d, a.lv, a.count, rbk_galois_elt(c, k)));
+        rck(rotate_add_batch_g(c, x.d, x.d, (u64 *)o.d, a.lv, a.count, rbk_galois_elt(c, k)));
         o.s = a.s;
         return o;
     }

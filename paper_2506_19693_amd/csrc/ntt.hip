@@ -890,7 +890,7 @@ static void launch16_logs(int logs, u64 *data, long poly_stride, int npoly, int 
 // The ModDown of a key switch converts the special-prime part to the Q basis
 // (conv, coefficient domain), transforms it and combines it with the Q part
 // of the key inner product: out_p = (sum_j d_j key_{j,p} - NTT(conv_p)) P^-1
-// (+ the addend).  Here the forward row pass of conv_p (after its column
+// (+ the addends).  Here the forward row pass of conv_p (after its column
 // pass) leaves its canonical outputs in its LDS tile and the same block
 // applies that epilogue, so the transformed conv is never written to and read
 // back from memory.  One block per (row tile, limb, ciphertext, polynomial).  Blocks
@@ -898,12 +898,16 @@ static void launch16_logs(int logs, u64 *data, long poly_stride, int npoly, int 
 // in which all ciphertexts and both polynomials of one (limb, tile) follow
 // each other: the tile's key words and ModUp digits are then re-read from
 // that XCD's L2.
+// ADD: 0 no addend; 1 `add` on polynomial 0 (read through add_g); 2 `add` on
+// both; 3 as 1, plus `add2` on both polynomials read in place (a rotation
+// added to a ciphertext).  add2 may be `out` itself: every position of add2 is
+// read by the thread that writes the same position of out.
 template <int LOGS, int BETA, int ADD>
 __global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ ext, long ext_stride, KsItems I,
                                                     u64 *conv, long conv_stride, const u64 *__restrict__ add,
-                                                    long add_stride, u64 *__restrict__ out, long out_stride,
-                                                    NttTables T, int logN, int L1, int E, int nT, int count,
-                                                    const u64 *Pinv, const u64 *Pinv_sh)
+                                                    long add_stride, const u64 *add2, long add2_stride, u64 *out,
+                                                    long out_stride, NttTables T, int logN, int L1, int E, int nT,
+                                                    int count, const u64 *Pinv, const u64 *Pinv_sh)
 {
     typedef Geo<LOGS> G;
     __shared__ u64 sm[G::LINES * G::LS];
@@ -931,6 +935,7 @@ __global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ 
     const u64 *kp = key + ((size_t)poly * nT + limb) * N;              // digit j at + j 2 nT N
     const bool do_add = (ADD >= 1 && poly == 0) || (ADD == 2 && poly == 1);
     const u64 *ad = ADD ? add + ct * add_stride + poly * per + li : nullptr;
+    const u64 *ad2 = ADD == 3 ? add2 + ct * add2_stride + poly * per + li : nullptr;
     u64 *o = out + ct * out_stride + poly * per + li;
 #pragma unroll
     for (int m = 0; m < 8; m++) {
@@ -961,6 +966,11 @@ __global__ __launch_bounds__(256, 4) void k_ntt_rows_md(const u64 *__restrict__ 
             v0 = add_mod(v0, a.x, p.q);
             v1 = add_mod(v1, a.y, p.q);
         }
+        if (ADD == 3) {
+            const u64x2 a2 = ld2(ad2 + pos);
+            v0 = add_mod(v0, a2.x, p.q);
+            v1 = add_mod(v1, a2.y, p.q);
+        }
         st2_nt(o + pos, v0, v1);
     }
 }
@@ -982,22 +992,25 @@ static void ntt_cols_fwd_launch(const rbk_ctx_impl *c, u64 *data, long poly_stri
 }
 
 static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *conv,
-                               long conv_stride, const u64 *add, long add_stride, int add_both, u64 *out,
-                               long out_stride, int level, int count, hipStream_t st)
+                               long conv_stride, const u64 *add, long add_stride, int add_both, const u64 *add2,
+                               long add2_stride, u64 *out, long out_stride, int level, int count, hipStream_t st)
 {
     const int L1 = level + 1, E = L1 + c->nP, logN = c->logN, logC = c->ntt_logC;
     const int beta_l = (L1 + c->alpha - 1) / c->alpha;
-    const int addm = add ? (add_both ? 2 : 1) : 0;
+    // a second addend goes with the rotation form (c0's addend only)
+    const int addm = add2 ? 3 : add ? (add_both ? 2 : 1) : 0;
     const dim3 grid((unsigned)(((size_t)1 << logN) / 4096 * 2 * (size_t)count * I.n * L1));
     kt_begin(c, KC_NTT_ROWS_MD, st);
 #define RMD_LAUNCH(LG, B, A)                                                                                     \
     hipLaunchKernelGGL((k_ntt_rows_md<LG, B, A>), grid, dim3(256), 0, st, ext, ext_stride, I, conv, conv_stride, add,   \
-                       add_stride, out, out_stride, c->tabs, logN, L1, E, c->nT, count, c->d_Pinv, c->d_Pinv_sh)
+                       add_stride, add2, add2_stride, out, out_stride, c->tabs, logN, L1, E, c->nT, count, c->d_Pinv,   \
+                       c->d_Pinv_sh)
 #define RMD_ADD(LG, B)                                                                                          \
     do {                                                                                                        \
         if (addm == 0) RMD_LAUNCH(LG, B, 0);                                                                    \
         else if (addm == 1) RMD_LAUNCH(LG, B, 1);                                                               \
-        else RMD_LAUNCH(LG, B, 2);                                                                              \
+        else if (addm == 2) RMD_LAUNCH(LG, B, 2);                                                               \
+        else RMD_LAUNCH(LG, B, 3);                                                                              \
     } while (0)
 #define RMD_BETA(LG)                                                                                            \
     switch (beta_l) {                                                                                           \
@@ -1020,7 +1033,8 @@ static void ntt_rows_md_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_s
 #undef RMD_LAUNCH
     // algorithmic bytes: conv (after its column pass) and the ModUp digits
     // read, the outputs written, the addends read, each item's key words read once
-    const double words = (double)count * I.n * L1 * (beta_l + 2 + 2 + addm) + 2.0 * I.n * beta_l * L1;
+    const int add_words = addm == 3 ? 3 : addm;
+    const double words = (double)count * I.n * L1 * (beta_l + 2 + 2 + add_words) + 2.0 * I.n * beta_l * L1;
     kt_end(c, KC_NTT_ROWS_MD, words * c->N * sizeof(u64), st);
 }
 
@@ -1299,26 +1313,28 @@ hipError_t ntt_inverse_from_launch(const rbk_ctx_impl *c, const u64 *src, long s
 
 void moddown_tail_items_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *conv,
                                const u64 *add, long add_stride, int add_both, u64 *out, long out_stride, int level,
-                               int count, hipStream_t st)
+                               int count, hipStream_t st, const u64 *add2, long add2_stride)
 {
     const int L1 = level + 1;
     const size_t N = c->N;
     const LimbMap qm{0, c->nQ, c->nQ};
     ntt_cols_fwd_launch(c, conv, (long)(L1 * N), 2 * count * I.n, L1, qm, st);
-    ntt_rows_md_launch(c, ext, ext_stride, I, conv, (long)(2 * L1 * N), add, add_stride, add_both, out, out_stride, level,
-                       count, st);
+    ntt_rows_md_launch(c, ext, ext_stride, I, conv, (long)(2 * L1 * N), add, add_stride, add_both, add2, add2_stride, out,
+                       out_stride, level, count, st);
 }
+
+bool moddown_add2_ok(const rbk_ctx_impl *c) { return c->nP > 0 && ntt_rows_md_ok(c); }
 
 void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
                          const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
-                         int count, u64 g, hipStream_t st)
+                         int count, u64 g, hipStream_t st, const u64 *add2, long add2_stride)
 {
     const int L1 = level + 1;
     const size_t N = c->N;
     const LimbMap qm{0, c->nQ, c->nQ};
     if (ntt_rows_md_ok(c)) {
         moddown_tail_items_launch(c, ext, ext_stride, one_item(key, g, add_g), conv, add, add_stride, add_both, out,
-                                  out_stride, level, count, st);
+                                  out_stride, level, count, st, add2, add2_stride);
         return;
     }
     ntt_launch(c, conv, (long)(L1 * N), 2 * count, L1, qm, false, st);

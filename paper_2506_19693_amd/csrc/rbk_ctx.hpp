@@ -194,6 +194,8 @@ void signed_to_limbs_launch(const rbk_ctx_impl *c, const i64 *v, u64 *out, int n
                             hipStream_t st);
 void tensor_launch(const rbk_ctx_impl *c, const u64 *a, const u64 *b, u64 *out, int level, int count, hipStream_t st);
 void automorph_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int nlimbs, u64 g, hipStream_t st);
+void automorph_polys_launch(const rbk_ctx_impl *c, const u64 *in, long in_stride, u64 *out, long out_stride, int npoly,
+                            int nlimbs, u64 g, hipStream_t st);
 void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, const u64 *own, long own_stride,
                         u64 *ext, long ext_stride, int level, int count, hipStream_t st);
 void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride, u64 *conv, long conv_stride, int level,
@@ -245,12 +247,16 @@ struct KsItems {
 bool moddown_items_ok(const rbk_ctx_impl *c);
 void moddown_head_items_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *tp,
                                int level, int count, hipStream_t st);
+// add2 (optional, the register geometries with special primes only:
+// moddown_add2_ok): a second addend on both polynomials, read in place, with
+// the rotation form of add (c0 only); it may be out itself
 void moddown_tail_items_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const KsItems &I, u64 *conv,
                                const u64 *add, long add_stride, int add_both, u64 *out, long out_stride, int level,
-                               int count, hipStream_t st);
+                               int count, hipStream_t st, const u64 *add2 = nullptr, long add2_stride = 0);
 void moddown_tail_launch(const rbk_ctx_impl *c, const u64 *ext, long ext_stride, const u64 *key, u64 *conv,
                          const u64 *add, long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level,
-                         int count, u64 g, hipStream_t st);
+                         int count, u64 g, hipStream_t st, const u64 *add2 = nullptr, long add2_stride = 0);
+bool moddown_add2_ok(const rbk_ctx_impl *c);
 void rescale_lift_launch(const rbk_ctx_impl *c, const u64 *last, u64 *lifted, int level, int npoly, hipStream_t st);
 void rescale_finish_launch(const rbk_ctx_impl *c, const u64 *in, const u64 *lifted, u64 *out, int level, int npoly,
                            hipStream_t st);
@@ -289,10 +295,16 @@ size_t ks_words(const rbk_ctx *c, int level, int count);
 // KS of count polynomials d (d_stride apart) with `key`: out = KS(d) + add
 // (add_both: both polynomials of add, else c0 only; perm_g: automorphism of
 // the digits first, 0 for none); base: ks_words() of workspace
+// (add2: a second addend on both polynomials, with the rotation form of add;
+// moddown_add2_ok only; it may be out itself)
 int keyswitch_run(rbk_ctx *c, const DevKey *key, u64 perm_g, const u64 *d, long d_stride, const u64 *add,
-                  long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count, u64 *base);
-// out = Rot_g of count contiguous ciphertexts [count][2][l+1][N]
+                  long add_stride, u64 add_g, int add_both, u64 *out, long out_stride, int level, int count, u64 *base,
+                  const u64 *add2 = nullptr, long add2_stride = 0);
+// out = Rot_g of count contiguous ciphertexts [count][2][l+1][N] (in and out
+// must not overlap)
 int rotate_batch_g(rbk_ctx *c, const u64 *in, u64 *out, int level, int count, u64 g);
+// out = add2 + Rot_g(in), same layout; add2 may be out itself or in
+int rotate_add_batch_g(rbk_ctx *c, const u64 *in, const u64 *add2, u64 *out, int level, int count, u64 g);
 int rbk_set_error(int code, const char *msg);
 // true when [a, a + a_words) and [b, b + b_words) share a word
 bool ranges_overlap(const u64 *a, size_t a_words, const u64 *b, size_t b_words);

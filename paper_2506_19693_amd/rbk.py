@@ -182,6 +182,7 @@ SIGNATURES = {
     "rbk_mult_relin_rescale_list": (ci, [vp, vp, vp, vp, ctypes.POINTER(ci), ci]),
     "rbk_mult_relin_rescale_multi": (ci, [vp, ctypes.POINTER(RbkMrItem), ci]),
     "rbk_rotate_hoisted_batch": (ci, [vp, vp, i64p, ci, vp, ci, ci]),
+    "rbk_rotate_add_batch": (ci, [vp, vp, vp, vp, ci, ci, ctypes.c_int64]),
     "rbk_boot_setup": (ci, [vp, ctypes.POINTER(RbkBootParams)]),
     "rbk_boot_rotations": (ci, [vp, i64p, ci]),
     "rbk_boot_info": (ci, [vp, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]),
@@ -824,6 +825,13 @@ class Context:
                 raise ValueError("limb outside its tensor")
             arr[k] = RbkNttItem(ctx.h, t.data_ptr() + 8 * off, int(prime), 0)
         _check(self.lib.rbk_ntt_list(self.h, arr, len(items), 1 if inverse else 0))
+
+    def rotate_add_batch(self, ct, k, add, level, out=None):
+        """add + Rot(ct, k) for [count][2][l+1][N] batches (add may be ct or out)."""
+        count = ct.shape[0]
+        out = self.empty(count, 2, level + 1, self.N) if out is None else out
+        _check(self.lib.rbk_rotate_add_batch(self.h, _ptr(ct), _ptr(add), _ptr(out), level, count, int(k)))
+        return out
 
     def rotate_hoisted_batch(self, ct, ks, level, out=None):
         count = ct.shape[0]

@@ -216,6 +216,37 @@ def test_ciphertext_ops_bit_exact(name):
         assert np.array_equal(down(p, d.rotate_hoisted(A, [0], level), level)[0], a)
 
 
+@pytest.mark.parametrize("name", list(PARAMS))
+def test_rotate_add_bit_exact(name):
+    """add + Rot(ct, k) in one pass (Section 3's Rot, then Add) against the
+    oracle's rotation and addition, for 3 ciphertexts: the addend another
+    batch, the input itself (the rotate-and-sum step), and the output
+    (accumulation in place).  At N = 2^13 the addend goes through the fused
+    ModDown, at 2^10 and 2^12 through a separate addition."""
+    from paper_2506_19693_amd import RbkError
+
+    p = pair(name)
+    o, d = p.orc, p.gpu
+    cnt = 3
+    for level in sorted({o.L, 1}):
+        a, b = p.rand_ct(level, lead=(cnt, 2)), p.rand_ct(level, lead=(cnt, 2))
+        A, B = up(p, a, level), up(p, b, level)
+        for k in (1, -3):
+            gal, key = p.gal[k]
+            rot = [o.rotate(level, key, gal, a[c]) for c in range(cnt)]
+            other = down(p, d.rotate_add_batch(A, k, B, level), level)
+            itself = down(p, d.rotate_add_batch(A, k, A, level), level)
+            acc = B.clone()
+            d.rotate_add_batch(A, k, acc, level, out=acc)
+            acc = down(p, acc, level)
+            for c in range(cnt):
+                assert np.array_equal(other[c], o.add(level, rot[c], b[c])), (level, k, c)
+                assert np.array_equal(itself[c], o.add(level, rot[c], a[c])), (level, k, c)
+                assert np.array_equal(acc[c], o.add(level, rot[c], b[c])), (level, k, c)
+    with pytest.raises(RbkError):                       # output over the input
+        d.rotate_add_batch(A, 1, B, 1, out=A)
+
+
 @pytest.mark.parametrize("name", ["tiny", "mid"])
 def test_batched_equals_plain(name):
     p = pair(name)
