@@ -16,6 +16,7 @@
 // (EvalMod runs the real and imaginary halves of the whole batch together).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -664,88 +665,115 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
     std::vector<int> gs;
     for (auto &e : L.ents)
         if (std::find(gs.begin(), gs.end(), e.g) == gs.end()) gs.push_back(e.g);
+    // the giant step without a rotation (if any) first: its products go
+    // straight into the sum
+    std::stable_partition(gs.begin(), gs.end(), [](int g) { return g == 0; });
     const int n_rot = (int)std::count_if(gs.begin(), gs.end(), [](int g) { return g != 0; });
     // Giant-step lanes: the giant steps are independent up to the final sum,
-    // so those with a rotation go round-robin over the context's side streams
-    // (each with key-switching workspace and registers of its own) and every
-    // lane keeps a partial sum; the context stream adds the partial sums.
-    // Modular sums do not depend on their order, so the residues are those of
-    // one lane.  One lane while timers run or the stream is captured (a
-    // captured graph stays one chain of kernels).
+    // so their rotations go round-robin over the context's side streams (each
+    // with key-switching workspace of its own) and every lane keeps a partial
+    // sum; the context stream adds the partial sums.  Modular sums do not
+    // depend on their order, so the residues are those of one lane.  One lane
+    // while timers run or the stream is captured (a captured graph stays one
+    // chain of kernels).
     const int nl = (c->lanes > 1 && !c->capturing && !c->timing && n_rot > 1 && side_streams(c) == RBK_OK)
                        ? std::min(c->lanes, n_rot)
                        : 0;
-    u64 *inner = take(), *total = take();
-    if (!inner || !total) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
-    u64 *l_inner[RBK_LANES] = {}, *l_acc[RBK_LANES] = {};
+    // The products of GT_MAX_G giant steps at a time, every baby step read
+    // once per pass; each rotated giant step's inner sum waits in a register
+    // for its rotation: one register per rotated giant step with lanes (the
+    // rotations run behind the products), else GT_MAX_G used in turn on the
+    // one stream.
+    const int n_inner = nl ? n_rot : std::min(n_rot, GT_MAX_G);
+    std::vector<u64 *> inner;
+    for (int i = 0; i < n_inner; i++) {
+        inner.push_back(take());
+        if (!inner.back()) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+    }
+    u64 *total = take();
+    if (!total) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+    u64 *l_acc[RBK_LANES] = {};
     bool l_have[RBK_LANES] = {};
     for (int k = 0; k < nl; k++) {
-        l_inner[k] = take();
         l_acc[k] = take();
-        if (!l_inner[k] || !l_acc[k]) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
+        if (!l_acc[k]) return rbk_set_error(RBK_ENOMEM, "bootstrapping registers");
     }
     const LimbMap qm{0, c->nQ, c->nQ};
-    if (nl) {
-        if (hipEventRecord(c->side_ev[RBK_LANES], c->stream) != hipSuccess) return rbk_set_error(RBK_EDEVICE, "fork");
-        for (int k = 0; k < nl; k++)
-            if (hipStreamWaitEvent(c->side[k], c->side_ev[RBK_LANES], 0) != hipSuccess)
-                return rbk_set_error(RBK_EDEVICE, "fork");
+    // baby-step slots: 0 is the input itself, then the hoisted rotations
+    const int n_slot = 1 + nb;
+    std::vector<const u64 *> bsrc(n_slot);
+    std::vector<long> bstride(n_slot);
+    bsrc[0] = x.d;
+    bstride[0] = (long)ctw;
+    for (int i = 0; i < nb; i++) {
+        bsrc[1 + i] = rots + (size_t)i * ctw;
+        bstride[1 + i] = (long)(nb * ctw);
     }
+    auto slot_of = [&](int b) {
+        return b == 0 ? 0 : 1 + (int)(std::find(babies.begin(), babies.end(), b) - babies.begin());
+    };
     bool have_total = false;
-    int lane = 0;
-    for (int g : gs) {
-        const bool on_lane = nl && g != 0;
-        const int k = lane;
-        hipStream_t st = on_lane ? c->side[k] : c->stream;
-        // the giant step without a rotation accumulates its products straight
-        // into the sum; a rotated one adds its rotation to the sum in the
-        // rotation's ModDown
-        const bool direct = g == 0;
-        u64 *in_buf = on_lane ? l_inner[k] : direct ? total : inner;
-        // the giant step's diagonal products, up to MAC_MAX_TERMS per pass
-        MacTerms T{};
-        bool first = !(direct && have_total);
-        for (auto &e : L.ents) {
-            if (e.g != g) continue;
-            if (e.b == 0) {
-                T.src[T.n] = x.d;
-                T.stride[T.n] = (long)ctw;
-            } else {
-                int bi = (int)(std::find(babies.begin(), babies.end(), e.b) - babies.begin());
-                T.src[T.n] = rots + (size_t)bi * ctw;
-                T.stride[T.n] = (long)(nb * ctw);
+    int lane = 0, n_done = 0;
+    for (size_t s0 = 0; s0 < gs.size() && rc == RBK_OK; s0 += GT_MAX_G) {
+        const int ng = (int)std::min<size_t>(GT_MAX_G, gs.size() - s0);
+        u64 *outs[GT_MAX_G] = {};
+        for (int j = 0, r = n_done; j < ng; j++) outs[j] = gs[s0 + j] == 0 ? total : inner[(r++) % n_inner];
+        for (int b0 = 0; b0 < n_slot; b0 += GT_MAX_B) {
+            GiantTerms T{};
+            T.ng = ng;
+            T.nb = std::min(GT_MAX_B, n_slot - b0);
+            for (int i = 0; i < T.nb; i++) {
+                T.src[i] = bsrc[b0 + i];
+                T.stride[i] = bstride[b0 + i];
             }
-            T.pt[T.n] = P.d_plain[e.plain];
-            if (++T.n == MAC_MAX_TERMS) {
-                mac_multi_launch(c, T, in_buf, lvl, n_ct, first ? 0 : 1, st);
-                first = false;
-                T.n = 0;
+            for (int j = 0; j < ng; j++) {
+                T.out[j] = outs[j];
+                T.add[j] = b0 > 0;
             }
+            for (auto &e : L.ents) {
+                const int j = (int)(std::find(gs.begin() + s0, gs.begin() + s0 + ng, e.g) - (gs.begin() + s0));
+                const int sl = slot_of(e.b) - b0;
+                if (j < ng && sl >= 0 && sl < T.nb) T.pt[j][sl] = P.d_plain[e.plain];
+            }
+            mac_giants_launch(c, T, lvl, n_ct, c->stream);
         }
-        if (T.n) mac_multi_launch(c, T, in_buf, lvl, n_ct, first ? 0 : 1, st);
-        if (direct) {
-            have_total = true;
-            continue;
-        }
-        const int64_t rk = (int64_t)g * L.n1 * L.h0;
-        if (on_lane) {
-            // the rotation on the lane's stream and workspace, into the lane's partial sum
-            std::swap(c->stream, c->side[k]);
-            std::swap(c->ws, P.lane_ws[k]);
-            std::swap(c->ws_words, P.lane_ws_words[k]);
-            rc = l_have[k] ? rotate_add(in_buf, l_acc[k], l_acc[k], lvl, n_ct, rk)
-                           : rotate(in_buf, l_acc[k], lvl, n_ct, rk);
-            std::swap(c->stream, c->side[k]);
-            std::swap(c->ws, P.lane_ws[k]);
-            std::swap(c->ws_words, P.lane_ws_words[k]);
+        if (gs[s0] == 0) have_total = true;
+        if (nl) {
+            // the lanes' rotations start once these products are written
+            if (hipEventRecord(c->side_ev[RBK_LANES], c->stream) != hipSuccess) {
+                rc = rbk_set_error(RBK_EDEVICE, "fork");
+                break;
+            }
+            for (int k = 0; k < nl && rc == RBK_OK; k++)
+                if (hipStreamWaitEvent(c->side[k], c->side_ev[RBK_LANES], 0) != hipSuccess)
+                    rc = rbk_set_error(RBK_EDEVICE, "fork");
             if (rc) break;
-            l_have[k] = true;
-            lane = (lane + 1) % nl;
-            continue;
         }
-        rc = have_total ? rotate_add(in_buf, total, total, lvl, n_ct, rk) : rotate(in_buf, total, lvl, n_ct, rk);
-        if (rc) break;
-        have_total = true;
+        for (int j = 0; j < ng; j++) {
+            const int g = gs[s0 + j];
+            if (g == 0) continue;
+            n_done++;
+            const int64_t rk = (int64_t)g * L.n1 * L.h0;
+            if (nl) {
+                // the rotation on the lane's stream and workspace, into the lane's partial sum
+                const int k = lane;
+                std::swap(c->stream, c->side[k]);
+                std::swap(c->ws, P.lane_ws[k]);
+                std::swap(c->ws_words, P.lane_ws_words[k]);
+                rc = l_have[k] ? rotate_add(outs[j], l_acc[k], l_acc[k], lvl, n_ct, rk)
+                               : rotate(outs[j], l_acc[k], lvl, n_ct, rk);
+                std::swap(c->stream, c->side[k]);
+                std::swap(c->ws, P.lane_ws[k]);
+                std::swap(c->ws_words, P.lane_ws_words[k]);
+                if (rc) break;
+                l_have[k] = true;
+                lane = (lane + 1) % nl;
+                continue;
+            }
+            rc = have_total ? rotate_add(outs[j], total, total, lvl, n_ct, rk) : rotate(outs[j], total, lvl, n_ct, rk);
+            if (rc) break;
+            have_total = true;
+        }
     }
     // join every lane, also after a failure: later work on the context stream
     // reuses the registers and workspaces the lanes still read
@@ -765,13 +793,10 @@ int Runner::lt(Reg &x, const BootLT &L, int n_ct)
             ew_launch(c, EW_ADD, total, l_acc[k], total, 2 * n_ct, lvl + 1, qm, c->stream);
         }
     }
-    for (int k = 0; k < nl; k++) {
-        give(l_inner[k]);
-        give(l_acc[k]);
-    }
+    for (int k = 0; k < nl; k++) give(l_acc[k]);
     if (!rc) rc = rbk_rescale_batch(c, total, x.d, lvl, n_ct);
     x.level = lvl - 1;
-    give(inner);
+    for (u64 *d : inner) give(d);
     give(total);
     return rc;
 }

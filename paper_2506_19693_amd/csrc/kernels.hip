@@ -837,6 +837,63 @@ void mac_multi_launch(const rbk_ctx_impl *c, const MacTerms &T, u64 *out, int le
     kt_end(c, KC_ELEMENTWISE, ct * count * (T.n + (add ? 2 : 1)) + ct / 2 * T.n, st);
 }
 
+// Several giant steps of a baby-step / giant-step product in one pass: each
+// baby-step ciphertext is read once per launch and multiplied into the inner
+// sums of up to GT_MAX_G giant steps (one position per thread, every
+// plaintext weight of the thread's position held in registers across the
+// batch), where a launch per giant step reads every baby step again.
+__global__ __launch_bounds__(EW_THREADS) void k_mac_giants(GiantTerms T, int logN, int L1, int count, const PrimeC *pc)
+{
+    const size_t N = (size_t)1 << logN;
+    const size_t n = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (n >= N) return;
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    const PrimeC p = pc[limb];
+    const size_t per = (size_t)L1 * N, lo = ((size_t)limb << logN) + n, off = (size_t)poly * per + lo;
+    u64 w[GT_MAX_G][GT_MAX_B];
+#pragma unroll
+    for (int j = 0; j < GT_MAX_G; j++)
+#pragma unroll
+        for (int b = 0; b < GT_MAX_B; b++) w[j][b] = (j < T.ng && b < T.nb && T.pt[j][b]) ? T.pt[j][b][lo] : 0;
+    for (int c = 0; c < count; c++) {
+        u128w acc[GT_MAX_G];
+#pragma unroll
+        for (int j = 0; j < GT_MAX_G; j++) acc[j] = {0, 0};
+#pragma unroll
+        for (int b = 0; b < GT_MAX_B; b++) {
+            if (b < T.nb) {
+                const u64 v = T.src[b][(size_t)c * T.stride[b] + off];
+#pragma unroll
+                for (int j = 0; j < GT_MAX_G; j++)
+                    if (j < T.ng && T.pt[j][b]) acc_wide(acc[j], mul_wide(v, w[j][b]));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < GT_MAX_G; j++)
+            if (j < T.ng) {
+                u64 *o = T.out[j] + (size_t)c * 2 * per + off;
+                u64 r = mac_finish(acc[j], p);
+                if (T.add[j]) r = add_mod(*o, r, p.q);
+                *o = r;
+            }
+    }
+}
+
+void mac_giants_launch(const rbk_ctx_impl *c, const GiantTerms &T, int level, int count, hipStream_t st)
+{
+    if (T.ng <= 0 || T.nb <= 0 || count <= 0) return;
+    dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), level + 1, 2);
+    kt_begin(c, KC_ELEMENTWISE, st);
+    hipLaunchKernelGGL(k_mac_giants, grid, dim3(EW_THREADS), 0, st, T, c->logN, level + 1, count, c->d_pc);
+    int n_pt = 0, n_rd = 0;
+    for (int j = 0; j < T.ng; j++) {
+        n_rd += T.add[j] ? 2 : 1;
+        for (int b = 0; b < T.nb; b++) n_pt += T.pt[j][b] ? 1 : 0;
+    }
+    const double ct = 2.0 * (level + 1) * c->N * sizeof(u64);
+    kt_end(c, KC_ELEMENTWISE, ct * count * (T.nb + n_rd) + ct * n_pt, st);
+}
+
 // ct + constant for count ciphertexts (the constant goes to every NTT point of c0)
 __global__ void k_add_scalar_batch(const u64 *a, u64 *out, size_t per, int logN, int count, const PrimeC *pc, ScalArg s)
 {

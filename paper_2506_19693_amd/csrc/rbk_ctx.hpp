@@ -284,6 +284,19 @@ struct MacTerms {
 // out[c] = sum_t src_t[c] (.) pt_t  (+ out[c] when add), count ciphertexts at level l
 void mac_multi_launch(const rbk_ctx_impl *c, const MacTerms &T, u64 *out, int level, int count, int add,
                       hipStream_t st);
+// up to GT_MAX_G giant steps of one BSGS product over GT_MAX_B baby-step
+// slots: out_j[c] = sum_b src_b[c] (.) pt_{j,b} (+ out_j[c] when add_j), count
+// ciphertexts at level l (pt_{j,b} null: no term; outs distinct from srcs)
+constexpr int GT_MAX_G = 4, GT_MAX_B = 8;
+struct GiantTerms {
+    const u64 *src[GT_MAX_B];  // baby slot b of ciphertext c at src[b] + c * stride[b]
+    long stride[GT_MAX_B];
+    u64 *out[GT_MAX_G];        // [count][2][l+1][N]
+    const u64 *pt[GT_MAX_G][GT_MAX_B];
+    int add[GT_MAX_G];
+    int nb, ng;
+};
+void mac_giants_launch(const rbk_ctx_impl *c, const GiantTerms &T, int level, int count, hipStream_t st);
 void add_scalar_batch_launch(const rbk_ctx_impl *c, const u64 *a, u64 *out, int level, int count, const ScalArg &s,
                              hipStream_t st);
 void boot_free(rbk_ctx_impl *c);
