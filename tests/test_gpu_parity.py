@@ -245,6 +245,13 @@ def test_rotate_add_bit_exact(name):
                 assert np.array_equal(acc[c], o.add(level, rot[c], b[c])), (level, k, c)
     with pytest.raises(RbkError):                       # output over the input
         d.rotate_add_batch(A, 1, B, 1, out=A)
+    # rbk_rotate in place (the output over the input) still gives the rotation
+    level = o.L
+    a = p.rand_ct(level)
+    A = up(p, a, level)
+    gal, key = p.gal[-3]
+    assert d.lib.rbk_rotate(d.h, A.data_ptr(), A.data_ptr(), level, -3) == 0
+    assert np.array_equal(down(p, A, level), o.rotate(level, key, gal, a))
 
 
 @pytest.mark.parametrize("name", ["tiny", "mid"])
