@@ -221,10 +221,12 @@ void automorph_polys_launch(const rbk_ctx_impl *c, const u64 *in, long in_stride
 // ---------------------------------------------------------------- base conversion
 
 #define BCONV_MAX_IN 16
-// the table is staged in LDS output-major, entry (i, o) at o * MAXIN + i, so
-// the inputs of one output sit at one address plus immediate offsets; n_out
-// is below the prime count
-#define BCONV_TAB(MAXIN) (RBK_MAX_PRIMES * (MAXIN))
+// the table is staged in LDS output-major, entry (i, o) at o * TS + i with the
+// row stride TS = MAXIN rounded up to even (16-byte aligned rows), so the
+// inputs of one output sit at one address plus immediate offsets; n_out is
+// below the prime count
+#define BCONV_TS(MAXIN) (((MAXIN) + 1) & ~1)
+#define BCONV_TAB(MAXIN) (RBK_MAX_PRIMES * BCONV_TS(MAXIN))
 
 // Base-conversion sums use the carry-free 30-bit split accumulation of
 // wide_arith.hpp (at most 16 terms of residues and table entries below 2^60).
@@ -277,8 +279,9 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
         dst = out + poly * out_stride;
     }
     // zero columns past n_in: every output sums all MAXIN terms without branches
-    for (int w = threadIdx.x; w < MAXIN * n_out; w += EW_THREADS) {
-        const int o = w / MAXIN, i = w % MAXIN;
+    constexpr int TS = BCONV_TS(MAXIN);
+    for (int w = threadIdx.x; w < TS * n_out; w += EW_THREADS) {
+        const int o = w / TS, i = w % TS;
         tab[w] = i < n_in ? split30(Mj[(size_t)i * m_stride + o]) : Half30{0, 0};
     }
     __syncthreads();
@@ -307,12 +310,15 @@ __global__ __launch_bounds__(EW_THREADS) void k_bconv(const u64 *in, long in_str
         Acc4 acc;
 #pragma unroll
         for (int i = 0; i < MAXIN; i++)
-            wa::acc4(acc, yh[i], tab[o * MAXIN + i]);
+            wa::acc4(acc, yh[i], tab[o * TS + i]);
         // n_in <= 16 terms, each y (< 2^60) times a table entry (< p): the sum
         // stays below p 2^64, so a plain REDC reduces it
         dst[(size_t)pos * N + k] = redc(acc4_sum(acc), p.q, p.qneg);
     }
 }
+
+// terms per output of the base-conversion kernel for n inputs
+static int bconv_terms(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n == 9 ? 9 : n == 10 ? 10 : n <= 12 ? 12 : 16; }
 
 void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride, const u64 *own, long own_stride,
                         u64 *ext, long ext_stride, int level, int count, hipStream_t st)
@@ -321,18 +327,19 @@ void bconv_modup_launch(const rbk_ctx_impl *c, const u64 *coef, long coef_stride
     int L1 = level + 1, E = L1 + c->nP;
     dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), T.beta, count);
     kt_begin(c, KC_BCONV_UP, st);
-    if (c->alpha <= 4)
-        hipLaunchKernelGGL((k_bconv<true, 4>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
-                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
-    else if (c->alpha <= 8)
-        hipLaunchKernelGGL((k_bconv<true, 8>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
-                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
-    else if (c->alpha <= 12)
-        hipLaunchKernelGGL((k_bconv<true, 12>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
-                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
-    else
-        hipLaunchKernelGGL((k_bconv<true, 16>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1,
-                           E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride);
+#define BCU(M)                                                                                                         \
+    hipLaunchKernelGGL((k_bconv<true, M>), grid, dim3(EW_THREADS), 0, st, coef, coef_stride, ext, ext_stride, c->logN, L1, \
+                       E, c->alpha, c->nP, c->nQ, T.d_A, T.d_Ash, T.d_M, (long)E, c->d_pc, own, own_stride)
+    // the digit size itself where it is common (no zero terms), else the next multiple of 4
+    switch (bconv_terms(c->alpha)) {
+    case 4: BCU(4); break;
+    case 8: BCU(8); break;
+    case 9: BCU(9); break;
+    case 10: BCU(10); break;
+    case 12: BCU(12); break;
+    default: BCU(16); break;
+    }
+#undef BCU
     kt_end(c, KC_BCONV_UP, (double)count * T.beta * E * c->N * sizeof(u64), st);
 }
 
@@ -342,18 +349,18 @@ void bconv_moddown_launch(const rbk_ctx_impl *c, const u64 *pcoef, long p_stride
     int L1 = level + 1;
     dim3 grid((unsigned)((c->N + EW_THREADS - 1) / EW_THREADS), 1, count);
     kt_begin(c, KC_BCONV_DOWN, st);
-    if (c->nP <= 4)
-        hipLaunchKernelGGL((k_bconv<false, 4>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
-                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
-    else if (c->nP <= 8)
-        hipLaunchKernelGGL((k_bconv<false, 8>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1,
-                           L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
-    else if (c->nP <= 12)
-        hipLaunchKernelGGL((k_bconv<false, 12>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN,
-                           L1, L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
-    else
-        hipLaunchKernelGGL((k_bconv<false, 16>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN,
-                           L1, L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0);
+#define BCD(M)                                                                                                           \
+    hipLaunchKernelGGL((k_bconv<false, M>), grid, dim3(EW_THREADS), 0, st, pcoef, p_stride, conv, conv_stride, c->logN, L1, \
+                       L1 + c->nP, c->alpha, c->nP, c->nQ, c->d_md_A, c->d_md_Ash, c->d_md_M, (long)c->nQ, c->d_pc, nullptr, 0)
+    switch (bconv_terms(c->nP)) {
+    case 4: BCD(4); break;
+    case 8: BCD(8); break;
+    case 9: BCD(9); break;
+    case 10: BCD(10); break;
+    case 12: BCD(12); break;
+    default: BCD(16); break;
+    }
+#undef BCD
     kt_end(c, KC_BCONV_DOWN, (double)count * (c->nP + L1) * c->N * sizeof(u64), st);
 }
 

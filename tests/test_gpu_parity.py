@@ -18,6 +18,11 @@ PARAMS = {
     "c0": (12, [50, 40, 40, 40], [50], 1),
     # N = 2^13 exercises the two-pass NTT inside the whole pipeline
     "mid": (13, [60, 50, 50, 50], [60, 60], 3),
+    # digits of 9 and 9 special primes, digits of 10 and 10 special primes: the
+    # base conversions of those exact input counts (the bootstrap's and the
+    # training step's shapes)
+    "nine": (11, [60] + [50] * 17, [60] * 9, 9),
+    "ten": (10, [60] + [50] * 20, [60] * 10, 10),
 }
 
 
