@@ -735,113 +735,11 @@ void monomial_half_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int np
     kt_end(c, KC_ELEMENTWISE, 2.0 * total * sizeof(u64), st);
 }
 
-// acc (+)= ct * pt for count ciphertexts (both polynomials), pt [l+1][N] shared.
-__global__ void k_mac_plain(u64 *acc, const u64 *ct, long ct_stride, const u64 *pt, int logN, int L1, int count, int first,
-                            const PrimeC *pc)
-{
-    const size_t N = (size_t)1 << logN;
-    const size_t per = (size_t)L1 * N;
-    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
-    if (i >= 2 * per * count) return;
-    size_t cc = i / (2 * per), r = i % (2 * per);
-    size_t rr = r % per;
-    int limb = (int)(rr >> logN);
-    const PrimeC p = pc[limb];
-    u64 v = mul_mod(ct[cc * ct_stride + r], pt[rr], p);
-    acc[i] = first ? v : add_mod(acc[i], v, p.q);
-}
-
-void mac_plain_launch(const rbk_ctx_impl *c, u64 *acc, const u64 *ct, long ct_stride, const u64 *pt, int level, int count,
-                      int first, hipStream_t st)
-{
-    size_t total = (size_t)2 * (level + 1) * c->N * count;
-    dim3 grid((unsigned)((total + EW_THREADS - 1) / EW_THREADS));
-    kt_begin(c, KC_ELEMENTWISE, st);
-    hipLaunchKernelGGL(k_mac_plain, grid, dim3(EW_THREADS), 0, st, acc, ct, ct_stride, pt, c->logN, level + 1, count,
-                       first, c->d_pc);
-    kt_end(c, KC_ELEMENTWISE, (first ? 2.0 : 3.0) * total * sizeof(u64) + (double)(level + 1) * c->N * sizeof(u64), st);
-}
-
-// out = sum_t src_t (.) pt_t (+ out when add): a BSGS giant step's diagonal
-// products in one pass.  Each thread keeps its plaintext residues in
-// registers and walks the ciphertexts of the batch; every product is below
-// q^2 and at most MAC_MAX_TERMS of them stay below q 2^64, so one REDC (and
-// one more to undo its 2^-64) ends the lazy 128-bit sum.  PAIR: each thread
-// takes two adjacent coefficients (16-byte accesses; every operand 16-byte
-// aligned), else one.
+// The lazy 128-bit sum of at most 16 products below q^2 stays below q 2^64:
+// one REDC, and one more to undo its 2^-64, end it.
 __device__ __forceinline__ u64 mac_finish(u128w acc, const PrimeC &p)
 {
     return redc(mul_wide(redc(acc, p.q, p.qneg), p.r2), p.q, p.qneg);
-}
-
-template <bool PAIR>
-__global__ __launch_bounds__(EW_THREADS) void k_mac_multi(MacTerms T, u64 *out, int logN, int L1, int count, int add,
-                                                          const PrimeC *pc)
-{
-    const size_t N = (size_t)1 << logN;
-    const size_t n = (PAIR ? 2 : 1) * ((size_t)blockIdx.x * EW_THREADS + threadIdx.x);
-    if (n >= N) return;
-    const int limb = blockIdx.y, poly = blockIdx.z;
-    const PrimeC p = pc[limb];
-    const size_t per = (size_t)L1 * N, off = (size_t)poly * per + ((size_t)limb << logN) + n;
-    if (PAIR) {
-        u64x2 w[MAC_MAX_TERMS];
-#pragma unroll
-        for (int t = 0; t < MAC_MAX_TERMS; t++)
-            if (t < T.n) w[t] = ld2(T.pt[t] + ((size_t)limb << logN) + n);
-#pragma unroll 2
-        for (int c = 0; c < count; c++) {
-            u128w a0 = {0, 0}, a1 = {0, 0};
-#pragma unroll
-            for (int t = 0; t < MAC_MAX_TERMS; t++)
-                if (t < T.n) {
-                    const u64x2 v = ld2(T.src[t] + (size_t)c * T.stride[t] + off);
-                    acc_wide(a0, mul_wide(v.x, w[t].x));
-                    acc_wide(a1, mul_wide(v.y, w[t].y));
-                }
-            u64 *o = out + (size_t)c * 2 * per + off;
-            u64 r0 = mac_finish(a0, p), r1 = mac_finish(a1, p);
-            if (add) {
-                const u64x2 prev = ld2(o);
-                r0 = add_mod(prev.x, r0, p.q);
-                r1 = add_mod(prev.y, r1, p.q);
-            }
-            st2(o, r0, r1);
-        }
-        return;
-    }
-    u64 w[MAC_MAX_TERMS];
-#pragma unroll
-    for (int t = 0; t < MAC_MAX_TERMS; t++)
-        if (t < T.n) w[t] = T.pt[t][((size_t)limb << logN) + n];
-    for (int c = 0; c < count; c++) {
-        u128w acc = {0, 0};
-#pragma unroll
-        for (int t = 0; t < MAC_MAX_TERMS; t++)
-            if (t < T.n) acc_wide(acc, mul_wide(T.src[t][(size_t)c * T.stride[t] + off], w[t]));
-        const u64 r = mac_finish(acc, p);
-        u64 *o = out + (size_t)c * 2 * per + off;
-        *o = add ? add_mod(*o, r, p.q) : r;
-    }
-}
-
-void mac_multi_launch(const rbk_ctx_impl *c, const MacTerms &T, u64 *out, int level, int count, int add, hipStream_t st)
-{
-    if (T.n <= 0) return;
-    bool pair = ((uintptr_t)out & 15) == 0;
-    for (int t = 0; t < T.n; t++)
-        pair = pair && ((uintptr_t)T.src[t] & 15) == 0 && ((uintptr_t)T.pt[t] & 15) == 0 && T.stride[t] % 2 == 0;
-    const size_t threads = pair ? c->N / 2 : c->N;
-    dim3 grid((unsigned)((threads + EW_THREADS - 1) / EW_THREADS), level + 1, 2);
-    kt_begin(c, KC_ELEMENTWISE, st);
-    if (pair)
-        hipLaunchKernelGGL(k_mac_multi<true>, grid, dim3(EW_THREADS), 0, st, T, out, c->logN, level + 1, count, add,
-                           c->d_pc);
-    else
-        hipLaunchKernelGGL(k_mac_multi<false>, grid, dim3(EW_THREADS), 0, st, T, out, c->logN, level + 1, count, add,
-                           c->d_pc);
-    const double ct = 2.0 * (level + 1) * c->N * sizeof(u64);
-    kt_end(c, KC_ELEMENTWISE, ct * count * (T.n + (add ? 2 : 1)) + ct / 2 * T.n, st);
 }
 
 // Several giant steps of a baby-step / giant-step product in one pass: each

@@ -272,18 +272,6 @@ void decode_launch(const rbk_ctx_impl *c, const u64 *pt_coef, int level, double 
 void decrypt_launch(const rbk_ctx_impl *c, const u64 *ct, u64 *pt, int level, hipStream_t st);
 void modraise_lift_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int level, int npoly, hipStream_t st);
 void monomial_half_launch(const rbk_ctx_impl *c, const u64 *in, u64 *out, int npoly, int level, int neg, hipStream_t st);
-void mac_plain_launch(const rbk_ctx_impl *c, u64 *acc, const u64 *ct, long ct_stride, const u64 *pt, int level, int count,
-                      int first, hipStream_t st);
-constexpr int MAC_MAX_TERMS = 16;
-struct MacTerms {
-    const u64 *src[MAC_MAX_TERMS];  // ciphertext batches [count][2][l+1][N], ciphertext c at src + c * stride
-    long stride[MAC_MAX_TERMS];
-    const u64 *pt[MAC_MAX_TERMS];   // plaintexts [l+1][N] (or more limbs; limbs 0..l are read)
-    int n;
-};
-// out[c] = sum_t src_t[c] (.) pt_t  (+ out[c] when add), count ciphertexts at level l
-void mac_multi_launch(const rbk_ctx_impl *c, const MacTerms &T, u64 *out, int level, int count, int add,
-                      hipStream_t st);
 // up to GT_MAX_G giant steps of one BSGS product over GT_MAX_B baby-step
 // slots: out_j[c] = sum_b src_b[c] (.) pt_{j,b} (+ out_j[c] when add_j), count
 // ciphertexts at level l (pt_{j,b} null: no term; outs distinct from srcs)
