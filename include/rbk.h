@@ -14,7 +14,9 @@
  *    The library never frees caller memory.
  *  - A ciphertext at level l is `uint64_t[2][l+1][N]`, a plaintext
  *    `uint64_t[l+1][N]`; limb i holds residues modulo q_i, canonical in
- *    [0, q_i).  Batched calls take `count` of them back to back.
+ *    [0, q_i).  Batched calls take `count` of them back to back.  Device
+ *    buffers start on a 16-byte boundary (the kernels move adjacent residue
+ *    pairs; device allocations are 256-byte aligned).
  *  - Device ciphertexts and plaintexts are in the NTT (evaluation) domain:
  *    limb i of the transform of a(X) holds a(psi_i^(2k+1)) at index
  *    bit_reverse(k), psi_i the smallest primitive 2N-th root modulo q_i.

@@ -1408,6 +1408,7 @@ extern "C" int rbk_rotate_add_batch(rbk_ctx *c, const uint64_t *ct, const uint64
 {
     if (!c || !ct || !add || !out || count < 1) return fail(RBK_EINVAL, "bad argument");
     if (check_level(c, level)) return RBK_ELEVEL;
+    if (((uintptr_t)ct | (uintptr_t)add | (uintptr_t)out) & 15) return fail(RBK_EINVAL, "rotate_add: unaligned buffer");
     const size_t words = (size_t)count * 2 * (level + 1) * c->N;
     if (ranges_overlap(ct, words, out, words)) return fail(RBK_EINVAL, "rotate_add: input and output overlap");
     if (add != out && ranges_overlap(add, words, out, words))
