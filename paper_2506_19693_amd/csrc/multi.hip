@@ -66,6 +66,14 @@ __device__ __forceinline__ int owner(const int *prefix, int n, int b)
     return lo;
 }
 
+// Up to MG ciphertexts of one context whose key inner products share their
+// key-word loads: one thread serves one position of one limb for all of them
+constexpr int MG = 8;
+struct MultiGroup {
+    int n, beta_max, l1_max;
+    int ct[MG];
+};
+
 // (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); d2 also into coef (its
 // coefficient form is computed in place there)
 __global__ __launch_bounds__(MT) void k_tensor_multi(const MultiCt *cts, const int *prefix, int n)
@@ -134,37 +142,47 @@ __global__ __launch_bounds__(MT) void k_bconv_up_multi(const MultiCt *cts, const
     }
 }
 
-// special-prime part of the key inner product, tp [2][nP][N]; one block
-// range of ceil(N / 2 / MT) blocks per special prime, two coefficients a thread
+// special-prime part of the key inner product, tp [2][nP][N]; per group of
+// ciphertexts one block range of ceil(N / 2 / MT) blocks per special prime,
+// two coefficients a thread, the key words loaded once for the group
 template <int BETA>
-__global__ __launch_bounds__(MT) void k_ip_p_multi(const MultiCt *cts, const int *prefix, int n)
+__global__ __launch_bounds__(MT) void k_ip_p_multi(const MultiCt *cts, const MultiGroup *grp, const int *prefix, int n)
 {
-    const int ct = owner(prefix, n, blockIdx.x);
-    const MultiCt &C = cts[ct];
-    const size_t N = (size_t)1 << C.logN;
-    const int L1 = C.level + 1, E = L1 + C.nP, beta = (L1 + C.alpha - 1) / C.alpha;
+    const int gi = owner(prefix, n, blockIdx.x);
+    const MultiGroup &G = grp[gi];
+    const MultiCt &C0 = cts[G.ct[0]];
+    const size_t N = (size_t)1 << C0.logN;
     const int bpl = (int)((N / 2 + MT - 1) / MT);
-    const int lb = blockIdx.x - prefix[ct];
+    const int lb = blockIdx.x - prefix[gi];
     const int t = lb / bpl;
     const size_t k = 2 * ((size_t)(lb % bpl) * MT + threadIdx.x);
     if (k >= N) return;
-    const int pr = C.nQ + t;
-    const PrimeC p = C.pc[pr];
-    u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
+    const int pr = C0.nQ + t;
+    const PrimeC p = C0.pc[pr];
+    u64x2 kb[BETA], ka[BETA];
 #pragma unroll
     for (int j = 0; j < BETA; j++)
-        if (j < beta) {
-            const u64x2 kb = ld2(C.key + (((size_t)j * 2 + 0) * C.nT + pr) * N + k);
-            const u64x2 ka = ld2(C.key + (((size_t)j * 2 + 1) * C.nT + pr) * N + k);
-            const u64x2 dd = ld2(C.ext + ((size_t)j * E + L1 + t) * N + k);
-            acc_wide(s0, mul_wide(dd.x, kb.x));
-            acc_wide(t0, mul_wide(dd.y, kb.y));
-            acc_wide(s1, mul_wide(dd.x, ka.x));
-            acc_wide(t1, mul_wide(dd.y, ka.y));
+        if (j < G.beta_max) {
+            kb[j] = ld2(C0.key + (((size_t)j * 2 + 0) * C0.nT + pr) * N + k);
+            ka[j] = ld2(C0.key + (((size_t)j * 2 + 1) * C0.nT + pr) * N + k);
         }
-    u64 *o = C.tp + (size_t)t * N + k;
-    st2(o, redc(s0, p.q, p.qneg), redc(t0, p.q, p.qneg));
-    st2(o + (size_t)C.nP * N, redc(s1, p.q, p.qneg), redc(t1, p.q, p.qneg));
+    for (int r = 0; r < G.n; r++) {
+        const MultiCt &C = cts[G.ct[r]];
+        const int L1 = C.level + 1, E = L1 + C.nP, beta = (L1 + C.alpha - 1) / C.alpha;
+        u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < BETA; j++)
+            if (j < beta) {
+                const u64x2 dd = ld2(C.ext + ((size_t)j * E + L1 + t) * N + k);
+                acc_wide(s0, mul_wide(dd.x, kb[j].x));
+                acc_wide(t0, mul_wide(dd.y, kb[j].y));
+                acc_wide(s1, mul_wide(dd.x, ka[j].x));
+                acc_wide(t1, mul_wide(dd.y, ka[j].y));
+            }
+        u64 *o = C.tp + (size_t)t * N + k;
+        st2(o, redc(s0, p.q, p.qneg), redc(t0, p.q, p.qneg));
+        st2(o + (size_t)C.nP * N, redc(s1, p.q, p.qneg), redc(t1, p.q, p.qneg));
+    }
 }
 
 // ModDown base conversion P -> Q_l of one polynomial (blocks per polynomial = ceil(N / MT))
@@ -204,42 +222,55 @@ __global__ __launch_bounds__(MT) void k_bconv_down_multi(const MultiCt *cts, con
     }
 }
 
-// Q positions: mr = (IP - conv) P^-1 + (d0, d1); one block range per limb
+// Q positions: mr = (IP - conv) P^-1 + (d0, d1); per group of ciphertexts one
+// block range per limb (up to the group's highest level), the key words
+// loaded once for the ciphertexts of the group that have the limb
 template <int BETA>
-__global__ __launch_bounds__(MT) void k_moddown_ip_multi(const MultiCt *cts, const int *prefix, int n)
+__global__ __launch_bounds__(MT) void k_moddown_ip_multi(const MultiCt *cts, const MultiGroup *grp, const int *prefix,
+                                                         int n)
 {
-    const int ct = owner(prefix, n, blockIdx.x);
-    const MultiCt &C = cts[ct];
-    const size_t N = (size_t)1 << C.logN;
-    const int L1 = C.level + 1, E = L1 + C.nP, beta = (L1 + C.alpha - 1) / C.alpha;
+    const int gi = owner(prefix, n, blockIdx.x);
+    const MultiGroup &G = grp[gi];
+    const MultiCt &C0 = cts[G.ct[0]];
+    const size_t N = (size_t)1 << C0.logN;
     const int bpl = (int)((N / 2 + MT - 1) / MT);
-    const int lb = blockIdx.x - prefix[ct];
+    const int lb = blockIdx.x - prefix[gi];
     const int i = lb / bpl;
     const size_t k = 2 * ((size_t)(lb % bpl) * MT + threadIdx.x);
     if (k >= N) return;
-    const PrimeC p = C.pc[i];
-    u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
+    const PrimeC p = C0.pc[i];
+    const u64 pinv = C0.Pinv[i], pinv_sh = C0.Pinv_sh[i];
+    u64x2 kb[BETA], ka[BETA];
 #pragma unroll
     for (int j = 0; j < BETA; j++)
-        if (j < beta) {
-            const u64x2 kb = ld2(C.key + (((size_t)j * 2 + 0) * C.nT + i) * N + k);
-            const u64x2 ka = ld2(C.key + (((size_t)j * 2 + 1) * C.nT + i) * N + k);
-            const u64x2 dd = ld2(C.ext + ((size_t)j * E + i) * N + k);
-            acc_wide(s0, mul_wide(dd.x, kb.x));
-            acc_wide(t0, mul_wide(dd.y, kb.y));
-            acc_wide(s1, mul_wide(dd.x, ka.x));
-            acc_wide(t1, mul_wide(dd.y, ka.y));
+        if (j < G.beta_max) {
+            kb[j] = ld2(C0.key + (((size_t)j * 2 + 0) * C0.nT + i) * N + k);
+            ka[j] = ld2(C0.key + (((size_t)j * 2 + 1) * C0.nT + i) * N + k);
         }
-    const size_t li = (size_t)i * N + k, per = (size_t)L1 * N;
-    const u64 pinv = C.Pinv[i], pinv_sh = C.Pinv_sh[i];
-    const u64x2 c0 = ld2(C.conv + li), c1 = ld2(C.conv + per + li);
-    const u64x2 a0 = ld2(C.d + li), a1 = ld2(C.d + per + li);
-    const u64 v0 = add_mod(shoup(sub_mod(redc(s0, p.q, p.qneg), c0.x, p.q), pinv, pinv_sh, p.q), a0.x, p.q);
-    const u64 w0 = add_mod(shoup(sub_mod(redc(t0, p.q, p.qneg), c0.y, p.q), pinv, pinv_sh, p.q), a0.y, p.q);
-    const u64 v1 = add_mod(shoup(sub_mod(redc(s1, p.q, p.qneg), c1.x, p.q), pinv, pinv_sh, p.q), a1.x, p.q);
-    const u64 w1 = add_mod(shoup(sub_mod(redc(t1, p.q, p.qneg), c1.y, p.q), pinv, pinv_sh, p.q), a1.y, p.q);
-    st2(C.mr + li, v0, w0);
-    st2(C.mr + per + li, v1, w1);
+    for (int r = 0; r < G.n; r++) {
+        const MultiCt &C = cts[G.ct[r]];
+        const int L1 = C.level + 1, E = L1 + C.nP, beta = (L1 + C.alpha - 1) / C.alpha;
+        if (i >= L1) continue;
+        u128w s0 = {0, 0}, s1 = {0, 0}, t0 = {0, 0}, t1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < BETA; j++)
+            if (j < beta) {
+                const u64x2 dd = ld2(C.ext + ((size_t)j * E + i) * N + k);
+                acc_wide(s0, mul_wide(dd.x, kb[j].x));
+                acc_wide(t0, mul_wide(dd.y, kb[j].y));
+                acc_wide(s1, mul_wide(dd.x, ka[j].x));
+                acc_wide(t1, mul_wide(dd.y, ka[j].y));
+            }
+        const size_t li = (size_t)i * N + k, per = (size_t)L1 * N;
+        const u64x2 c0 = ld2(C.conv + li), c1 = ld2(C.conv + per + li);
+        const u64x2 a0 = ld2(C.d + li), a1 = ld2(C.d + per + li);
+        const u64 v0 = add_mod(shoup(sub_mod(redc(s0, p.q, p.qneg), c0.x, p.q), pinv, pinv_sh, p.q), a0.x, p.q);
+        const u64 w0 = add_mod(shoup(sub_mod(redc(t0, p.q, p.qneg), c0.y, p.q), pinv, pinv_sh, p.q), a0.y, p.q);
+        const u64 v1 = add_mod(shoup(sub_mod(redc(s1, p.q, p.qneg), c1.x, p.q), pinv, pinv_sh, p.q), a1.x, p.q);
+        const u64 w1 = add_mod(shoup(sub_mod(redc(t1, p.q, p.qneg), c1.y, p.q), pinv, pinv_sh, p.q), a1.y, p.q);
+        st2(C.mr + li, v0, w0);
+        st2(C.mr + per + li, v1, w1);
+    }
 }
 
 // rescale step 0: last[poly] = limb l of mr (blocks per polynomial = ceil(N / MT))
@@ -325,8 +356,43 @@ extern "C" int rbk_mult_relin_rescale_multi(rbk_ctx *c, const rbk_mr_item *items
 
     std::vector<MultiCt> cts((size_t)n);
     std::vector<NttItem> l_coef, l_ext, l_tp, l_conv, l_last, l_lift;
-    std::vector<int> p_ew(n + 1, 0), p_up(n + 1, 0), p_ipp(n + 1, 0), p_poly(n + 1, 0), p_mdip(n + 1, 0),
-        p_rs(n + 1, 0);
+    std::vector<int> p_ew(n + 1, 0), p_up(n + 1, 0), p_poly(n + 1, 0), p_rs(n + 1, 0);
+    // groups of up to MG ciphertexts of one context (their key inner products
+    // share the key-word loads), in the order the contexts first appear
+    std::vector<MultiGroup> groups;
+    {
+        std::vector<std::pair<const rbk_ctx *, int>> open;   // context -> its group being filled
+        for (int i = 0; i < n; i++) {
+            const rbk_ctx *ic = items[i].ctx;
+            int gi = -1;
+            for (auto &o : open)
+                if (o.first == ic && groups[o.second].n < MG) gi = o.second;
+            if (gi < 0) {
+                groups.push_back(MultiGroup{});
+                gi = (int)groups.size() - 1;
+                bool found = false;
+                for (auto &o : open)
+                    if (o.first == ic) {
+                        o.second = gi;
+                        found = true;
+                    }
+                if (!found) open.emplace_back(ic, gi);
+            }
+            MultiGroup &g = groups[gi];
+            const int L1 = items[i].level + 1;
+            g.ct[g.n++] = i;
+            g.beta_max = std::max(g.beta_max, (L1 + ic->alpha - 1) / ic->alpha);
+            g.l1_max = std::max(g.l1_max, L1);
+        }
+    }
+    const int ng = (int)groups.size();
+    std::vector<int> p_ipp(ng + 1, 0), p_mdip(ng + 1, 0);
+    for (int gi = 0; gi < ng; gi++) {
+        const rbk_ctx *ic = items[groups[gi].ct[0]].ctx;
+        const int bH = (int)((ic->N / 2 + MT - 1) / MT);
+        p_ipp[gi + 1] = p_ipp[gi] + ic->nP * bH;
+        p_mdip[gi + 1] = p_mdip[gi] + groups[gi].l1_max * bH;
+    }
     u64 *w = ws;
     for (int i = 0; i < n; i++) {
         rbk_ctx *ic = items[i].ctx;
@@ -367,12 +433,10 @@ extern "C" int rbk_mult_relin_rescale_multi(rbk_ctx *c, const rbk_mr_item *items
         C.lifted = C.last + 2 * N;
         w = C.lifted + 2 * (size_t)l * N;
         // block ranges of every kernel
-        const int bN = (int)((N + MT - 1) / MT), bH = (int)((N / 2 + MT - 1) / MT);
+        const int bN = (int)((N + MT - 1) / MT);
         p_ew[i + 1] = p_ew[i] + (int)(((size_t)L1 * N + MT - 1) / MT);
         p_up[i + 1] = p_up[i] + beta * bN;
-        p_ipp[i + 1] = p_ipp[i] + ic->nP * bH;
         p_poly[i + 1] = p_poly[i] + 2 * bN;
-        p_mdip[i + 1] = p_mdip[i] + L1 * bH;
         p_rs[i + 1] = p_rs[i] + (int)((2 * (size_t)l * N + MT - 1) / MT);
         // transforms: limbs each ciphertext owns
         auto item = [&](u64 *p, int prime) { return NttItem{p, ic->d_tabs, prime, ic->logN, ic->ntt_logC, 0}; };
@@ -395,6 +459,7 @@ extern "C" int rbk_mult_relin_rescale_multi(rbk_ctx *c, const rbk_mr_item *items
     }
     DescBlob b;
     const size_t o_cts = b.put(cts.data(), cts.size());
+    const size_t o_grp = b.put(groups.data(), groups.size());
     const size_t o_ew = b.put(p_ew.data(), p_ew.size()), o_up = b.put(p_up.data(), p_up.size());
     const size_t o_ipp = b.put(p_ipp.data(), p_ipp.size()), o_poly = b.put(p_poly.data(), p_poly.size());
     const size_t o_mdip = b.put(p_mdip.data(), p_mdip.size()), o_rs = b.put(p_rs.data(), p_rs.size());
@@ -422,6 +487,7 @@ extern "C" int rbk_mult_relin_rescale_multi(rbk_ctx *c, const rbk_mr_item *items
     const char *dev = desc_upload(c, b, &rc);
     if (!dev) return rc;
     const MultiCt *dc = reinterpret_cast<const MultiCt *>(dev + o_cts);
+    const MultiGroup *dg = reinterpret_cast<const MultiGroup *>(dev + o_grp);
     auto pre = [&](size_t o) { return reinterpret_cast<const int *>(dev + o); };
     hipStream_t st = c->stream;
     auto ntt = [&](const Packed &P, bool inverse) {
@@ -446,7 +512,7 @@ extern "C" int rbk_mult_relin_rescale_multi(rbk_ctx *c, const rbk_mr_item *items
     ntt(P_ext, false);
     kt_begin(c, KC_IP_P, st);
 #define IPM(B) \
-    case B: hipLaunchKernelGGL(k_ip_p_multi<B>, grid(p_ipp), dim3(MT), 0, st, dc, pre(o_ipp), n); break;
+    case B: hipLaunchKernelGGL(k_ip_p_multi<B>, grid(p_ipp), dim3(MT), 0, st, dc, dg, pre(o_ipp), ng); break;
     switch (max_beta) { IPM(1) IPM(2) IPM(3) IPM(4) IPM(5) IPM(6) IPM(7) default: IPM(8) }
 #undef IPM
     kt_end(c, KC_IP_P, 0.0, st);
@@ -462,7 +528,7 @@ extern "C" int rbk_mult_relin_rescale_multi(rbk_ctx *c, const rbk_mr_item *items
     ntt(P_conv, false);
     kt_begin(c, KC_MODDOWN_IP, st);
 #define MDM(B) \
-    case B: hipLaunchKernelGGL(k_moddown_ip_multi<B>, grid(p_mdip), dim3(MT), 0, st, dc, pre(o_mdip), n); break;
+    case B: hipLaunchKernelGGL(k_moddown_ip_multi<B>, grid(p_mdip), dim3(MT), 0, st, dc, dg, pre(o_mdip), ng); break;
     switch (max_beta) { MDM(1) MDM(2) MDM(3) MDM(4) MDM(5) MDM(6) MDM(7) default: MDM(8) }
 #undef MDM
     kt_end(c, KC_MODDOWN_IP, 0.0, st);
